@@ -1,0 +1,626 @@
+/*
+ * gcmc_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct FP64 CPU reference for the grand-canonical
+ * Monte Carlo (GCMC) energy path of Schwiebert et al., "An Efficient Cell List
+ * Implementation for Monte Carlo Simulation on GPUs" (arXiv 1408.3764).
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may load
+ * this library.  It shares no code, header, table or constant with the GPU
+ * library; the two are written independently from the paper and from the
+ * readings listed in the project's design notes.
+ *
+ * Every energy here is the plain all-pairs definition (the cell list of the
+ * paper only prunes pairs beyond the cutoff, so its result is the all-pairs
+ * result).  The one cell-list routine in this file exists only to check the
+ * GPU's cell assignment and neighbour sets bit-exactly.
+ *
+ * Compile with -O2 -ffp-contract=off (no FMA contraction anywhere).
+ *
+ * Pins (tests that tie this file to the paper and to mathematics rather than
+ * to itself) cover: the pair potential (closed forms), the tail correction
+ * (numerical quadrature and exact rational differences), minimum image (two-
+ * particle box across the boundary), half-sum identity, translation
+ * invariance, cell list = all-pairs brute force, the paper's worked numbers
+ * for the cell grid, the ideal-gas Poisson limit of the acceptance rules,
+ * Philox known-answer vectors, and finite differences for the gradients.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_MAX_SPECIES 4
+
+/* Force field, box and ensemble parameters.  eps/sigma are pair tables
+ * (ns x ns, symmetric), already mixed by the caller. */
+typedef struct {
+    double L[3];
+    double rc;
+    int32_t ns;
+    int32_t pad0;
+    double eps[ORACLE_MAX_SPECIES * ORACLE_MAX_SPECIES];
+    double sigma[ORACLE_MAX_SPECIES * ORACLE_MAX_SPECIES];
+    double beta;      /* 1/(k_B T), Eq. (2) */
+    double mu;        /* chemical potential, Eqs. (4)-(5) */
+    double lambda3;   /* thermal de Broglie wavelength cubed, Eqs. (4)-(5) */
+    double max_disp;  /* half-width of the uniform displacement cube */
+    double p_disp;    /* DisplacePercent of Algorithm 1 (as a fraction) */
+} oracle_params;
+
+/* One record per attempted move of the chain. */
+typedef struct {
+    int32_t type;      /* 0 displacement, 1 insertion, 2 deletion */
+    int32_t index;     /* particle index (displacement/deletion), new id (insertion) */
+    int32_t accepted;  /* 1 if the move was accepted */
+    int32_t flags;     /* bit0: rejected because N == 0 */
+    double dU_pair;    /* pair part of the energy change */
+    double dU_tail;    /* tail-correction part of the energy change */
+    double sumabs;     /* sum of |u| over the terms of dU_pair (tolerance scale) */
+    double x, y, z;    /* trial position (new position / insertion point / deleted particle) */
+    double arg;        /* log of the acceptance ratio */
+    double a;          /* the uniform A of the acceptance test */
+} oracle_log;
+
+/* ------------------------------------------------------------------------ */
+/* Compensated summation (Neumaier's variant of Kahan summation).           */
+/* ------------------------------------------------------------------------ */
+typedef struct { double s, c; } nsum;
+
+static void nsum_add(nsum* a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double nsum_get(const nsum* a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 counter-based generator, written from its definition in    */
+/* Salmon, Moraes, Dror and Shaw, "Parallel Random Numbers: As Easy as      */
+/* 1, 2, 3", SC'11: ten rounds, each a pair of 32x32->64 multiplications    */
+/* by the two round multipliers, with the key bumped by the two Weyl        */
+/* constants between rounds.                                                */
+/* ------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* A double in [0,1) from two 32-bit words: 27 high bits of a, 26 of b. */
+double oracle_u01(uint32_t a, uint32_t b)
+{
+    double hi = (double)(a >> 5);
+    double lo = (double)(b >> 6);
+    return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
+}
+
+/* The eight uniforms of one move.  key = (seed low, seed high);
+ * counter = (move low, move high, box id, j) for j = 0..3; each call gives
+ * two doubles, from output words (0,1) and (2,3).
+ *   u[0] = R of Algorithm 1 (move type)     u[1] = Source of Algorithm 1
+ *   u[2] = particle pick                    u[3] = A of the acceptance test
+ *   u[4..6] = position / displacement       u[7] = spare                     */
+void oracle_move_draws(uint64_t seed, uint64_t move, uint32_t box, double u[8])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (uint32_t j = 0; j < 4; ++j) {
+        uint32_t ctr[4] = {(uint32_t)move, (uint32_t)(move >> 32), box, j};
+        uint32_t w[4];
+        oracle_philox4x32_10(ctr, key, w);
+        u[2 * j] = oracle_u01(w[0], w[1]);
+        u[2 * j + 1] = oracle_u01(w[2], w[3]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lennard-Jones pair energy, Eq. (1), truncated (not shifted) at rc: only  */
+/* pairs strictly inside the cutoff contribute (Sec. 1 and Algorithm 3).    */
+/* ------------------------------------------------------------------------ */
+double oracle_lj_r2(double r2, double eps, double sigma, double rc)
+{
+    if (!(r2 < rc * rc))
+        return 0.0;
+    if (eps == 0.0)
+        return 0.0;
+    if (r2 == 0.0)
+        return INFINITY;
+    double sr2 = (sigma * sigma) / r2;
+    double sr6 = sr2 * sr2 * sr2;
+    double sr12 = sr6 * sr6;
+    return 4.0 * eps * (sr12 - sr6);
+}
+
+/* Minimum-image separation along one axis of length L (coordinates are kept
+ * in [0, L)).  This is the "true distance under periodic boundary
+ * conditions" of Algorithms 3, 4, 6 and 7. */
+double oracle_min_image(double d, double L)
+{
+    double h = 0.5 * L;
+    if (d > h)
+        d -= L;
+    else if (d < -h)
+        d += L;
+    return d;
+}
+
+double oracle_dist2(const double L[3], double xi, double yi, double zi, double xj, double yj, double zj)
+{
+    double dx = oracle_min_image(xj - xi, L[0]);
+    double dy = oracle_min_image(yj - yi, L[1]);
+    double dz = oracle_min_image(zj - zi, L[2]);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+static double pair_u(const oracle_params* p, int32_t a, int32_t b, double r2)
+{
+    int ns = p->ns;
+    return oracle_lj_r2(r2, p->eps[a * ns + b], p->sigma[a * ns + b], p->rc);
+}
+
+/* Energy of a particle of species ps at (px,py,pz) with every particle j of
+ * the configuration except `exclude` (Algorithms 3 and 4: one contribution
+ * per other particle).  sumabs = sum of |u| (scale for tolerances). */
+void oracle_position_energy(int64_t n, const double* x, const double* y, const double* z, const int32_t* sp,
+                            double px, double py, double pz, int32_t ps, int64_t exclude,
+                            const oracle_params* p, double out[2])
+{
+    nsum s = {0, 0}, a = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == exclude)
+            continue;
+        double r2 = oracle_dist2(p->L, px, py, pz, x[j], y[j], z[j]);
+        double u = pair_u(p, ps, sp ? sp[j] : 0, r2);
+        nsum_add(&s, u);
+        nsum_add(&a, fabs(u));
+    }
+    out[0] = nsum_get(&s);
+    out[1] = nsum_get(&a);
+}
+
+/* Total pair energy over the N(N-1)/2 unique pairs (Sec. 3.1.1), and the
+ * per-particle energies e_i = sum_{j != i} u(r_ij) when e != NULL.
+ * out[0] = U_pair, out[1] = sum over pairs of |u|, out[2] = U_tail. */
+double oracle_tail_energy(const int64_t* counts, const oracle_params* p);
+
+void oracle_total_energy(int64_t n, const double* x, const double* y, const double* z, const int32_t* sp,
+                         const oracle_params* p, double out[3], double* e)
+{
+    nsum s = {0, 0}, a = {0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            double r2 = oracle_dist2(p->L, x[i], y[i], z[i], x[j], y[j], z[j]);
+            double u = pair_u(p, sp ? sp[i] : 0, sp ? sp[j] : 0, r2);
+            nsum_add(&s, u);
+            nsum_add(&a, fabs(u));
+        }
+    }
+    out[0] = nsum_get(&s);
+    out[1] = nsum_get(&a);
+    int64_t counts[ORACLE_MAX_SPECIES] = {0};
+    for (int64_t i = 0; i < n; ++i)
+        counts[sp ? sp[i] : 0] += 1;
+    out[2] = oracle_tail_energy(counts, p);
+    if (e) {
+        for (int64_t i = 0; i < n; ++i) {
+            double pe[2];
+            oracle_position_energy(n, x, y, z, sp, x[i], y[i], z[i], sp ? sp[i] : 0, i, p, pe);
+            e[i] = pe[0];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tail correction (Sec. 1 names it; the paper gives no formula).  The      */
+/* textbook closed form for a truncated LJ potential with a uniform pair    */
+/* distribution beyond rc, ordered double sum over species:                 */
+/*   U_tail = (8 pi / (3 V)) sum_a sum_b N_a N_b K_ab,                     */
+/*   K_ab = eps_ab sigma_ab^3 [ (sigma_ab/rc)^9 / 3 - (sigma_ab/rc)^3 ].     */
+/* ------------------------------------------------------------------------ */
+static double tail_k(const oracle_params* p, int a, int b)
+{
+    int ns = p->ns;
+    double eps = p->eps[a * ns + b], sig = p->sigma[a * ns + b];
+    double q = sig / p->rc;
+    double q3 = q * q * q;
+    double q9 = q3 * q3 * q3;
+    return eps * sig * sig * sig * (q9 / 3.0 - q3);
+}
+
+static double box_volume(const oracle_params* p) { return (p->L[0] * p->L[1]) * p->L[2]; }
+
+double oracle_tail_energy(const int64_t* counts, const oracle_params* p)
+{
+    double V = box_volume(p);
+    double s = 0.0;
+    for (int a = 0; a < p->ns; ++a)
+        for (int b = 0; b < p->ns; ++b)
+            s += (double)counts[a] * (double)counts[b] * tail_k(p, a, b);
+    return (8.0 * M_PI / (3.0 * V)) * s;
+}
+
+/* U_tail(N + sign * e_s) - U_tail(N), expanded algebraically from the closed
+ * form above (sign = +1 insertion, -1 deletion of a particle of species s):
+ *   (8 pi/(3V)) [ 2 sign sum_b N_b K_sb + K_ss ]. */
+double oracle_tail_delta(const int64_t* counts, int32_t s, int32_t sign, const oracle_params* p)
+{
+    double V = box_volume(p);
+    double acc = 0.0;
+    for (int b = 0; b < p->ns; ++b)
+        acc += (double)counts[b] * tail_k(p, s, b);
+    return (8.0 * M_PI / (3.0 * V)) * (2.0 * (double)sign * acc + tail_k(p, s, s));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Acceptance, Eqs. (2)-(5).  arg is the log of the ratio inside min[1, .]. */
+/*   displacement:  -beta dU                                   (Eq. 3)      */
+/*   insertion:     ln(V / (Lambda^3 (N+1))) + beta (mu - dU)  (Eq. 4, with */
+/*                  the sign of the exponent read as in Eq. 5 / Frenkel &   */
+/*                  Smit)                                                   */
+/*   deletion:      ln(Lambda^3 N / V) - beta (mu + dU)        (Eq. 5)      */
+/* Accept iff arg >= 0 or A < exp(arg), with A uniform in [0,1); a NaN dU   */
+/* is rejected.                                                             */
+/* ------------------------------------------------------------------------ */
+double oracle_accept_arg(int32_t type, double dU, int64_t n, const oracle_params* p)
+{
+    double V = box_volume(p);
+    if (type == 0)
+        return -(p->beta * dU);
+    if (type == 1)
+        return log(V / (p->lambda3 * (double)(n + 1))) + p->beta * (p->mu - dU);
+    return log((p->lambda3 * (double)n) / V) - p->beta * (p->mu + dU);
+}
+
+int32_t oracle_accept(double arg, double dU, double A)
+{
+    if (isnan(dU))
+        return 0;
+    if (arg >= 0.0)
+        return 1;
+    return A < exp(arg) ? 1 : 0;
+}
+
+/* Periodic wrap of a coordinate back into [0, L). */
+static double wrap_coord(double x, double L)
+{
+    if (x >= L)
+        x -= L;
+    else if (x < 0.0)
+        x += L;
+    if (x >= L)
+        x = 0.0;
+    return x;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The serial GCMC chain of Algorithm 1, with the displacement of           */
+/* Algorithm 2 and the insertion/deletion of Algorithm 5, every energy      */
+/* change computed all-pairs.  Single species only.                         */
+/*                                                                          */
+/* Per move (counter = counter0 + m):                                       */
+/*   R < p_disp -> displacement; else Source < 0.5 -> deletion; else        */
+/*   insertion.  Displacement and deletion pick i = min(floor(u N), N-1)    */
+/*   and are rejected when N == 0.  Displacement: x' = wrap(x + d (2u-1))   */
+/*   per axis.  Insertion: x = wrap(L u).  On accepted insertion the new    */
+/*   particle gets index N; on accepted deletion particle N-1 takes index i.*/
+/* State: x,y,z[max_n], *n, *U (total energy incl. tail, running).          */
+/* Returns 0, or -1 if an insertion would exceed max_n (an error, never a   */
+/* rejection), or -2 for an unsupported parameter set.                      */
+/* ------------------------------------------------------------------------ */
+int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, double* U_io,
+                 const oracle_params* p, uint64_t seed, uint32_t box, uint64_t counter0, int64_t n_moves,
+                 oracle_log* log_out)
+{
+    if (p->ns != 1)
+        return -2;
+    int64_t n = *n_io;
+    double U = *U_io;
+    for (int64_t m = 0; m < n_moves; ++m) {
+        double u[8];
+        oracle_move_draws(seed, counter0 + (uint64_t)m, box, u);
+        oracle_log rec;
+        memset(&rec, 0, sizeof rec);
+        int32_t type;
+        if (u[0] < p->p_disp)
+            type = 0;
+        else if (u[1] < 0.5)
+            type = 2;
+        else
+            type = 1;
+        rec.type = type;
+        rec.a = u[3];
+        if (type != 1 && n == 0) {
+            rec.index = -1;
+            rec.flags = 1;
+            rec.accepted = 0;
+            if (log_out)
+                log_out[m] = rec;
+            continue;
+        }
+        int64_t i = 0;
+        if (type != 1) {
+            i = (int64_t)floor(u[2] * (double)n);
+            if (i > n - 1)
+                i = n - 1;
+        }
+        double dUp = 0.0, dUt = 0.0, sabs = 0.0;
+        double nx = 0, ny = 0, nz = 0;
+        if (type == 0) {
+            nx = wrap_coord(x[i] + p->max_disp * (2.0 * u[4] - 1.0), p->L[0]);
+            ny = wrap_coord(y[i] + p->max_disp * (2.0 * u[5] - 1.0), p->L[1]);
+            nz = wrap_coord(z[i] + p->max_disp * (2.0 * u[6] - 1.0), p->L[2]);
+            double eo[2], en[2];
+            oracle_position_energy(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, eo);
+            oracle_position_energy(n, x, y, z, NULL, nx, ny, nz, 0, i, p, en);
+            dUp = en[0] - eo[0];
+            sabs = en[1] + eo[1];
+            rec.index = (int32_t)i;
+        } else if (type == 1) {
+            nx = wrap_coord(p->L[0] * u[4], p->L[0]);
+            ny = wrap_coord(p->L[1] * u[5], p->L[1]);
+            nz = wrap_coord(p->L[2] * u[6], p->L[2]);
+            double en[2];
+            oracle_position_energy(n, x, y, z, NULL, nx, ny, nz, 0, -1, p, en);
+            int64_t counts[1] = {n};
+            dUp = en[0];
+            sabs = en[1];
+            dUt = oracle_tail_delta(counts, 0, +1, p);
+            rec.index = (int32_t)n;
+        } else {
+            nx = x[i]; ny = y[i]; nz = z[i];
+            double eo[2];
+            oracle_position_energy(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, eo);
+            int64_t counts[1] = {n};
+            dUp = -eo[0];
+            sabs = eo[1];
+            dUt = oracle_tail_delta(counts, 0, -1, p);
+            rec.index = (int32_t)i;
+        }
+        double dU = dUp + dUt;
+        double arg = oracle_accept_arg(type, dU, n, p);
+        int32_t acc = oracle_accept(arg, dU, u[3]);
+        rec.dU_pair = dUp;
+        rec.dU_tail = dUt;
+        rec.sumabs = sabs;
+        rec.x = nx; rec.y = ny; rec.z = nz;
+        rec.arg = arg;
+        if (acc) {
+            if (type == 0) {
+                x[i] = nx; y[i] = ny; z[i] = nz;
+            } else if (type == 1) {
+                if (n >= max_n) {
+                    *n_io = n;
+                    *U_io = U;
+                    return -1;
+                }
+                x[n] = nx; y[n] = ny; z[n] = nz;
+                n += 1;
+            } else {
+                x[i] = x[n - 1]; y[i] = y[n - 1]; z[i] = z[n - 1];
+                n -= 1;
+            }
+            U += dU;
+        }
+        rec.accepted = acc;
+        if (log_out)
+            log_out[m] = rec;
+    }
+    *n_io = n;
+    *U_io = U;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cell grid and neighbour sets, used only to check the GPU's cell list     */
+/* bit-exactly (Sec. 3.2).                                                  */
+/*                                                                          */
+/* Cells per axis: the largest T with S = L/T >= rc, at least 3 (the paper's*/
+/* rule: "if L < 3 rc, S = L/3"), i.e. M = max(3, floor(L/rc)); a request   */
+/* req_m > 0 overrides it (smaller cells).  invS = M/L.  Half-width of the  */
+/* stencil k = ceil(rc invS); the stencil along an axis is the 2k+1 cells   */
+/* around the particle's cell with periodic wrap, or all M cells when       */
+/* 2k+1 >= M.  Cell of a coordinate: min(floor(x invS), M-1).               */
+/* ------------------------------------------------------------------------ */
+void oracle_grid(const double L[3], double rc, const int32_t req_m[3], int32_t M[3], double invS[3],
+                 int32_t k[3], int32_t span[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        int32_t m = (int32_t)floor(L[a] / rc);
+        if (m < 3)
+            m = 3;
+        if (req_m && req_m[a] > 0)
+            m = req_m[a];
+        M[a] = m;
+        invS[a] = (double)m / L[a];
+        int32_t kk = (int32_t)ceil(rc * invS[a]);
+        if (kk < 1)
+            kk = 1;
+        k[a] = kk;
+        span[a] = (2 * kk + 1 >= m) ? m : 2 * kk + 1;
+    }
+}
+
+static int32_t axis_cell(double x, double invS, int32_t M)
+{
+    int64_t c = (int64_t)floor(x * invS);
+    if (c > M - 1)
+        c = M - 1;
+    if (c < 0)
+        c = 0;
+    return (int32_t)c;
+}
+
+int64_t oracle_cell_of(double x, double y, double z, const int32_t M[3], const double invS[3])
+{
+    int64_t cx = axis_cell(x, invS[0], M[0]);
+    int64_t cy = axis_cell(y, invS[1], M[1]);
+    int64_t cz = axis_cell(z, invS[2], M[2]);
+    return (cz * M[1] + cy) * M[0] + cx;
+}
+
+/* Axis-wise stencil membership: is cell coordinate c within the stencil of
+ * centre coordinate c0 on an axis of M cells with half-width k? */
+static int in_axis_stencil(int32_t c, int32_t c0, int32_t k, int32_t M)
+{
+    if (2 * k + 1 >= M)
+        return 1;
+    for (int32_t t = -k; t <= k; ++t) {
+        int32_t w = ((c0 + t) % M + M) % M;
+        if (w == c)
+            return 1;
+    }
+    return 0;
+}
+
+/* Sorted ids j != exclude of the particles whose cell lies in the stencil of
+ * the cell of (px,py,pz).  Returns the number of ids (writes at most max_out). */
+int64_t oracle_neighbor_ids(int64_t n, const double* x, const double* y, const double* z,
+                            double px, double py, double pz, int64_t exclude,
+                            const double L[3], double rc, const int32_t req_m[3],
+                            int64_t* out, int64_t max_out)
+{
+    int32_t M[3], k[3], span[3];
+    double invS[3];
+    oracle_grid(L, rc, req_m, M, invS, k, span);
+    int32_t c0[3] = {axis_cell(px, invS[0], M[0]), axis_cell(py, invS[1], M[1]), axis_cell(pz, invS[2], M[2])};
+    int64_t cnt = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == exclude)
+            continue;
+        int32_t cj[3] = {axis_cell(x[j], invS[0], M[0]), axis_cell(y[j], invS[1], M[1]),
+                         axis_cell(z[j], invS[2], M[2])};
+        int ok = 1;
+        for (int a = 0; a < 3 && ok; ++a)
+            ok = in_axis_stencil(cj[a], c0[a], k[a], M[a]);
+        if (ok) {
+            if (cnt < max_out)
+                out[cnt] = j;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Analytic gradient of U = U_pair + U_tail (derivative of Eq. (1)).        */
+/*   dU/dr_i = sum_j (24 eps / r^2) (2 s12 - s6) d_ij, d_ij = r_j - r_i     */
+/*             (minimum image), s6 = (sigma^2/r^2)^3, s12 = s6^2.           */
+/*   dU/deps[a][b], dU/dsig[a][b]: the derivative with respect to the       */
+/*   matrix entry, each unordered pair of species types (a,b), a != b,      */
+/*   contributing half to [a][b] and half to [b][a] (the derivative of U    */
+/*   written with the symmetrised tables); the tail term (ordered double    */
+/*   sum) contributes its (a,b) term to [a][b].  rc is held fixed.          */
+/* Pairs beyond the cutoff contribute nothing (truncated potential).        */
+/* ------------------------------------------------------------------------ */
+static void pair_grad_terms(const oracle_params* p, int32_t a, int32_t b, double r2,
+                            double* coef, double* deps, double* dsig)
+{
+    int ns = p->ns;
+    double eps = p->eps[a * ns + b], sig = p->sigma[a * ns + b];
+    *coef = 0.0; *deps = 0.0; *dsig = 0.0;
+    if (!(r2 < p->rc * p->rc) || r2 == 0.0)
+        return;
+    double sr2 = (sig * sig) / r2;
+    double s6 = sr2 * sr2 * sr2;
+    double s12 = s6 * s6;
+    *coef = (24.0 * eps / r2) * (2.0 * s12 - s6);
+    *deps = 4.0 * (s12 - s6);
+    *dsig = (4.0 * eps / sig) * (12.0 * s12 - 6.0 * s6);
+}
+
+/* Gradient of one particle's position (O(N)): gi[3]. */
+void oracle_particle_gradient(int64_t n, const double* x, const double* y, const double* z, const int32_t* sp,
+                              int64_t i, const oracle_params* p, double gi[3])
+{
+    nsum gx = {0, 0}, gy = {0, 0}, gz = {0, 0};
+    int32_t a = sp ? sp[i] : 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i)
+            continue;
+        double dx = oracle_min_image(x[j] - x[i], p->L[0]);
+        double dy = oracle_min_image(y[j] - y[i], p->L[1]);
+        double dz = oracle_min_image(z[j] - z[i], p->L[2]);
+        double r2 = (dx * dx + dy * dy) + dz * dz;
+        double coef, de, ds;
+        pair_grad_terms(p, a, sp ? sp[j] : 0, r2, &coef, &de, &ds);
+        nsum_add(&gx, coef * dx);
+        nsum_add(&gy, coef * dy);
+        nsum_add(&gz, coef * dz);
+    }
+    gi[0] = nsum_get(&gx);
+    gi[1] = nsum_get(&gy);
+    gi[2] = nsum_get(&gz);
+}
+
+void oracle_gradients(int64_t n, const double* x, const double* y, const double* z, const int32_t* sp,
+                      const oracle_params* p, double* gx, double* gy, double* gz, double* d_eps, double* d_sig)
+{
+    int ns = p->ns;
+    if (gx) {
+        for (int64_t i = 0; i < n; ++i) {
+            double g[3];
+            oracle_particle_gradient(n, x, y, z, sp, i, p, g);
+            gx[i] = g[0]; gy[i] = g[1]; gz[i] = g[2];
+        }
+    }
+    nsum de[ORACLE_MAX_SPECIES * ORACLE_MAX_SPECIES], ds[ORACLE_MAX_SPECIES * ORACLE_MAX_SPECIES];
+    memset(de, 0, sizeof de);
+    memset(ds, 0, sizeof ds);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            int32_t a = sp ? sp[i] : 0, b = sp ? sp[j] : 0;
+            double r2 = oracle_dist2(p->L, x[i], y[i], z[i], x[j], y[j], z[j]);
+            double coef, e1, s1;
+            pair_grad_terms(p, a, b, r2, &coef, &e1, &s1);
+            if (a == b) {
+                nsum_add(&de[a * ns + b], e1);
+                nsum_add(&ds[a * ns + b], s1);
+            } else {
+                nsum_add(&de[a * ns + b], 0.5 * e1);
+                nsum_add(&de[b * ns + a], 0.5 * e1);
+                nsum_add(&ds[a * ns + b], 0.5 * s1);
+                nsum_add(&ds[b * ns + a], 0.5 * s1);
+            }
+        }
+    }
+    int64_t counts[ORACLE_MAX_SPECIES] = {0};
+    for (int64_t i = 0; i < n; ++i)
+        counts[sp ? sp[i] : 0] += 1;
+    double V = box_volume(p);
+    for (int a = 0; a < ns; ++a) {
+        for (int b = 0; b < ns; ++b) {
+            double eps = p->eps[a * ns + b], sig = p->sigma[a * ns + b];
+            double q = sig / p->rc;
+            double q3 = q * q * q, q9 = q3 * q3 * q3;
+            double pref = (8.0 * M_PI / (3.0 * V)) * (double)counts[a] * (double)counts[b];
+            /* d/d eps of eps sig^3 (q^9/3 - q^3) and d/d sig of the same */
+            double t_e = sig * sig * sig * (q9 / 3.0 - q3);
+            double t_s = eps * (4.0 * sig * sig * q9 - 6.0 * sig * sig * q3);
+            d_eps[a * ns + b] = nsum_get(&de[a * ns + b]) + pref * t_e;
+            d_sig[a * ns + b] = nsum_get(&ds[a * ns + b]) + pref * t_s;
+        }
+    }
+}

@@ -1,0 +1,441 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+None of these compares the oracle with itself: each uses a closed form, an
+exact rational computation, a quadrature, an independent brute-force definition,
+an invariant, a statistical law, or a number the paper prints.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1408_3764_amd import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (the seeded generator shared by both sides)
+# --------------------------------------------------------------------------
+def test_philox_known_answers(orc):
+    path = os.path.join(ROOT, "tests", "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        w = [int(v, 16) for v in r]
+        out = orc.philox4x32_10(w[0:4], w[4:6])
+        assert [int(v) for v in out] == w[6:10]
+
+
+def test_u01_bounds(orc):
+    # 27 + 26 bits -> multiples of 2^-53 in [0, 1)
+    assert orc.u01(0, 0) == 0.0
+    assert orc.u01(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0 ** -53
+    assert orc.u01(1 << 5, 0) == 2.0 ** -27
+    assert orc.u01(0, 1 << 6) == 2.0 ** -53
+
+
+def test_move_draw_layout(orc):
+    # counter (move lo, move hi, box, j), key (seed lo, seed hi), doubles from words (0,1),(2,3)
+    seed, move, box = 0x0123456789ABCDEF, (7 << 32) | 5, 3
+    u = orc.move_draws(seed, move, box)
+    for j in range(4):
+        w = orc.philox4x32_10([5, 7, box, j], [seed & 0xFFFFFFFF, seed >> 32])
+        assert u[2 * j] == orc.u01(w[0], w[1])
+        assert u[2 * j + 1] == orc.u01(w[2], w[3])
+
+
+# --------------------------------------------------------------------------
+# Eq. (1): the Lennard-Jones pair energy, truncated at rc
+# --------------------------------------------------------------------------
+def _lj_exact(r, eps=1, sig=1):
+    q = Fraction(sig) / Fraction(r)
+    return 4 * Fraction(eps) * (q ** 12 - q ** 6)
+
+
+def test_lj_closed_forms(orc):
+    assert orc.lj_r2(1.0, 1.0, 1.0, 2.5) == 0.0                       # u(sigma) = 0
+    rmin2 = 2.0 ** (1.0 / 3.0)                                         # r_min^2 = 2^(1/3)
+    assert orc.lj_r2(rmin2, 1.0, 1.0, 2.5) == pytest.approx(-1.0, rel=1e-15, abs=1e-15)
+    for r in (0.9, 1.5, 2.0, 2.4999):
+        assert orc.lj_r2(r * r, 1.0, 1.0, 2.5) == pytest.approx(float(_lj_exact(Fraction(r))), rel=1e-14)
+    assert orc.lj_r2(1.5 ** 2, 1.0, 1.0, 2.5) == pytest.approx(-0.320336594278575, rel=1e-14)
+    # scaling: u_{eps,sig}(r) = eps * u_{1,1}(r/sig)
+    for eps, sig, r in ((0.8, 1.2, 1.7), (2.0, 0.9, 1.1)):
+        assert orc.lj_r2(r * r, eps, sig, 10.0) == pytest.approx(
+            eps * float(_lj_exact(Fraction(r) / Fraction(sig))), rel=1e-13)
+
+
+def test_lj_cutoff_strict(orc):
+    rc = 2.5
+    assert orc.lj_r2(rc * rc, 1.0, 1.0, rc) == 0.0                    # r == rc is outside
+    below = np.nextafter(rc * rc, 0.0)
+    assert orc.lj_r2(below, 1.0, 1.0, rc) < 0.0                        # just inside counts
+    assert orc.lj_r2(9.0, 1.0, 1.0, 2.5) == 0.0
+    assert orc.lj_r2(0.0, 1.0, 1.0, 2.5) == math.inf                   # overlap: +inf, rejected later
+    assert orc.lj_r2(0.0, 0.0, 1.0, 2.5) == 0.0                        # ideal gas never interacts
+
+
+# --------------------------------------------------------------------------
+# Minimum image: independent definition = min over all 27 periodic images
+# --------------------------------------------------------------------------
+def _bruteforce_energy(pos, L, rc, eps=1.0, sig=1.0):
+    """Pure-Python all-pairs energy, distance = minimum over the 27 image shifts."""
+    n = len(pos)
+    shifts = np.array([[a, b, c] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)], dtype=float)
+    U = Fraction(0)
+    for i in range(n):
+        for j in range(i + 1, n):
+            d = pos[j] - pos[i] + shifts * L
+            r2 = float(np.min((d * d).sum(axis=1)))
+            if r2 < rc * rc:
+                U += _lj_exact(Fraction(math.sqrt(r2)), eps, sig)
+    return float(U)
+
+
+def test_two_particle_across_boundary(orc):
+    L = np.array([10.0, 11.0, 12.0])
+    p = orc.make_params(L, 2.5)
+    for pos in (np.array([[0.25, 5.0, 6.0], [8.75, 5.0, 6.0]]),          # r = 1.5 through x = 0
+                np.array([[0.2, 0.3, 0.4], [9.3, 10.5, 11.6]])):        # diagonal through a corner
+        d = pos[1] - pos[0]
+        d -= L * np.round(d / L)
+        r = float(np.sqrt((d * d).sum()))
+        U = orc.total_energy(pos, p)["U_pair"]
+        assert U == pytest.approx(float(_lj_exact(Fraction(r))), rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_allpairs_equals_image_bruteforce(orc, seed):
+    b = workloads.random_box(24, [5.6, 6.1, 7.3], seed=seed)
+    p = orc.make_params(b.L, 2.5)
+    U = orc.total_energy(b.pos, p)["U_pair"]
+    assert U == pytest.approx(_bruteforce_energy(b.pos, b.L, 2.5), rel=1e-12, abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Tail correction: closed form vs quadrature of the definition
+# --------------------------------------------------------------------------
+def test_tail_closed_form_vs_quadrature(orc):
+    from scipy.integrate import quad
+    for rc in (2.5, 3.0):
+        L = np.array([13.0, 14.0, 15.0])
+        V = float((L[0] * L[1]) * L[2])
+        p = orc.make_params(L, rc)
+        N = 1234
+        integ, _ = quad(lambda r: r * r * 4.0 * (r ** -12 - r ** -6), rc, np.inf, epsabs=0, epsrel=1e-13)
+        ref = 2.0 * math.pi * N * N / V * integ
+        assert orc.tail_energy([N], p) == pytest.approx(ref, rel=1e-11)
+    # per-N^2/V constants for unit LJ
+    p = orc.make_params([1.0, 1.0, 1.0], 2.5)
+    assert orc.tail_energy([1], p) == pytest.approx(-0.535433102066, rel=1e-11)
+    p = orc.make_params([1.0, 1.0, 1.0], 3.0)
+    assert orc.tail_energy([1], p) == pytest.approx(-0.310138880850, rel=1e-11)
+
+
+def test_tail_mixture_vs_quadrature(orc):
+    from scipy.integrate import quad
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    L = np.array([20.0, 21.0, 22.0])
+    V = float((L[0] * L[1]) * L[2])
+    rc = 3.0
+    p = orc.make_params(L, rc, eps=eps, sigma=sig)
+    counts = [700, 300]
+    ref = 0.0
+    for a in range(2):
+        for b in range(2):
+            f = lambda r, e=eps[a, b], s=sig[a, b]: r * r * 4.0 * e * ((s / r) ** 12 - (s / r) ** 6)
+            integ, _ = quad(f, rc, np.inf, epsabs=0, epsrel=1e-13)
+            ref += 2.0 * math.pi / V * counts[a] * counts[b] * integ
+    assert orc.tail_energy(counts, p) == pytest.approx(ref, rel=1e-11)
+
+
+def test_tail_delta_exact_differences(orc):
+    """The algebraic insertion/deletion delta equals U(N +- e_s) - U(N)."""
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    for ns in (1, 2):
+        p = orc.make_params([30.0, 31.0, 32.0], 3.0, eps=eps[:ns, :ns], sigma=sig[:ns, :ns])
+        base = [262144, 1000][:ns]
+        for sp in range(ns):
+            for sign in (+1, -1):
+                after = list(base)
+                after[sp] += sign
+                ref = orc.tail_energy(after, p) - orc.tail_energy(base, p)
+                got = orc.tail_delta(base, sp, sign, p)
+                assert abs(got - ref) <= 1e-12 * abs(orc.tail_energy(base, p))
+                if ns == 1:
+                    # exact rational: U_tail is k N^2, so the delta is k ((N +- 1)^2 - N^2)
+                    k1 = Fraction(orc.tail_energy([1], p))
+                    exact = k1 * (Fraction(base[0] + sign) ** 2 - Fraction(base[0]) ** 2)
+                    assert got == pytest.approx(float(exact), rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Invariants of the total energy
+# --------------------------------------------------------------------------
+def test_half_sum_identity(orc):
+    b = workloads.random_box(300, 9.0, seed=11)
+    p = orc.make_params(b.L, 2.5)
+    r = orc.total_energy(b.pos, p, per_particle=True)
+    assert 0.5 * math.fsum(r["e"]) == pytest.approx(r["U_pair"], rel=1e-13)
+
+
+def test_translation_invariance(orc):
+    b = workloads.random_box(300, [9.0, 10.0, 11.0], seed=12)
+    p = orc.make_params(b.L, 2.5)
+    U0 = orc.total_energy(b.pos, p)["U_pair"]
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        shift = rng.uniform(-20, 20, 3)
+        q = np.mod(b.pos + shift, b.L)
+        q = np.where(q >= b.L, 0.0, q)
+        U = orc.total_energy(q, p)["U_pair"]
+        assert U == pytest.approx(U0, rel=1e-12)
+        # and the energy change of a fixed trial displacement is invariant too
+        t = b.pos[7] + np.array([0.2, -0.1, 0.25])
+        e0 = orc.position_energy(b.pos, p, np.mod(t, b.L), exclude=7)[0]
+        e1 = orc.position_energy(q, p, np.mod(t + shift, b.L), exclude=7)[0]
+        assert e1 == pytest.approx(e0, rel=1e-12, abs=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Cell grid: the paper's worked numbers (Sec. 3.2.2, Sec. 3.3, Sec. 3.3.2)
+# --------------------------------------------------------------------------
+def test_cell_size_worked_example(orc, golden):
+    g = golden["cell_size_example"]
+    r = orc.grid([g["L"]] * 3, g["rc"])
+    assert int(r["M"][0]) == g["T"]
+    S = g["L"] / r["M"][0]
+    assert round(S, g["S_print_digits"]) == g["S_printed"]
+    assert S >= g["rc"]
+    sm = golden["small_box_rule"]
+    r = orc.grid([sm["L"]] * 3, sm["rc"])
+    assert int(r["M"][0]) == sm["T"]
+    assert int(r["span"][0]) == 3                                     # the whole axis is in the stencil
+
+
+def test_cell_count_exact_box_length(orc):
+    # L = cbrt(8000) = 20 exactly gives 8 cells of side 2.5; 8000**(1/3) would give 7
+    assert int(orc.grid([np.cbrt(8000.0)] * 3, 2.5)["M"][0]) == 8
+    assert int(orc.grid([8000.0 ** (1 / 3)] * 3, 2.5)["M"][0]) == 7
+
+
+def test_stencil_volume_numbers(golden):
+    g = golden["stencil_volume"]
+    assert round(4.0 / 3.0 * math.pi * g["rc"] ** 3, 2) == g["sphere_volume"]
+    assert 27 * g["S_a"] ** 3 > g["cells_volume_a"]
+    assert 27 * g["S_b"] ** 3 == g["cells_volume_b"]
+    assert (4.0 / 3.0 * math.pi * g["rc"] ** 3) / (27 * g["S_b"] ** 3) < g["max_useful_fraction"]
+
+
+def test_microcell_offset_example(orc, golden):
+    """sigma-sized cells with rc = 2.5: the stencil of cell (7,6,5) is the 7x7x7 cube (4,3,2)..(10,9,8)."""
+    g = golden["microcell_offset_example"]
+    L = 20.0
+    req = np.array([20, 20, 20], dtype=np.int32)                       # unit cells
+    r = orc.grid([L] * 3, 2.5, req)
+    assert list(r["span"]) == [g["cube"]] * 3
+    cells = np.array([[x + 0.5, y + 0.5, z + 0.5] for x in range(20) for y in range(20) for z in range(20)])
+    ids = orc.neighbor_ids(cells, np.array(g["center"]) + 0.5, [L] * 3, 2.5, req_m=req)
+    got = cells[ids] - 0.5
+    lo, hi = np.array(g["first_cell"]), np.array(g["last_cell"])
+    assert len(ids) == g["cube"] ** 3
+    assert np.all(got.min(axis=0) == lo) and np.all(got.max(axis=0) == hi)
+
+
+def test_paper_box_volumes(golden):
+    g = golden["table1_box_volumes"]
+    assert round(g["n_small"] / g["rho"], g["print_decimals"]) == g["V_small"]
+    # The printed 436905.6 is N/rho for rho = 0.6 only to 2.5e-6 relative (N/0.6 = 436906.7);
+    # the workloads take V = N/rho exactly (a reading of an inconsistency in the paper).
+    assert g["n_large"] / g["rho"] == pytest.approx(g["V_large"], rel=3e-6)
+
+
+# --------------------------------------------------------------------------
+# Cell list = all-pairs (brute force on tiny boxes, including points at faces)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L,n,seed", [(7.4, 120, 1), (10.0, 300, 2), (12.7, 300, 3), ([7.6, 10.0, 12.7], 250, 4)])
+def test_cell_list_covers_cutoff(orc, L, n, seed):
+    b = workloads.random_box(n, L, seed=seed)
+    pos = b.pos.copy()
+    g = orc.grid(b.L, 2.5)
+    # push a few particles to within 1e-12 of cell faces
+    rng = np.random.default_rng(seed)
+    for i in range(0, n, 17):
+        a = rng.integers(0, 3)
+        f = rng.integers(0, g["M"][a]) * (b.L[a] / g["M"][a])
+        pos[i, a] = min(max(f + rng.choice([-1e-12, 0.0, 1e-12]), 0.0), np.nextafter(b.L[a], 0))
+    p = orc.make_params(b.L, 2.5)
+    rc2 = 2.5 * 2.5
+    for i in range(0, n, 5):
+        ids = orc.neighbor_ids(pos, pos[i], b.L, 2.5, exclude=i)
+        d = pos - pos[i]
+        d -= b.L * np.round(d / b.L)
+        r2 = (d * d).sum(axis=1)
+        within = set(np.nonzero(r2 < rc2)[0]) - {i}
+        missing = within - set(ids.tolist())
+        for j in missing:   # only pairs at the cutoff to rounding accuracy may be missed
+            assert abs(math.sqrt(r2[j]) - 2.5) <= 1e-12 * 2.5
+        e_all = orc.position_energy(pos, p, pos[i], exclude=i)[0]
+        e_cell = math.fsum(orc.lj_r2(orc.min_image(pos[j, 0] - pos[i, 0], b.L[0]) ** 2
+                                     + orc.min_image(pos[j, 1] - pos[i, 1], b.L[1]) ** 2
+                                     + orc.min_image(pos[j, 2] - pos[i, 2], b.L[2]) ** 2, 1.0, 1.0, 2.5)
+                           for j in ids)
+        assert e_cell == pytest.approx(e_all, rel=1e-13, abs=1e-13)
+
+
+# --------------------------------------------------------------------------
+# GCMC acceptance: ideal-gas limit (Poisson), displacement accepts all
+# --------------------------------------------------------------------------
+def test_ideal_gas_poisson(orc):
+    """eps = 0: N is Poisson with mean V exp(beta mu) / Lambda^3.  Pins the sign of
+    the insertion exponent and the prefactors of Eqs. (4)-(5)."""
+    L = np.array([4.0, 4.0, 4.0])
+    V = 64.0
+    beta, mu = 1.0 / 1.3, -0.4
+    mean = V * math.exp(beta * mu) / 1.0
+    p = orc.make_params(L, 1.5, eps=0.0, beta=beta, mu=mu)
+    pos = np.zeros((0, 3))
+    n_moves = 400_000
+    _, _, log = orc.chain(pos, n_moves, p, seed=99, max_n=400)
+    d = np.where(log["accepted"] == 1, np.where(log["type"] == 1, 1, np.where(log["type"] == 2, -1, 0)), 0)
+    n_t = np.cumsum(d)[50_000:]
+    nb = 50
+    means = np.array([c.mean() for c in np.array_split(n_t, nb)])
+    se = means.std(ddof=1) / math.sqrt(nb)
+    assert abs(n_t.mean() - mean) < 5 * se + 0.01 * mean, (n_t.mean(), mean, se)
+    assert n_t.var() == pytest.approx(mean, rel=0.1)
+    # the flipped reading exp(-beta(mu - dU)) would give V exp(-beta mu): far away
+    assert abs(V * math.exp(-beta * mu) - n_t.mean()) > 20 * se
+
+
+def test_ideal_gas_displacements_all_accepted(orc):
+    b = workloads.random_box(50, 6.0, seed=3)
+    p = orc.make_params(b.L, 2.5, eps=0.0, p_disp=1.0)
+    _, _, log = orc.chain(b.pos, 2000, p, seed=7)
+    assert np.all(log["type"] == 0) and np.all(log["accepted"] == 1)
+
+
+def test_chain_energy_bookkeeping(orc):
+    """Running U (sum of accepted dU) equals the recomputed U_pair + U_tail after many moves."""
+    b = workloads.random_box(200, 8.0, seed=21, T=1.2)
+    p = orc.make_params(b.L, 2.5, beta=1.0 / 1.2, mu=-3.0)
+    t0 = orc.total_energy(b.pos, p)
+    U0 = t0["U_pair"] + t0["U_tail"]
+    pos, U, log = orc.chain(b.pos, 3000, p, seed=5, U0=U0)
+    t1 = orc.total_energy(pos, p)
+    assert U == pytest.approx(t1["U_pair"] + t1["U_tail"], rel=1e-10, abs=1e-9)
+    kinds = {int(t): int(log["accepted"][log["type"] == t].sum()) for t in (0, 1, 2)}
+    assert kinds[0] > 0 and kinds[1] > 0 and kinds[2] > 0
+    assert len(pos) == 200 + kinds[1] - kinds[2]
+
+
+def test_chain_empty_box_rejects(orc):
+    p = orc.make_params([6.0] * 3, 2.5, mu=-30.0)
+    _, _, log = orc.chain(np.zeros((0, 3)), 300, p, seed=3)
+    empty = (log["flags"] & 1) == 1
+    assert np.all(log["type"][empty] != 1) and np.all(log["accepted"][empty] == 0)
+    assert empty.any()
+
+
+def test_acceptance_rule_forms(orc):
+    """Eq. (3)-(5) with Lambda^3 = 1: ratio = min(1, B_F), V B_F'/(N+1), N B_F''/V."""
+    p = orc.make_params([5.0, 6.0, 7.0], 2.5, beta=0.5, mu=-1.5, lambda3=2.0)
+    V = 210.0
+    assert math.exp(orc.accept_arg(0, 0.7, 10, p)) == pytest.approx(math.exp(-0.5 * 0.7), rel=1e-14)
+    assert math.exp(orc.accept_arg(1, 0.7, 10, p)) == pytest.approx(
+        V / (2.0 * 11) * math.exp(0.5 * (-1.5 - 0.7)), rel=1e-14)
+    assert math.exp(orc.accept_arg(2, 0.7, 10, p)) == pytest.approx(
+        2.0 * 10 / V * math.exp(-0.5 * (-1.5 + 0.7)), rel=1e-14)
+    assert orc.accept(0.1, 0.0, 0.999) == 1
+    assert orc.accept(-1.0, 1.0, math.exp(-1.0)) == 0                 # strict A < ratio
+    assert orc.accept(-math.inf, math.inf, 0.0) == 0
+    assert orc.accept(0.0, float("nan"), 0.0) == 0
+
+
+# --------------------------------------------------------------------------
+# Gradients: closed form, Newton's third law, homogeneity, virial, FD
+# --------------------------------------------------------------------------
+def test_two_particle_force_closed_form(orc):
+    L = np.array([10.0, 10.0, 10.0])
+    p = orc.make_params(L, 2.5)
+    for r in (1.05, 1.3, 2.2):
+        pos = np.array([[1.0, 2.0, 3.0], [1.0 + r, 2.0, 3.0]])
+        g, _, _ = orc.gradients(pos, p)
+        dudr = float(-24 * (2 * Fraction(r) ** -13 - Fraction(r) ** -7))   # d/dr 4(r^-12 - r^-6)
+        assert g[1, 0] == pytest.approx(dudr, rel=1e-13)
+        assert g[0, 0] == pytest.approx(-dudr, rel=1e-13)
+        assert abs(g[0, 1]) < 1e-15 and abs(g[1, 2]) < 1e-15
+
+
+def test_gradient_invariants(orc):
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    b = workloads.random_box(160, 9.0, seed=31, species_counts=[80, 80], eps=eps, sigma=sig)
+    p = orc.make_params(b.L, 3.0, eps=eps, sigma=sig)
+    g, de, ds = orc.gradients(b.pos, p, species=b.species)
+    scale = np.abs(g).sum()
+    assert np.all(np.abs(g.sum(axis=0)) <= 1e-12 * scale)            # Newton's third law
+    tot = orc.total_energy(b.pos, p, species=b.species)
+    # Euler: U is linear in eps
+    assert (eps * de).sum() == pytest.approx(tot["U_pair"] + tot["U_tail"], rel=1e-12)
+    # virial: sum sigma dU_pair/dsigma = sum_pairs r * dU/dr contribution (pure-Python pair loop)
+    tail_s = 0.0
+    V = b.volume
+    counts = np.bincount(b.species, minlength=2)
+    for a in range(2):
+        for c in range(2):
+            q = sig[a, c] / 3.0
+            tail_s += 8 * math.pi / (3 * V) * counts[a] * counts[c] * eps[a, c] * (
+                4 * sig[a, c] ** 3 * q ** 9 - 6 * sig[a, c] ** 3 * q ** 3)
+    vir = 0.0
+    for i in range(b.n):
+        d = b.pos - b.pos[i]
+        d -= b.L * np.round(d / b.L)
+        r2 = (d * d).sum(axis=1)
+        for j in range(i + 1, b.n):
+            if r2[j] < 9.0:
+                s2 = sig[b.species[i], b.species[j]] ** 2 / r2[j]
+                s6 = s2 ** 3
+                vir += 24 * eps[b.species[i], b.species[j]] * (2 * s6 * s6 - s6)   # = -r u'(r)
+    assert (sig * ds).sum() - tail_s == pytest.approx(vir, rel=1e-11)
+
+
+def test_gradient_finite_differences(orc):
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    b = workloads.random_box(120, 8.5, seed=41, species_counts=[60, 60], eps=eps, sigma=sig)
+    rc = 3.0
+    p = orc.make_params(b.L, rc, eps=eps, sigma=sig)
+    g, de, ds = orc.gradients(b.pos, p, species=b.species)
+    h = 1e-6
+
+    def U(pos, e=eps, s=sig):
+        q = orc.make_params(b.L, rc, eps=e, sigma=s)
+        t = orc.total_energy(pos, q, species=b.species)
+        return t["U_pair"] + t["U_tail"]
+
+    rng = np.random.default_rng(0)
+    checked = 0
+    for i in rng.choice(b.n, 20, replace=False):
+        d = b.pos - b.pos[i]
+        d -= b.L * np.round(d / b.L)
+        r = np.sqrt((d * d).sum(axis=1))
+        if np.any(np.abs(r - rc) < 10 * h):
+            continue
+        for a in range(3):
+            pp = b.pos.copy(); pp[i, a] += h
+            pm = b.pos.copy(); pm[i, a] -= h
+            fd = (U(pp) - U(pm)) / (2 * h)
+            assert fd == pytest.approx(g[i, a], rel=1e-5, abs=1e-6)
+        checked += 1
+    assert checked >= 10
+    # parameters: a symmetric perturbation of an off-diagonal entry moves both [a][b] and [b][a]
+    for (a, c) in ((0, 0), (0, 1), (1, 1)):
+        E = np.zeros((2, 2)); E[a, c] = E[c, a] = 1.0
+        fd_e = (U(b.pos, e=eps + h * E) - U(b.pos, e=eps - h * E)) / (2 * h)
+        fd_s = (U(b.pos, s=sig + h * E) - U(b.pos, s=sig - h * E)) / (2 * h)
+        want_e = de[a, c] + (de[c, a] if a != c else 0.0)
+        want_s = ds[a, c] + (ds[c, a] if a != c else 0.0)
+        assert fd_e == pytest.approx(want_e, rel=1e-6)
+        assert fd_s == pytest.approx(want_s, rel=1e-5)
