@@ -1,0 +1,285 @@
+/*
+ * gcmc.h -- C ABI of the MI355X (gfx950) grand-canonical Monte Carlo cell-list
+ * library.
+ *
+ * The method is that of Schwiebert, Hailat, Rushaidat, Mick and Potoff, "An
+ * Efficient Cell List Implementation for Monte Carlo Simulation on GPUs"
+ * (arXiv 1408.3764): Lennard-Jones particles (Eq. 1) in a periodic box, trial
+ * displacements, insertions and deletions accepted with the Metropolis rules of
+ * Eqs. (2)-(5); each trial's energy change is the sum of the pair energies of
+ * one particle with the particles in the cells around it (Sec. 3.2), split
+ * across GPU threads and reduced; the cell list is updated incrementally when a
+ * move is accepted (Sec. 3.2.5).
+ *
+ * Conventions for every entry point:
+ *   - Return value: GCMC_OK (0) or a GCMC_ERR_* code; gcmc_last_error() gives a
+ *     message for the calling thread.  No C++ exception crosses this boundary.
+ *   - d_* arguments are DEVICE pointers owned by the caller (e.g. torch tensors),
+ *     h_* arguments are HOST pointers owned by the caller.  The library owns the
+ *     memory behind gcmc_box and gcmc_batch (allocated at create, freed at
+ *     destroy).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     asynchronously; only gcmc_sync_status, gcmc_get_* and gcmc_export_state
+ *     block.  One box may be used by one stream at a time.
+ *   - Errors found on the device (a cell over capacity, N reaching max_n) are
+ *     latched in the box: the offending move is NOT applied, the chain stops
+ *     there, later kernels on the box do nothing, and gcmc_sync_status returns
+ *     the code.  gcmc_cell_build clears it (e.g. after growing the capacity), so
+ *     the chain can resume from the move counter it stopped at.
+ *   - Coordinates are reduced units (sigma = epsilon = k_B = 1 for one species)
+ *     and must lie in [0, L) per axis.
+ */
+#ifndef GCMC_H
+#define GCMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GCMC_OK = 0,
+    GCMC_ERR_INVALID_ARG = 1,   /* bad argument: rc > L/2, n > max_n, bad species, ... */
+    GCMC_ERR_OOM = 2,           /* device allocation failed */
+    GCMC_ERR_CELL_OVERFLOW = 3, /* a cell would exceed its capacity (Sec. 3.2.2: fixed-size cell arrays) */
+    GCMC_ERR_CAPACITY = 4,      /* an insertion would exceed max_n */
+    GCMC_ERR_HIP = 5,           /* a HIP runtime call failed */
+    GCMC_ERR_POISONED = 6,      /* the box holds a latched device error */
+    GCMC_ERR_UNSUPPORTED = 7    /* valid but not implemented (e.g. a chain over a mixture) */
+};
+
+enum { GCMC_MOVE_DISPLACE = 0, GCMC_MOVE_INSERT = 1, GCMC_MOVE_DELETE = 2 };
+
+#define GCMC_MAX_SPECIES 4
+
+typedef struct gcmc_box gcmc_box;
+typedef struct gcmc_batch gcmc_batch;
+
+/* Box description (host struct, copied at create).
+ *   L, rc        box edges and cutoff (rc <= L_a / 2 on every axis).
+ *   beta, mu     1/(k_B T) of Eq. (2) and the chemical potential of Eqs. (4)-(5).
+ *   lambda3      Lambda^3 of Eqs. (4)-(5).
+ *   max_disp     half-width of the uniform displacement cube.
+ *   p_disp       DisplacePercent of Algorithm 1, as a fraction.
+ *   n_species    1..GCMC_MAX_SPECIES; eps/sigma are HOST n_species^2 pair tables
+ *                (symmetric, already mixed).
+ *   max_n        particle capacity (insertions beyond it are GCMC_ERR_CAPACITY).
+ *   cell_m       cells per axis, 0 = the paper's rule M = max(3, floor(L/rc))
+ *                (Sec. 3.2.2); a larger M gives cells smaller than rc and a
+ *                wider stencil of 2k+1 cells, k = ceil(rc M / L).
+ *   cell_cap     per-cell capacity, 0 = automatic.
+ *   seed, box_id Philox4x32-10 key and the third counter word of the move stream. */
+typedef struct {
+    double L[3];
+    double rc;
+    double beta;
+    double mu;
+    double lambda3;
+    double max_disp;
+    double p_disp;
+    int32_t n_species;
+    int32_t cell_cap;
+    const double* eps;
+    const double* sigma;
+    int64_t max_n;
+    int32_t cell_m[3];
+    uint32_t box_id;
+    uint64_t seed;
+} gcmc_box_desc;
+
+/* One trial move for the host-driven entry points (40 bytes, device array).
+ *   type     GCMC_MOVE_*.
+ *   index    particle to displace or delete (0 <= index < N).
+ *   x, y, z  displacement: the new position; insertion: the position; unused
+ *            for deletion.  Must lie in [0, L).
+ *   species  species of an inserted particle. */
+typedef struct {
+    int32_t type;
+    int32_t index;
+    double x, y, z;
+    int32_t species;
+    int32_t pad;
+} gcmc_move;
+
+/* Chain statistics written by gcmc_step / gcmc_batch_step (device struct). */
+typedef struct {
+    int64_t attempts[3];   /* per move type */
+    int64_t accepts[3];
+    int64_t n;             /* N after the last move */
+    int64_t moves_done;    /* moves processed (less than asked if an error stopped the chain) */
+    double u_pair;         /* running pair energy after the last move */
+    double u_tail;         /* tail correction at the final N */
+    double sum_n;          /* sum over processed moves of N after the move */
+    double sum_u;          /* sum over processed moves of u_pair + u_tail after the move */
+    int32_t error;         /* GCMC_OK or the latched GCMC_ERR_* */
+    int32_t pad;
+    int64_t error_move;    /* move counter at which the error was raised, else -1 */
+    int64_t stencils;      /* neighbour-cell stencils gathered (a same-cell displacement shares one) */
+    int64_t candidates;    /* candidate particle records read from those stencils */
+    int64_t pair_evals;    /* pair distances evaluated (candidates x positions evaluated against them) */
+    int64_t in_cutoff;     /* of those, pairs strictly inside the cutoff */
+} gcmc_stats;
+
+/* Optional per-move record of gcmc_step (64 bytes, device array of n_moves). */
+typedef struct {
+    int32_t type;      /* GCMC_MOVE_* */
+    int32_t index;     /* particle index (displace/delete), new index N (insert), -1 if N == 0 */
+    int32_t accepted;
+    int32_t flags;     /* bit0: rejected because the box was empty */
+    double dU_pair;
+    double dU_tail;
+    double x, y, z;    /* trial position */
+    double arg;        /* log of the acceptance ratio */
+} gcmc_log;
+
+/* Geometry chosen at create (host struct). */
+typedef struct {
+    int32_t cell_m[3];   /* cells per axis */
+    int32_t span[3];     /* stencil cells per axis */
+    int32_t cell_cap;    /* per-cell capacity */
+    int32_t n_species;
+    int64_t n_cells;
+    int64_t max_n;
+    double inv_s[3];     /* M_a / L_a */
+} gcmc_box_info;
+
+/* ---------------------------------------------------------------- boxes */
+
+/* Create a box from n particles given as device SoA arrays (d_species may be
+ * NULL for one species) and bin them into the cell list (the initial binning of
+ * Sec. 3.2.1, atomic slot claims, then a per-cell ordering by particle index so
+ * the layout is deterministic).  Blocks until the binning is done so that an
+ * overflow is reported here.  *out receives the box. */
+int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* d_y, const double* d_z,
+                    const int32_t* d_species, int64_t n, void* stream, gcmc_box** out);
+int gcmc_box_destroy(gcmc_box* box);
+int gcmc_box_get_info(const gcmc_box* box, gcmc_box_info* h_info);
+
+/* Re-bin the current particles (Sec. 3.2.1), optionally with a new per-cell
+ * capacity (new_cap > 0 reallocates).  Clears a latched cell-overflow error, so
+ * a chain stopped by an overflow can resume at its error_move counter. */
+int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream);
+
+/* Replace the positions of the current particles (same N and species) and
+ * re-bin; used by the autograd wrapper between forward passes. */
+int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z, void* stream);
+
+/* ------------------------------------------------------------ the moves */
+
+/* Energy change of n_moves independent trial moves against the current
+ * configuration, no commit (the per-move energy of Algorithms 6 and 7: the
+ * stencil cells around the old and/or new position, one candidate per lane,
+ * wavefront then workgroup reduction).  d_moves[n_moves] as gcmc_move;
+ * d_dU_pair[n_moves] receives the pair part (displacement: new - old;
+ * insertion: + energy at the point; deletion: - energy of the particle);
+ * d_dU_tail[n_moves] (may be NULL) the tail-correction change. */
+int gcmc_delta_energy(gcmc_box* box, const gcmc_move* d_moves, int64_t n_moves, double* d_dU_pair,
+                      double* d_dU_tail, void* stream);
+
+/* The same quantities over all N particles, without the cell list (the
+ * no-cell-list path of Algorithms 3 and 4): many workgroups per move, partial
+ * sums reduced by a second kernel in a fixed order. */
+int gcmc_delta_energy_allpairs(gcmc_box* box, const gcmc_move* d_moves, int64_t n_moves, double* d_dU_pair,
+                               double* d_dU_tail, void* stream);
+
+/* Apply one accepted move (device gcmc_move) whose pair-energy change is
+ * *d_dU_pair (as returned by gcmc_delta_energy): position write, N +- 1, the
+ * running pair energy, and the
+ * incremental cell update of Sec. 3.2.5 (remove from the old cell by swapping
+ * in the cell's last entry, append to the new cell; nothing when the cell is
+ * unchanged); a deletion moves particle N-1 to the freed index. */
+int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair, void* stream);
+
+/* Launch shape of the move kernels: `waves` wavefronts per workgroup and
+ * `rows` candidate slots per lane per pass (the autotuner's choice; the
+ * supported pairs are 1x8, 2x8, 4x2, 4x4, 4x8, 8x2, 8x4, 16x2). */
+int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows);
+
+/* Run n_moves moves of the Markov chain of Algorithm 1 on the device in one
+ * persistent launch (Sec. 3.3.4: one kernel call for many moves): move m uses
+ * the Philox4x32-10 stream with key = seed and counter
+ * (counter0 + m low, high, box_id, j), j = 0..3, giving eight uniforms
+ * (R, Source, particle pick, A, three position draws, spare); R < p_disp is a
+ * displacement, else Source < 0.5 a deletion, else an insertion.  Single
+ * species only.  d_stats (may be NULL) receives the chain statistics and d_log
+ * (may be NULL) one record per move. */
+int gcmc_step(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_stats, gcmc_log* d_log,
+              void* stream);
+
+/* The same chain with every energy computed over all particles (no cell
+ * list), two launches per move (evaluate over many workgroups; reduce, decide
+ * and commit in one), for comparison with gcmc_step. */
+int gcmc_step_allpairs(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_stats,
+                       gcmc_log* d_log, void* stream);
+
+/* --------------------------------------------------------- total energy */
+
+/* Total energy (Sec. 3.1.1): d_U[0] = U_pair = (1/2) sum_i e_i over the cell
+ * stencils (all_pairs = 0) or over all pairs (all_pairs = 1), d_U[1] = U_tail.
+ * d_e[N] (may be NULL) receives e_i = sum_{j != i} u(r_ij) in particle order.
+ * Also resets the running energy of the chain to d_U[0]. */
+int gcmc_total_energy(gcmc_box* box, int32_t all_pairs, double* d_U, double* d_e, void* stream);
+
+/* Gradient of U = U_pair + U_tail (Eq. 1 differentiated; rc held fixed):
+ * d_grad[3*N] (SoA: x block, y block, z block) = dU/dr_i; d_deps and d_dsig
+ * [n_species^2] = dU/d eps_ab and dU/d sigma_ab, where an unordered species
+ * pair a != b contributes half to [a][b] and half to [b][a].  Any of the three
+ * outputs may be NULL. */
+int gcmc_backward(gcmc_box* box, double* d_grad, double* d_deps, double* d_dsig, void* stream);
+
+/* ------------------------------------------------------------- batches */
+
+/* Group existing single-species boxes (all must stay alive) so that
+ * gcmc_batch_step advances all of them in one persistent launch, one
+ * workgroup per box, boxes ordered by decreasing N. */
+int gcmc_batch_create(gcmc_box* const* boxes, int32_t n_boxes, gcmc_batch** out);
+int gcmc_batch_destroy(gcmc_batch* batch);
+/* Advance every box of the batch by moves_per_box moves (counter0 + m, the
+ * box's own box_id and seed).  d_stats[n_boxes] (may be NULL), in the order
+ * the boxes were given. */
+int gcmc_batch_step(gcmc_batch* batch, int64_t moves_per_box, uint64_t counter0, gcmc_stats* d_stats,
+                    void* stream);
+
+/* ---------------------------------------------------- inspection / state */
+
+/* Copy the current particles out (blocks): d_x, d_y, d_z [>= N] (may be NULL),
+ * d_species [>= N] (may be NULL); *h_n receives N. */
+int gcmc_get_particles(gcmc_box* box, double* d_x, double* d_y, double* d_z, int32_t* d_species, int64_t* h_n,
+                       void* stream);
+
+/* Copy the cell list out (blocks): d_cell_of[N] the cell of each particle,
+ * d_count[n_cells], d_ids[n_cells * cell_cap] cell-major particle ids (entries
+ * past a cell's count are unspecified).  Any pointer may be NULL. */
+int gcmc_get_cells(gcmc_box* box, int32_t* d_cell_of, int32_t* d_count, int32_t* d_ids, void* stream);
+
+/* Neighbour candidates (the particles in the stencil cells of a point, the
+ * moving particle excluded) of n points, gathered by the same device code as
+ * the energy kernels.  d_points[3*n] SoA (x block, y, z), d_exclude[n] (id or
+ * -1), d_ids[n * max_ids] receives the ids in unspecified order, d_counts[n]
+ * the full count (ids beyond max_ids are dropped). */
+int gcmc_neighbor_ids(gcmc_box* box, const double* d_points, const int32_t* d_exclude, int64_t n,
+                      int32_t max_ids, int32_t* d_ids, int32_t* d_counts, void* stream);
+
+/* Checkpoint (blocks): N, running pair energy and latched error. */
+int gcmc_export_state(gcmc_box* box, int64_t* h_n, double* h_u_pair, int32_t* h_error);
+/* Restore N particles (device SoA, n <= max_n) and the running energy, then
+ * re-bin; the Philox counter is the caller's, so resuming at counter c replays
+ * the chain exactly. */
+int gcmc_import_state(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z,
+                      const int32_t* d_species, int64_t n, double u_pair, void* stream);
+
+/* Block until the box's queued work is done; returns its latched error. */
+int gcmc_sync_status(gcmc_box* box);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* gcmc_last_error(void);
+
+/* Library version string. */
+const char* gcmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCMC_H */

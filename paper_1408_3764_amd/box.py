@@ -1,0 +1,252 @@
+"""Python-side handle of one box / one batch of boxes on the GPU.
+
+Marshalling only: numpy/torch arrays in, device tensors handed to the C ABI
+(``_lib``), results copied back.  Every computation happens in libgcmc.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import LOG_DTYPE, MOVE_DTYPE, STATS_DTYPE
+
+
+def _dev(a, dtype, device):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+def _struct_to_device(arr: np.ndarray, device) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(arr).view(np.uint8).copy()).to(device)
+
+
+def _struct_from_device(t: torch.Tensor, dtype) -> np.ndarray:
+    return t.cpu().numpy().view(dtype).copy()
+
+
+class Box:
+    """One periodic box of Lennard-Jones particles held by the GPU library."""
+
+    def __init__(self, pos, L, rc, beta=1.0, mu=0.0, lambda3=1.0, max_disp=0.3, p_disp=1.0 / 3.0, eps=1.0,
+                 sigma=1.0, species=None, max_n=None, cell_m=None, cell_cap=0, seed=0, box_id=0,
+                 device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.stream = stream
+        pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+        n = pos.shape[0]
+        e = np.atleast_2d(np.asarray(eps, dtype=np.float64))
+        s = np.atleast_2d(np.asarray(sigma, dtype=np.float64))
+        self.ns = e.shape[0]
+        self._eps = np.ascontiguousarray(e.reshape(-1))
+        self._sig = np.ascontiguousarray(s.reshape(-1))
+        d = _lib.BoxDesc()
+        Lv = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+        for a in range(3):
+            d.L[a] = float(Lv[a])
+            d.cell_m[a] = 0 if cell_m is None else int(np.broadcast_to(cell_m, (3,))[a])
+        d.rc, d.beta, d.mu, d.lambda3 = float(rc), float(beta), float(mu), float(lambda3)
+        d.max_disp, d.p_disp = float(max_disp), float(p_disp)
+        d.n_species = self.ns
+        d.cell_cap = int(cell_cap)
+        d.eps = self._eps.ctypes.data_as(C.POINTER(C.c_double))
+        d.sigma = self._sig.ctypes.data_as(C.POINTER(C.c_double))
+        d.max_n = int(max_n if max_n is not None else max(n, 1))
+        d.box_id = int(box_id)
+        d.seed = int(seed)
+        self.desc = d
+        self.L = Lv.copy()
+        self.rc = float(rc)
+        x = _dev(pos[:, 0], torch.float64, self.device)
+        y = _dev(pos[:, 1], torch.float64, self.device)
+        z = _dev(pos[:, 2], torch.float64, self.device)
+        sp = None if species is None else _dev(species, torch.int32, self.device)
+        self.handle = _lib.gcmc_box_create(d, x, y, z, sp, n, stream)
+        self.max_n = d.max_n
+
+    @classmethod
+    def from_workload(cls, wb, max_n=None, **kw):
+        kw.setdefault("seed", wb.seed)
+        return cls(wb.pos, wb.L, wb.rc, beta=wb.beta, mu=wb.mu, lambda3=wb.lambda3, max_disp=wb.max_disp,
+                   p_disp=wb.p_disp, eps=wb.eps, sigma=wb.sigma, species=wb.species,
+                   max_n=max_n if max_n is not None else wb.n, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.gcmc_box_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ info
+    def info(self):
+        i = _lib.gcmc_box_get_info(self.handle)
+        return {"cell_m": list(i.cell_m), "span": list(i.span), "cell_cap": i.cell_cap, "n_species": i.n_species,
+                "n_cells": i.n_cells, "max_n": i.max_n, "inv_s": list(i.inv_s)}
+
+    def set_launch(self, waves, rows):
+        _lib.gcmc_box_set_launch(self.handle, waves, rows)
+
+    # ----------------------------------------------------------------- moves
+    def delta_energy(self, moves: np.ndarray, all_pairs=False):
+        moves = np.asarray(moves, dtype=MOVE_DTYPE)
+        m = len(moves)
+        dm = _struct_to_device(moves, self.device)
+        dp = torch.empty(m, dtype=torch.float64, device=self.device)
+        dt = torch.empty(m, dtype=torch.float64, device=self.device)
+        f = _lib.gcmc_delta_energy_allpairs if all_pairs else _lib.gcmc_delta_energy
+        f(self.handle, dm, m, dp, dt, self.stream)
+        return dp.cpu().numpy(), dt.cpu().numpy()
+
+    def commit(self, move, dU_pair):
+        mv = np.asarray([move], dtype=MOVE_DTYPE) if not isinstance(move, np.ndarray) else move.reshape(1)
+        dm = _struct_to_device(mv, self.device)
+        du = torch.tensor([float(dU_pair)], dtype=torch.float64, device=self.device)
+        _lib.gcmc_commit(self.handle, dm, du, self.stream)
+        self.sync()
+
+    def step(self, n_moves, counter0=0, log=False, all_pairs=False):
+        st = torch.zeros(STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        lg = torch.zeros(max(1, n_moves) * LOG_DTYPE.itemsize, dtype=torch.uint8, device=self.device) if log else None
+        f = _lib.gcmc_step_allpairs if all_pairs else _lib.gcmc_step
+        f(self.handle, n_moves, counter0, st, lg, self.stream)
+        stats = _struct_from_device(st, STATS_DTYPE)[0]
+        lgs = _struct_from_device(lg, LOG_DTYPE)[:n_moves] if log else None
+        return stats, lgs
+
+    # --------------------------------------------------------------- energy
+    def total_energy(self, all_pairs=False, per_particle=False):
+        U = torch.zeros(2, dtype=torch.float64, device=self.device)
+        n = self.n
+        e = torch.zeros(max(n, 1), dtype=torch.float64, device=self.device) if per_particle else None
+        _lib.gcmc_total_energy(self.handle, 1 if all_pairs else 0, U, e, self.stream)
+        u = U.cpu().numpy()
+        out = {"U_pair": float(u[0]), "U_tail": float(u[1])}
+        if per_particle:
+            out["e"] = e[:n].cpu().numpy()
+        return out
+
+    def backward(self, positions=True, params=True):
+        n = self.n
+        g = torch.zeros(3 * max(n, 1), dtype=torch.float64, device=self.device) if positions else None
+        de = torch.zeros(self.ns * self.ns, dtype=torch.float64, device=self.device) if params else None
+        ds = torch.zeros(self.ns * self.ns, dtype=torch.float64, device=self.device) if params else None
+        _lib.gcmc_backward(self.handle, g, de, ds, self.stream)
+        out = {}
+        if positions:
+            out["grad"] = g[: 3 * n].view(3, n).t().cpu().numpy()
+        if params:
+            out["d_eps"] = de.view(self.ns, self.ns).cpu().numpy()
+            out["d_sigma"] = ds.view(self.ns, self.ns).cpu().numpy()
+        return out
+
+    # ----------------------------------------------------------- inspection
+    @property
+    def n(self):
+        return self.export_state()[0]
+
+    def particles(self):
+        n = self.n
+        x = torch.zeros(max(n, 1), dtype=torch.float64, device=self.device)
+        y, z = torch.zeros_like(x), torch.zeros_like(x)
+        sp = torch.zeros(max(n, 1), dtype=torch.int32, device=self.device)
+        n = _lib.gcmc_get_particles(self.handle, x, y, z, sp, self.stream)
+        pos = torch.stack([x[:n], y[:n], z[:n]], dim=1).cpu().numpy()
+        return pos, sp[:n].cpu().numpy()
+
+    def cells(self):
+        info = self.info()
+        n = self.n
+        cell_of = torch.zeros(max(n, 1), dtype=torch.int32, device=self.device)
+        count = torch.zeros(info["n_cells"], dtype=torch.int32, device=self.device)
+        ids = torch.zeros(info["n_cells"] * info["cell_cap"], dtype=torch.int32, device=self.device)
+        _lib.gcmc_get_cells(self.handle, cell_of, count, ids, self.stream)
+        return (cell_of[:n].cpu().numpy(), count.cpu().numpy(),
+                ids.view(info["n_cells"], info["cell_cap"]).cpu().numpy())
+
+    def neighbor_ids(self, points, exclude=None, max_ids=4096):
+        points = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+        m = len(points)
+        pts = _dev(points.T.reshape(-1), torch.float64, self.device)
+        ex = _dev(np.full(m, -1) if exclude is None else exclude, torch.int32, self.device)
+        ids = torch.zeros(max(1, m * max_ids), dtype=torch.int32, device=self.device)
+        cnt = torch.zeros(max(m, 1), dtype=torch.int32, device=self.device)
+        _lib.gcmc_neighbor_ids(self.handle, pts, ex, m, max_ids, ids, cnt, self.stream)
+        ids = ids.cpu().numpy().reshape(max(m, 1), max_ids)
+        cnt = cnt.cpu().numpy()
+        return [np.sort(ids[i, : min(cnt[i], max_ids)]) for i in range(m)], cnt[:m]
+
+    def export_state(self):
+        return _lib.gcmc_export_state(self.handle)
+
+    def import_state(self, pos, u_pair, species=None):
+        pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+        x = _dev(pos[:, 0], torch.float64, self.device)
+        y = _dev(pos[:, 1], torch.float64, self.device)
+        z = _dev(pos[:, 2], torch.float64, self.device)
+        sp = None if species is None else _dev(species, torch.int32, self.device)
+        _lib.gcmc_import_state(self.handle, x, y, z, sp, len(pos), u_pair, self.stream)
+
+    def set_positions(self, pos):
+        pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+        x = _dev(pos[:, 0], torch.float64, self.device)
+        y = _dev(pos[:, 1], torch.float64, self.device)
+        z = _dev(pos[:, 2], torch.float64, self.device)
+        _lib.gcmc_set_positions(self.handle, x, y, z, self.stream)
+
+    def cell_build(self, new_cap=0):
+        _lib.gcmc_cell_build(self.handle, new_cap, self.stream)
+
+    def sync(self):
+        rc = _lib.gcmc_sync_status(self.handle)
+        if rc:
+            raise _lib.GcmcError(rc, _lib.gcmc_last_error())
+
+    def status(self):
+        return _lib.gcmc_sync_status(self.handle)
+
+
+class Batch:
+    """Many boxes advanced together by one persistent launch."""
+
+    def __init__(self, boxes: Sequence[Box]):
+        self.boxes = list(boxes)
+        self.device = self.boxes[0].device
+        self.handle = _lib.gcmc_batch_create([b.handle for b in self.boxes])
+
+    def step(self, moves_per_box, counter0=0, stream=None):
+        st = torch.zeros(len(self.boxes) * STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        _lib.gcmc_batch_step(self.handle, moves_per_box, counter0, st, stream)
+        return _struct_from_device(st, STATS_DTYPE)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.gcmc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_moves(types, index=None, pos=None, species=None) -> np.ndarray:
+    types = np.asarray(types, dtype=np.int32)
+    m = len(types)
+    mv = np.zeros(m, dtype=MOVE_DTYPE)
+    mv["type"] = types
+    if index is not None:
+        mv["index"] = np.asarray(index, dtype=np.int32)
+    if pos is not None:
+        pos = np.asarray(pos, dtype=np.float64).reshape(m, 3)
+        mv["x"], mv["y"], mv["z"] = pos[:, 0], pos[:, 1], pos[:, 2]
+    if species is not None:
+        mv["species"] = np.asarray(species, dtype=np.int32)
+    return mv

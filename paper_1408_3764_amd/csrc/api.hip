@@ -1,0 +1,208 @@
+// C ABI entry points for the moves, the energies and the batches.  Argument
+// checking and launch configuration only; all arithmetic is in the kernels.
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "gcmc_internal.h"
+
+using namespace gcmc;
+
+static int poisoned_check(gcmc_box* box, hipStream_t s, BoxState* h) {
+    int rc = read_box_state(box, h, s);
+    if (rc) return rc;
+    if (h->error) return set_error(GCMC_ERR_POISONED, "box holds a latched device error");
+    return GCMC_OK;
+}
+
+extern "C" {
+
+int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    if (!chain_cfg_exists(waves, rows)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported waves x rows");
+    box->waves = waves;
+    box->rows = rows;
+    return GCMC_OK;
+}
+
+int gcmc_delta_energy(gcmc_box* box, const gcmc_move* d_moves, int64_t n_moves, double* d_dU_pair,
+                      double* d_dU_tail, void* stream) {
+    if (!box || (n_moves > 0 && (!d_moves || !d_dU_pair)) || n_moves < 0)
+        return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
+    if (n_moves == 0) return GCMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    launch_delta(box->d_desc, box->d.ns > 1, n_moves, d_moves, d_dU_pair, d_dU_tail, s);
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+int gcmc_delta_energy_allpairs(gcmc_box* box, const gcmc_move* d_moves, int64_t n_moves, double* d_dU_pair,
+                               double* d_dU_tail, void* stream) {
+    if (!box || (n_moves > 0 && (!d_moves || !d_dU_pair)) || n_moves < 0)
+        return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
+    if (n_moves == 0) return GCMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    BoxState h;
+    int rc = read_box_state(box, &h, s);
+    if (rc) return rc;
+    const int64_t chunk = ap_chunk_len();
+    const int64_t nch = std::max<int64_t>(1, (h.n + chunk - 1) / chunk);
+    for (int64_t m0 = 0; m0 < n_moves; m0 += 65535) {
+        const int64_t nm = std::min<int64_t>(65535, n_moves - m0);
+        if ((rc = ensure_scratch(box, nm * nch * 2))) return rc;
+        if (launch_delta_allpairs(box->d_desc, h.n, d_moves + m0, nm, box->scratch, d_dU_pair + m0,
+                                  d_dU_tail ? d_dU_tail + m0 : nullptr, s))
+            return set_error(GCMC_ERR_INVALID_ARG, "too many moves");
+        GCMC_HIP(hipGetLastError());
+    }
+    return GCMC_OK;
+}
+
+int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair, void* stream) {
+    if (!box || !d_move || !d_dU_pair) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    launch_commit(box->d_desc, d_move, d_dU_pair, (hipStream_t)stream);
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+int gcmc_step(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_stats, gcmc_log* d_log,
+              void* stream) {
+    if (!box || n_moves < 0) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
+    if (box->d.ns != 1) return set_error(GCMC_ERR_UNSUPPORTED, "the chain supports one species");
+    if (launch_chain(box->d_desc, nullptr, 1, box->waves, box->rows, n_moves, counter0, d_stats, d_log,
+                     (hipStream_t)stream))
+        return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+int gcmc_step_allpairs(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_stats, gcmc_log* d_log,
+                       void* stream) {
+    if (!box || n_moves < 0) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
+    if (box->d.ns != 1) return set_error(GCMC_ERR_UNSUPPORTED, "the chain supports one species");
+    hipStream_t s = (hipStream_t)stream;
+    if (!box->ap_chain) {
+        if (hipMalloc(&box->ap_chain, ap_chain_state_bytes()) != hipSuccess) {
+            box->ap_chain = nullptr;
+            return set_error(GCMC_ERR_OOM, "chain state allocation failed");
+        }
+    }
+    const int64_t chunk = ap_chunk_len();
+    const int64_t nch = std::max<int64_t>(1, (box->d.max_n + chunk - 1) / chunk);
+    int rc = ensure_scratch(box, nch * 2);
+    if (rc) return rc;
+    launch_ap_chain_begin(box->ap_chain, counter0, s);
+    for (int64_t m = 0; m < n_moves; ++m) launch_ap_chain_move(box->d_desc, box->ap_chain, nch, box->scratch, d_log, s);
+    if (d_stats) launch_ap_chain_end(box->d_desc, box->ap_chain, d_stats, s);
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+int gcmc_total_energy(gcmc_box* box, int32_t all_pairs, double* d_U, double* d_e, void* stream) {
+    if (!box || !d_U) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    BoxState h;
+    int rc = poisoned_check(box, s, &h);
+    if (rc) return rc;
+    const int64_t need = total_partials_needed(box->d, h.maxcount, all_pairs != 0, h.n);
+    if ((rc = ensure_scratch(box, need))) return rc;
+    const int r = launch_total(box->d, box->d_desc, h.maxcount, all_pairs != 0, d_e, box->scratch, box->scratch_len,
+                               d_U, s, h.n);
+    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
+    if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+int gcmc_backward(gcmc_box* box, double* d_grad, double* d_deps, double* d_dsig, void* stream) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    BoxState h;
+    int rc = poisoned_check(box, s, &h);
+    if (rc) return rc;
+    if ((rc = ensure_scratch(box, grad_partials_needed(box->d, h.maxcount)))) return rc;
+    const int r = launch_grad(box->d, box->d_desc, h.maxcount, d_grad, box->scratch, d_deps, d_dsig, s);
+    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+int gcmc_neighbor_ids(gcmc_box* box, const double* d_points, const int32_t* d_exclude, int64_t n, int32_t max_ids,
+                      int32_t* d_ids, int32_t* d_counts, void* stream) {
+    if (!box || n < 0 || max_ids < 0 || (n > 0 && (!d_points || !d_ids || !d_counts)))
+        return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
+    if (n == 0) return GCMC_OK;
+    launch_neighbors(box->d_desc, d_points, d_exclude, n, max_ids, d_ids, d_counts, (hipStream_t)stream);
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+// ---------------------------------------------------------------- batches
+int gcmc_batch_create(gcmc_box* const* boxes, int32_t n_boxes, gcmc_batch** out) {
+    if (!boxes || n_boxes < 1 || !out) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
+    *out = nullptr;
+    std::vector<int64_t> ns(n_boxes);
+    for (int32_t b = 0; b < n_boxes; ++b) {
+        if (!boxes[b]) return set_error(GCMC_ERR_INVALID_ARG, "NULL box");
+        if (boxes[b]->d.ns != 1) return set_error(GCMC_ERR_UNSUPPORTED, "the chain supports one species");
+        BoxState h;
+        int rc = read_box_state(boxes[b], &h, nullptr);
+        if (rc) return rc;
+        ns[b] = h.n;
+    }
+    gcmc_batch* bt = new gcmc_batch();
+    memset(bt, 0, sizeof(*bt));
+    bt->n = n_boxes;
+    bt->boxes = new gcmc_box*[n_boxes];
+    for (int32_t b = 0; b < n_boxes; ++b) bt->boxes[b] = boxes[b];
+    std::vector<int32_t> order(n_boxes);
+    std::iota(order.begin(), order.end(), 0);
+    // largest boxes first, so the longest-running workgroups start first
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return ns[a] > ns[c]; });
+    if (hipMalloc(&bt->d_descs, sizeof(DevBox) * n_boxes) != hipSuccess ||
+        hipMalloc(&bt->d_order, sizeof(int32_t) * n_boxes) != hipSuccess) {
+        gcmc_batch_destroy(bt);
+        return set_error(GCMC_ERR_OOM, "batch allocation failed");
+    }
+    bt->h_order = new int32_t[n_boxes];
+    for (int32_t b = 0; b < n_boxes; ++b) bt->h_order[b] = order[b];
+    GCMC_HIP(hipMemcpy(bt->d_order, order.data(), sizeof(int32_t) * n_boxes, hipMemcpyHostToDevice));
+    *out = bt;
+    return GCMC_OK;
+}
+
+int gcmc_batch_destroy(gcmc_batch* bt) {
+    if (!bt) return set_error(GCMC_ERR_INVALID_ARG, "batch is NULL");
+    (void)hipDeviceSynchronize();
+    if (bt->d_descs) (void)hipFree(bt->d_descs);
+    if (bt->d_order) (void)hipFree(bt->d_order);
+    delete[] bt->boxes;
+    delete[] bt->h_order;
+    delete bt;
+    return GCMC_OK;
+}
+
+int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gcmc_stats* d_stats, void* stream) {
+    if (!bt || moves_per_box < 0) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    // descriptors in launch order (refreshed: a rebuild may have moved a cell array)
+    std::vector<DevBox> h(bt->n);
+    for (int32_t q = 0; q < bt->n; ++q) h[q] = bt->boxes[bt->h_order[q]]->d;
+    GCMC_HIP(hipMemcpyAsync(bt->d_descs, h.data(), sizeof(DevBox) * bt->n, hipMemcpyHostToDevice, s));
+    GCMC_HIP(hipStreamSynchronize(s));
+    const gcmc_box* b0 = bt->boxes[0];
+    if (launch_chain(bt->d_descs, bt->d_order, bt->n, b0->waves, b0->rows, moves_per_box, counter0, d_stats, nullptr,
+                     s))
+        return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+}  // extern "C"
+
+static_assert(sizeof(gcmc_box_desc) == 128, "gcmc_box_desc layout");
+static_assert(sizeof(gcmc_move) == 40, "gcmc_move layout");
+static_assert(sizeof(gcmc_stats) == 144, "gcmc_stats layout");
+static_assert(sizeof(gcmc_log) == 64, "gcmc_log layout");

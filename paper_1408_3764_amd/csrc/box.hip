@@ -1,0 +1,517 @@
+// Box lifetime, cell-list construction (binning), inspection and checkpoints.
+//
+// Binning follows Sec. 3.2.1 of the paper: every particle claims a unique slot
+// of its cell with an atomic increment of the cell's counter.  Slot order from
+// atomics is arbitrary, so a second pass orders each cell's entries by particle
+// index; the layout (and with it every floating-point sum order) is then a
+// function of the configuration alone.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "gcmc_internal.h"
+
+namespace gcmc {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+    return set_error(GCMC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ kernels
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Copy SoA input into the particle records; flags coordinates outside [0, L)
+// and bad species in st->error.
+__global__ void k_upload(DevBox B, const double* __restrict__ x, const double* __restrict__ y,
+                         const double* __restrict__ z, const int32_t* __restrict__ sp, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double px = x[i], py = y[i], pz = z[i];
+        const int32_t s = sp ? sp[i] : 0;
+        const bool ok = (px >= 0.0) && (px < B.L[0]) && (py >= 0.0) && (py < B.L[1]) && (pz >= 0.0) &&
+                        (pz < B.L[2]) && s >= 0 && s < B.ns;
+        if (!ok) atomicMax(&B.st->error, (int32_t)GCMC_ERR_INVALID_ARG);
+        B.pos[i] = make_double4(px, py, pz, pack_meta(s, 0));
+    }
+}
+
+__device__ __forceinline__ int64_t cell_of_point(const DevBox& B, double x, double y, double z) {
+    const int32_t cx = axis_cell(x, B.invS[0], B.M[0]);
+    const int32_t cy = axis_cell(y, B.invS[1], B.M[1]);
+    const int32_t cz = axis_cell(z, B.invS[2], B.M[2]);
+    return ((int64_t)cz * B.M[1] + cy) * B.M[0] + cx;
+}
+
+// Pass 1: occupancy only (to size the cells).
+__global__ void k_count(DevBox B, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double4 p = B.pos[i];
+        const int64_t c = cell_of_point(B, p.x, p.y, p.z);
+        const int32_t k = atomicAdd(&B.count[c], 1);
+        atomicMax(&B.st->maxcount, k + 1);
+    }
+}
+
+// Pass 2: claim a slot and write the cell entry.
+__global__ void k_bin(DevBox B, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double4 p = B.pos[i];
+        const int64_t c = cell_of_point(B, p.x, p.y, p.z);
+        const int32_t k = atomicAdd(&B.count[c], 1);
+        if (k < B.cap) {
+            B.ent[c * B.cap + k] = make_double4(p.x, p.y, p.z, pack_meta(meta_species(p.w), (int32_t)i));
+        } else {
+            atomicMax(&B.st->error, (int32_t)GCMC_ERR_CELL_OVERFLOW);
+        }
+    }
+}
+
+// Pass 3: order each cell by particle id, set the back-pointers, and gather
+// the maximum occupancy and the species counts.
+__global__ void k_sort_cells(DevBox B) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < B.ncells;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int32_t cnt = B.count[c];
+        if (cnt > B.cap) cnt = B.cap;
+        double4* e = B.ent + c * B.cap;
+        for (int32_t a = 1; a < cnt; ++a) {
+            const double4 v = e[a];
+            const int32_t id = meta_low(v.w);
+            int32_t b = a - 1;
+            while (b >= 0 && meta_low(e[b].w) > id) {
+                e[b + 1] = e[b];
+                --b;
+            }
+            e[b + 1] = v;
+        }
+        for (int32_t a = 0; a < cnt; ++a) {
+            const double4 v = e[a];
+            const int32_t id = meta_low(v.w);
+            B.pos[id].w = pack_meta(meta_species(v.w), (int32_t)(c * B.cap + a));
+            atomicAdd((unsigned long long*)&B.st->nsp[meta_species(v.w)], 1ull);
+        }
+        if (cnt > 0) atomicMax(&B.st->maxcount, cnt);
+    }
+}
+
+__global__ void k_reset_state(BoxState* st, int64_t n, double u_pair, int keep_error) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->n = n;
+        st->u_pair = u_pair;
+        st->maxcount = 0;
+        if (!keep_error) {
+            st->error = GCMC_OK;
+            st->error_move = -1;
+        }
+        for (int s = 0; s < kMaxSpecies; ++s) st->nsp[s] = 0;
+        st->counter = 0;
+    }
+}
+
+__global__ void k_clear_overflow(BoxState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && st->error == GCMC_ERR_CELL_OVERFLOW) {
+        st->error = GCMC_OK;
+    }
+}
+
+__global__ void k_get_particles(DevBox B, double* x, double* y, double* z, int32_t* sp) {
+    const int64_t n = B.st->n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double4 p = B.pos[i];
+        if (x) x[i] = p.x;
+        if (y) y[i] = p.y;
+        if (z) z[i] = p.z;
+        if (sp) sp[i] = meta_species(p.w);
+    }
+}
+
+__global__ void k_get_cells(DevBox B, int32_t* cell_of, int32_t* count, int32_t* ids) {
+    const int64_t n = B.st->n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (cell_of)
+        for (int64_t i = t0; i < n; i += stride) cell_of[i] = (int32_t)(meta_low(B.pos[i].w) / B.cap);
+    if (count)
+        for (int64_t c = t0; c < B.ncells; c += stride) count[c] = B.count[c];
+    if (ids)
+        for (int64_t q = t0; q < B.ncells * B.cap; q += stride) ids[q] = meta_low(B.ent[q].w);
+}
+
+static int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (int)g;
+}
+
+}  // namespace gcmc
+
+using namespace gcmc;
+
+// ------------------------------------------------------------------ host helpers
+static int validate_desc(const gcmc_box_desc* d, int64_t n) {
+    if (!d) return set_error(GCMC_ERR_INVALID_ARG, "desc is NULL");
+    if (d->n_species < 1 || d->n_species > kMaxSpecies)
+        return set_error(GCMC_ERR_INVALID_ARG, "n_species must be 1..4");
+    if (!d->eps || !d->sigma) return set_error(GCMC_ERR_INVALID_ARG, "eps/sigma tables are NULL");
+    if (!(d->rc > 0.0)) return set_error(GCMC_ERR_INVALID_ARG, "rc must be positive");
+    for (int a = 0; a < 3; ++a) {
+        if (!(d->L[a] > 0.0)) return set_error(GCMC_ERR_INVALID_ARG, "box edges must be positive");
+        if (d->rc > 0.5 * d->L[a]) return set_error(GCMC_ERR_INVALID_ARG, "rc > L/2 breaks the minimum image");
+        if (d->cell_m[a] < 0) return set_error(GCMC_ERR_INVALID_ARG, "cell_m must be >= 0");
+    }
+    if (n < 0 || d->max_n < n || d->max_n < 1 || d->max_n > (int64_t)INT32_MAX)
+        return set_error(GCMC_ERR_INVALID_ARG, "need 0 <= n <= max_n < 2^31");
+    const int ns = d->n_species;
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            if (d->eps[a * ns + b] != d->eps[b * ns + a] || d->sigma[a * ns + b] != d->sigma[b * ns + a])
+                return set_error(GCMC_ERR_INVALID_ARG, "eps/sigma tables must be symmetric");
+            if (!(d->sigma[a * ns + b] > 0.0) || d->eps[a * ns + b] < 0.0)
+                return set_error(GCMC_ERR_INVALID_ARG, "need sigma > 0 and eps >= 0");
+        }
+    if (!(d->beta > 0.0) || !(d->lambda3 > 0.0) || d->max_disp < 0.0 || d->p_disp < 0.0 || d->p_disp > 1.0)
+        return set_error(GCMC_ERR_INVALID_ARG, "need beta > 0, lambda3 > 0, max_disp >= 0, 0 <= p_disp <= 1");
+    return GCMC_OK;
+}
+
+// Cells per axis (the paper's rule, or the caller's larger count), the
+// stencil half-width and extent.
+static int setup_grid(DevBox& B, const gcmc_box_desc* d) {
+    for (int a = 0; a < 3; ++a) {
+        int64_t m = (int64_t)floor(d->L[a] / d->rc);
+        if (m < 3) m = 3;
+        if (d->cell_m[a] > 0) m = d->cell_m[a];
+        if (m > 1023) return set_error(GCMC_ERR_INVALID_ARG, "at most 1023 cells per axis");
+        B.M[a] = (int32_t)m;
+        B.invS[a] = (double)m / d->L[a];
+        int32_t kk = (int32_t)ceil(d->rc * B.invS[a]);
+        if (kk < 1) kk = 1;
+        B.k[a] = kk;
+        B.full[a] = (2 * kk + 1 >= B.M[a]) ? 1 : 0;
+        B.span[a] = B.full[a] ? B.M[a] : 2 * kk + 1;
+        B.L[a] = d->L[a];
+        B.hL[a] = 0.5 * d->L[a];
+    }
+    B.ncells = (int64_t)B.M[0] * B.M[1] * B.M[2];
+    B.nstencil = B.span[0] * B.span[1] * B.span[2];
+    if (B.nstencil > kMaxStencil)
+        return set_error(GCMC_ERR_INVALID_ARG, "stencil larger than 1024 cells: use fewer, larger cells");
+    return GCMC_OK;
+}
+
+static void setup_params(DevBox& B, const gcmc_box_desc* d) {
+    const int ns = d->n_species;
+    B.ns = ns;
+    B.rc2 = d->rc * d->rc;
+    B.beta = d->beta;
+    B.mu = d->mu;
+    B.lambda3 = d->lambda3;
+    B.max_disp = d->max_disp;
+    B.p_disp = d->p_disp;
+    B.V = (d->L[0] * d->L[1]) * d->L[2];
+    B.seed = d->seed;
+    B.box_id = d->box_id;
+    B.max_n = d->max_n;
+    const double pre = 8.0 * M_PI / (3.0 * B.V);
+    for (int a = 0; a < kMaxSpecies * kMaxSpecies; ++a) {
+        B.eps4[a] = 0.0;
+        B.sig2[a] = 1.0;
+        B.tailK[a] = 0.0;
+    }
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            const double e = d->eps[a * ns + b], s = d->sigma[a * ns + b];
+            B.eps4[a * ns + b] = 4.0 * e;
+            B.sig2[a * ns + b] = s * s;
+            const double q = s / d->rc, q3 = q * q * q;
+            B.tailK[a * ns + b] = pre * e * (s * s * s) * (q3 * q3 * q3 / 3.0 - q3);
+        }
+}
+
+static int auto_cap(int32_t maxcount) {
+    int c = (int)ceil(1.5 * maxcount) + 4;
+    c = (c + 3) & ~3;
+    return c < 8 ? 8 : c;
+}
+
+// Bin the first n particles of B.pos into a fresh cell array.
+static int bin_particles(gcmc_box* box, int64_t n, hipStream_t s, bool keep_error, double u_pair) {
+    DevBox& B = box->d;
+    k_reset_state<<<1, 1, 0, s>>>(B.st, n, u_pair, keep_error ? 1 : 0);
+    k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
+    if (n > 0) k_bin<<<grid_for(n), 256, 0, s>>>(B, n);
+    k_sort_cells<<<grid_for(B.ncells), 256, 0, s>>>(B);
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
+static int alloc_cells(gcmc_box* box, int32_t cap) {
+    DevBox& B = box->d;
+    if (B.ent) {
+        GCMC_HIP(hipFree(B.ent));
+        B.ent = nullptr;
+    }
+    const size_t bytes = (size_t)B.ncells * (size_t)cap * sizeof(double4);
+    if (hipMalloc(&B.ent, bytes) != hipSuccess) {
+        B.ent = nullptr;
+        return set_error(GCMC_ERR_OOM, "cell array allocation failed");
+    }
+    B.cap = cap;
+    return GCMC_OK;
+}
+
+static int sync_desc(gcmc_box* box) {
+    GCMC_HIP(hipMemcpy(box->d_desc, &box->d, sizeof(DevBox), hipMemcpyHostToDevice));
+    return GCMC_OK;
+}
+
+static int read_state(gcmc_box* box, BoxState* h, hipStream_t s) {
+    GCMC_HIP(hipMemcpyAsync(h, box->d.st, sizeof(BoxState), hipMemcpyDeviceToHost, s));
+    GCMC_HIP(hipStreamSynchronize(s));
+    return GCMC_OK;
+}
+
+namespace gcmc {
+int read_box_state(gcmc_box* box, BoxState* h, hipStream_t s) { return read_state(box, h, s); }
+
+int ensure_scratch(gcmc_box* box, int64_t len) {
+    if (box->scratch_len >= len) return GCMC_OK;
+    if (box->scratch) {
+        GCMC_HIP(hipDeviceSynchronize());
+        GCMC_HIP(hipFree(box->scratch));
+        box->scratch = nullptr;
+        box->scratch_len = 0;
+    }
+    if (hipMalloc(&box->scratch, (size_t)len * sizeof(double)) != hipSuccess) {
+        box->scratch = nullptr;
+        return set_error(GCMC_ERR_OOM, "scratch allocation failed");
+    }
+    box->scratch_len = len;
+    return GCMC_OK;
+}
+}  // namespace gcmc
+
+static void free_box(gcmc_box* box) {
+    if (!box) return;
+    if (box->d.pos) (void)hipFree(box->d.pos);
+    if (box->d.ent) (void)hipFree(box->d.ent);
+    if (box->d.count) (void)hipFree(box->d.count);
+    if (box->d.st) (void)hipFree(box->d.st);
+    if (box->d_desc) (void)hipFree(box->d_desc);
+    if (box->scratch) (void)hipFree(box->scratch);
+    if (box->ap_chain) (void)hipFree(box->ap_chain);
+    delete box;
+}
+
+extern "C" {
+
+const char* gcmc_last_error(void) { return g_last_error.c_str(); }
+
+const char* gcmc_version(void) { return "gcmc-gfx950 0.1"; }
+
+int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* d_y, const double* d_z,
+                    const int32_t* d_species, int64_t n, void* stream, gcmc_box** out) {
+    g_last_error.clear();
+    if (!out) return set_error(GCMC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate_desc(desc, n);
+    if (rc) return rc;
+    if (n > 0 && (!d_x || !d_y || !d_z)) return set_error(GCMC_ERR_INVALID_ARG, "coordinate arrays are NULL");
+    hipStream_t s = (hipStream_t)stream;
+    gcmc_box* box = new gcmc_box();
+    memset(box, 0, sizeof(*box));
+    GCMC_HIP(hipGetDevice(&box->device));
+    box->waves = 4;
+    box->rows = 4;
+    DevBox& B = box->d;
+    if ((rc = setup_grid(B, desc))) {
+        free_box(box);
+        return rc;
+    }
+    setup_params(B, desc);
+    if (hipMalloc(&B.pos, (size_t)B.max_n * sizeof(double4)) != hipSuccess ||
+        hipMalloc(&B.count, (size_t)B.ncells * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&B.st, sizeof(BoxState)) != hipSuccess || hipMalloc(&box->d_desc, sizeof(DevBox)) != hipSuccess) {
+        free_box(box);
+        return set_error(GCMC_ERR_OOM, "box allocation failed");
+    }
+    // upload and count occupancy to size the cells
+    k_reset_state<<<1, 1, 0, s>>>(B.st, n, 0.0, 0);
+    if (n > 0) k_upload<<<grid_for(n), 256, 0, s>>>(B, d_x, d_y, d_z, d_species, n);
+    k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
+    if (n > 0) k_count<<<grid_for(n), 256, 0, s>>>(B, n);
+    BoxState h;
+    if ((rc = read_state(box, &h, s))) {
+        free_box(box);
+        return rc;
+    }
+    if (h.error) {
+        free_box(box);
+        return set_error(GCMC_ERR_INVALID_ARG, "coordinates must lie in [0, L) and species in [0, n_species)");
+    }
+    const int32_t cap = desc->cell_cap > 0 ? desc->cell_cap : auto_cap(h.maxcount);
+    if (h.maxcount > cap) {
+        free_box(box);
+        return set_error(GCMC_ERR_CELL_OVERFLOW, "cell_cap smaller than the densest cell");
+    }
+    if ((rc = alloc_cells(box, cap)) || (rc = bin_particles(box, n, s, false, 0.0)) || (rc = read_state(box, &h, s))) {
+        free_box(box);
+        return rc;
+    }
+    if (h.error) {
+        free_box(box);
+        return set_error(h.error, "binning failed");
+    }
+    if ((rc = sync_desc(box))) {
+        free_box(box);
+        return rc;
+    }
+    *out = box;
+    return GCMC_OK;
+}
+
+int gcmc_box_destroy(gcmc_box* box) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    (void)hipDeviceSynchronize();
+    free_box(box);
+    return GCMC_OK;
+}
+
+int gcmc_box_get_info(const gcmc_box* box, gcmc_box_info* info) {
+    if (!box || !info) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    for (int a = 0; a < 3; ++a) {
+        info->cell_m[a] = box->d.M[a];
+        info->span[a] = box->d.span[a];
+        info->inv_s[a] = box->d.invS[a];
+    }
+    info->cell_cap = box->d.cap;
+    info->n_species = box->d.ns;
+    info->n_cells = box->d.ncells;
+    info->max_n = box->d.max_n;
+    return GCMC_OK;
+}
+
+int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    if (new_cap < 0) return set_error(GCMC_ERR_INVALID_ARG, "new_cap must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    BoxState h;
+    int rc = read_state(box, &h, s);
+    if (rc) return rc;
+    if (h.error && h.error != GCMC_ERR_CELL_OVERFLOW)
+        return set_error(GCMC_ERR_POISONED, "box holds a latched error that a rebuild does not clear");
+    if (new_cap > 0 && new_cap != box->d.cap) {
+        if ((rc = alloc_cells(box, new_cap))) return rc;
+    }
+    k_clear_overflow<<<1, 1, 0, s>>>(box->d.st);
+    // keep N, running energy and the error move counter; re-bin
+    const int64_t n = h.n;
+    if ((rc = bin_particles(box, n, s, true, h.u_pair))) return rc;
+    if ((rc = read_state(box, &h, s))) return rc;
+    if ((rc = sync_desc(box))) return rc;
+    if (h.maxcount > box->d.cap) return set_error(GCMC_ERR_CELL_OVERFLOW, "cell_cap smaller than the densest cell");
+    return GCMC_OK;
+}
+
+int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z, void* stream) {
+    if (!box || !d_x || !d_y || !d_z) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    BoxState h;
+    int rc = read_state(box, &h, s);
+    if (rc) return rc;
+    if (h.error) return set_error(GCMC_ERR_POISONED, "box holds a latched error");
+    // species are kept: copy them out of the records first
+    int32_t* sp = nullptr;
+    if (h.n > 0) {
+        GCMC_HIP(hipMallocAsync((void**)&sp, (size_t)h.n * sizeof(int32_t), s));
+        k_get_particles<<<grid_for(h.n), 256, 0, s>>>(box->d, nullptr, nullptr, nullptr, sp);
+        k_upload<<<grid_for(h.n), 256, 0, s>>>(box->d, d_x, d_y, d_z, sp, h.n);
+        GCMC_HIP(hipFreeAsync(sp, s));
+    }
+    if ((rc = read_state(box, &h, s))) return rc;
+    if (h.error) return set_error(GCMC_ERR_INVALID_ARG, "coordinates must lie in [0, L)");
+    if ((rc = bin_particles(box, h.n, s, false, h.u_pair))) return rc;
+    if ((rc = read_state(box, &h, s))) return rc;
+    if (h.error) return set_error(h.error, "re-binning overflowed a cell; rebuild with a larger cell_cap");
+    return GCMC_OK;
+}
+
+int gcmc_get_particles(gcmc_box* box, double* d_x, double* d_y, double* d_z, int32_t* d_species, int64_t* h_n,
+                       void* stream) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    BoxState h;
+    int rc = read_state(box, &h, s);
+    if (rc) return rc;
+    if (h.n > 0) k_get_particles<<<grid_for(h.n), 256, 0, s>>>(box->d, d_x, d_y, d_z, d_species);
+    GCMC_HIP(hipGetLastError());
+    GCMC_HIP(hipStreamSynchronize(s));
+    if (h_n) *h_n = h.n;
+    return GCMC_OK;
+}
+
+int gcmc_get_cells(gcmc_box* box, int32_t* d_cell_of, int32_t* d_count, int32_t* d_ids, void* stream) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    k_get_cells<<<grid_for(box->d.ncells * box->d.cap), 256, 0, s>>>(box->d, d_cell_of, d_count, d_ids);
+    GCMC_HIP(hipGetLastError());
+    GCMC_HIP(hipStreamSynchronize(s));
+    return GCMC_OK;
+}
+
+int gcmc_export_state(gcmc_box* box, int64_t* h_n, double* h_u_pair, int32_t* h_error) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    BoxState h;
+    GCMC_HIP(hipDeviceSynchronize());
+    GCMC_HIP(hipMemcpy(&h, box->d.st, sizeof(BoxState), hipMemcpyDeviceToHost));
+    if (h_n) *h_n = h.n;
+    if (h_u_pair) *h_u_pair = h.u_pair;
+    if (h_error) *h_error = h.error;
+    return GCMC_OK;
+}
+
+int gcmc_import_state(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z,
+                      const int32_t* d_species, int64_t n, double u_pair, void* stream) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    if (n < 0 || n > box->d.max_n) return set_error(GCMC_ERR_INVALID_ARG, "need 0 <= n <= max_n");
+    if (n > 0 && (!d_x || !d_y || !d_z)) return set_error(GCMC_ERR_INVALID_ARG, "coordinate arrays are NULL");
+    hipStream_t s = (hipStream_t)stream;
+    k_reset_state<<<1, 1, 0, s>>>(box->d.st, n, u_pair, 0);
+    if (n > 0) k_upload<<<grid_for(n), 256, 0, s>>>(box->d, d_x, d_y, d_z, d_species, n);
+    BoxState h;
+    int rc = read_state(box, &h, s);
+    if (rc) return rc;
+    if (h.error) return set_error(GCMC_ERR_INVALID_ARG, "coordinates must lie in [0, L) and species in range");
+    if ((rc = bin_particles(box, n, s, false, u_pair))) return rc;
+    if ((rc = read_state(box, &h, s))) return rc;
+    if (h.error) return set_error(h.error, "binning overflowed a cell; rebuild with a larger cell_cap");
+    return GCMC_OK;
+}
+
+int gcmc_sync_status(gcmc_box* box) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    GCMC_HIP(hipDeviceSynchronize());
+    BoxState h;
+    GCMC_HIP(hipMemcpy(&h, box->d.st, sizeof(BoxState), hipMemcpyDeviceToHost));
+    if (h.error) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "box holds latched error %d raised at move %lld", h.error, (long long)h.error_move);
+        return set_error(h.error, buf);
+    }
+    return GCMC_OK;
+}
+
+}  // extern "C"

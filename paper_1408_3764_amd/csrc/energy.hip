@@ -1,0 +1,709 @@
+// Total energy, the all-pairs (no cell list) energy path, and the gradient.
+//
+// Total energy over the cell list: G = the power of two at or above the
+// largest cell count; a workgroup of 256 lanes covers 256/G cells, lane k of a
+// cell owns that cell's k-th particle, and all lanes of a cell walk the same
+// stencil cells together, so each candidate entry is one 32-byte load shared
+// by the G lanes of its group.  e_i is summed per lane, U_pair = (1/2) sum e_i
+// (Sec. 3.1.1 computes each unique pair once; here each pair is met from both
+// ends, which needs no atomics), workgroup partials are summed by one more
+// workgroup in a fixed order.
+//
+// The all-pairs path (Algorithms 3 and 4 without a cell list) streams the
+// particle records in chunks, one chunk per workgroup, with the same
+// fixed-order second pass.
+#include "gcmc_internal.h"
+
+namespace gcmc {
+
+constexpr int kBlk = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    const int nw = blockDim.x / kWave;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    return t;
+}
+
+__device__ __forceinline__ void build_stencil_tab(const DevBox& B, uint32_t* tab) {
+    const int sx = B.span[0], sy = B.span[1];
+    for (int t = threadIdx.x; t < B.nstencil; t += blockDim.x) {
+        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
+        tab[t] = (uint32_t)tx | ((uint32_t)ty << 10) | ((uint32_t)tz << 20);
+    }
+}
+
+__device__ __forceinline__ void cell_coords(const DevBox& B, int64_t c, int32_t& cx, int32_t& cy, int32_t& cz) {
+    cx = (int32_t)(c % B.M[0]);
+    const int64_t r = c / B.M[0];
+    cy = (int32_t)(r % B.M[1]);
+    cz = (int32_t)(r / B.M[1]);
+}
+
+// ------------------------------------------------------ cell-list total
+// Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
+template <bool MIX>
+__global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__ boxp, int lg, double* e_out,
+                                                       double* partial) {
+    __shared__ uint32_t tab[kMaxStencil];
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    build_stencil_tab(B, tab);
+    __syncthreads();
+    const int G = 1 << lg;
+    const int cells_per_blk = kBlk >> lg;
+    const int64_t c = (int64_t)blockIdx.x * cells_per_blk + (threadIdx.x >> lg);
+    const int k = threadIdx.x & (G - 1);
+    double ei = 0.0;
+    if (c < B.ncells) {
+        const int32_t cnt = B.count[c];
+        const bool own = k < cnt;
+        const double4 me = B.ent[c * B.cap + (own ? k : 0)];
+        const int32_t myid = own ? meta_low(me.w) : -1;
+        const int sa = meta_species(me.w);
+        int32_t cx, cy, cz;
+        cell_coords(B, c, cx, cy, cz);
+        if (cnt > 0) {
+            for (int t = 0; t < B.nstencil; ++t) {
+                const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
+                const int32_t nc = B.count[nb];
+                const double4* ne = B.ent + nb * B.cap;
+                for (int j = 0; j < nc; ++j) {
+                    const double4 o = ne[j];
+                    if (own && meta_low(o.w) != myid) {
+                        const double r2 = dist2(B, me.x, me.y, me.z, o.x, o.y, o.z);
+                        if (MIX) {
+                            const int q = sa * B.ns + meta_species(o.w);
+                            ei += lj_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q]);
+                        } else {
+                            ei += lj_from_r2(r2, B.rc2, B.eps4[0], B.sig2[0]);
+                        }
+                    }
+                }
+            }
+        }
+        if (own && e_out) e_out[myid] = ei;
+    }
+    const double s = block_sum(ei, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// --------------------------------------------------------- all-pairs total
+template <bool MIX>
+__global__ __launch_bounds__(kBlk) void k_total_allpairs(const DevBox* __restrict__ boxp, double* e_out,
+                                                          double* partial) {
+    __shared__ double4 tile[kBlk];
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    const int64_t n = B.st->n;
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    const bool own = i < n;
+    const double4 me = B.pos[own ? i : 0];
+    const int sa = meta_species(me.w);
+    double ei = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += kBlk) {
+        const int64_t j = j0 + threadIdx.x;
+        __syncthreads();
+        tile[threadIdx.x] = B.pos[j < n ? j : 0];
+        __syncthreads();
+        const int lim = (n - j0) < kBlk ? (int)(n - j0) : kBlk;
+        for (int q = 0; q < lim; ++q) {
+            const double4 o = tile[q];
+            if (own && j0 + q != i) {
+                const double r2 = dist2(B, me.x, me.y, me.z, o.x, o.y, o.z);
+                if (MIX) {
+                    const int qq = sa * B.ns + meta_species(o.w);
+                    ei += lj_from_r2(r2, B.rc2, B.eps4[qq], B.sig2[qq]);
+                } else {
+                    ei += lj_from_r2(r2, B.rc2, B.eps4[0], B.sig2[0]);
+                }
+            }
+        }
+    }
+    if (own && e_out) e_out[i] = ei;
+    const double s = block_sum(ei, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// U_pair = 0.5 * sum(partial) in a fixed order; U_tail from the species
+// counts; the running pair energy is reset to U_pair.
+__global__ __launch_bounds__(kBlk) void k_total_finish(const DevBox* __restrict__ boxp, const double* partial,
+                                                        int64_t np, double* U) {
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < np; q += kBlk) s += partial[q];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        const double up = 0.5 * s;
+        double ut = 0.0;
+        for (int a = 0; a < B.ns; ++a)
+            for (int b = 0; b < B.ns; ++b)
+                ut += (double)B.st->nsp[a] * (double)B.st->nsp[b] * B.tailK[a * B.ns + b];
+        U[0] = up;
+        U[1] = ut;
+        if (B.st->error == GCMC_OK) B.st->u_pair = up;
+    }
+}
+
+// ------------------------------------------------------ all-pairs moves
+// The trial of move m of the all-pairs chain, or of a caller-given move.
+struct APTrial {
+    int type, npos, sp;
+    int64_t idx;
+    double p[2][3];
+    bool valid;
+};
+
+__device__ __forceinline__ void ap_chunk_sums(const DevBox& B, const APTrial& T, int64_t n, int64_t j0,
+                                              int64_t j1, bool mix, double& sa, double& sb) {
+    sa = 0.0;
+    sb = 0.0;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+        if (j == T.idx) continue;
+        const double4 o = B.pos[j];
+        int q = 0;
+        if (mix) q = T.sp * B.ns + meta_species(o.w);
+        const double r2a = dist2(B, T.p[0][0], T.p[0][1], T.p[0][2], o.x, o.y, o.z);
+        sa += lj_from_r2(r2a, B.rc2, B.eps4[q], B.sig2[q]);
+        if (T.npos == 2) {
+            const double r2b = dist2(B, T.p[1][0], T.p[1][1], T.p[1][2], o.x, o.y, o.z);
+            sb += lj_from_r2(r2b, B.rc2, B.eps4[q], B.sig2[q]);
+        }
+    }
+}
+
+__device__ __forceinline__ APTrial ap_trial_from_move(const DevBox& B, const gcmc_move& mv, int64_t n) {
+    APTrial T;
+    T.valid = true;
+    T.type = mv.type;
+    T.idx = -1;
+    T.npos = 1;
+    T.sp = 0;
+    if (mv.type == GCMC_MOVE_INSERT) {
+        T.valid = mv.species >= 0 && mv.species < B.ns;
+        T.sp = mv.species;
+        T.p[0][0] = mv.x; T.p[0][1] = mv.y; T.p[0][2] = mv.z;
+        return T;
+    }
+    if ((mv.type != GCMC_MOVE_DISPLACE && mv.type != GCMC_MOVE_DELETE) || mv.index < 0 || mv.index >= n) {
+        T.valid = false;
+        return T;
+    }
+    T.idx = mv.index;
+    const double4 pi = B.pos[T.idx];
+    T.sp = meta_species(pi.w);
+    T.p[0][0] = pi.x; T.p[0][1] = pi.y; T.p[0][2] = pi.z;
+    if (mv.type == GCMC_MOVE_DISPLACE) {
+        T.npos = 2;
+        T.p[1][0] = mv.x; T.p[1][1] = mv.y; T.p[1][2] = mv.z;
+    }
+    return T;
+}
+
+// grid (chunks, moves): scratch[(m * chunks + chunk) * 2 + {0,1}]
+__global__ __launch_bounds__(kBlk) void k_delta_ap_partial(const DevBox* __restrict__ boxp, const gcmc_move* moves,
+                                                            int64_t chunk, double* scratch) {
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    const int64_t n = B.st->n;
+    const int64_t m = blockIdx.y;
+    const APTrial T = ap_trial_from_move(B, moves[m], n);
+    const int64_t j0 = (int64_t)blockIdx.x * chunk;
+    int64_t j1 = j0 + chunk;
+    if (j1 > n) j1 = n;
+    double sa = 0.0, sb = 0.0;
+    if (T.valid) ap_chunk_sums(B, T, n, j0, j1, B.ns > 1, sa, sb);
+    sa = block_sum(sa, red);
+    sb = block_sum(sb, red);
+    if (threadIdx.x == 0) {
+        scratch[(m * gridDim.x + blockIdx.x) * 2] = sa;
+        scratch[(m * gridDim.x + blockIdx.x) * 2 + 1] = sb;
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_delta_ap_finish(const DevBox* __restrict__ boxp, const gcmc_move* moves,
+                                                           int64_t nchunks, const double* scratch, double* dU_pair,
+                                                           double* dU_tail) {
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    const int64_t n = B.st->n;
+    const int64_t m = blockIdx.x;
+    const APTrial T = ap_trial_from_move(B, moves[m], n);
+    double sa = 0.0, sb = 0.0;
+    for (int64_t q = threadIdx.x; q < nchunks; q += kBlk) {
+        sa += scratch[(m * nchunks + q) * 2];
+        sb += scratch[(m * nchunks + q) * 2 + 1];
+    }
+    sa = block_sum(sa, red);
+    sb = block_sum(sb, red);
+    if (threadIdx.x == 0) {
+        int64_t nsp[kMaxSpecies];
+        for (int s = 0; s < kMaxSpecies; ++s) nsp[s] = B.st->nsp[s];
+        double p, t;
+        if (!T.valid) {
+            p = __builtin_nan("");
+            t = __builtin_nan("");
+        } else if (T.type == GCMC_MOVE_DISPLACE) {
+            p = sb - sa;
+            t = 0.0;
+        } else if (T.type == GCMC_MOVE_INSERT) {
+            p = sa;
+            t = tail_change(B, nsp, T.sp, +1);
+        } else {
+            p = -sa;
+            t = tail_change(B, nsp, T.sp, -1);
+        }
+        dU_pair[m] = p;
+        if (dU_tail) dU_tail[m] = t;
+    }
+}
+
+// ------------------------------------------------ all-pairs chain (A12)
+// Device-side chain bookkeeping of the all-pairs path.
+struct APChain {
+    uint64_t counter;   // next move counter
+    uint64_t ctr0;      // first counter of this call
+    int64_t att[3], acc[3];
+    double sum_n, sum_u;
+    int64_t moves_done;
+    int64_t candidates, pair_evals;
+};
+
+__device__ __forceinline__ APTrial ap_trial_from_draws(const DevBox& B, const U8& u, int64_t n) {
+    APTrial T;
+    T.valid = true;
+    T.sp = 0;
+    T.type = (u.u[0] < B.p_disp) ? GCMC_MOVE_DISPLACE : ((u.u[1] < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
+    T.idx = -1;
+    T.npos = 1;
+    if (T.type == GCMC_MOVE_INSERT) {
+        for (int a = 0; a < 3; ++a) T.p[0][a] = wrap_into_box(B.L[a] * u.u[4 + a], B.L[a]);
+        return T;
+    }
+    if (n == 0) {
+        T.valid = false;
+        return T;
+    }
+    int64_t i = (int64_t)floor(u.u[2] * (double)n);
+    if (i > n - 1) i = n - 1;
+    T.idx = i;
+    const double4 pi = B.pos[i];
+    T.p[0][0] = pi.x; T.p[0][1] = pi.y; T.p[0][2] = pi.z;
+    if (T.type == GCMC_MOVE_DISPLACE) {
+        T.npos = 2;
+        for (int a = 0; a < 3; ++a)
+            T.p[1][a] = wrap_into_box(T.p[0][a] + B.max_disp * (2.0 * u.u[4 + a] - 1.0), B.L[a]);
+    }
+    return T;
+}
+
+__global__ __launch_bounds__(kBlk) void k_ap_chain_eval(const DevBox* __restrict__ boxp, const APChain* ch,
+                                                         int64_t chunk, double* scratch) {
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    if (B.st->error != GCMC_OK) return;
+    const int64_t n = B.st->n;
+    const U8 u = move_uniforms(B.seed, ch->counter, B.box_id);
+    const APTrial T = ap_trial_from_draws(B, u, n);
+    const int64_t j0 = (int64_t)blockIdx.x * chunk;
+    int64_t j1 = j0 + chunk;
+    if (j1 > n) j1 = n;
+    double sa = 0.0, sb = 0.0;
+    if (T.valid) ap_chunk_sums(B, T, n, j0, j1, false, sa, sb);
+    sa = block_sum(sa, red);
+    sb = block_sum(sb, red);
+    if (threadIdx.x == 0) {
+        scratch[blockIdx.x * 2] = sa;
+        scratch[blockIdx.x * 2 + 1] = sb;
+    }
+}
+
+__device__ int commit_ap(const DevBox& B, const APTrial& T, const double4& meta_rec, int64_t n, int32_t& maxc);
+
+__global__ __launch_bounds__(kBlk) void k_ap_chain_decide(const DevBox* __restrict__ boxp, APChain* ch,
+                                                           int64_t nchunks, const double* scratch, gcmc_log* log) {
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    BoxState* st = B.st;
+    if (st->error != GCMC_OK) return;
+    const int64_t n = st->n;
+    const uint64_t ctr = ch->counter;
+    const U8 u = move_uniforms(B.seed, ctr, B.box_id);
+    const APTrial T = ap_trial_from_draws(B, u, n);
+    double sa = 0.0, sb = 0.0;
+    for (int64_t q = threadIdx.x; q < nchunks; q += kBlk) {
+        sa += scratch[q * 2];
+        sb += scratch[q * 2 + 1];
+    }
+    sa = block_sum(sa, red);
+    sb = block_sum(sb, red);
+    if (threadIdx.x != 0) return;
+    const int64_t m = (int64_t)(ctr - ch->ctr0);
+    const double tk = B.tailK[0];
+    ch->att[T.type] += 1;
+    gcmc_log r;
+    r.type = T.type;
+    r.flags = 0;
+    r.accepted = 0;
+    r.dU_pair = 0.0;
+    r.dU_tail = 0.0;
+    r.arg = 0.0;
+    r.x = r.y = r.z = 0.0;
+    int64_t n_after = n;
+    if (!T.valid) {
+        r.index = -1;
+        r.flags = 1;
+    } else {
+        double dUp, dUt;
+        if (T.type == GCMC_MOVE_DISPLACE) {
+            dUp = sb - sa;
+            dUt = 0.0;
+        } else if (T.type == GCMC_MOVE_INSERT) {
+            dUp = sa;
+            dUt = tk * (2.0 * (double)n + 1.0);
+        } else {
+            dUp = -sa;
+            dUt = tk * (1.0 - 2.0 * (double)n);
+        }
+        const double dU = dUp + dUt;
+        const double arg = accept_log_ratio(B, T.type, dU, n);
+        const bool ok = metropolis(arg, dU, u.u[3]);
+        r.index = (T.type == GCMC_MOVE_INSERT) ? (int32_t)n : (int32_t)T.idx;
+        r.dU_pair = dUp;
+        r.dU_tail = dUt;
+        r.arg = arg;
+        const int w = (T.type == GCMC_MOVE_DISPLACE) ? 1 : 0;
+        r.x = T.p[w][0]; r.y = T.p[w][1]; r.z = T.p[w][2];
+        const int64_t others = (T.idx >= 0) ? n - 1 : n;
+        ch->candidates += others;
+        ch->pair_evals += others * T.npos;
+        if (ok) {
+            int32_t mc = st->maxcount;
+            const double4 rec = (T.idx >= 0) ? B.pos[T.idx] : make_double4(0, 0, 0, 0);
+            const int e = commit_ap(B, T, rec, n, mc);
+            if (e != GCMC_OK) {
+                ch->att[T.type] -= 1;
+                st->error = e;
+                st->error_move = (int64_t)ctr;
+                return;
+            }
+            st->maxcount = mc;
+            n_after = n + ((T.type == GCMC_MOVE_INSERT) ? 1 : ((T.type == GCMC_MOVE_DELETE) ? -1 : 0));
+            st->n = n_after;
+            st->nsp[0] = n_after;
+            st->u_pair += dUp;
+            ch->acc[T.type] += 1;
+            r.accepted = 1;
+        }
+    }
+    if (log) log[m] = r;
+    ch->sum_n += (double)n_after;
+    ch->sum_u += st->u_pair + tk * (double)n_after * (double)n_after;
+    ch->moves_done = m + 1;
+    ch->counter = ctr + 1;
+}
+
+__global__ void k_ap_chain_begin(APChain* ch, uint64_t ctr0) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ch->counter = ctr0;
+        ch->ctr0 = ctr0;
+        for (int t = 0; t < 3; ++t) ch->att[t] = ch->acc[t] = 0;
+        ch->sum_n = ch->sum_u = 0.0;
+        ch->moves_done = 0;
+        ch->candidates = ch->pair_evals = 0;
+    }
+}
+
+__global__ void k_ap_chain_end(const DevBox* __restrict__ boxp, const APChain* ch, gcmc_stats* stats) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const DevBox& B = *boxp;
+    gcmc_stats o;
+    for (int t = 0; t < 3; ++t) {
+        o.attempts[t] = ch->att[t];
+        o.accepts[t] = ch->acc[t];
+    }
+    o.n = B.st->n;
+    o.moves_done = ch->moves_done;
+    o.u_pair = B.st->u_pair;
+    o.u_tail = B.tailK[0] * (double)o.n * (double)o.n;
+    o.sum_n = ch->sum_n;
+    o.sum_u = ch->sum_u;
+    o.error = B.st->error;
+    o.pad = 0;
+    o.error_move = B.st->error_move;
+    o.stencils = ch->moves_done;
+    o.candidates = ch->candidates;
+    o.pair_evals = ch->pair_evals;
+    o.in_cutoff = -1;   // not counted on the all-pairs path
+    *stats = o;
+}
+
+// The all-pairs chain keeps the cell list up to date as well (same commit).
+__device__ int commit_ap(const DevBox& B, const APTrial& T, const double4& rec, int64_t n, int32_t& maxc) {
+    const int cap = B.cap;
+    auto cell_of = [&](const double* p) {
+        const int32_t cx = axis_cell(p[0], B.invS[0], B.M[0]);
+        const int32_t cy = axis_cell(p[1], B.invS[1], B.M[1]);
+        const int32_t cz = axis_cell(p[2], B.invS[2], B.M[2]);
+        return ((int64_t)cz * B.M[1] + cy) * B.M[0] + cx;
+    };
+    auto remove = [&](int64_t c, int64_t loc) {
+        const int32_t nc = B.count[c];
+        const int64_t last = c * cap + nc - 1;
+        if (loc != last) {
+            const double4 e = B.ent[last];
+            B.ent[loc] = e;
+            B.pos[meta_low(e.w)].w = pack_meta(meta_species(e.w), (int32_t)loc);
+        }
+        B.count[c] = nc - 1;
+    };
+    if (T.type == GCMC_MOVE_DISPLACE) {
+        const int64_t c0 = cell_of(T.p[0]), c1 = cell_of(T.p[1]);
+        const int64_t loc = meta_low(rec.w);
+        if (c0 == c1) {
+            B.ent[loc] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)T.idx));
+            B.pos[T.idx] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], rec.w);
+            return GCMC_OK;
+        }
+        const int32_t nc = B.count[c1];
+        if (nc >= cap) return GCMC_ERR_CELL_OVERFLOW;
+        remove(c0, loc);
+        const int64_t nl = c1 * cap + nc;
+        B.ent[nl] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)T.idx));
+        B.count[c1] = nc + 1;
+        B.pos[T.idx] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)nl));
+        if (nc + 1 > maxc) maxc = nc + 1;
+        return GCMC_OK;
+    }
+    if (T.type == GCMC_MOVE_INSERT) {
+        if (n >= B.max_n) return GCMC_ERR_CAPACITY;
+        const int64_t c0 = cell_of(T.p[0]);
+        const int32_t nc = B.count[c0];
+        if (nc >= cap) return GCMC_ERR_CELL_OVERFLOW;
+        const int64_t nl = c0 * cap + nc;
+        B.ent[nl] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)n));
+        B.count[c0] = nc + 1;
+        B.pos[n] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)nl));
+        if (nc + 1 > maxc) maxc = nc + 1;
+        return GCMC_OK;
+    }
+    const int64_t c0 = cell_of(T.p[0]);
+    remove(c0, meta_low(rec.w));
+    if (T.idx != n - 1) {
+        const double4 last = B.pos[n - 1];
+        B.pos[T.idx] = last;
+        B.ent[meta_low(last.w)].w = pack_meta(meta_species(last.w), (int32_t)T.idx);
+    }
+    return GCMC_OK;
+}
+
+// ------------------------------------------------------------- gradient
+// Per particle: dU/dr_i = sum_j (24 eps / r^2)(2 s12 - s6) d_ij, written by
+// particle id; parameter partials per block: [0, ns^2) d eps, [ns^2, 2 ns^2)
+// d sigma, each pair met twice contributing half from each end.
+template <bool MIX>
+__global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ boxp, int lg, double* grad,
+                                                      double* partial) {
+    __shared__ uint32_t tab[kMaxStencil];
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    build_stencil_tab(B, tab);
+    __syncthreads();
+    const int64_t n = B.st->n;
+    const int G = 1 << lg;
+    const int cells_per_blk = kBlk >> lg;
+    const int64_t c = (int64_t)blockIdx.x * cells_per_blk + (threadIdx.x >> lg);
+    const int k = threadIdx.x & (G - 1);
+    const int ns = B.ns;
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    double de[kMaxSpecies] = {0, 0, 0, 0}, ds[kMaxSpecies] = {0, 0, 0, 0};
+    int sa = 0;
+    bool own = false;
+    int32_t myid = -1;
+    if (c < B.ncells) {
+        const int32_t cnt = B.count[c];
+        own = k < cnt;
+        const double4 me = B.ent[c * B.cap + (own ? k : 0)];
+        myid = own ? meta_low(me.w) : -1;
+        sa = meta_species(me.w);
+        int32_t cx, cy, cz;
+        cell_coords(B, c, cx, cy, cz);
+        if (cnt > 0) {
+            for (int t = 0; t < B.nstencil; ++t) {
+                const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
+                const int32_t nc = B.count[nb];
+                const double4* ne = B.ent + nb * B.cap;
+                for (int j = 0; j < nc; ++j) {
+                    const double4 o = ne[j];
+                    if (!own || meta_low(o.w) == myid) continue;
+                    const double dx = nearest_image(o.x - me.x, B.L[0], B.hL[0]);
+                    const double dy = nearest_image(o.y - me.y, B.L[1], B.hL[1]);
+                    const double dz = nearest_image(o.z - me.z, B.L[2], B.hL[2]);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (!(r2 < B.rc2) || r2 == 0.0) continue;
+                    const int sb = meta_species(o.w);
+                    const int q = MIX ? sa * ns + sb : 0;
+                    const double eps4 = B.eps4[q], sig2 = B.sig2[q];
+                    const double sr2 = sig2 / r2;
+                    const double s6 = sr2 * sr2 * sr2;
+                    const double s12 = s6 * s6;
+                    const double coef = (6.0 * eps4 / r2) * (2.0 * s12 - s6);
+                    gx += coef * dx;
+                    gy += coef * dy;
+                    gz += coef * dz;
+                    const double t_e = 0.5 * 4.0 * (s12 - s6);
+                    const double t_s = 0.5 * (eps4 / sqrt(sig2)) * (12.0 * s12 - 6.0 * s6);
+                    if (MIX) {
+                        for (int b = 0; b < kMaxSpecies; ++b)
+                            if (b == sb) {
+                                de[b] += t_e;
+                                ds[b] += t_s;
+                            }
+                    } else {
+                        de[0] += t_e;
+                        ds[0] += t_s;
+                    }
+                }
+            }
+        }
+        if (own && grad) {
+            grad[myid] = gx;
+            grad[n + myid] = gy;
+            grad[2 * n + myid] = gz;
+        }
+    }
+    // parameter partials: entry (a, b) gets the lanes with own species a
+    for (int a = 0; a < ns; ++a) {
+        for (int b = 0; b < ns; ++b) {
+            const bool mine = own && sa == a;
+            const double ve = block_sum(mine ? de[b] : 0.0, red);
+            const double vs = block_sum(mine ? ds[b] : 0.0, red);
+            if (threadIdx.x == 0) {
+                partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + a * ns + b] = ve;
+                partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + kMaxSpecies * kMaxSpecies + a * ns + b] =
+                    vs;
+            }
+        }
+    }
+}
+
+// Sum the parameter partials in order and add the tail-correction terms.
+__global__ __launch_bounds__(kBlk) void k_grad_finish(const DevBox* __restrict__ boxp, const double* partial,
+                                                       int64_t np, double* deps, double* dsig) {
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    const int ns = B.ns;
+    const int stride = 2 * kMaxSpecies * kMaxSpecies;
+    for (int q = 0; q < ns * ns; ++q) {
+        double se = 0.0, ss = 0.0;
+        for (int64_t b = threadIdx.x; b < np; b += kBlk) {
+            se += partial[b * stride + q];
+            ss += partial[b * stride + kMaxSpecies * kMaxSpecies + q];
+        }
+        se = block_sum(se, red);
+        ss = block_sum(ss, red);
+        if (threadIdx.x == 0) {
+            const int a = q / ns, b = q % ns;
+            const double pre = (8.0 * M_PI / (3.0 * B.V)) * (double)B.st->nsp[a] * (double)B.st->nsp[b];
+            const double e = 0.25 * B.eps4[q], s = sqrt(B.sig2[q]);
+            const double x = s / sqrt(B.rc2), x3 = x * x * x, x9 = x3 * x3 * x3;
+            if (deps) deps[q] = se + pre * (s * s * s) * (x9 / 3.0 - x3);
+            if (dsig) dsig[q] = ss + pre * e * (s * s) * (4.0 * x9 - 6.0 * x3);
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers
+int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_pairs, double* e_out,
+                 double* partial, int64_t partial_len, double* U, hipStream_t s, int64_t n) {
+    const bool mix = hb.ns > 1;
+    int64_t nb;
+    if (all_pairs) {
+        nb = (n + kBlk - 1) / kBlk;
+        if (nb < 1) nb = 1;
+        if (nb > partial_len) return -1;
+        if (mix)
+            hipLaunchKernelGGL(k_total_allpairs<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, e_out, partial);
+        else
+            hipLaunchKernelGGL(k_total_allpairs<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, e_out, partial);
+    } else {
+        int lg = maxc <= 1 ? 0 : 32 - __builtin_clz((unsigned)(maxc - 1));
+        if (lg > 8) return -2;
+        const int cpb = kBlk >> lg;
+        nb = (hb.ncells + cpb - 1) / cpb;
+        if (nb > partial_len) return -1;
+        if (mix)
+            hipLaunchKernelGGL(k_total_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, e_out, partial);
+        else
+            hipLaunchKernelGGL(k_total_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, e_out, partial);
+    }
+    hipLaunchKernelGGL(k_total_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, U);
+    return 0;
+}
+
+int64_t total_partials_needed(const DevBox& hb, int32_t maxc, bool all_pairs, int64_t n) {
+    if (all_pairs) return (n + kBlk - 1) / kBlk + 1;
+    int lg = maxc <= 1 ? 0 : 32 - __builtin_clz((unsigned)(maxc - 1));
+    if (lg > 8) lg = 8;
+    const int cpb = kBlk >> lg;
+    return (hb.ncells + cpb - 1) / cpb + 1;
+}
+
+int64_t grad_partials_needed(const DevBox& hb, int32_t maxc) {
+    return total_partials_needed(hb, maxc, false, 0) * 2 * kMaxSpecies * kMaxSpecies;
+}
+
+int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* grad, double* partial, double* deps,
+                double* dsig, hipStream_t s) {
+    int lg = maxc <= 1 ? 0 : 32 - __builtin_clz((unsigned)(maxc - 1));
+    if (lg > 8) return -2;
+    const int cpb = kBlk >> lg;
+    const int64_t nb = (hb.ncells + cpb - 1) / cpb;
+    if (hb.ns > 1)
+        hipLaunchKernelGGL(k_grad_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, grad, partial);
+    else
+        hipLaunchKernelGGL(k_grad_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, grad, partial);
+    if (deps || dsig)
+        hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, deps, dsig);
+    return 0;
+}
+
+int64_t ap_chunk_len() { return 8 * kBlk; }
+
+int launch_delta_allpairs(const DevBox* d_box, int64_t n, const gcmc_move* moves, int64_t n_moves, double* scratch,
+                          double* dp, double* dt, hipStream_t s) {
+    const int64_t chunk = ap_chunk_len();
+    int64_t nch = (n + chunk - 1) / chunk;
+    if (nch < 1) nch = 1;
+    if (n_moves > 65535) return -1;
+    hipLaunchKernelGGL(k_delta_ap_partial, dim3((unsigned)nch, (unsigned)n_moves), dim3(kBlk), 0, s, d_box, moves,
+                       chunk, scratch);
+    hipLaunchKernelGGL(k_delta_ap_finish, dim3((unsigned)n_moves), dim3(kBlk), 0, s, d_box, moves, nch, scratch, dp,
+                       dt);
+    return 0;
+}
+
+size_t ap_chain_state_bytes() { return sizeof(APChain); }
+
+void launch_ap_chain_begin(void* ch, uint64_t ctr0, hipStream_t s) {
+    hipLaunchKernelGGL(k_ap_chain_begin, dim3(1), dim3(64), 0, s, (APChain*)ch, ctr0);
+}
+
+void launch_ap_chain_move(const DevBox* d_box, void* ch, int64_t nch, double* scratch, gcmc_log* log,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_ap_chain_eval, dim3((unsigned)nch), dim3(kBlk), 0, s, d_box, (const APChain*)ch,
+                       ap_chunk_len(), scratch);
+    hipLaunchKernelGGL(k_ap_chain_decide, dim3(1), dim3(kBlk), 0, s, d_box, (APChain*)ch, nch, scratch, log);
+}
+
+void launch_ap_chain_end(const DevBox* d_box, const void* ch, gcmc_stats* stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_ap_chain_end, dim3(1), dim3(64), 0, s, d_box, (const APChain*)ch, stats);
+}
+
+}  // namespace gcmc

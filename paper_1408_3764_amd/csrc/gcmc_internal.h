@@ -1,0 +1,259 @@
+// Internal definitions shared by the gfx950 kernels and the host side of the
+// C ABI: the device box descriptor, the device-resident box state and the
+// device math (Philox4x32-10, minimum image, Lennard-Jones, wavefront sums).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/gcmc.h"
+
+namespace gcmc {
+
+constexpr int kWave = 64;
+constexpr int kMaxSpecies = GCMC_MAX_SPECIES;
+constexpr int kMaxStencil = 1024;   // stencil cells kept in LDS (span_x * span_y * span_z)
+
+// Device-resident mutable state of one box.
+struct BoxState {
+    int64_t n;            // particle count N
+    double u_pair;        // running pair energy
+    int32_t maxcount;     // upper bound of every cell's count (monotone)
+    int32_t error;        // latched GCMC_ERR_*
+    int64_t error_move;   // move counter of the error, -1 if none
+    int64_t nsp[kMaxSpecies];  // particles per species
+    int64_t counter;      // spare (kept zero)
+};
+
+// Everything a kernel needs about one box (read-only during a launch).
+// Particle record (pos) and cell entry (ent) are both 32 bytes:
+//   pos[i] = {x, y, z, meta}, meta = (species << 32) | loc, loc = c * cap + k
+//   ent[c * cap + k] = {x, y, z, meta}, meta = (species << 32) | particle id
+struct DevBox {
+    double4* pos;
+    double4* ent;
+    int32_t* count;
+    BoxState* st;
+    double L[3];
+    double hL[3];        // 0.5 * L
+    double invS[3];      // M / L
+    int32_t M[3];
+    int32_t span[3];     // stencil cells per axis
+    int32_t k[3];        // stencil half-width
+    int32_t full[3];     // 1 if the stencil covers the whole axis
+    int32_t cap;
+    int32_t ns;
+    int64_t ncells;
+    int64_t max_n;
+    double rc2;
+    double beta, mu, lambda3, max_disp, p_disp;
+    double V;
+    double eps4[kMaxSpecies * kMaxSpecies];   // 4 * eps_ab
+    double sig2[kMaxSpecies * kMaxSpecies];   // sigma_ab^2
+    double tailK[kMaxSpecies * kMaxSpecies];  // (8 pi / 3V) eps sigma^3 (q^9/3 - q^3), q = sigma / rc
+    uint64_t seed;
+    uint32_t box_id;
+    int32_t nstencil;    // span_x * span_y * span_z
+};
+
+// ------------------------------------------------------------------ packing
+__host__ __device__ __forceinline__ double pack_meta(int32_t species, int32_t low) {
+    uint64_t v = ((uint64_t)(uint32_t)species << 32) | (uint64_t)(uint32_t)low;
+    return __builtin_bit_cast(double, v);
+}
+__host__ __device__ __forceinline__ int32_t meta_low(double m) {
+    return (int32_t)(uint32_t)__builtin_bit_cast(uint64_t, m);
+}
+__host__ __device__ __forceinline__ int32_t meta_species(double m) {
+    return (int32_t)(__builtin_bit_cast(uint64_t, m) >> 32);
+}
+
+// -------------------------------------------------------- Philox4x32-10
+// Salmon et al., SC'11: ten rounds of two 32x32->64 products with the round
+// multipliers, key bumped by the Weyl constants between rounds.
+struct U8 { double u[8]; };
+
+__device__ __forceinline__ void philox_block(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                             uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ double to_unit(uint32_t a, uint32_t b) {
+    // 27 + 26 random bits -> a multiple of 2^-53 in [0, 1)
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * 0x1.0p-53;
+}
+
+// The eight uniforms of move `ctr` of box `box` (layout documented in gcmc.h).
+__device__ __forceinline__ U8 move_uniforms(uint64_t seed, uint64_t ctr, uint32_t box) {
+    U8 o;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+        uint32_t c0 = (uint32_t)ctr, c1 = (uint32_t)(ctr >> 32), c2 = box, c3 = j;
+        philox_block(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+        o.u[2 * j] = to_unit(c0, c1);
+        o.u[2 * j + 1] = to_unit(c2, c3);
+    }
+    return o;
+}
+
+// ------------------------------------------------------------- geometry
+__device__ __forceinline__ double nearest_image(double d, double L, double h) {
+    if (d > h) return d - L;
+    if (d < -h) return d + L;
+    return d;
+}
+
+__device__ __forceinline__ double wrap_into_box(double x, double L) {
+    if (x >= L) x -= L;
+    else if (x < 0.0) x += L;
+    if (x >= L) x = 0.0;
+    return x;
+}
+
+__device__ __forceinline__ int32_t axis_cell(double x, double invS, int32_t M) {
+    int32_t c = (int32_t)floor(x * invS);
+    return c > M - 1 ? M - 1 : (c < 0 ? 0 : c);
+}
+
+// Linear cell index of a stencil slot t around centre cell (cx, cy, cz).
+__device__ __forceinline__ int64_t stencil_cell(const DevBox& B, uint32_t packed, int32_t cx, int32_t cy,
+                                                int32_t cz) {
+    const int32_t tx = packed & 0x3FF, ty = (packed >> 10) & 0x3FF, tz = packed >> 20;
+    int32_t x = B.full[0] ? tx : cx - B.k[0] + tx;
+    int32_t y = B.full[1] ? ty : cy - B.k[1] + ty;
+    int32_t z = B.full[2] ? tz : cz - B.k[2] + tz;
+    x += (x < 0) ? B.M[0] : 0; x -= (x >= B.M[0]) ? B.M[0] : 0;
+    y += (y < 0) ? B.M[1] : 0; y -= (y >= B.M[1]) ? B.M[1] : 0;
+    z += (z < 0) ? B.M[2] : 0; z -= (z >= B.M[2]) ? B.M[2] : 0;
+    return ((int64_t)z * B.M[1] + y) * B.M[0] + x;
+}
+
+// ------------------------------------------------------- Lennard-Jones
+// u = 4 eps [(sigma/r)^12 - (sigma/r)^6] inside the cutoff, 0 outside;
+// +inf at r = 0 (overlap), 0 for eps = 0.
+__device__ __forceinline__ double lj_from_r2(double r2, double rc2, double eps4, double sig2) {
+    if (!(r2 < rc2) || eps4 == 0.0) return 0.0;
+    if (r2 == 0.0) return __builtin_inf();
+    const double sr2 = sig2 / r2;
+    const double s6 = sr2 * sr2 * sr2;
+    return eps4 * (s6 * s6 - s6);
+}
+
+__device__ __forceinline__ double dist2(const DevBox& B, double px, double py, double pz, double qx, double qy,
+                                        double qz) {
+    const double dx = nearest_image(qx - px, B.L[0], B.hL[0]);
+    const double dy = nearest_image(qy - py, B.L[1], B.hL[1]);
+    const double dz = nearest_image(qz - pz, B.L[2], B.hL[2]);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+// --------------------------------------------------- wavefront reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_max_i(int32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        int32_t o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------- acceptance
+// Log of the acceptance ratio (Eqs. 3-5; insertion with exponent
+// beta (mu - dU)), then accept iff arg >= 0 or A < exp(arg); NaN rejects.
+__device__ __forceinline__ double accept_log_ratio(const DevBox& B, int type, double dU, int64_t n) {
+    if (type == GCMC_MOVE_DISPLACE) return -(B.beta * dU);
+    if (type == GCMC_MOVE_INSERT) return log(B.V / (B.lambda3 * (double)(n + 1))) + B.beta * (B.mu - dU);
+    return log((B.lambda3 * (double)n) / B.V) - B.beta * (B.mu + dU);
+}
+
+__device__ __forceinline__ bool metropolis(double arg, double dU, double A) {
+    if (dU != dU) return false;
+    if (arg >= 0.0) return true;
+    return A < exp(arg);
+}
+
+// Tail-correction change for inserting (sign = +1) or deleting (sign = -1) a
+// particle of species s given the per-species counts.
+__device__ __forceinline__ double tail_change(const DevBox& B, const int64_t* nsp, int s, int sign) {
+    double acc = 0.0;
+    for (int b = 0; b < B.ns; ++b) acc += (double)nsp[b] * B.tailK[s * B.ns + b];
+    return (double)(2 * sign) * acc + B.tailK[s * B.ns + s];
+}
+
+}  // namespace gcmc
+
+// ------------------------------------------------------------ host side
+struct gcmc_box {
+    gcmc::DevBox d;          // host copy of the descriptor
+    gcmc::DevBox* d_desc;    // device copy (batched kernels)
+    double* scratch;         // reduction partials (library-owned)
+    int64_t scratch_len;     // doubles
+    void* ap_chain;          // all-pairs chain bookkeeping (device)
+    int device;
+    int waves, rows;         // launch shape of the move kernels
+};
+
+struct gcmc_batch {
+    gcmc_box** boxes;        // host array, in the caller's order
+    int32_t n;
+    gcmc::DevBox* d_descs;   // device array, launch order (decreasing N)
+    int32_t* d_order;        // launch slot -> caller index (device)
+    int32_t* h_order;        // the same on the host
+};
+
+namespace gcmc {
+int set_error(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+// moves.hip
+int launch_chain(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int rows, int64_t n_moves,
+                 uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
+bool chain_cfg_exists(int waves, int rows);
+int launch_delta(const DevBox* d_box, bool mix, int64_t n_moves, const gcmc_move* moves, double* dp, double* dt,
+                 hipStream_t s);
+void launch_commit(const DevBox* d_box, const gcmc_move* move, const double* dU, hipStream_t s);
+void launch_neighbors(const DevBox* d_box, const double* pts, const int32_t* excl, int64_t n, int32_t max_ids,
+                      int32_t* ids, int32_t* counts, hipStream_t s);
+
+// energy.hip
+int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_pairs, double* e_out,
+                 double* partial, int64_t partial_len, double* U, hipStream_t s, int64_t n);
+int64_t total_partials_needed(const DevBox& hb, int32_t maxc, bool all_pairs, int64_t n);
+int64_t grad_partials_needed(const DevBox& hb, int32_t maxc);
+int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* grad, double* partial, double* deps,
+                double* dsig, hipStream_t s);
+int64_t ap_chunk_len();
+int launch_delta_allpairs(const DevBox* d_box, int64_t n, const gcmc_move* moves, int64_t n_moves, double* scratch,
+                          double* dp, double* dt, hipStream_t s);
+size_t ap_chain_state_bytes();
+void launch_ap_chain_begin(void* ch, uint64_t ctr0, hipStream_t s);
+void launch_ap_chain_move(const DevBox* d_box, void* ch, int64_t nch, double* scratch, gcmc_log* log,
+                          hipStream_t s);
+void launch_ap_chain_end(const DevBox* d_box, const void* ch, gcmc_stats* stats, hipStream_t s);
+
+// box.hip
+int read_box_state(gcmc_box* box, BoxState* h, hipStream_t s);
+int ensure_scratch(gcmc_box* box, int64_t len);
+}  // namespace gcmc
+
+#define GCMC_HIP(call)                                                       \
+    do {                                                                     \
+        hipError_t _e = (call);                                              \
+        if (_e != hipSuccess) return gcmc::check_hip(_e, #call);             \
+    } while (0)

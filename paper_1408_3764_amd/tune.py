@@ -1,0 +1,94 @@
+"""Launch-shape and cell-size selection for the move kernels.
+
+The move kernel's shape is (waves per workgroup, candidate slots per lane per
+pass).  A move's candidate slots are (stencil cells) x G, G = the power of two
+at or above the fullest cell, doubled when a displacement leaves its cell; one
+pass of W waves x R rows covers 64 W R slots, so the heuristic picks the
+smallest workgroup that covers a cross-cell displacement in one pass (one
+memory round trip), and :func:`autotune_chain` measures the candidates on a
+copy of the box and caches the winner per workload shape.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+SHAPES = [(1, 8), (2, 8), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4), (16, 2)]
+CACHE_ENV = "GCMC_TUNE_CACHE"
+
+
+def _slots(box):
+    info = box.info()
+    cell_of, count, _ = box.cells()
+    maxc = int(count.max()) if len(count) else 1
+    g = 1
+    while g < maxc:
+        g *= 2
+    nst = info["span"][0] * info["span"][1] * info["span"][2]
+    return nst * g
+
+
+def chain_shape(box):
+    """Smallest shape whose one pass covers the two stencils of a cross-cell displacement."""
+    need = 2 * _slots(box)
+    best = None
+    for w, r in SHAPES:
+        cover = 64 * w * r
+        if cover >= need:
+            key = (w * r, w)          # fewest slots per pass, then fewest waves
+            if best is None or key < best[0]:
+                best = (key, (w, r))
+    return best[1] if best else (16, 2)
+
+
+def batch_shape(boxes):
+    """Batched boxes: one workgroup per box, a single wave when the stencil fits it."""
+    need = max(_slots(b) for b in boxes[:8])
+    for w, r in ((1, 8), (2, 8), (4, 4), (4, 8), (8, 4)):
+        if 64 * w * r >= need:
+            return (w, r)
+    return (8, 4)
+
+
+def _cache_path():
+    return os.environ.get(CACHE_ENV, "")
+
+
+def autotune_chain(make_box, n_moves=2000, shapes=SHAPES, key=None):
+    """Time each launch shape on a fresh box from make_box() and return the fastest.
+    Every shape runs the same chain (counter-based draws), so the comparison is
+    between identical work.  The result is cached in $GCMC_TUNE_CACHE (JSON) under key."""
+    import torch
+    path = _cache_path()
+    if key and path and os.path.exists(path):
+        try:
+            c = json.load(open(path))
+            if key in c:
+                return tuple(c[key])
+        except (OSError, ValueError):
+            pass
+    best = None
+    timings = {}
+    for w, r in shapes:
+        b = make_box()
+        b.set_launch(w, r)
+        b.step(200, counter0=0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        b.step(n_moves, counter0=200)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        timings["%dx%d" % (w, r)] = dt
+        if best is None or dt < best[0]:
+            best = (dt, (w, r))
+        b.close()
+    if key and path:
+        try:
+            c = json.load(open(path)) if os.path.exists(path) else {}
+        except (OSError, ValueError):
+            c = {}
+        c[key] = list(best[1])
+        with open(path, "w") as f:
+            json.dump(c, f)
+    return best[1], timings

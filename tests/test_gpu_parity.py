@@ -1,0 +1,443 @@
+"""Parity of the gfx950 library (through its C ABI) with the CPU oracle.
+
+Bit-exact: cell assignment, cell membership, neighbour sets, chain decisions
+(move types, indices, trial positions, accept/reject away from ties), final
+configurations.  Within tolerance: energy deltas (1e-10 of the magnitude sum),
+total energies, gradients (1e-7).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1408_3764_amd import workloads
+from tests.helpers import assert_du, compare_chain_logs, DU_REL
+
+pytestmark = pytest.mark.gpu
+
+
+def _box(wb, **kw):
+    from paper_1408_3764_amd.box import Box
+    return Box.from_workload(wb, **kw)
+
+
+def _params(wb, **over):
+    kw = dict(eps=wb.eps, sigma=wb.sigma, beta=wb.beta, mu=wb.mu, lambda3=wb.lambda3, max_disp=wb.max_disp,
+              p_disp=wb.p_disp)
+    kw.update(over)
+    return oracle.make_params(wb.L, wb.rc, **kw)
+
+
+SMALL_CASES = {
+    "L10_M4": dict(n=300, L=10.0, seed=1),
+    "L7.4_M3_whole_box": dict(n=120, L=7.4, seed=2),
+    "aniso": dict(n=250, L=[7.6, 10.0, 12.7], seed=3),
+    "L12.7": dict(n=500, L=12.7, seed=4),
+}
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return workloads.small()
+
+
+def _random_moves(wb, rng, m, n):
+    from paper_1408_3764_amd.box import make_moves
+    types = rng.integers(0, 3, m)
+    idx = rng.integers(0, n, m)
+    pos = rng.random((m, 3)) * wb.L
+    disp = wb.pos[idx] + rng.uniform(-0.3, 0.3, (m, 3))
+    disp = np.mod(disp, wb.L)
+    disp = np.where(disp >= wb.L, 0.0, disp)
+    # a third of the displacements are large jumps (cross-cell)
+    far = rng.random(m) < 0.3
+    disp[far] = pos[far]
+    p = np.where((types == 0)[:, None], disp, pos)
+    return make_moves(types, idx, p)
+
+
+def _oracle_deltas(wb, p, moves):
+    dp, dt, sa = [], [], []
+    n = wb.n
+    counts = [n] if wb.species is None else np.bincount(wb.species, minlength=wb.eps.shape[0])
+    for mv in moves:
+        t, i = int(mv["type"]), int(mv["index"])
+        pt = (mv["x"], mv["y"], mv["z"])
+        sp = None if wb.species is None else wb.species
+        if t == 0:
+            s_i = 0 if sp is None else int(sp[i])
+            eo = oracle.position_energy(wb.pos, p, wb.pos[i], exclude=i, species=sp, point_species=s_i)
+            en = oracle.position_energy(wb.pos, p, pt, exclude=i, species=sp, point_species=s_i)
+            dp.append(en[0] - eo[0]); sa.append(en[1] + eo[1]); dt.append(0.0)
+        elif t == 1:
+            s_i = int(mv["species"])
+            en = oracle.position_energy(wb.pos, p, pt, exclude=-1, species=sp, point_species=s_i)
+            dp.append(en[0]); sa.append(en[1]); dt.append(oracle.tail_delta(counts, s_i, +1, p))
+        else:
+            s_i = 0 if sp is None else int(sp[i])
+            eo = oracle.position_energy(wb.pos, p, wb.pos[i], exclude=i, species=sp, point_species=s_i)
+            dp.append(-eo[0]); sa.append(eo[1]); dt.append(oracle.tail_delta(counts, s_i, -1, p))
+    return np.array(dp), np.array(dt), np.array(sa)
+
+
+# ------------------------------------------------------------------ cells
+@pytest.mark.parametrize("case", list(SMALL_CASES))
+def test_cell_assignment_bitexact(case):
+    c = SMALL_CASES[case]
+    wb = workloads.random_box(c["n"], c["L"], seed=c["seed"])
+    b = _box(wb)
+    cell_of, count, ids = b.cells()
+    ref = oracle.cell_of(wb.pos, wb.L, wb.rc)
+    assert np.array_equal(cell_of.astype(np.int64), ref)
+    assert np.array_equal(count, np.bincount(ref, minlength=len(count)))
+    for cidx in np.nonzero(count)[0]:
+        assert sorted(ids[cidx, : count[cidx]].tolist()) == sorted(np.nonzero(ref == cidx)[0].tolist())
+    g = oracle.grid(wb.L, wb.rc)
+    assert b.info()["cell_m"] == list(g["M"]) and b.info()["span"] == list(g["span"])
+
+
+def test_cell_assignment_c1_exact_grid(c1):
+    b = _box(c1)
+    assert b.info()["cell_m"] == [8, 8, 8]
+    cell_of, count, _ = b.cells()
+    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(c1.pos, c1.L, c1.rc))
+
+
+@pytest.mark.parametrize("case", list(SMALL_CASES))
+def test_neighbor_sets_bitexact(case):
+    c = SMALL_CASES[case]
+    wb = workloads.random_box(c["n"], c["L"], seed=c["seed"])
+    b = _box(wb)
+    rng = np.random.default_rng(c["seed"])
+    g = oracle.grid(wb.L, wb.rc)
+    pts = [wb.pos[i] for i in range(0, wb.n, 7)]
+    excl = list(range(0, wb.n, 7))
+    for _ in range(20):   # random points and points within an ulp of cell faces
+        q = rng.random(3) * wb.L
+        a = rng.integers(0, 3)
+        face = rng.integers(0, g["M"][a]) * (wb.L[a] / g["M"][a])
+        q[a] = min(max(face + rng.choice([-1e-12, 0.0, 1e-12]), 0.0), np.nextafter(wb.L[a], 0))
+        pts.append(q)
+        excl.append(-1)
+    got, cnt = b.neighbor_ids(np.array(pts), np.array(excl))
+    for k, (q, ex) in enumerate(zip(pts, excl)):
+        ref = oracle.neighbor_ids(wb.pos, q, wb.L, wb.rc, exclude=ex)
+        assert cnt[k] == len(ref)
+        assert np.array_equal(got[k], np.sort(ref)), (k, q)
+
+
+def test_neighbor_sets_small_cells():
+    """Cells smaller than rc (k = 2, 5x5x5 stencil) give the oracle's sets too."""
+    wb = workloads.random_box(400, 11.0, seed=9)
+    req = np.array([8, 8, 8], dtype=np.int32)
+    b = _box(wb, cell_m=req)
+    assert b.info()["span"] == [5, 5, 5]
+    got, cnt = b.neighbor_ids(wb.pos[:50], np.arange(50))
+    for i in range(50):
+        ref = oracle.neighbor_ids(wb.pos, wb.pos[i], wb.L, wb.rc, exclude=i, req_m=req)
+        assert np.array_equal(got[i], np.sort(ref))
+
+
+# ----------------------------------------------------------- energy deltas
+@pytest.mark.parametrize("case", list(SMALL_CASES))
+@pytest.mark.parametrize("all_pairs", [False, True])
+def test_delta_energy_parity(case, all_pairs):
+    c = SMALL_CASES[case]
+    wb = workloads.random_box(c["n"], c["L"], seed=c["seed"])
+    p = _params(wb)
+    b = _box(wb, max_n=wb.n + 10)
+    rng = np.random.default_rng(100 + c["seed"])
+    moves = _random_moves(wb, rng, 300, wb.n)
+    gp, gt = b.delta_energy(moves, all_pairs=all_pairs)
+    rp, rt, sa = _oracle_deltas(wb, p, moves)
+    assert_du(gp, rp, sa, "dU_pair %s" % case)
+    assert np.allclose(gt, rt, rtol=1e-12, atol=1e-15)
+
+
+def test_delta_energy_c1_and_small_cells(c1):
+    p = _params(c1)
+    rng = np.random.default_rng(7)
+    moves = _random_moves(c1, rng, 400, c1.n)
+    rp, rt, sa = _oracle_deltas(c1, p, moves)
+    for cm in (None, [16, 16, 16]):
+        b = _box(c1, max_n=c1.n + 10, cell_m=cm)
+        gp, gt = b.delta_energy(moves)
+        assert_du(gp, rp, sa, "C1 cell_m=%s" % cm)
+        assert np.allclose(gt, rt, rtol=1e-12)
+
+
+@pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (8, 4), (16, 2)])
+def test_chain_launch_shapes_agree(c1, waves, rows):
+    """Every launch shape gives the oracle's chain (the tuner may pick any)."""
+    p = _params(c1)
+    _, _, olog = oracle.chain(c1.pos, 300, p, seed=c1.seed, max_n=c1.n + 400,
+                              U0=0.0)
+    b = _box(c1, max_n=c1.n + 400)
+    b.set_launch(waves, rows)
+    _, glog = b.step(300, counter0=0, log=True)
+    assert compare_chain_logs(glog, olog, c1.beta) == 300
+
+
+def test_delta_energy_mixture():
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    wb = workloads.random_box(500, 13.0, rc=3.0, seed=5, species_counts=[250, 250], eps=eps, sigma=sig)
+    p = _params(wb)
+    b = _box(wb, max_n=wb.n + 10)
+    rng = np.random.default_rng(3)
+    moves = _random_moves(wb, rng, 300, wb.n)
+    moves["species"] = rng.integers(0, 2, len(moves))
+    gp, gt = b.delta_energy(moves)
+    rp, rt, sa = _oracle_deltas(wb, p, moves)
+    assert_du(gp, rp, sa, "mixture")
+    assert np.allclose(gt, rt, rtol=1e-12)
+
+
+def test_delta_energy_edge_cases():
+    """Overlap (r = 0) gives +inf, out-of-range indices give NaN, an empty box gives 0."""
+    from paper_1408_3764_amd.box import Box, make_moves
+    wb = workloads.random_box(50, 8.0, seed=3)
+    b = _box(wb, max_n=60)
+    mv = make_moves([1, 0, 2, 2, 1], [0, 3, -1, 50, 0], [wb.pos[5], wb.pos[3], wb.pos[0], wb.pos[0], [0.0, 0.0, 0.0]])
+    gp, gt = b.delta_energy(mv)
+    assert gp[0] == math.inf
+    assert gp[1] == 0.0 or abs(gp[1]) < 1e-12          # displacement onto itself
+    assert math.isnan(gp[2]) and math.isnan(gp[3])
+    e = Box(np.zeros((0, 3)), [8.0] * 3, 2.5, max_n=10)
+    gp, gt = e.delta_energy(make_moves([1], [0], [[1.0, 2.0, 3.0]]))
+    assert gp[0] == 0.0 and gt[0] == pytest.approx(oracle.tail_delta([0], 0, +1, oracle.make_params([8.0] * 3, 2.5)))
+
+
+# ----------------------------------------------------------- total energy
+@pytest.mark.parametrize("case", list(SMALL_CASES))
+def test_total_energy_parity(case):
+    c = SMALL_CASES[case]
+    wb = workloads.random_box(c["n"], c["L"], seed=c["seed"])
+    p = _params(wb)
+    ref = oracle.total_energy(wb.pos, p, per_particle=True)
+    b = _box(wb)
+    for ap in (False, True):
+        got = b.total_energy(all_pairs=ap, per_particle=True)
+        assert abs(got["U_pair"] - ref["U_pair"]) <= 1e-10 * ref["sumabs"]
+        assert got["U_tail"] == pytest.approx(ref["U_tail"], rel=1e-13)
+        assert np.allclose(got["e"], ref["e"], rtol=0, atol=1e-10 * max(1.0, np.abs(ref["e"]).max()))
+
+
+def test_total_energy_c1(c1):
+    p = _params(c1)
+    ref = oracle.total_energy(c1.pos, p)
+    b = _box(c1)
+    for ap in (False, True):
+        got = b.total_energy(all_pairs=ap)
+        assert abs(got["U_pair"] - ref["U_pair"]) <= 1e-10 * ref["sumabs"]
+
+
+# ------------------------------------------------------------------ chain
+def test_chain_parity_c1(c1):
+    """1,000 moves of the small configuration: the GPU chain is the oracle's chain."""
+    p = _params(c1)
+    t0 = oracle.total_energy(c1.pos, p)
+    opos, oU, olog = oracle.chain(c1.pos, c1.n_moves, p, seed=c1.seed, max_n=c1.n + 1001,
+                                  U0=t0["U_pair"] + t0["U_tail"])
+    b = _box(c1, max_n=c1.n + 1001)
+    b.total_energy()
+    stats, glog = b.step(c1.n_moves, counter0=0, log=True)
+    k = compare_chain_logs(glog, olog, c1.beta, "C1")
+    assert k == c1.n_moves
+    assert int(stats["error"]) == 0 and int(stats["moves_done"]) == c1.n_moves
+    gpos, _ = b.particles()
+    assert np.array_equal(gpos, opos)
+    acc = [(olog["accepted"][olog["type"] == t] == 1).sum() for t in range(3)]
+    assert list(stats["accepts"]) == acc
+    assert stats["u_pair"] + stats["u_tail"] == pytest.approx(oU, rel=1e-9)
+    # the running energy is the recomputed one
+    U = b.total_energy()
+    assert U["U_pair"] == pytest.approx(stats["u_pair"], rel=1e-9)
+    assert acc[0] > 0 and acc[1] > 0 and acc[2] > 0
+
+
+def test_chain_resume_split_equals_whole(c1):
+    """Counter-based draws: two calls of 400 + 600 moves = one call of 1,000."""
+    a = _box(c1, max_n=c1.n + 1001)
+    a.step(1000, counter0=0)
+    b = _box(c1, max_n=c1.n + 1001)
+    b.step(400, counter0=0)
+    b.step(600, counter0=400)
+    pa, _ = a.particles()
+    pb, _ = b.particles()
+    assert np.array_equal(pa, pb)
+
+
+def test_chain_deterministic(c1):
+    a = _box(c1, max_n=c1.n + 1001)
+    b = _box(c1, max_n=c1.n + 1001)
+    sa, la = a.step(1000, log=True)
+    sb, lb = b.step(1000, log=True)
+    assert la.tobytes() == lb.tobytes()
+    assert np.array_equal(a.particles()[0], b.particles()[0])
+
+
+def test_allpairs_chain_parity(c1):
+    p = _params(c1)
+    _, _, olog = oracle.chain(c1.pos, 300, p, seed=c1.seed, max_n=c1.n + 301)
+    b = _box(c1, max_n=c1.n + 301)
+    stats, glog = b.step(300, counter0=0, log=True, all_pairs=True)
+    assert compare_chain_logs(glog, olog, c1.beta, "all-pairs chain") == 300
+    assert int(stats["moves_done"]) == 300
+    # the cell list was kept up to date by the all-pairs commits
+    cell_of, _, _ = b.cells()
+    pos, _ = b.particles()
+    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(pos, c1.L, c1.rc))
+
+
+def test_host_driven_commit_matches_chain():
+    """gcmc_delta_energy + gcmc_commit, driven from the host with the oracle's decisions."""
+    wb = workloads.random_box(200, 9.0, seed=12, T=1.2)
+    p = _params(wb, beta=1 / 1.2, mu=-3.0)
+    opos, _, olog = oracle.chain(wb.pos, 400, p, seed=44, max_n=700)
+    from paper_1408_3764_amd.box import make_moves
+    b = _box(wb, max_n=700)
+    cur = wb.pos.copy()
+    for rec in olog:
+        if not rec["accepted"]:
+            continue
+        t = int(rec["type"])
+        mv = make_moves([t], [rec["index"]], [[rec["x"], rec["y"], rec["z"]]])
+        gp, _ = b.delta_energy(mv)
+        assert abs(gp[0] - rec["dU_pair"]) <= DU_REL * max(abs(rec["dU_pair"]), rec["sumabs"])
+        b.commit(mv[0], gp[0])
+    gpos, _ = b.particles()
+    assert np.array_equal(gpos, opos)
+    cell_of, _, _ = b.cells()
+    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(opos, wb.L, wb.rc))
+
+
+def test_ideal_gas_on_gpu():
+    """eps = 0: N is Poisson with mean V exp(beta mu)."""
+    from paper_1408_3764_amd.box import Box
+    L, beta, mu = 6.0, 1.0 / 1.3, -0.4
+    mean = L ** 3 * math.exp(beta * mu)
+    # an empty box sizes its cells for nothing: give the cells room for ~160 particles
+    b = Box(np.zeros((0, 3)), [L] * 3, 2.5, beta=beta, mu=mu, eps=0.0, max_n=2000, seed=77, cell_cap=64)
+    st, _ = b.step(50_000, counter0=0)
+    assert int(st["error"]) == 0
+    ns = []
+    for k in range(40):
+        st, _ = b.step(10_000, counter0=50_000 + k * 10_000)
+        assert int(st["error"]) == 0
+        ns.append(st["sum_n"] / 10_000)
+    ns = np.array(ns)
+    se = ns.std(ddof=1) / math.sqrt(len(ns))
+    assert abs(ns.mean() - mean) < 5 * se + 0.01 * mean, (ns.mean(), mean)
+
+
+# -------------------------------------------------------- error handling
+def test_overflow_latches_and_resumes(c1):
+    """A cell over capacity stops the chain before the move; rebuilding with a
+    larger capacity and resuming at the stop gives the uninterrupted chain."""
+    import dataclasses
+    M = 20_000
+    wb = dataclasses.replace(c1, mu=3.0)                 # insertions favoured: cells grow
+    ref = _box(wb, max_n=c1.n + M + 1, cell_cap=64)
+    ref.step(M, counter0=0)
+    assert ref.status() == 0
+    cnt = ref.cells()[1]
+    b = _box(wb, max_n=c1.n + M + 1)
+    maxc = int(b.cells()[1].max())
+    b2 = _box(wb, max_n=c1.n + M + 1, cell_cap=maxc)   # no headroom: the first growth overflows
+    st, _ = b2.step(M, counter0=0)
+    assert int(st["error"]) == 3
+    stop = int(st["error_move"])
+    assert 0 <= stop < M and int(st["moves_done"]) == stop
+    assert b2.status() == 3
+    b2.cell_build(new_cap=64)
+    assert b2.status() == 0
+    st2, _ = b2.step(M - stop, counter0=stop)
+    assert int(st2["error"]) == 0
+    assert np.array_equal(b2.particles()[0], ref.particles()[0])
+
+
+def test_capacity_error():
+    from paper_1408_3764_amd.box import Box
+    b = Box(np.zeros((0, 3)), [8.0] * 3, 2.5, mu=5.0, max_n=5, seed=1)
+    st, _ = b.step(500)
+    assert int(st["error"]) == 4 and int(st["n"]) == 5
+
+
+def test_invalid_arguments():
+    from paper_1408_3764_amd import _lib
+    from paper_1408_3764_amd.box import Box
+    with pytest.raises(_lib.GcmcError) as e:
+        Box(np.zeros((0, 3)), [4.0] * 3, 2.5)                 # rc > L/2
+    assert e.value.code == 1
+    with pytest.raises(_lib.GcmcError):
+        Box(np.array([[1.0, 2.0, 9.0]]), [8.0] * 3, 2.5)      # outside [0, L)
+    with pytest.raises(_lib.GcmcError):
+        Box(np.zeros((3, 3)), [8.0] * 3, 2.5, max_n=2)          # n > max_n
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    m = Box(np.array([[1.0, 1.0, 1.0]]), [8.0] * 3, 2.5, eps=eps, sigma=sig, species=[1], max_n=4)
+    with pytest.raises(_lib.GcmcError) as e:
+        m.step(10)                                              # the chain is single-species
+    assert e.value.code == 7
+
+
+def test_checkpoint_roundtrip(c1):
+    a = _box(c1, max_n=c1.n + 2001)
+    a.total_energy()
+    a.step(700, counter0=0)
+    pos, _ = a.particles()
+    n, u, err = a.export_state()
+    b = _box(c1, max_n=c1.n + 2001)
+    b.import_state(pos, u)
+    a.step(500, counter0=700)
+    b.step(500, counter0=700)
+    assert np.array_equal(a.particles()[0], b.particles()[0])
+    assert a.export_state()[1] == pytest.approx(b.export_state()[1], rel=1e-11)
+
+
+# --------------------------------------------------------------- gradients
+def test_backward_parity_mixture():
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    wb = workloads.random_box(400, 12.0, rc=3.0, seed=8, species_counts=[200, 200], eps=eps, sigma=sig)
+    p = _params(wb)
+    g_ref, de_ref, ds_ref = oracle.gradients(wb.pos, p, species=wb.species)
+    b = _box(wb)
+    got = b.backward()
+    scale = np.abs(g_ref).max()
+    assert np.allclose(got["grad"], g_ref, rtol=1e-7, atol=1e-7 * scale)
+    assert np.allclose(got["d_eps"], de_ref, rtol=1e-7)
+    assert np.allclose(got["d_sigma"], ds_ref, rtol=1e-7)
+
+
+def test_backward_single_species(c1):
+    p = _params(c1)
+    b = _box(c1)
+    got = b.backward()
+    rng = np.random.default_rng(2)
+    for i in rng.choice(c1.n, 40, replace=False):
+        ref = oracle.particle_gradient(c1.pos, i, p)
+        assert np.allclose(got["grad"][i], ref, rtol=1e-7, atol=1e-9 * max(1.0, np.abs(ref).max()))
+    assert np.abs(got["grad"].sum(axis=0)).max() <= 1e-9 * np.abs(got["grad"]).sum()
+    # U is linear in eps
+    U = b.total_energy()
+    assert got["d_eps"][0, 0] == pytest.approx(U["U_pair"] + U["U_tail"], rel=1e-10)
+
+
+# ------------------------------------------------------------------ batch
+def test_batch_matches_single_boxes():
+    from paper_1408_3764_amd.box import Batch, Box
+    sizes = [130, 400, 900, 260, 1500]
+    wbs = [workloads.cubic_box(n, rho, T, 2.5, 500 + k) for k, (n, rho, T) in
+           enumerate(zip(sizes, [0.3, 0.5, 0.8, 0.6, 0.4], [0.9, 1.2, 1.5, 1.0, 1.1]))]
+    boxes = [Box.from_workload(w, max_n=w.n + 301, box_id=k, seed=99) for k, w in enumerate(wbs)]
+    bt = Batch(boxes)
+    stats = bt.step(300, counter0=0)
+    for k, w in enumerate(wbs):
+        p = _params(w)
+        opos, _, olog = oracle.chain(w.pos, 300, p, seed=99, box=k, max_n=w.n + 301)
+        assert int(stats[k]["n"]) == len(opos)
+        gpos, _ = boxes[k].particles()
+        assert np.array_equal(gpos, opos), k
+        assert list(stats[k]["accepts"]) == [int(((olog["type"] == t) & (olog["accepted"] == 1)).sum())
+                                             for t in range(3)]
