@@ -52,6 +52,7 @@ enum {
 enum { GCMC_MOVE_DISPLACE = 0, GCMC_MOVE_INSERT = 1, GCMC_MOVE_DELETE = 2 };
 
 #define GCMC_MAX_SPECIES 4
+#define GCMC_COUNTER_CONTINUE 0xFFFFFFFFFFFFFFFFull
 
 typedef struct gcmc_box gcmc_box;
 typedef struct gcmc_batch gcmc_batch;
@@ -165,6 +166,11 @@ int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream);
  * re-bin; used by the autograd wrapper between forward passes. */
 int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z, void* stream);
 
+/* Replace the force field: h_eps, h_sigma are HOST n_species^2 pair tables
+ * (symmetric, eps >= 0, sigma > 0), as in gcmc_box_desc.  Blocks until work
+ * already queued on the box is done. */
+int gcmc_set_params(gcmc_box* box, const double* h_eps, const double* h_sigma);
+
 /* ------------------------------------------------------------ the moves */
 
 /* Energy change of n_moves independent trial moves against the current
@@ -193,7 +199,7 @@ int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair,
 
 /* Launch shape of the move kernels: `waves` wavefronts per workgroup and
  * `rows` candidate slots per lane per pass (the autotuner's choice; the
- * supported pairs are 1x8, 2x8, 4x2, 4x4, 4x8, 8x2, 8x4, 16x2). */
+ * supported pairs are 1x8, 2x8, 4x2, 4x4, 4x8, 8x2, 8x4). */
 int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows);
 
 /* Run n_moves moves of the Markov chain of Algorithm 1 on the device in one
@@ -202,8 +208,11 @@ int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows);
  * (counter0 + m low, high, box_id, j), j = 0..3, giving eight uniforms
  * (R, Source, particle pick, A, three position draws, spare); R < p_disp is a
  * displacement, else Source < 0.5 a deletion, else an insertion.  Single
- * species only.  d_stats (may be NULL) receives the chain statistics and d_log
- * (may be NULL) one record per move. */
+ * species only.  counter0 = GCMC_COUNTER_CONTINUE starts at the box's device
+ * counter (the move after the last one run), so a captured HIP graph of
+ * gcmc_step calls continues the chain each time it is replayed.  d_stats (may
+ * be NULL) receives the chain statistics and d_log (may be NULL) one record per
+ * move. */
 int gcmc_step(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_stats, gcmc_log* d_log,
               void* stream);
 
@@ -236,8 +245,11 @@ int gcmc_backward(gcmc_box* box, double* d_grad, double* d_deps, double* d_dsig,
 int gcmc_batch_create(gcmc_box* const* boxes, int32_t n_boxes, gcmc_batch** out);
 int gcmc_batch_destroy(gcmc_batch* batch);
 /* Advance every box of the batch by moves_per_box moves (counter0 + m, the
- * box's own box_id and seed).  d_stats[n_boxes] (may be NULL), in the order
- * the boxes were given. */
+ * box's own box_id and seed; GCMC_COUNTER_CONTINUE: each box's device
+ * counter).  d_stats[n_boxes] (may be NULL), in the order the boxes were
+ * given.  Enqueues one kernel and no host synchronisation, so it can be
+ * captured in a HIP graph (unless a box was rebuilt since the last call, which
+ * re-uploads the descriptors). */
 int gcmc_batch_step(gcmc_batch* batch, int64_t moves_per_box, uint64_t counter0, gcmc_stats* d_stats,
                     void* stream);
 

@@ -24,11 +24,13 @@ ERRORS = {
 GCMC_ERR_INVALID_ARG, GCMC_ERR_OOM, GCMC_ERR_CELL_OVERFLOW, GCMC_ERR_CAPACITY = 1, 2, 3, 4
 GCMC_ERR_HIP, GCMC_ERR_POISONED, GCMC_ERR_UNSUPPORTED = 5, 6, 7
 DISPLACE, INSERT, DELETE = 0, 1, 2
+COUNTER_CONTINUE = 0xFFFFFFFFFFFFFFFF
 MAX_SPECIES = 4
 
 # every symbol include/gcmc.h declares
 EXPORTS = [
     "gcmc_box_create", "gcmc_box_destroy", "gcmc_box_get_info", "gcmc_cell_build", "gcmc_set_positions",
+    "gcmc_set_params",
     "gcmc_delta_energy", "gcmc_delta_energy_allpairs", "gcmc_commit", "gcmc_box_set_launch", "gcmc_step",
     "gcmc_step_allpairs", "gcmc_total_energy", "gcmc_backward", "gcmc_batch_create", "gcmc_batch_destroy",
     "gcmc_batch_step", "gcmc_get_particles", "gcmc_get_cells", "gcmc_neighbor_ids", "gcmc_export_state",
@@ -92,6 +94,7 @@ def lib():
         "gcmc_box_get_info": [vp, C.POINTER(BoxInfo)],
         "gcmc_cell_build": [vp, i32, vp],
         "gcmc_set_positions": [vp, dp, dp, dp, vp],
+        "gcmc_set_params": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "gcmc_delta_energy": [vp, dp, i64, dp, dp, vp],
         "gcmc_delta_energy_allpairs": [vp, dp, i64, dp, dp, vp],
         "gcmc_commit": [vp, dp, dp, vp],
@@ -165,6 +168,13 @@ def gcmc_cell_build(box, new_cap=0, stream=None):
 
 def gcmc_set_positions(box, x, y, z, stream=None):
     check(lib().gcmc_set_positions(box, ptr(x), ptr(y), ptr(z), stream_handle(stream)))
+
+
+def gcmc_set_params(box, eps, sigma):
+    e = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1)
+    s = np.ascontiguousarray(sigma, dtype=np.float64).reshape(-1)
+    check(lib().gcmc_set_params(box, e.ctypes.data_as(C.POINTER(C.c_double)),
+                                s.ctypes.data_as(C.POINTER(C.c_double))))
 
 
 def gcmc_delta_energy(box, moves, n, dU_pair, dU_tail, stream=None):

@@ -200,6 +200,28 @@ class Box:
         z = _dev(pos[:, 2], torch.float64, self.device)
         _lib.gcmc_set_positions(self.handle, x, y, z, self.stream)
 
+    def set_params(self, eps, sigma):
+        _lib.gcmc_set_params(self.handle, np.asarray(eps, dtype=np.float64), np.asarray(sigma, dtype=np.float64))
+
+    def set_positions_device(self, pos: torch.Tensor):
+        """pos: (N, 3) float64 device tensor with the current N."""
+        x, y, z = (pos[:, a].contiguous() for a in range(3))
+        _lib.gcmc_set_positions(self.handle, x, y, z, self.stream)
+
+    def total_energy_device(self, all_pairs=False):
+        """(U_pair, U_tail) as a device tensor, no host synchronisation."""
+        U = torch.empty(2, dtype=torch.float64, device=self.device)
+        _lib.gcmc_total_energy(self.handle, 1 if all_pairs else 0, U, None, self.stream)
+        return U
+
+    def backward_device(self, n):
+        """(dU/dpos (n,3), dU/deps (ns,ns), dU/dsigma (ns,ns)) as device tensors."""
+        g = torch.empty(3 * max(n, 1), dtype=torch.float64, device=self.device)
+        de = torch.empty(self.ns * self.ns, dtype=torch.float64, device=self.device)
+        ds = torch.empty_like(de)
+        _lib.gcmc_backward(self.handle, g, de, ds, self.stream)
+        return g[: 3 * n].view(3, n).t(), de.view(self.ns, self.ns), ds.view(self.ns, self.ns)
+
     def cell_build(self, new_cap=0):
         _lib.gcmc_cell_build(self.handle, new_cap, self.stream)
 

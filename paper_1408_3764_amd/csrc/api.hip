@@ -168,6 +168,9 @@ int gcmc_batch_create(gcmc_box* const* boxes, int32_t n_boxes, gcmc_batch** out)
     }
     bt->h_order = new int32_t[n_boxes];
     for (int32_t b = 0; b < n_boxes; ++b) bt->h_order[b] = order[b];
+    bt->h_descs = new DevBox[n_boxes];
+    for (int32_t q = 0; q < n_boxes; ++q) bt->h_descs[q] = bt->boxes[order[q]]->d;
+    GCMC_HIP(hipMemcpy(bt->d_descs, bt->h_descs, sizeof(DevBox) * n_boxes, hipMemcpyHostToDevice));
     GCMC_HIP(hipMemcpy(bt->d_order, order.data(), sizeof(int32_t) * n_boxes, hipMemcpyHostToDevice));
     *out = bt;
     return GCMC_OK;
@@ -180,6 +183,7 @@ int gcmc_batch_destroy(gcmc_batch* bt) {
     if (bt->d_order) (void)hipFree(bt->d_order);
     delete[] bt->boxes;
     delete[] bt->h_order;
+    delete[] bt->h_descs;
     delete bt;
     return GCMC_OK;
 }
@@ -187,11 +191,15 @@ int gcmc_batch_destroy(gcmc_batch* bt) {
 int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gcmc_stats* d_stats, void* stream) {
     if (!bt || moves_per_box < 0) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
-    // descriptors in launch order (refreshed: a rebuild may have moved a cell array)
-    std::vector<DevBox> h(bt->n);
-    for (int32_t q = 0; q < bt->n; ++q) h[q] = bt->boxes[bt->h_order[q]]->d;
-    GCMC_HIP(hipMemcpyAsync(bt->d_descs, h.data(), sizeof(DevBox) * bt->n, hipMemcpyHostToDevice, s));
-    GCMC_HIP(hipStreamSynchronize(s));
+    // descriptors in launch order: re-uploaded only when a box was rebuilt
+    bool changed = false;
+    for (int32_t q = 0; q < bt->n && !changed; ++q)
+        changed = memcmp(&bt->h_descs[q], &bt->boxes[bt->h_order[q]]->d, sizeof(DevBox)) != 0;
+    if (changed) {
+        for (int32_t q = 0; q < bt->n; ++q) bt->h_descs[q] = bt->boxes[bt->h_order[q]]->d;
+        GCMC_HIP(hipMemcpyAsync(bt->d_descs, bt->h_descs, sizeof(DevBox) * bt->n, hipMemcpyHostToDevice, s));
+        GCMC_HIP(hipStreamSynchronize(s));
+    }
     const gcmc_box* b0 = bt->boxes[0];
     if (launch_chain(bt->d_descs, bt->d_order, bt->n, b0->waves, b0->rows, moves_per_box, counter0, d_stats, nullptr,
                      s))

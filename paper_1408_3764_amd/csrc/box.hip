@@ -106,6 +106,7 @@ __global__ void k_sort_cells(DevBox B) {
     }
 }
 
+// keep_error: a rebuild keeps the latched error, its move and the move counter.
 __global__ void k_reset_state(BoxState* st, int64_t n, double u_pair, int keep_error) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->n = n;
@@ -114,9 +115,9 @@ __global__ void k_reset_state(BoxState* st, int64_t n, double u_pair, int keep_e
         if (!keep_error) {
             st->error = GCMC_OK;
             st->error_move = -1;
+            st->counter = 0;
         }
         for (int s = 0; s < kMaxSpecies; ++s) st->nsp[s] = 0;
-        st->counter = 0;
     }
 }
 
@@ -447,6 +448,37 @@ int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, cons
     if ((rc = read_state(box, &h, s))) return rc;
     if (h.error) return set_error(h.error, "re-binning overflowed a cell; rebuild with a larger cell_cap");
     return GCMC_OK;
+}
+
+int gcmc_set_params(gcmc_box* box, const double* h_eps, const double* h_sigma) {
+    if (!box || !h_eps || !h_sigma) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    const int ns = box->d.ns;
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            if (h_eps[a * ns + b] != h_eps[b * ns + a] || h_sigma[a * ns + b] != h_sigma[b * ns + a])
+                return set_error(GCMC_ERR_INVALID_ARG, "eps/sigma tables must be symmetric");
+            if (!(h_sigma[a * ns + b] > 0.0) || !(h_eps[a * ns + b] >= 0.0))
+                return set_error(GCMC_ERR_INVALID_ARG, "need sigma > 0 and eps >= 0");
+        }
+    gcmc_box_desc d;
+    memset(&d, 0, sizeof d);
+    for (int a = 0; a < 3; ++a) d.L[a] = box->d.L[a];
+    d.rc = sqrt(box->d.rc2);
+    d.beta = box->d.beta;
+    d.mu = box->d.mu;
+    d.lambda3 = box->d.lambda3;
+    d.max_disp = box->d.max_disp;
+    d.p_disp = box->d.p_disp;
+    d.n_species = ns;
+    d.eps = h_eps;
+    d.sigma = h_sigma;
+    d.seed = box->d.seed;
+    d.box_id = box->d.box_id;
+    d.max_n = box->d.max_n;
+    GCMC_HIP(hipDeviceSynchronize());
+    setup_params(box->d, &d);
+    box->d.rc2 = d.rc * d.rc;
+    return sync_desc(box);
 }
 
 int gcmc_get_particles(gcmc_box* box, double* d_x, double* d_y, double* d_z, int32_t* d_species, int64_t* h_n,

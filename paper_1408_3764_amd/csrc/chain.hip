@@ -1,0 +1,421 @@
+// The persistent Markov-chain kernel: one workgroup advances one box through
+// many moves of Algorithm 1 in a single launch (the paper's multi-move kernel,
+// Sec. 3.3.4), with device-side Philox draws and Metropolis tests.
+//
+// A move is a dependent sequence of memory round trips, so the kernel is built
+// to expose as few of them as possible per move:
+//  * the stencil gather of the move (cell counters and 32-byte cell entries of
+//    every stencil slot) is one round trip for all lanes;
+//  * while it is in flight the next move's Philox draws are computed and the
+//    record of the particle it will pick is loaded (assuming N unchanged);
+//  * the counters of the centre cells and the last entry of the old cell come
+//    back with the gather, so the commit (Sec. 3.2.5: swap-with-last removal,
+//    append) is stores only;
+//  * after a commit, a prefetched record the commit touched, or a pick that a
+//    changed N moved, is loaded again.
+// The chain is exactly the sequential one: every prefetch is validated before
+// use.
+#include "trial.h"
+
+namespace gcmc {
+
+// The part of a move known before its gather.
+struct Head {
+    U8 u;
+    int type;
+    int64_t idx;       // picked particle, -1 for insertion or empty box
+    double4 rec;       // pos[idx]
+    double4 rlast;     // pos[N-1] (deletion: the particle that takes idx)
+};
+
+__device__ __forceinline__ int move_type(const DevBox& B, const U8& u) {
+    return (u.u[0] < B.p_disp) ? GCMC_MOVE_DISPLACE : ((u.u[1] < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
+}
+
+__device__ __forceinline__ int64_t pick_index(const U8& u, int64_t n) {
+    int64_t i = (int64_t)floor(u.u[2] * (double)n);
+    return i > n - 1 ? n - 1 : i;
+}
+
+// Draws, type and pick of move ctr for N = n; issues the record loads.
+__device__ __forceinline__ void head_of(const DevBox& B, uint64_t ctr, int64_t n, Head& H) {
+    H.u = move_uniforms(B.seed, ctr, B.box_id);
+    H.type = move_type(B, H.u);
+    H.idx = -1;
+    if (H.type != GCMC_MOVE_INSERT && n > 0) {
+        H.idx = pick_index(H.u, n);
+        H.rec = B.pos[H.idx];
+        if (H.type == GCMC_MOVE_DELETE) H.rlast = B.pos[n - 1];
+    }
+}
+
+__device__ __forceinline__ int centre_slot(const DevBox& B, const int32_t* c) {
+    const int tx = B.full[0] ? c[0] : B.k[0];
+    const int ty = B.full[1] ? c[1] : B.k[1];
+    const int tz = B.full[2] ? c[2] : B.k[2];
+    return (tz * B.span[1] + ty) * B.span[0] + tx;
+}
+
+template <int W, int R>
+__global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ boxes,
+                                                     const int32_t* __restrict__ order, int64_t n_moves,
+                                                     uint64_t ctr0, gcmc_stats* stats, gcmc_log* log) {
+    __shared__ uint32_t tab[kMaxStencil];
+    __shared__ double red[2][2 * W];
+    __shared__ int32_t sh_cnt[2][2];     // counters of the two centre cells, per buffer
+    __shared__ double4 sh_last[2];       // last entry of the old centre cell, per buffer
+    __shared__ int64_t wred[3][W];
+    const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const DevBox& B = boxes[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int lane_wave = tid / kWave;
+    BoxState* st = B.st;
+
+    if (ctr0 == GCMC_COUNTER_CONTINUE) ctr0 = (uint64_t)st->counter;
+    int64_t N = st->n;
+    double U = st->u_pair;
+    int32_t maxc = st->maxcount;
+    int32_t err = st->error;
+    int64_t err_move = st->error_move;
+    int64_t att[3] = {0, 0, 0}, acc_n[3] = {0, 0, 0};
+    double sum_n = 0.0, sum_u = 0.0;
+    const double tk = B.tailK[0];
+    const int cap = B.cap;
+    int64_t m = 0;
+    int ev = 0;
+    int64_t stencils = 0;
+    Work wk;
+    build_stencil(B, tab);
+    __syncthreads();
+
+    if (err == GCMC_OK && B.ns != 1) {
+        err = GCMC_ERR_UNSUPPORTED;
+        err_move = (int64_t)ctr0;
+    }
+    if (err == GCMC_OK && n_moves > 0) {
+        Head H;
+        head_of(B, ctr0, N, H);
+        for (; m < n_moves; ++m) {
+            const uint64_t ctr = ctr0 + (uint64_t)m;
+            att[H.type] += 1;
+            // ---------------------------------------------------- empty box
+            if (H.type != GCMC_MOVE_INSERT && N == 0) {
+                if (log && tid == 0) {
+                    gcmc_log r;
+                    r.type = H.type; r.index = -1; r.accepted = 0; r.flags = 1;
+                    r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0;
+                    log[(size_t)bi * n_moves + m] = r;
+                }
+                sum_n += 0.0;
+                sum_u += U;
+                if (m + 1 < n_moves) head_of(B, ctr + 1, N, H);
+                continue;
+            }
+            // ------------------------------------------------------ trial
+            Trial T;
+            T.type = __builtin_amdgcn_readfirstlane(H.type);
+            T.sp = 0;
+            T.idx = H.idx;
+            if (H.type == GCMC_MOVE_INSERT) {
+                T.npos = 1;
+                T.same = 0;
+                T.meta = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) T.p[0][a] = wrap_into_box(B.L[a] * H.u.u[4 + a], B.L[a]);
+                locate(B, T, 0);
+            } else {
+                T.meta = H.rec.w;
+                T.p[0][0] = H.rec.x; T.p[0][1] = H.rec.y; T.p[0][2] = H.rec.z;
+                locate(B, T, 0);
+                if (H.type == GCMC_MOVE_DISPLACE) {
+                    T.npos = 2;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        T.p[1][a] = wrap_into_box(T.p[0][a] + B.max_disp * (2.0 * H.u.u[4 + a] - 1.0), B.L[a]);
+                    locate(B, T, 1);
+                    T.same = __builtin_amdgcn_readfirstlane(T.cl[0] == T.cl[1] ? 1 : 0);
+                } else {
+                    T.npos = 1;
+                    T.same = 0;
+                }
+            }
+            const int lg = log2_ceil(maxc);
+            const int NS = B.nstencil << lg;
+            const int two = (T.npos == 2 && !T.same) ? 1 : 0;
+            const int total = NS << two;
+            const int gmask = (1 << lg) - 1;
+            const int tc0 = centre_slot(B, T.c[0]);
+            const int tc1 = two ? centre_slot(B, T.c[1]) : -1;
+            const int buf = ev & 1;
+            const int32_t excl = (int32_t)T.idx;
+            double sa = 0.0, sb = 0.0;
+            Head Hn;
+            bool have_next = false;
+            // -------------------------------------- gather + evaluate passes
+            for (int base = 0; base < total; base += kWave * W * R) {
+                double4 e[R];
+                int32_t cnt[R], kk[R], tt[R], which[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int s = base + r * kWave * W + tid;
+                    const bool in = s < total;
+                    const int w = (two && s >= NS) ? 1 : 0;
+                    const int q = in ? s - w * NS : 0;
+                    const int t = q >> lg;
+                    const int k = q & gmask;
+                    const int32_t cx = w ? T.c[1][0] : T.c[0][0];
+                    const int32_t cy = w ? T.c[1][1] : T.c[0][1];
+                    const int32_t cz = w ? T.c[1][2] : T.c[0][2];
+                    const int64_t c = stencil_cell(B, tab[t], cx, cy, cz);
+                    const int kc = k < cap ? k : cap - 1;
+                    cnt[r] = in ? B.count[c] : 0;
+                    e[r] = B.ent[c * cap + kc];
+                    kk[r] = k;
+                    tt[r] = in ? t : -1;
+                    which[r] = w;
+                }
+                if (!have_next) {
+                    // overlaps the gather: next move's draws and its record (N assumed unchanged)
+                    if (m + 1 < n_moves) head_of(B, ctr + 1, N, Hn);
+                    have_next = true;
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int tcen = which[r] ? tc1 : tc0;
+                    if (tt[r] == tcen) {
+                        if (kk[r] == 0) sh_cnt[buf][which[r]] = cnt[r];
+                        if (which[r] == 0 && kk[r] == cnt[r] - 1) sh_last[buf] = e[r];
+                    }
+                    const bool valid = kk[r] < cnt[r] && meta_low(e[r].w) != excl;
+                    if (valid) {
+                        wk.cand += 1;
+                        if (T.npos == 1) {
+                            sa += pair_energy_w<false>(B, T.p[0], 0, e[r], wk.incut);
+                            wk.evals += 1;
+                        } else if (!two) {
+                            sa += pair_energy_w<false>(B, T.p[0], 0, e[r], wk.incut);
+                            sb += pair_energy_w<false>(B, T.p[1], 0, e[r], wk.incut);
+                            wk.evals += 2;
+                        } else if (which[r]) {
+                            sb += pair_energy_w<false>(B, T.p[1], 0, e[r], wk.incut);
+                            wk.evals += 1;
+                        } else {
+                            sa += pair_energy_w<false>(B, T.p[0], 0, e[r], wk.incut);
+                            wk.evals += 1;
+                        }
+                    }
+                }
+            }
+            ++ev;
+            stencils += two ? 2 : 1;
+            // ----------------------------------------------------- reduce
+            double ea = wave_sum_uniform(sa);
+            double eb = (T.npos == 2) ? wave_sum_uniform(sb) : 0.0;
+            if (W > 1) {
+                if ((tid & (kWave - 1)) == 0) {
+                    red[buf][2 * lane_wave] = ea;
+                    red[buf][2 * lane_wave + 1] = eb;
+                }
+                __syncthreads();
+                double ta = 0.0, tb = 0.0;
+#pragma unroll
+                for (int v = 0; v < W; ++v) {
+                    ta += red[buf][2 * v];
+                    tb += red[buf][2 * v + 1];
+                }
+                ea = ta;
+                eb = tb;
+            }
+            // ----------------------------------------------------- decide
+            // Branch-free: the move type is wave-uniform, and computing the
+            // energy change with selects keeps it out of exec-masked regions.
+            const bool is_disp = T.type == GCMC_MOVE_DISPLACE, is_ins = T.type == GCMC_MOVE_INSERT;
+            const double dUp = is_disp ? (eb - ea) : (is_ins ? ea : -ea);
+            const double dUt = is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
+            const double dU = dUp + dUt;
+            const double arg = accept_log_ratio(B, T.type, dU, N);
+            const bool ok = __builtin_amdgcn_readfirstlane(metropolis(arg, dU, H.u.u[3]) ? 1 : 0) != 0;
+            // ----------------------------------------------------- commit
+            const int64_t n_old = N;
+            int64_t touched0 = -1, touched1 = -1;
+            if (ok) {
+                if (W == 1) __syncthreads();   // LDS records of this wave visible to lane 0
+                const int32_t cnt0 = __builtin_amdgcn_readfirstlane(sh_cnt[buf][0]);
+                const int32_t cnt1 = two ? __builtin_amdgcn_readfirstlane(sh_cnt[buf][1]) : 0;
+                const double4 elast = sh_last[buf];
+                int e = GCMC_OK;
+                if (T.type == GCMC_MOVE_INSERT) {
+                    if (N >= B.max_n) e = GCMC_ERR_CAPACITY;
+                    else if (cnt0 >= cap) e = GCMC_ERR_CELL_OVERFLOW;
+                } else if (T.type == GCMC_MOVE_DISPLACE && two) {
+                    if (cnt1 >= cap) e = GCMC_ERR_CELL_OVERFLOW;
+                }
+                if (e != GCMC_OK) {
+                    err = e;
+                    err_move = (int64_t)ctr;
+                    att[T.type] -= 1;
+                    break;
+                }
+                const int64_t loc = meta_low(T.meta);
+                const int64_t c0 = T.cl[0], c1 = T.cl[1];
+                // swap-with-last removal from the old cell (displacement across cells, deletion)
+                const bool removes = (T.type == GCMC_MOVE_DELETE) || (T.type == GCMC_MOVE_DISPLACE && two);
+                const int64_t last = c0 * cap + cnt0 - 1;
+                const bool swap = removes && loc != last;
+                const int32_t id_last = swap ? meta_low(elast.w) : -1;
+                if (tid == 0) {
+                    if (swap) {
+                        B.ent[loc] = elast;
+                        B.pos[id_last].w = pack_meta(meta_species(elast.w), (int32_t)loc);
+                    }
+                    if (removes) B.count[c0] = cnt0 - 1;
+                    if (T.type == GCMC_MOVE_DISPLACE) {
+                        if (!two) {
+                            B.ent[loc] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)T.idx));
+                            B.pos[T.idx] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], T.meta);
+                        } else {
+                            const int64_t nl = c1 * cap + cnt1;
+                            B.ent[nl] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)T.idx));
+                            B.count[c1] = cnt1 + 1;
+                            B.pos[T.idx] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)nl));
+                        }
+                    } else if (T.type == GCMC_MOVE_INSERT) {
+                        const int64_t nl = c0 * cap + cnt0;
+                        B.ent[nl] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(0, (int32_t)N));
+                        B.count[c0] = cnt0 + 1;
+                        B.pos[N] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(0, (int32_t)nl));
+                    } else if (T.idx != N - 1) {
+                        // particle N-1 takes index idx
+                        double4 r = H.rlast;
+                        if (id_last == (int32_t)(N - 1)) r.w = pack_meta(meta_species(r.w), (int32_t)loc);
+                        B.pos[T.idx] = r;
+                        B.ent[meta_low(r.w)].w = pack_meta(meta_species(r.w), (int32_t)T.idx);
+                    }
+                }
+                if (T.type == GCMC_MOVE_DISPLACE && two && cnt1 + 1 > maxc) maxc = cnt1 + 1;
+                if (T.type == GCMC_MOVE_INSERT && cnt0 + 1 > maxc) maxc = cnt0 + 1;
+                touched0 = (T.type == GCMC_MOVE_INSERT) ? N : T.idx;
+                touched1 = id_last;
+                acc_n[T.type] += 1;
+                N += (T.type == GCMC_MOVE_INSERT) ? 1 : ((T.type == GCMC_MOVE_DELETE) ? -1 : 0);
+                U += dUp;
+                __syncthreads();   // commit stores complete and visible to the workgroup
+            }
+            if (log && tid == 0) {
+                gcmc_log r;
+                r.type = T.type;
+                r.index = (T.type == GCMC_MOVE_INSERT) ? (int32_t)n_old : (int32_t)T.idx;
+                r.accepted = ok ? 1 : 0;
+                r.flags = 0;
+                r.dU_pair = dUp;
+                r.dU_tail = dUt;
+                const int w = (T.type == GCMC_MOVE_DISPLACE) ? 1 : 0;
+                r.x = T.p[w][0]; r.y = T.p[w][1]; r.z = T.p[w][2];
+                r.arg = arg;
+                log[(size_t)bi * n_moves + m] = r;
+            }
+            sum_n += (double)N;
+            sum_u += U + tk * (double)N * (double)N;
+            // ------------------------------------- validate the prefetch
+            if (m + 1 < n_moves) {
+                if (Hn.type != GCMC_MOVE_INSERT && N > 0) {
+                    const int64_t i2 = pick_index(Hn.u, N);
+                    if (N != n_old || Hn.idx < 0 || i2 != Hn.idx || i2 == touched0 || i2 == touched1) {
+                        Hn.idx = i2;
+                        Hn.rec = B.pos[i2];
+                    }
+                    if (Hn.type == GCMC_MOVE_DELETE &&
+                        (N != n_old || N - 1 == touched0 || N - 1 == touched1))
+                        Hn.rlast = B.pos[N - 1];
+                } else {
+                    Hn.idx = -1;
+                }
+                H = Hn;
+            }
+        }
+    }
+    // launch-wide work counters
+    {
+        int64_t c = wk.cand, e = wk.evals, q = wk.incut;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            c += __shfl_xor(c, off, kWave);
+            e += __shfl_xor(e, off, kWave);
+            q += __shfl_xor(q, off, kWave);
+        }
+        __syncthreads();
+        if ((tid & (kWave - 1)) == 0) {
+            wred[0][lane_wave] = c;
+            wred[1][lane_wave] = e;
+            wred[2][lane_wave] = q;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        st->n = N;
+        st->u_pair = U;
+        st->maxcount = maxc;
+        st->nsp[0] = N;
+        st->counter = (int64_t)(ctr0 + (uint64_t)m);
+        if (err != GCMC_OK && st->error == GCMC_OK) {
+            st->error = err;
+            st->error_move = err_move;
+        }
+        if (stats) {
+            gcmc_stats o;
+            for (int t = 0; t < 3; ++t) {
+                o.attempts[t] = att[t];
+                o.accepts[t] = acc_n[t];
+            }
+            o.n = N;
+            o.moves_done = m;
+            o.u_pair = U;
+            o.u_tail = tk * (double)N * (double)N;
+            o.sum_n = sum_n;
+            o.sum_u = sum_u;
+            o.error = st->error;
+            o.pad = 0;
+            o.error_move = st->error_move;
+            o.stencils = stencils;
+            o.candidates = o.pair_evals = o.in_cutoff = 0;
+            for (int v = 0; v < W; ++v) {
+                o.candidates += wred[0][v];
+                o.pair_evals += wred[1][v];
+                o.in_cutoff += wred[2][v];
+            }
+            stats[bi] = o;
+        }
+    }
+}
+
+using chain_fn = void (*)(const DevBox*, const int32_t*, int64_t, uint64_t, gcmc_stats*, gcmc_log*);
+
+struct ChainCfg {
+    int w, r;
+    chain_fn f;
+};
+
+static const ChainCfg kChainCfgs[] = {
+    {1, 8, k_chain<1, 8>}, {2, 8, k_chain<2, 8>}, {4, 2, k_chain<4, 2>}, {4, 4, k_chain<4, 4>},
+    {4, 8, k_chain<4, 8>}, {8, 2, k_chain<8, 2>}, {8, 4, k_chain<8, 4>},
+};
+
+int launch_chain(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int rows, int64_t n_moves,
+                 uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s) {
+    for (const ChainCfg& c : kChainCfgs) {
+        if (c.w == waves && c.r == rows) {
+            hipLaunchKernelGGL(c.f, dim3(n_boxes), dim3(kWave * c.w), 0, s, d_boxes, d_order, n_moves, ctr0, stats,
+                               log);
+            return 0;
+        }
+    }
+    return -1;
+}
+
+bool chain_cfg_exists(int waves, int rows) {
+    for (const ChainCfg& c : kChainCfgs)
+        if (c.w == waves && c.r == rows) return true;
+    return false;
+}
+
+}  // namespace gcmc

@@ -24,7 +24,7 @@ struct BoxState {
     int32_t error;        // latched GCMC_ERR_*
     int64_t error_move;   // move counter of the error, -1 if none
     int64_t nsp[kMaxSpecies];  // particles per species
-    int64_t counter;      // spare (kept zero)
+    int64_t counter;      // move counter after the last move the chain ran
 };
 
 // Everything a kernel needs about one box (read-only during a launch).
@@ -164,6 +164,32 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Cross-lane move of a double by a DPP pattern (each 32-bit half moved).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the wavefront, returned identically to every lane: DPP exchanges
+// within quads (xor 1, xor 2) and rotations by 4 and 8 within each row of 16
+// leave every lane of a row with that row's sum; the four row sums are then
+// read from lanes 0, 16, 32, 48 and added in a fixed order.
+__device__ __forceinline__ double wave_sum_uniform(double v) {
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0x124>(v);   // row_ror:4
+    v += dpp_move<0x128>(v);   // row_ror:8
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 __device__ __forceinline__ int32_t wave_max_i(int32_t v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -213,6 +239,7 @@ struct gcmc_batch {
     gcmc_box** boxes;        // host array, in the caller's order
     int32_t n;
     gcmc::DevBox* d_descs;   // device array, launch order (decreasing N)
+    gcmc::DevBox* h_descs;   // what d_descs holds (to detect a rebuilt box)
     int32_t* d_order;        // launch slot -> caller index (device)
     int32_t* h_order;        // the same on the host
 };

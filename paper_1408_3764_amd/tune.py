@@ -14,7 +14,7 @@ import json
 import os
 import time
 
-SHAPES = [(1, 8), (2, 8), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4), (16, 2)]
+SHAPES = [(1, 8), (2, 8), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4)]
 CACHE_ENV = "GCMC_TUNE_CACHE"
 
 
@@ -39,7 +39,7 @@ def chain_shape(box):
             key = (w * r, w)          # fewest slots per pass, then fewest waves
             if best is None or key < best[0]:
                 best = (key, (w, r))
-    return best[1] if best else (16, 2)
+    return best[1] if best else (8, 4)
 
 
 def batch_shape(boxes):
