@@ -2,24 +2,27 @@
 // many moves of Algorithm 1 in a single launch (the paper's multi-move kernel,
 // Sec. 3.3.4), with device-side Philox draws and Metropolis tests.
 //
-// A move is a dependent sequence of memory round trips, so the kernel is built
-// to expose as few of them as possible per move:
-//  * the stencil gather of the move (cell counters and 32-byte cell entries of
-//    every stencil slot) is one round trip for all lanes;
-//  * while it is in flight the next move's Philox draws are computed and the
-//    record of the particle it will pick is loaded (assuming N unchanged);
-//  * the counters of the centre cells and the last entry of the old cell come
-//    back with the gather, so the commit (Sec. 3.2.5: swap-with-last removal,
-//    append) is stores only;
-//  * after a commit, a prefetched record the commit touched, or a pick that a
-//    changed N moved, is loaded again.
-// The chain is exactly the sequential one: every prefetch is validated before
-// use.
+// On one compute unit a move is bound by vector-instruction issue and by the
+// latency of its memory round trips, so the kernel keeps both small:
+//  * slot decomposition (stencil cell, entry, which position) of every lane's
+//    rows is computed once per occupancy level, with the linear offset of the
+//    stencil cell from the centre cell; for a centre cell away from the box
+//    faces a candidate's address is one add and one multiply-add;
+//  * the counters and 32-byte entries of all slots are loaded in one round
+//    trip; while it is in flight the next move's draws are computed (one
+//    Philox block per lane, four lanes) and the record of the particle it will
+//    pick is loaded, and ln A and the log prefactor of this move are formed;
+//  * each wavefront compacts its valid candidates (k below the cell's count,
+//    not the moving particle) into LDS and evaluates only those;
+//  * the centre cells' counters and the old cell's last entry come back with
+//    the gather, so the commit (Sec. 3.2.5: swap-with-last removal, append) is
+//    stores only; prefetched records are validated after it.
+// Wave-uniform decisions go through readfirstlane so they never sit in
+// exec-masked code.  The chain is exactly the sequential one.
 #include "trial.h"
 
 namespace gcmc {
 
-// The part of a move known before its gather.
 struct Head {
     U8 u;
     int type;
@@ -39,8 +42,8 @@ __device__ __forceinline__ int64_t pick_index(const U8& u, int64_t n) {
 
 // Draws, type and pick of move ctr for N = n; issues the record loads.
 __device__ __forceinline__ void head_of(const DevBox& B, uint64_t ctr, int64_t n, Head& H) {
-    H.u = move_uniforms(B.seed, ctr, B.box_id);
-    H.type = move_type(B, H.u);
+    H.u = move_uniforms_lanes(B.seed, ctr, B.box_id);
+    H.type = __builtin_amdgcn_readfirstlane(move_type(B, H.u));
     H.idx = -1;
     if (H.type != GCMC_MOVE_INSERT && n > 0) {
         H.idx = pick_index(H.u, n);
@@ -56,19 +59,79 @@ __device__ __forceinline__ int centre_slot(const DevBox& B, const int32_t* c) {
     return (tz * B.span[1] + ty) * B.span[0] + tx;
 }
 
+// Cell of position w of the trial, made wave-uniform (the positions are the
+// same in every lane; saying so keeps the stencil arithmetic scalar).
+__device__ __forceinline__ void locate_uniform(const DevBox& B, Trial& T, int w) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        T.c[w][a] = __builtin_amdgcn_readfirstlane(axis_cell(T.p[w][a], B.invS[a], B.M[a]));
+    T.cl[w] = ((int64_t)T.c[w][2] * B.M[1] + T.c[w][1]) * B.M[0] + T.c[w][0];
+}
+
+__device__ __forceinline__ bool interior(const DevBox& B, const int32_t* c) {
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok = ok && c[a] >= B.k[a] && c[a] <= B.M[a] - 1 - B.k[a];
+    return ok;
+}
+
+// A register copy of the descriptor fields the chain uses (single species),
+// every field passed through readfirstlane so it stays in scalar registers.
+__device__ __forceinline__ DevBox hot_copy(const DevBox& G) {
+    DevBox B;
+    B.pos = unip(G.pos);
+    B.ent = unip(G.ent);
+    B.count = unip(G.count);
+    B.st = unip(G.st);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        B.L[a] = unid(G.L[a]);
+        B.hL[a] = unid(G.hL[a]);
+        B.invS[a] = unid(G.invS[a]);
+        B.M[a] = uni(G.M[a]);
+        B.span[a] = uni(G.span[a]);
+        B.k[a] = uni(G.k[a]);
+        B.full[a] = uni(G.full[a]);
+    }
+    B.cap = uni(G.cap);
+    B.ns = uni(G.ns);
+    B.ncells = uni64(G.ncells);
+    B.max_n = uni64(G.max_n);
+    B.rc2 = unid(G.rc2);
+    B.beta = unid(G.beta);
+    B.mu = unid(G.mu);
+    B.lambda3 = unid(G.lambda3);
+    B.max_disp = unid(G.max_disp);
+    B.p_disp = unid(G.p_disp);
+    B.V = unid(G.V);
+    B.eps4[0] = unid(G.eps4[0]);
+    B.sig2[0] = unid(G.sig2[0]);
+    B.tailK[0] = unid(G.tailK[0]);
+    B.seed = (uint64_t)uni64((int64_t)G.seed);
+    B.box_id = (uint32_t)uni((int32_t)G.box_id);
+    B.nstencil = uni(G.nstencil);
+    return B;
+}
+
+// Packed per-row slot description: k | t << 10 | which << 21 | valid << 22.
+constexpr int kSlotT = 10, kSlotW = 21, kSlotV = 22;
+
 template <int W, int R>
 __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ boxes,
                                                      const int32_t* __restrict__ order, int64_t n_moves,
-                                                     uint64_t ctr0, gcmc_stats* stats, gcmc_log* log) {
+                                                     uint64_t ctr0, gcmc_stats* stats, gcmc_log* trace) {
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[2][2 * W];
     __shared__ int32_t sh_cnt[2][2];     // counters of the two centre cells, per buffer
     __shared__ double4 sh_last[2];       // last entry of the old centre cell, per buffer
     __shared__ int64_t wred[3][W];
+    __shared__ double4 cbuf[W][kWave * R];   // per-wavefront compacted candidates
     const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
-    const DevBox& B = boxes[blockIdx.x];
+    const DevBox B = hot_copy(boxes[blockIdx.x]);
     const int tid = threadIdx.x;
-    const int lane_wave = tid / kWave;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    double4* my = cbuf[wv];
     BoxState* st = B.st;
 
     if (ctr0 == GCMC_COUNTER_CONTINUE) ctr0 = (uint64_t)st->counter;
@@ -81,12 +144,20 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
     double sum_n = 0.0, sum_u = 0.0;
     const double tk = B.tailK[0];
     const int cap = B.cap;
+    const int M0 = B.M[0], M01 = B.M[0] * B.M[1];
+    const bool no_full = !(B.full[0] | B.full[1] | B.full[2]);
+    const int tcen_fast = (B.k[2] * B.span[1] + B.k[1]) * B.span[0] + B.k[0];
     int64_t m = 0;
     int ev = 0;
     int64_t stencils = 0;
     Work wk;
     build_stencil(B, tab);
     __syncthreads();
+
+    // per-lane slot table for the current occupancy level
+    int lg_cached = -1;
+    bool fast_ok = false;
+    int32_t sk[R], soff[R];
 
     if (err == GCMC_OK && B.ns != 1) {
         err = GCMC_ERR_UNSUPPORTED;
@@ -100,20 +171,19 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
             att[H.type] += 1;
             // ---------------------------------------------------- empty box
             if (H.type != GCMC_MOVE_INSERT && N == 0) {
-                if (log && tid == 0) {
+                if (trace && tid == 0) {
                     gcmc_log r;
                     r.type = H.type; r.index = -1; r.accepted = 0; r.flags = 1;
                     r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0;
-                    log[(size_t)bi * n_moves + m] = r;
+                    trace[(size_t)bi * n_moves + m] = r;
                 }
-                sum_n += 0.0;
                 sum_u += U;
                 if (m + 1 < n_moves) head_of(B, ctr + 1, N, H);
                 continue;
             }
             // ------------------------------------------------------ trial
             Trial T;
-            T.type = __builtin_amdgcn_readfirstlane(H.type);
+            T.type = H.type;
             T.sp = 0;
             T.idx = H.idx;
             if (H.type == GCMC_MOVE_INSERT) {
@@ -122,63 +192,105 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 T.meta = 0.0;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) T.p[0][a] = wrap_into_box(B.L[a] * H.u.u[4 + a], B.L[a]);
-                locate(B, T, 0);
+                locate_uniform(B, T, 0);
             } else {
                 T.meta = H.rec.w;
                 T.p[0][0] = H.rec.x; T.p[0][1] = H.rec.y; T.p[0][2] = H.rec.z;
-                locate(B, T, 0);
+                locate_uniform(B, T, 0);
                 if (H.type == GCMC_MOVE_DISPLACE) {
                     T.npos = 2;
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
                         T.p[1][a] = wrap_into_box(T.p[0][a] + B.max_disp * (2.0 * H.u.u[4 + a] - 1.0), B.L[a]);
-                    locate(B, T, 1);
+                    locate_uniform(B, T, 1);
                     T.same = __builtin_amdgcn_readfirstlane(T.cl[0] == T.cl[1] ? 1 : 0);
                 } else {
                     T.npos = 1;
                     T.same = 0;
                 }
             }
-            const int lg = log2_ceil(maxc);
+            const int lg = __builtin_amdgcn_readfirstlane(log2_ceil(maxc));
             const int NS = B.nstencil << lg;
             const int two = (T.npos == 2 && !T.same) ? 1 : 0;
             const int total = NS << two;
             const int gmask = (1 << lg) - 1;
-            const int tc0 = centre_slot(B, T.c[0]);
-            const int tc1 = two ? centre_slot(B, T.c[1]) : -1;
+            if (lg != lg_cached) {
+                // slot table of this occupancy level (both stencils' ranges)
+                lg_cached = lg;
+                fast_ok = no_full && (2 * NS <= kWave * W * R) && lg <= 10;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int s = r * kWave * W + tid;
+                    const int w = s >= NS ? 1 : 0;
+                    const int q = s - w * NS;
+                    const int t = (s < 2 * NS) ? (q >> lg) : 0;
+                    const int k = q & gmask;
+                    const uint32_t pk = tab[t];
+                    const int dx = (int)(pk & 0x3FF) - B.k[0];
+                    const int dy = (int)((pk >> 10) & 0x3FF) - B.k[1];
+                    const int dz = (int)(pk >> 20) - B.k[2];
+                    soff[r] = dz * M01 + dy * M0 + dx;
+                    sk[r] = (k & 0x3FF) | (t << kSlotT) | (w << kSlotW) | ((s < 2 * NS ? 1 : 0) << kSlotV);
+                }
+            }
+            const bool fast = __builtin_amdgcn_readfirstlane(
+                                  (fast_ok && interior(B, T.c[0]) && (!two || interior(B, T.c[1]))) ? 1 : 0) != 0;
             const int buf = ev & 1;
             const int32_t excl = (int32_t)T.idx;
+            const int tc0 = fast ? tcen_fast : centre_slot(B, T.c[0]);
+            const int tc1 = two ? (fast ? tcen_fast : centre_slot(B, T.c[1])) : -1;
+            const int32_t cl0 = (int32_t)T.cl[0], cl1 = (int32_t)T.cl[1];
             double sa = 0.0, sb = 0.0;
             Head Hn;
             bool have_next = false;
+            double lnA = 0.0, lpref = 0.0;
             // -------------------------------------- gather + evaluate passes
             for (int base = 0; base < total; base += kWave * W * R) {
                 double4 e[R];
                 int32_t cnt[R], kk[R], tt[R], which[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int s = base + r * kWave * W + tid;
-                    const bool in = s < total;
-                    const int w = (two && s >= NS) ? 1 : 0;
-                    const int q = in ? s - w * NS : 0;
-                    const int t = q >> lg;
-                    const int k = q & gmask;
-                    const int32_t cx = w ? T.c[1][0] : T.c[0][0];
-                    const int32_t cy = w ? T.c[1][1] : T.c[0][1];
-                    const int32_t cz = w ? T.c[1][2] : T.c[0][2];
-                    const int64_t c = stencil_cell(B, tab[t], cx, cy, cz);
+                    int32_t c;
+                    bool in;
+                    int k, t, w;
+                    if (fast) {
+                        const int32_t pk = sk[r];
+                        w = (pk >> kSlotW) & 1;
+                        in = ((pk >> kSlotV) & 1) && (two || !w);
+                        k = pk & 0x3FF;
+                        t = (pk >> kSlotT) & 0x7FF;
+                        c = (w ? cl1 : cl0) + soff[r];
+                    } else {
+                        const int s = base + r * kWave * W + tid;
+                        in = s < total;
+                        w = (two && s >= NS) ? 1 : 0;
+                        const int q = in ? s - w * NS : 0;
+                        t = q >> lg;
+                        k = q & gmask;
+                        const int32_t cx = w ? T.c[1][0] : T.c[0][0];
+                        const int32_t cy = w ? T.c[1][1] : T.c[0][1];
+                        const int32_t cz = w ? T.c[1][2] : T.c[0][2];
+                        c = (int32_t)stencil_cell(B, tab[t], cx, cy, cz);
+                    }
+                    if (!in) c = cl0;
                     const int kc = k < cap ? k : cap - 1;
                     cnt[r] = in ? B.count[c] : 0;
-                    e[r] = B.ent[c * cap + kc];
+                    e[r] = B.ent[(size_t)(uint32_t)c * (uint32_t)cap + kc];
                     kk[r] = k;
                     tt[r] = in ? t : -1;
                     which[r] = w;
                 }
                 if (!have_next) {
-                    // overlaps the gather: next move's draws and its record (N assumed unchanged)
+                    // overlaps the gather: this move's ln A and log prefactor, the next
+                    // move's draws and record (N assumed unchanged)
+                    lnA = log(H.u.u[3]);
+                    if (T.type == GCMC_MOVE_INSERT) lpref = log(B.V / (B.lambda3 * (double)(N + 1)));
+                    else if (T.type == GCMC_MOVE_DELETE) lpref = log((B.lambda3 * (double)N) / B.V);
                     if (m + 1 < n_moves) head_of(B, ctr + 1, N, Hn);
                     have_next = true;
                 }
+                // centre records, then compaction of the valid candidates of this wavefront
+                int nv = 0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int tcen = which[r] ? tc1 : tc0;
@@ -187,24 +299,33 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                         if (which[r] == 0 && kk[r] == cnt[r] - 1) sh_last[buf] = e[r];
                     }
                     const bool valid = kk[r] < cnt[r] && meta_low(e[r].w) != excl;
+                    const uint64_t bal = __ballot(valid);
                     if (valid) {
-                        wk.cand += 1;
-                        if (T.npos == 1) {
-                            sa += pair_energy_w<false>(B, T.p[0], 0, e[r], wk.incut);
-                            wk.evals += 1;
-                        } else if (!two) {
-                            sa += pair_energy_w<false>(B, T.p[0], 0, e[r], wk.incut);
-                            sb += pair_energy_w<false>(B, T.p[1], 0, e[r], wk.incut);
-                            wk.evals += 2;
-                        } else if (which[r]) {
-                            sb += pair_energy_w<false>(B, T.p[1], 0, e[r], wk.incut);
-                            wk.evals += 1;
-                        } else {
-                            sa += pair_energy_w<false>(B, T.p[0], 0, e[r], wk.incut);
-                            wk.evals += 1;
-                        }
+                        const int at = nv + __popcll(bal & ((1ull << lane) - 1ull));
+                        my[at] = make_double4(e[r].x, e[r].y, e[r].z, (double)which[r]);
+                    }
+                    nv += __popcll(bal);
+                }
+                __builtin_amdgcn_wave_barrier();
+                wk.cand += (lane == 0) ? nv : 0;
+                for (int j = lane; j < nv; j += kWave) {
+                    const double4 c4 = my[j];
+                    if (T.npos == 1) {
+                        sa += pair_energy_w<false>(B, T.p[0], 0, c4, wk.incut);
+                        wk.evals += 1;
+                    } else if (!two) {
+                        sa += pair_energy_w<false>(B, T.p[0], 0, c4, wk.incut);
+                        sb += pair_energy_w<false>(B, T.p[1], 0, c4, wk.incut);
+                        wk.evals += 2;
+                    } else if (c4.w != 0.0) {
+                        sb += pair_energy_w<false>(B, T.p[1], 0, c4, wk.incut);
+                        wk.evals += 1;
+                    } else {
+                        sa += pair_energy_w<false>(B, T.p[0], 0, c4, wk.incut);
+                        wk.evals += 1;
                     }
                 }
+                __builtin_amdgcn_wave_barrier();
             }
             ++ev;
             stencils += two ? 2 : 1;
@@ -212,9 +333,9 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
             double ea = wave_sum_uniform(sa);
             double eb = (T.npos == 2) ? wave_sum_uniform(sb) : 0.0;
             if (W > 1) {
-                if ((tid & (kWave - 1)) == 0) {
-                    red[buf][2 * lane_wave] = ea;
-                    red[buf][2 * lane_wave + 1] = eb;
+                if (lane == 0) {
+                    red[buf][2 * wv] = ea;
+                    red[buf][2 * wv + 1] = eb;
                 }
                 __syncthreads();
                 double ta = 0.0, tb = 0.0;
@@ -227,14 +348,14 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 eb = tb;
             }
             // ----------------------------------------------------- decide
-            // Branch-free: the move type is wave-uniform, and computing the
-            // energy change with selects keeps it out of exec-masked regions.
+            // Accept iff ln A < ln(ratio) (Eqs. 3-5); the same test as A < min(1, ratio).
             const bool is_disp = T.type == GCMC_MOVE_DISPLACE, is_ins = T.type == GCMC_MOVE_INSERT;
             const double dUp = is_disp ? (eb - ea) : (is_ins ? ea : -ea);
             const double dUt = is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
             const double dU = dUp + dUt;
-            const double arg = accept_log_ratio(B, T.type, dU, N);
-            const bool ok = __builtin_amdgcn_readfirstlane(metropolis(arg, dU, H.u.u[3]) ? 1 : 0) != 0;
+            const double arg = is_disp ? -(B.beta * dU)
+                                       : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
+            const bool ok = __builtin_amdgcn_readfirstlane((dU == dU && lnA < arg) ? 1 : 0) != 0;
             // ----------------------------------------------------- commit
             const int64_t n_old = N;
             int64_t touched0 = -1, touched1 = -1;
@@ -301,7 +422,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 U += dUp;
                 __syncthreads();   // commit stores complete and visible to the workgroup
             }
-            if (log && tid == 0) {
+            if (trace && tid == 0) {
                 gcmc_log r;
                 r.type = T.type;
                 r.index = (T.type == GCMC_MOVE_INSERT) ? (int32_t)n_old : (int32_t)T.idx;
@@ -312,7 +433,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 const int w = (T.type == GCMC_MOVE_DISPLACE) ? 1 : 0;
                 r.x = T.p[w][0]; r.y = T.p[w][1]; r.z = T.p[w][2];
                 r.arg = arg;
-                log[(size_t)bi * n_moves + m] = r;
+                trace[(size_t)bi * n_moves + m] = r;
             }
             sum_n += (double)N;
             sum_u += U + tk * (double)N * (double)N;
@@ -344,10 +465,10 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
             q += __shfl_xor(q, off, kWave);
         }
         __syncthreads();
-        if ((tid & (kWave - 1)) == 0) {
-            wred[0][lane_wave] = c;
-            wred[1][lane_wave] = e;
-            wred[2][lane_wave] = q;
+        if (lane == 0) {
+            wred[0][wv] = c;
+            wred[1][wv] = e;
+            wred[2][wv] = q;
         }
         __syncthreads();
     }

@@ -58,6 +58,24 @@ struct DevBox {
     int32_t nstencil;    // span_x * span_y * span_z
 };
 
+// ------------------------------------------------------- uniform values
+// readfirstlane of a value every lane holds: the result lives in scalar
+// registers and, unlike a field loaded from the descriptor, is not reloaded
+// from memory inside loops.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double unid(double v) {
+    return __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, v)));
+}
+template <class T>
+__device__ __forceinline__ T* unip(T* p) {
+    return (T*)(uintptr_t)uni64((int64_t)(uintptr_t)p);
+}
+
 // ------------------------------------------------------------------ packing
 __host__ __device__ __forceinline__ double pack_meta(int32_t species, int32_t low) {
     uint64_t v = ((uint64_t)(uint32_t)species << 32) | (uint64_t)(uint32_t)low;
@@ -106,11 +124,30 @@ __device__ __forceinline__ U8 move_uniforms(uint64_t seed, uint64_t ctr, uint32_
     return o;
 }
 
+// The same eight uniforms with a quarter of the vector work: lane j (mod 4)
+// computes Philox block j and the sixteen words are read from lanes 0..3.
+// Every lane of the wavefront must be active.
+__device__ __forceinline__ double read_lane(double v, int lane);
+__device__ __forceinline__ U8 move_uniforms_lanes(uint64_t seed, uint64_t ctr, uint32_t box) {
+    uint32_t c0 = (uint32_t)ctr, c1 = (uint32_t)(ctr >> 32), c2 = box, c3 = (uint32_t)(__lane_id() & 3);
+    philox_block(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double a = to_unit(c0, c1), b = to_unit(c2, c3);
+    U8 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        o.u[2 * j] = read_lane(a, j);
+        o.u[2 * j + 1] = read_lane(b, j);
+    }
+    return o;
+}
+
 // ------------------------------------------------------------- geometry
+// Minimum image along one axis of length L (h = L/2), coordinates in [0, L):
+// d - L if d > h, d + L if d < -h, else d (two selects, no branches; the
+// second select cannot fire after the first did, since |d| < L).
 __device__ __forceinline__ double nearest_image(double d, double L, double h) {
-    if (d > h) return d - L;
-    if (d < -h) return d + L;
-    return d;
+    const double a = d > h ? d - L : d;
+    return a < -h ? a + L : a;
 }
 
 __device__ __forceinline__ double wrap_into_box(double x, double L) {
