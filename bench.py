@@ -44,6 +44,44 @@ def alg_bytes(stats, nstencil):
             + sum(acc) * 72)
 
 
+# Sources each chain kernel is compiled from: a traffic record taken with
+# rocprofv3 counters is used only while these files are unchanged.
+KERNEL_SOURCES = {
+    "k_chain": ["chain.hip", "trial.h", "gcmc_internal.h"],
+    "k_chain_spec": ["spec.hip", "trial.h", "gcmc_internal.h"],
+}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1408_3764_amd", "csrc")
+    for f in KERNEL_SOURCES[kernel] + ["../../include/gcmc.h"]:
+        with open(os.path.normpath(os.path.join(csrc, f)), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, shape, workload, moves_per_launch):
+    """HBM bytes per launch from the committed counter summaries under profiles/:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the same kernel, launch shape
+    and workload, each scaled by what the counter reads for a copy of known size.
+    None when no record matches or the kernel's sources changed since."""
+    import glob
+    import re
+    want = kernel_source_hash(kernel)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for m in re.finditer(r"<!-- traffic (\{.*?\}) -->", fh.read()):
+                r = json.loads(m.group(1))
+                if (r["kernel"] == kernel and tuple(r["launch"]) == tuple(shape) and r["workload"] == workload
+                        and r["source_hash"] == want):
+                    per_move = (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"]) * 1024.0 \
+                        / r["moves_per_launch"]
+                    return per_move * moves_per_launch, os.path.relpath(path, ROOT)
+    return None, None
+
+
 def workload_by_name(name):
     from paper_1408_3764_amd import workloads
     return {"slab": workloads.slab, "large": workloads.large, "small": workloads.small}[name]()
@@ -72,15 +110,28 @@ def main():
     ap.add_argument("--workload", default="slab", choices=["slab", "large", "small"])
     ap.add_argument("--moves-per-step", type=int, default=0, help="0: the workload's move count")
     ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--rows", type=int, default=0, help="with --waves: rows per wavefront, 0 = speculative kernel")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-allpairs", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="heuristic launch shape instead of timing them")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (reference for the traffic counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "launches": 3}))
+        return
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (the chain of one box is a "
-              "dependent sequence; see the sharding notes in DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path here (one box's chain is a "
+              "dependent sequence; independent boxes would shard by box). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -95,24 +146,28 @@ def main():
     wb = workload_by_name(args.workload)
     log("workload %s: N=%d generated in %.1fs" % (wb.name, wb.n, time.perf_counter() - t))
     mps = args.moves_per_step or wb.n_moves
-    total_moves = mps * (args.steps + args.warmup)
+    total_moves = mps * (args.steps + args.warmup) + 40_000   # + the moves the tuner runs
     box = Box.from_workload(wb, max_n=wb.n + total_moves + 1)
     info = box.info()
     nst = info["span"][0] * info["span"][1] * info["span"][2]
-    if args.waves and args.rows:
+    U0 = box.total_energy()
+    tuning = None
+    if args.waves:
         box.set_launch(args.waves, args.rows)
         shape = (args.waves, args.rows)
-    else:
+    elif args.no_tune:
         shape = tune.chain_shape(box)
         box.set_launch(*shape)
-    U0 = box.total_energy()
+    else:
+        # time every launch shape on this machine (the chain continues on its device counter)
+        shape, tuning = tune.autotune_live(box)
+        log("tuned launch %dx%d: %s" % (shape[0], shape[1], {k: round(v * 1e3, 2) for k, v in tuning.items()}))
     log("box: cells %s cap %d stencil %d, launch %dx%d, U0=%.6f" % (info["cell_m"], info["cell_cap"], nst,
                                                                      shape[0], shape[1], U0["U_pair"]))
+    from paper_1408_3764_amd._lib import COUNTER_CONTINUE
     stream = torch.cuda.current_stream()
-    ctr = 0
     for w in range(args.warmup):
-        box.step(mps, counter0=ctr)
-        ctr += mps
+        box.step(mps, counter0=COUNTER_CONTINUE)
     torch.cuda.synchronize()
     evs = []
     stats_all = []
@@ -121,9 +176,8 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        st, _ = box.step(mps, counter0=ctr)
+        st, _ = box.step(mps, counter0=COUNTER_CONTINUE)
         e1.record(stream)
-        ctr += mps
         evs.append((e0, e1))
         stats_all.append(st)
     torch.cuda.synchronize()
@@ -142,6 +196,8 @@ def main():
     achieved = bytes_per_launch / avg_launch_s / 1e9
     log("timed %d x %d moves: %.3fs wall, launch avg %.2f ms, %.0f moves/s, %.3g pair evals/s" %
         (args.steps, mps, wall, 1e3 * avg_launch_s, moves / wall, pair_evals / wall))
+    kname = "k_chain_spec" if shape[1] == 0 else "k_chain"
+    traffic, traffic_src = measured_traffic(kname, shape, wb.name, mps)
     acc = np.sum([s["accepts"] for s in stats_all], axis=0)
     att = np.sum([s["attempts"] for s in stats_all], axis=0)
 
@@ -167,23 +223,38 @@ def main():
         "acceptance": {"displace": float(acc[0] / max(att[0], 1)), "insert": float(acc[1] / max(att[1], 1)),
                        "delete": float(acc[2] / max(att[2], 1))},
         "us_per_move": 1e6 * wall / moves,
-        "roofline": {"bound": "hbm", "kernel": "k_chain", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": bytes_per_launch, "avg_launch_ms": 1e3 * avg_launch_s},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": traffic_src, "alg_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": 1e3 * avg_launch_s},
     }
 
-    if not args.no_allpairs and args.workload != "slab":
-        # the no-cell-list path of the paper, same chain, a bounded number of moves
-        ab = Box.from_workload(wb, max_n=wb.n + 2001)
+    if not args.no_allpairs:
+        # the paper's comparison of its cell list with the no-cell-list GPU code, on the
+        # 262,144-particle box (rc = 3.0): the same chain through both paths
+        lw = wb if args.workload == "large" else workload_by_name("large")
+        cb = Box.from_workload(lw, max_n=lw.n + 30001)
+        cb.set_launch(*tune.chain_shape(cb))
+        cb.step(1000, counter0=0)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        sc, _ = cb.step(20000, counter0=1000)
+        torch.cuda.synchronize()
+        dc = time.perf_counter() - tc
+        cb.close()
+        ab = Box.from_workload(lw, max_n=lw.n + 2001)
         ab.step(50, counter0=0, all_pairs=True)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         sa, _ = ab.step(1000, counter0=50, all_pairs=True)
         torch.cuda.synchronize()
         da = time.perf_counter() - ta
-        out["allpairs"] = {"moves_per_s": 1000 / da, "pair_evals_per_s": int(sa["pair_evals"]) / da,
-                           "moves": 1000}
         ab.close()
+        out["cell_vs_allpairs"] = {"workload": lw.name,
+                                   "cell_list": {"moves_per_s": 20000 / dc, "pair_evals_per_s": int(sc["pair_evals"]) / dc},
+                                   "all_pairs": {"moves_per_s": 1000 / da, "pair_evals_per_s": int(sa["pair_evals"]) / da},
+                                   "speedup": (20000 / dc) / (1000 / da)}
+        log("cell list vs all pairs at N=%d: %.0f vs %.0f moves/s" % (lw.n, 20000 / dc, 1000 / da))
 
     if not args.no_batched:
         from paper_1408_3764_amd import workloads
@@ -191,18 +262,29 @@ def main():
         wbs = workloads.batched()
         log("batched: %d boxes, N total %d, generated in %.1fs" % (len(wbs), sum(w.n for w in wbs),
                                                                  time.perf_counter() - tb))
-        boxes = [Box.from_workload(w, max_n=w.n + 2101, box_id=k) for k, w in enumerate(wbs)]
-        bshape = tune.batch_shape(boxes)
+        boxes = [Box.from_workload(w, max_n=w.n + 3001, box_id=k) for k, w in enumerate(wbs)]
+        bt = Batch(boxes)
+        # time the shapes that fit a batch (one workgroup per box) and keep the fastest
+        btimes = {}
+        for bshape in ((1, 8), (2, 8), (4, 4), (4, 2), (4, 0), (8, 0)):
+            for b in boxes:
+                b.set_launch(*bshape)
+            bt.step(50, counter0=COUNTER_CONTINUE)
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            bt.step(300, counter0=COUNTER_CONTINUE)
+            torch.cuda.synchronize()
+            btimes[bshape] = time.perf_counter() - tq
+        bshape = min(btimes, key=btimes.get)
         for b in boxes:
             b.set_launch(*bshape)
-        bt = Batch(boxes)
-        bt.step(100, counter0=0)
+        log("batched tuning (s per 300 moves/box): %s" % {"%dx%d" % k: round(v, 4) for k, v in btimes.items()})
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         tb = time.perf_counter()
         e0.record(stream)
-        bst = bt.step(1000, counter0=100)
+        bst = bt.step(1000, counter0=COUNTER_CONTINUE)
         e1.record(stream)
         torch.cuda.synchronize()
         db = time.perf_counter() - tb

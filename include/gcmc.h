@@ -197,9 +197,14 @@ int gcmc_delta_energy_allpairs(gcmc_box* box, const gcmc_move* d_moves, int64_t 
  * unchanged); a deletion moves particle N-1 to the freed index. */
 int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair, void* stream);
 
-/* Launch shape of the move kernels: `waves` wavefronts per workgroup and
- * `rows` candidate slots per lane per pass (the autotuner's choice; the
- * supported pairs are 1x8, 2x8, 4x2, 4x4, 4x8, 8x2, 8x4). */
+/* Launch shape of the chain kernels (the autotuner's choice).  rows > 0: one
+ * move at a time, `waves` wavefronts per workgroup and `rows` candidate slots
+ * per lane per pass (1x8, 2x8, 4x2, 4x4, 4x8, 8x2, 8x4).  rows = 0:
+ * speculative rounds, `waves` (4, 8 or 16) consecutive moves evaluated at once,
+ * one per wavefront, against the round's starting state and committed in
+ * order, each only if nothing it read has changed since (the same chain, move
+ * for move); needs one species, at most 32 stencil cells and
+ * 2 x stencil cells x cell_cap <= 4096, else GCMC_ERR_UNSUPPORTED. */
 int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows);
 
 /* Run n_moves moves of the Markov chain of Algorithm 1 on the device in one

@@ -21,7 +21,14 @@ extern "C" {
 
 int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows) {
     if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
-    if (!chain_cfg_exists(waves, rows)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported waves x rows");
+    if (rows == 0) {
+        if (!spec_cfg_exists(waves)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported speculative width");
+        if (!spec_supported(box->d))
+            return set_error(GCMC_ERR_UNSUPPORTED, "speculative rounds need one species, <= 32 stencil cells "
+                                                   "and 2 x stencil x cell_cap <= 4096");
+    } else if (!chain_cfg_exists(waves, rows)) {
+        return set_error(GCMC_ERR_INVALID_ARG, "unsupported waves x rows");
+    }
     box->waves = waves;
     box->rows = rows;
     return GCMC_OK;
@@ -71,9 +78,14 @@ int gcmc_step(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_s
               void* stream) {
     if (!box || n_moves < 0) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
     if (box->d.ns != 1) return set_error(GCMC_ERR_UNSUPPORTED, "the chain supports one species");
-    if (launch_chain(box->d_desc, nullptr, 1, box->waves, box->rows, n_moves, counter0, d_stats, d_log,
-                     (hipStream_t)stream))
-        return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
+    int r;
+    if (box->rows == 0 && spec_supported(box->d))
+        r = launch_chain_spec(box->d_desc, nullptr, 1, box->waves, n_moves, counter0, d_stats, d_log,
+                              (hipStream_t)stream);
+    else
+        r = launch_chain(box->d_desc, nullptr, 1, box->waves, box->rows ? box->rows : 4, n_moves, counter0,
+                         d_stats, d_log, (hipStream_t)stream);
+    if (r) return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }
@@ -201,9 +213,16 @@ int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gc
         GCMC_HIP(hipStreamSynchronize(s));
     }
     const gcmc_box* b0 = bt->boxes[0];
-    if (launch_chain(bt->d_descs, bt->d_order, bt->n, b0->waves, b0->rows, moves_per_box, counter0, d_stats, nullptr,
-                     s))
-        return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
+    bool spec = b0->rows == 0;
+    for (int32_t q = 0; q < bt->n && spec; ++q) spec = spec_supported(bt->boxes[q]->d);
+    int r;
+    if (spec)
+        r = launch_chain_spec(bt->d_descs, bt->d_order, bt->n, b0->waves, moves_per_box, counter0, d_stats, nullptr,
+                              s);
+    else
+        r = launch_chain(bt->d_descs, bt->d_order, bt->n, b0->waves, b0->rows ? b0->rows : 4, moves_per_box,
+                         counter0, d_stats, nullptr, s);
+    if (r) return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }

@@ -75,44 +75,6 @@ __device__ __forceinline__ bool interior(const DevBox& B, const int32_t* c) {
     return ok;
 }
 
-// A register copy of the descriptor fields the chain uses (single species),
-// every field passed through readfirstlane so it stays in scalar registers.
-__device__ __forceinline__ DevBox hot_copy(const DevBox& G) {
-    DevBox B;
-    B.pos = unip(G.pos);
-    B.ent = unip(G.ent);
-    B.count = unip(G.count);
-    B.st = unip(G.st);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        B.L[a] = unid(G.L[a]);
-        B.hL[a] = unid(G.hL[a]);
-        B.invS[a] = unid(G.invS[a]);
-        B.M[a] = uni(G.M[a]);
-        B.span[a] = uni(G.span[a]);
-        B.k[a] = uni(G.k[a]);
-        B.full[a] = uni(G.full[a]);
-    }
-    B.cap = uni(G.cap);
-    B.ns = uni(G.ns);
-    B.ncells = uni64(G.ncells);
-    B.max_n = uni64(G.max_n);
-    B.rc2 = unid(G.rc2);
-    B.beta = unid(G.beta);
-    B.mu = unid(G.mu);
-    B.lambda3 = unid(G.lambda3);
-    B.max_disp = unid(G.max_disp);
-    B.p_disp = unid(G.p_disp);
-    B.V = unid(G.V);
-    B.eps4[0] = unid(G.eps4[0]);
-    B.sig2[0] = unid(G.sig2[0]);
-    B.tailK[0] = unid(G.tailK[0]);
-    B.seed = (uint64_t)uni64((int64_t)G.seed);
-    B.box_id = (uint32_t)uni((int32_t)G.box_id);
-    B.nstencil = uni(G.nstencil);
-    return B;
-}
-
 // Packed per-row slot description: k | t << 10 | which << 21 | valid << 22.
 constexpr int kSlotT = 10, kSlotW = 21, kSlotV = 22;
 

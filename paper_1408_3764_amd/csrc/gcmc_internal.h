@@ -289,6 +289,12 @@ int check_hip(hipError_t e, const char* what);
 int launch_chain(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int rows, int64_t n_moves,
                  uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 bool chain_cfg_exists(int waves, int rows);
+
+// spec.hip
+bool spec_supported(const DevBox& hb);
+bool spec_cfg_exists(int waves);
+int launch_chain_spec(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
+                      uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 int launch_delta(const DevBox* d_box, bool mix, int64_t n_moves, const gcmc_move* moves, double* dp, double* dt,
                  hipStream_t s);
 void launch_commit(const DevBox* d_box, const gcmc_move* move, const double* dU, hipStream_t s);

@@ -1,0 +1,561 @@
+// Speculative evaluation of consecutive moves of one chain, committed in order
+// (the exact chain of Algorithm 1; not the "keep the first accepted" scheme the
+// paper lists as future work, which would change the sampled distribution).
+//
+// A round takes the next W moves.  Wavefront w evaluates move m + w against
+// the state at the start of the round:
+//   * its Philox draws, type, pick (with the round's N) and trial positions;
+//   * the counters of its stencil cells (one lane per cell, both stencils of a
+//     displacement that leaves its cell: at most 64 cells), an in-wave prefix
+//     sum of the counters, an owner table in LDS mapping each flattened
+//     candidate to its cell, and then exactly the candidates' 32-byte records
+//     (one memory round trip for the counters, one for the records);
+//   * the pair sums, reduced across the wavefront, and ln A.
+// Wavefront 0 then walks the round's moves in order.  A move's evaluation is
+// used only if nothing it read has changed since the round started: its pick
+// recomputed with the current N is the one it evaluated, the particle record
+// it read was not touched by an earlier commit of the round, and no cell
+// modified by an earlier commit lies in one of its stencils.  Then the tail
+// correction and the acceptance prefactor are taken at the current N, the
+// Metropolis test is applied and an accepted move is committed (stores only;
+// the records it needs came back with its evaluation).  The first move that
+// fails the check ends the round and is evaluated again in the next one, so
+// every move is decided on exactly the state the sequential chain would have.
+#include "trial.h"
+
+namespace gcmc {
+
+constexpr int kSpecOwn = 4096;   // flattened candidates per wavefront (owner table bytes)
+
+struct SpecRec {
+    double dUp, lnA, u2, lpref;
+    double p0[3], p1[3];
+    double4 rec, rlast, elast;
+    int64_t idx;
+    int32_t type, flags, two, pad;
+    int32_t c0[3], c1[3];
+    int32_t cl0, cl1, cnt0, cnt1;
+    int32_t cand, evals, incut, pad2;
+};
+
+// Inclusive prefix sum over the wavefront's lanes (DPP row shifts, then the
+// row broadcasts of gfx9 carry each row's total into the next rows).
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_max_u(int32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int32_t o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int spec_type(const DevBox& B, const U8& u) {
+    return (u.u[0] < B.p_disp) ? GCMC_MOVE_DISPLACE : ((u.u[1] < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
+}
+
+__device__ __forceinline__ int64_t spec_pick(double u, int64_t n) {
+    int64_t i = (int64_t)floor(u * (double)n);
+    return i > n - 1 ? n - 1 : i;
+}
+
+__device__ __forceinline__ int32_t spec_axis_cell(double x, double invS, int32_t M) {
+    return __builtin_amdgcn_readfirstlane(axis_cell(x, invS, M));
+}
+
+// Is cell (x, y, z) inside the stencil of centre cell c?
+__device__ __forceinline__ bool in_stencil(const DevBox& B, int32_t x, int32_t y, int32_t z, const int32_t* c) {
+    const int32_t v[3] = {x, y, z};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int32_t d = v[a] - c[a];
+        d = d < 0 ? -d : d;
+        const int32_t e = B.M[a] - d;
+        d = e < d ? e : d;
+        in = in && (B.full[a] || d <= B.k[a]);
+    }
+    return in;
+}
+
+// One wavefront evaluates move ctr against the current state.
+template <int CR>
+__device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, const int32_t* offs, uint8_t* own,
+                                          uint64_t ctr, int64_t N, bool no_full, SpecRec* out) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const U8 u = move_uniforms_lanes(B.seed, ctr, B.box_id);
+    const int type = __builtin_amdgcn_readfirstlane(spec_type(B, u));
+    if (type != GCMC_MOVE_INSERT && N == 0) {
+        if (lane == 0) {
+            out->type = type;
+            out->flags = 1;
+            out->lnA = 0.0;
+            out->u2 = u.u[2];
+            out->cand = out->evals = out->incut = 0;
+        }
+        return;
+    }
+    int64_t idx = -1;
+    double4 rec = make_double4(0, 0, 0, 0), rlast = make_double4(0, 0, 0, 0);
+    double p0[3], p1[3];
+    if (type == GCMC_MOVE_INSERT) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p0[a] = wrap_into_box(B.L[a] * u.u[4 + a], B.L[a]);
+    } else {
+        idx = spec_pick(u.u[2], N);
+        rec = B.pos[idx];
+        if (type == GCMC_MOVE_DELETE) rlast = B.pos[N - 1];
+        p0[0] = rec.x; p0[1] = rec.y; p0[2] = rec.z;
+    }
+    int32_t c0[3], c1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c0[a] = spec_axis_cell(p0[a], B.invS[a], B.M[a]);
+    const int32_t cl0 = (c0[2] * B.M[1] + c0[1]) * B.M[0] + c0[0];
+    int32_t cl1 = cl0;
+    int same = 1;
+    if (type == GCMC_MOVE_DISPLACE) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p1[a] = wrap_into_box(p0[a] + B.max_disp * (2.0 * u.u[4 + a] - 1.0), B.L[a]);
+            c1[a] = spec_axis_cell(p1[a], B.invS[a], B.M[a]);
+        }
+        cl1 = (c1[2] * B.M[1] + c1[1]) * B.M[0] + c1[0];
+        same = __builtin_amdgcn_readfirstlane(cl1 == cl0 ? 1 : 0);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p1[a] = p0[a];
+            c1[a] = c0[a];
+        }
+    }
+    const int two = (type == GCMC_MOVE_DISPLACE && !same) ? 1 : 0;
+    const int nst = B.nstencil;
+    const int ncs = two ? 2 * nst : nst;
+    // ---- counters of the stencil cells, one lane per cell
+    const bool fast = __builtin_amdgcn_readfirstlane(
+                          (no_full && c0[0] >= B.k[0] && c0[0] <= B.M[0] - 1 - B.k[0] && c0[1] >= B.k[1] &&
+                           c0[1] <= B.M[1] - 1 - B.k[1] && c0[2] >= B.k[2] && c0[2] <= B.M[2] - 1 - B.k[2] &&
+                           (!two || (c1[0] >= B.k[0] && c1[0] <= B.M[0] - 1 - B.k[0] && c1[1] >= B.k[1] &&
+                                     c1[1] <= B.M[1] - 1 - B.k[1] && c1[2] >= B.k[2] &&
+                                     c1[2] <= B.M[2] - 1 - B.k[2])))
+                              ? 1
+                              : 0) != 0;
+    const int wh = lane >= nst ? 1 : 0;
+    const int t = lane - wh * nst;
+    const bool cell_lane = lane < ncs;
+    int32_t cell = cl0;
+    if (cell_lane) {
+        if (fast) {
+            cell = (wh ? cl1 : cl0) + offs[t];
+        } else {
+            cell = (int32_t)stencil_cell(B, tab[t], wh ? c1[0] : c0[0], wh ? c1[1] : c0[1], wh ? c1[2] : c0[2]);
+        }
+    }
+    const int32_t cnt = cell_lane ? B.count[cell] : 0;
+    const int32_t incl = wave_incl_scan(cnt);
+    const int32_t pre = incl - cnt;
+    const int32_t total = __builtin_amdgcn_readlane(incl, 63);
+    const int tc = ((B.full[2] ? c0[2] : B.k[2]) * B.span[1] + (B.full[1] ? c0[1] : B.k[1])) * B.span[0] +
+                   (B.full[0] ? c0[0] : B.k[0]);
+    const int tc1 = two ? nst + ((B.full[2] ? c1[2] : B.k[2]) * B.span[1] + (B.full[1] ? c1[1] : B.k[1])) * B.span[0] +
+                              (B.full[0] ? c1[0] : B.k[0])
+                        : tc;
+    const int32_t cnt0 = __builtin_amdgcn_readlane(cnt, tc);
+    const int32_t cnt1 = __builtin_amdgcn_readlane(cnt, tc1);
+    // ---- owner of each flattened candidate
+    const int kmax = wave_max_u(cnt);
+    for (int k = 0; k < kmax; ++k)
+        if (k < cnt) own[pre + k] = (uint8_t)lane;
+    const int32_t cellbase = cell * B.cap - pre;   // record index of flattened candidate q: q + cellbase[owner]
+    __builtin_amdgcn_wave_barrier();
+    // last entry of the old centre cell (removal by swap-with-last)
+    double4 elast = make_double4(0, 0, 0, 0);
+    if (cnt0 > 0) elast = B.ent[(size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)];
+    // ---- candidates
+    const int32_t excl = (int32_t)idx;
+    double sa = 0.0, sb = 0.0;
+    int32_t n_cand = 0, n_eval = 0, n_in = 0;
+    int64_t incut = 0;
+    for (int base = 0; base < total; base += kWave * CR) {
+        double4 e[CR];
+        int32_t wsel[CR];
+        bool ok[CR];
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            const int q = base + r * kWave + lane;
+            ok[r] = q < total;
+            const int j = ok[r] ? own[q] : 0;
+            const int32_t cb = __shfl(cellbase, j, kWave);
+            wsel[r] = j >= nst ? 1 : 0;
+            e[r] = B.ent[(size_t)(uint32_t)(ok[r] ? cb + q : cl0 * B.cap)];
+        }
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            if (ok[r] && meta_low(e[r].w) != excl) {
+                n_cand += 1;
+                if (type != GCMC_MOVE_DISPLACE) {
+                    sa += pair_energy_w<false>(B, p0, 0, e[r], incut);
+                    n_eval += 1;
+                } else if (!two) {
+                    sa += pair_energy_w<false>(B, p0, 0, e[r], incut);
+                    sb += pair_energy_w<false>(B, p1, 0, e[r], incut);
+                    n_eval += 2;
+                } else if (wsel[r]) {
+                    sb += pair_energy_w<false>(B, p1, 0, e[r], incut);
+                    n_eval += 1;
+                } else {
+                    sa += pair_energy_w<false>(B, p0, 0, e[r], incut);
+                    n_eval += 1;
+                }
+            }
+        }
+    }
+    n_in = (int32_t)incut;
+    const double ea = wave_sum_uniform(sa);
+    const double eb = (type == GCMC_MOVE_DISPLACE) ? wave_sum_uniform(sb) : 0.0;
+    const double dUp = (type == GCMC_MOVE_DISPLACE) ? (eb - ea) : ((type == GCMC_MOVE_INSERT) ? ea : -ea);
+    // work counters of this evaluation (wave sums)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        n_cand += __shfl_xor(n_cand, off, kWave);
+        n_eval += __shfl_xor(n_eval, off, kWave);
+        n_in += __shfl_xor(n_in, off, kWave);
+    }
+    const double lnA = log(u.u[3]);
+    double lpref = 0.0;
+    if (type == GCMC_MOVE_INSERT) lpref = log(B.V / (B.lambda3 * (double)(N + 1)));
+    else if (type == GCMC_MOVE_DELETE) lpref = log((B.lambda3 * (double)N) / B.V);
+    if (lane == 0) {
+        out->dUp = dUp;
+        out->lnA = lnA;
+        out->lpref = lpref;
+        out->u2 = u.u[2];
+        out->type = type;
+        out->flags = 0;
+        out->two = two;
+        out->idx = idx;
+        out->rec = rec;
+        out->rlast = rlast;
+        out->elast = elast;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            out->p0[a] = p0[a];
+            out->p1[a] = p1[a];
+            out->c0[a] = c0[a];
+            out->c1[a] = c1[a];
+        }
+        out->cl0 = cl0;
+        out->cl1 = cl1;
+        out->cnt0 = cnt0;
+        out->cnt1 = cnt1;
+        out->cand = n_cand;
+        out->evals = n_eval;
+        out->incut = n_in;
+    }
+}
+
+template <int W, int CR>
+__global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restrict__ boxes,
+                                                          const int32_t* __restrict__ order, int64_t n_moves,
+                                                          uint64_t ctr0, gcmc_stats* stats, gcmc_log* trace) {
+    __shared__ uint32_t tab[kMaxStencil];
+    __shared__ int32_t offs[64];
+    __shared__ SpecRec recs[W];
+    __shared__ uint8_t own[W][kSpecOwn];
+    __shared__ int64_t sh_state[4];       // N, moves done, error, error move
+    __shared__ double sh_u;
+    __shared__ int32_t sh_maxc;
+    const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const DevBox B = hot_copy(boxes[blockIdx.x]);
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    BoxState* st = B.st;
+
+    if (ctr0 == GCMC_COUNTER_CONTINUE) ctr0 = (uint64_t)st->counter;
+    int64_t N = st->n;
+    double U = st->u_pair;
+    int32_t maxc = st->maxcount;
+    int32_t err = st->error;
+    int64_t err_move = st->error_move;
+    const double tk = B.tailK[0];
+    const int cap = B.cap;
+    const bool no_full = !(B.full[0] | B.full[1] | B.full[2]);
+    // statistics (wavefront 0 keeps them)
+    // (per-type counters as separate scalars: a dynamically indexed array would live in scratch)
+    int64_t att0 = 0, att1 = 0, att2 = 0, acc0 = 0, acc1 = 0, acc2 = 0;
+    double sum_n = 0.0, sum_u = 0.0;
+    int64_t stencils = 0, cand = 0, evals = 0, incut = 0;
+    for (int t = tid; t < B.nstencil; t += blockDim.x) {
+        const int sx = B.span[0], sy = B.span[1];
+        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
+        tab[t] = (uint32_t)tx | ((uint32_t)ty << 10) | ((uint32_t)tz << 20);
+        if (t < 64) offs[t] = ((tz - B.k[2]) * B.M[1] + (ty - B.k[1])) * B.M[0] + (tx - B.k[0]);
+    }
+    __syncthreads();
+    if (err == GCMC_OK && B.ns != 1) {
+        err = GCMC_ERR_UNSUPPORTED;
+        err_move = (int64_t)ctr0;
+    }
+    int64_t m = 0;
+    while (err == GCMC_OK && m < n_moves) {
+        // ------------------------------------------------ evaluate W moves
+        if (m + wv < n_moves) spec_eval<CR>(B, tab, offs, own[wv], ctr0 + (uint64_t)(m + wv), N, no_full, &recs[wv]);
+        __syncthreads();
+        // ------------------------------------------------ in-order commit
+        if (wv == 0) {
+            const int64_t n_round = N;
+            int32_t modcell = -1, touched = -1;   // lane-held lists of this round
+            int nmod = 0, ntouch = 0;
+            int k = 0;
+            const int kend = (n_moves - m) < W ? (int)(n_moves - m) : W;
+            for (; k < kend; ++k) {
+                const SpecRec& R = recs[k];
+                const uint64_t ctr = ctr0 + (uint64_t)(m + k);
+                const int type = __builtin_amdgcn_readfirstlane(R.type);
+                // the empty-box rejection holds only while the box is still empty
+                if (R.flags & 1) {
+                    if (N != 0) break;
+                    att0 += type == 0; att1 += type == 1; att2 += type == 2;
+                    if (trace && lane == 0) {
+                        gcmc_log r;
+                        r.type = type; r.index = -1; r.accepted = 0; r.flags = 1;
+                        r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0;
+                        trace[(size_t)bi * n_moves + m + k] = r;
+                    }
+                    sum_u += U;
+                    continue;
+                }
+                const int64_t idx = R.idx;
+                if (type != GCMC_MOVE_INSERT) {
+                    if (N != n_round && spec_pick(R.u2, N) != idx) break;
+                    if (__ballot(lane < ntouch && touched == (int32_t)idx) != 0) break;
+                }
+                // a cell changed by an earlier commit of this round inside one of its stencils
+                int32_t cc[3] = {R.c0[0], R.c0[1], R.c0[2]};
+                int32_t cn[3] = {R.c1[0], R.c1[1], R.c1[2]};
+                bool hit = false;
+                if (lane < nmod) {
+                    const int32_t mx = modcell % B.M[0];
+                    const int32_t my = (modcell / B.M[0]) % B.M[1];
+                    const int32_t mz = modcell / (B.M[0] * B.M[1]);
+                    hit = in_stencil(B, mx, my, mz, cc) || (type == GCMC_MOVE_DISPLACE && in_stencil(B, mx, my, mz, cn));
+                }
+                if (__ballot(hit) != 0) break;
+                // ---- decide at the current N
+                const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
+                const double dUp = R.dUp;
+                const double dUt =
+                    is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
+                const double dU = dUp + dUt;
+                double lpref = R.lpref;
+                if (!is_disp && N != n_round)
+                    lpref = is_ins ? log(B.V / (B.lambda3 * (double)(N + 1))) : log((B.lambda3 * (double)N) / B.V);
+                const double arg = is_disp ? -(B.beta * dU)
+                                           : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
+                const bool ok = __builtin_amdgcn_readfirstlane((dU == dU && R.lnA < arg) ? 1 : 0) != 0;
+                const int two = R.two;
+                const int32_t cnt0 = R.cnt0, cnt1 = R.cnt1;
+                const int64_t n_old = N;
+                if (ok) {
+                    int e = GCMC_OK;
+                    if (is_ins) {
+                        if (N >= B.max_n) e = GCMC_ERR_CAPACITY;
+                        else if (cnt0 >= cap) e = GCMC_ERR_CELL_OVERFLOW;
+                    } else if (is_disp && two) {
+                        if (cnt1 >= cap) e = GCMC_ERR_CELL_OVERFLOW;
+                    }
+                    if (e != GCMC_OK) {
+                        err = e;
+                        err_move = (int64_t)ctr;
+                        break;
+                    }
+                    const int64_t loc = meta_low(R.rec.w);
+                    const int64_t c0 = R.cl0, c1 = R.cl1;
+                    const bool removes = (type == GCMC_MOVE_DELETE) || (is_disp && two);
+                    const int64_t last = c0 * cap + cnt0 - 1;
+                    const bool swap = removes && loc != last;
+                    const int32_t id_last = swap ? meta_low(R.elast.w) : -1;
+                    // the record of particle N-1 as of now (kept as scalars so that it stays in registers)
+                    double rlx = R.rlast.x, rly = R.rlast.y, rlz = R.rlast.z, rlw = R.rlast.w;
+                    if (type == GCMC_MOVE_DELETE && idx != N - 1) {
+                        const bool stale = (N != n_round) ||
+                                           (__ballot(lane < ntouch && touched == (int32_t)(N - 1)) != 0);
+                        if (stale) {
+                            // this wavefront's own earlier commit stores must have landed
+                            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+                            const double4 v = B.pos[N - 1];
+                            rlx = v.x; rly = v.y; rlz = v.z; rlw = v.w;
+                        }
+                    }
+                    if (lane == 0) {
+                        if (swap) {
+                            B.ent[loc] = R.elast;
+                            B.pos[id_last].w = pack_meta(meta_species(R.elast.w), (int32_t)loc);
+                        }
+                        if (removes) B.count[c0] = cnt0 - 1;
+                        if (is_disp) {
+                            if (!two) {
+                                B.ent[loc] = make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)idx));
+                                B.pos[idx] = make_double4(R.p1[0], R.p1[1], R.p1[2], R.rec.w);
+                            } else {
+                                const int64_t nl = c1 * cap + cnt1;
+                                B.ent[nl] = make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)idx));
+                                B.count[c1] = cnt1 + 1;
+                                B.pos[idx] = make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)nl));
+                            }
+                        } else if (is_ins) {
+                            const int64_t nl = c0 * cap + cnt0;
+                            B.ent[nl] = make_double4(R.p0[0], R.p0[1], R.p0[2], pack_meta(0, (int32_t)N));
+                            B.count[c0] = cnt0 + 1;
+                            B.pos[N] = make_double4(R.p0[0], R.p0[1], R.p0[2], pack_meta(0, (int32_t)nl));
+                        } else if (idx != N - 1) {
+                            if (id_last == (int32_t)(N - 1)) rlw = pack_meta(meta_species(rlw), (int32_t)loc);
+                            B.pos[idx] = make_double4(rlx, rly, rlz, rlw);
+                            B.ent[meta_low(rlw)].w = pack_meta(meta_species(rlw), (int32_t)idx);
+                        }
+                    }
+                    // what later moves of this round must not have read
+                    if (lane == nmod) modcell = (int32_t)c0;
+                    nmod += 1;
+                    if (is_disp && two) {
+                        if (lane == nmod) modcell = (int32_t)c1;
+                        nmod += 1;
+                    }
+                    if (lane == ntouch) touched = is_ins ? (int32_t)N : (int32_t)idx;
+                    ntouch += 1;
+                    if (swap) {
+                        if (lane == ntouch) touched = id_last;
+                        ntouch += 1;
+                    }
+                    if (type == GCMC_MOVE_DELETE) {
+                        if (lane == ntouch) touched = (int32_t)(N - 1);
+                        ntouch += 1;
+                    }
+                    if (is_disp && two && cnt1 + 1 > maxc) maxc = cnt1 + 1;
+                    if (is_ins && cnt0 + 1 > maxc) maxc = cnt0 + 1;
+                    acc0 += type == 0; acc1 += type == 1; acc2 += type == 2;
+                    N += is_ins ? 1 : (type == GCMC_MOVE_DELETE ? -1 : 0);
+                    U += dUp;
+                }
+                att0 += type == 0; att1 += type == 1; att2 += type == 2;
+                stencils += two ? 2 : 1;
+                cand += R.cand;
+                evals += R.evals;
+                incut += R.incut;
+                if (trace && lane == 0) {
+                    gcmc_log r;
+                    r.type = type;
+                    r.index = is_ins ? (int32_t)n_old : (int32_t)idx;
+                    r.accepted = ok ? 1 : 0;
+                    r.flags = 0;
+                    r.dU_pair = dUp;
+                    r.dU_tail = dUt;
+                    r.x = is_disp ? R.p1[0] : R.p0[0];
+                    r.y = is_disp ? R.p1[1] : R.p0[1];
+                    r.z = is_disp ? R.p1[2] : R.p0[2];
+                    r.arg = arg;
+                    trace[(size_t)bi * n_moves + m + k] = r;
+                }
+                sum_n += (double)N;
+                sum_u += U + tk * (double)N * (double)N;
+                if (nmod > kWave - 2 || ntouch > kWave - 3) {
+                    ++k;
+                    break;
+                }
+            }
+            if (lane == 0) {
+                sh_state[0] = N;
+                sh_state[1] = m + k;
+                sh_state[2] = err;
+                sh_state[3] = err_move;
+                sh_u = U;
+                sh_maxc = maxc;
+            }
+        }
+        __syncthreads();   // commit stores done and visible; the new state published
+        N = sh_state[0];
+        m = sh_state[1];
+        err = (int32_t)sh_state[2];
+        err_move = sh_state[3];
+        U = sh_u;
+        maxc = sh_maxc;
+    }
+    if (tid == 0) {
+        st->n = N;
+        st->u_pair = U;
+        st->maxcount = maxc;
+        st->nsp[0] = N;
+        st->counter = (int64_t)(ctr0 + (uint64_t)m);
+        if (err != GCMC_OK && st->error == GCMC_OK) {
+            st->error = err;
+            st->error_move = err_move;
+        }
+        if (stats) {
+            gcmc_stats o;
+            o.attempts[0] = att0; o.attempts[1] = att1; o.attempts[2] = att2;
+            o.accepts[0] = acc0; o.accepts[1] = acc1; o.accepts[2] = acc2;
+            o.n = N;
+            o.moves_done = m;
+            o.u_pair = U;
+            o.u_tail = tk * (double)N * (double)N;
+            o.sum_n = sum_n;
+            o.sum_u = sum_u;
+            o.error = st->error;
+            o.pad = 0;
+            o.error_move = st->error_move;
+            o.stencils = stencils;
+            o.candidates = cand;
+            o.pair_evals = evals;
+            o.in_cutoff = incut;
+            stats[bi] = o;
+        }
+    }
+}
+
+using spec_fn = void (*)(const DevBox*, const int32_t*, int64_t, uint64_t, gcmc_stats*, gcmc_log*);
+
+struct SpecCfg {
+    int w;
+    spec_fn f;
+};
+
+static const SpecCfg kSpecCfgs[] = {
+    {4, k_chain_spec<4, 8>}, {8, k_chain_spec<8, 8>}, {16, k_chain_spec<16, 4>},
+};
+
+// The speculative kernel handles one species, stencils of at most 32 cells
+// and at most kSpecOwn flattened candidates per move.
+bool spec_supported(const DevBox& hb) {
+    return hb.ns == 1 && hb.nstencil <= 32 && (int64_t)2 * hb.nstencil * hb.cap <= kSpecOwn &&
+           hb.ncells * (int64_t)hb.cap < ((int64_t)1 << 31);
+}
+
+bool spec_cfg_exists(int waves) {
+    for (const SpecCfg& c : kSpecCfgs)
+        if (c.w == waves) return true;
+    return false;
+}
+
+int launch_chain_spec(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
+                      uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s) {
+    for (const SpecCfg& c : kSpecCfgs) {
+        if (c.w == waves) {
+            hipLaunchKernelGGL(c.f, dim3(n_boxes), dim3(kWave * c.w), 0, s, d_boxes, d_order, n_moves, ctr0, stats,
+                               log);
+            return 0;
+        }
+    }
+    return -1;
+}
+
+}  // namespace gcmc

@@ -15,6 +15,10 @@ import os
 import time
 
 SHAPES = [(1, 8), (2, 8), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4)]
+# rows = 0: the speculative kernel, W consecutive moves evaluated at once and
+# committed in order (one species, stencils of at most 32 cells)
+SPEC_SHAPES = [(4, 0), (8, 0), (16, 0)]
+SPEC_OWN = 4096   # flattened candidates a speculative wavefront can hold
 CACHE_ENV = "GCMC_TUNE_CACHE"
 
 
@@ -29,8 +33,18 @@ def _slots(box):
     return nst * g
 
 
+def spec_supported(box):
+    info = box.info()
+    nst = info["span"][0] * info["span"][1] * info["span"][2]
+    return info["n_species"] == 1 and nst <= 32 and 2 * nst * info["cell_cap"] <= SPEC_OWN
+
+
 def chain_shape(box):
-    """Smallest shape whose one pass covers the two stencils of a cross-cell displacement."""
+    """The speculative kernel with eight wavefronts where it applies; otherwise
+    the smallest per-move shape whose one pass covers the two stencils of a
+    cross-cell displacement."""
+    if spec_supported(box):
+        return (8, 0)
     need = 2 * _slots(box)
     best = None
     for w, r in SHAPES:
@@ -55,6 +69,32 @@ def _cache_path():
     return os.environ.get(CACHE_ENV, "")
 
 
+def autotune_live(box, n_moves=3000, shapes=None):
+    """Time each launch shape on the box itself, continuing its chain (the
+    device move counter), and leave the fastest set.  Returns (shape, timings)."""
+    import torch
+    from ._lib import COUNTER_CONTINUE
+    if shapes is None:
+        shapes = SHAPES + (SPEC_SHAPES if spec_supported(box) else [])
+    timings = {}
+    best = None
+    for w, r in shapes:
+        box.set_launch(w, r)
+        box.step(300, counter0=COUNTER_CONTINUE)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, _ = box.step(n_moves, counter0=COUNTER_CONTINUE)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if int(st["error"]) != 0:
+            raise RuntimeError("chain error %d while tuning" % int(st["error"]))
+        timings["%dx%d" % (w, r)] = dt
+        if best is None or dt < best[0]:
+            best = (dt, (w, r))
+    box.set_launch(*best[1])
+    return best[1], timings
+
+
 def autotune_chain(make_box, n_moves=2000, shapes=SHAPES, key=None):
     """Time each launch shape on a fresh box from make_box() and return the fastest.
     Every shape runs the same chain (counter-based draws), so the comparison is
@@ -65,7 +105,7 @@ def autotune_chain(make_box, n_moves=2000, shapes=SHAPES, key=None):
         try:
             c = json.load(open(path))
             if key in c:
-                return tuple(c[key])
+                return tuple(c[key]), {}
         except (OSError, ValueError):
             pass
     best = None

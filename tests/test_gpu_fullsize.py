@@ -53,9 +53,10 @@ def _chain_check(wb, n_moves, shape=None):
     return b, k
 
 
-def test_large_chain_matches_oracle(large):
-    """N=262,144, rc=3.0: 300 moves in the tuned launch shape, bit-exact decisions."""
-    _, k = _chain_check(large, 300)
+@pytest.mark.parametrize("shape", [None, (4, 4), (16, 0)])
+def test_large_chain_matches_oracle(large, shape):
+    """N=262,144, rc=3.0: 300 moves, bit-exact decisions (per-move and speculative kernels)."""
+    _, k = _chain_check(large, 300, shape)
     assert k == 300
 
 
@@ -113,9 +114,10 @@ def test_large_total_energy_sampled(large):
     assert cell["U_tail"] == pytest.approx(oracle.tail_energy([large.n], p), rel=1e-13)
 
 
-def test_slab_chain_matches_oracle(slab):
-    """The 1.5M-particle slab in the tuned launch shape: 150 moves, bit-exact decisions."""
-    _, k = _chain_check(slab, 150)
+@pytest.mark.parametrize("shape", [None, (4, 4), (16, 0)])
+def test_slab_chain_matches_oracle(slab, shape):
+    """The 1.5M-particle slab: 150 moves, bit-exact decisions (per-move and speculative kernels)."""
+    _, k = _chain_check(slab, 150, shape)
     assert k == 150
 
 

@@ -168,7 +168,7 @@ def test_delta_energy_c1_and_small_cells(c1):
         assert np.allclose(gt, rt, rtol=1e-12)
 
 
-@pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (4, 8), (8, 4)])
+@pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (4, 8), (8, 4), (4, 0), (8, 0), (16, 0)])
 def test_chain_launch_shapes_agree(c1, waves, rows):
     """Every launch shape gives the oracle's chain (the tuner may pick any)."""
     p = _params(c1)
@@ -255,6 +255,37 @@ def test_chain_parity_c1(c1):
     U = b.total_energy()
     assert U["U_pair"] == pytest.approx(stats["u_pair"], rel=1e-9)
     assert acc[0] > 0 and acc[1] > 0 and acc[2] > 0
+
+
+@pytest.mark.parametrize("width", [8, 16])
+def test_speculative_chain_parity_c1(c1, width):
+    """Speculative rounds (W moves evaluated at once, committed in order) give the
+    sequential chain: 1,000 moves, same decisions and final configuration."""
+    p = _params(c1)
+    t0 = oracle.total_energy(c1.pos, p)
+    opos, oU, olog = oracle.chain(c1.pos, c1.n_moves, p, seed=c1.seed, max_n=c1.n + 1001,
+                                  U0=t0["U_pair"] + t0["U_tail"])
+    b = _box(c1, max_n=c1.n + 1001)
+    b.set_launch(width, 0)
+    b.total_energy()
+    stats, glog = b.step(c1.n_moves, counter0=0, log=True)
+    assert compare_chain_logs(glog, olog, c1.beta, "speculative C1") == c1.n_moves
+    assert np.array_equal(b.particles()[0], opos)
+    assert stats["u_pair"] + stats["u_tail"] == pytest.approx(oU, rel=1e-9)
+    cell_of, count, ids = b.cells()
+    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(opos, c1.L, c1.rc))
+
+
+def test_speculative_dense_conflicts():
+    """A small dense box where most rounds end early (spatial conflicts, N changes)."""
+    wb = workloads.random_box(300, 8.0, rc=2.5, T=1.2, mu=2.0, seed=77)
+    p = _params(wb)
+    _, _, olog = oracle.chain(wb.pos, 3000, p, seed=wb.seed, max_n=wb.n + 3001)
+    for width in (4, 16):
+        b = _box(wb, max_n=wb.n + 3001)
+        b.set_launch(width, 0)
+        _, glog = b.step(3000, counter0=0, log=True)
+        assert compare_chain_logs(glog, olog, wb.beta, "dense speculative") == 3000
 
 
 def test_chain_resume_split_equals_whole(c1):
@@ -425,12 +456,15 @@ def test_backward_single_species(c1):
 
 
 # ------------------------------------------------------------------ batch
-def test_batch_matches_single_boxes():
+@pytest.mark.parametrize("shape", [(2, 8), (8, 0)])
+def test_batch_matches_single_boxes(shape):
     from paper_1408_3764_amd.box import Batch, Box
     sizes = [130, 400, 900, 260, 1500]
     wbs = [workloads.cubic_box(n, rho, T, 2.5, 500 + k) for k, (n, rho, T) in
            enumerate(zip(sizes, [0.3, 0.5, 0.8, 0.6, 0.4], [0.9, 1.2, 1.5, 1.0, 1.1]))]
     boxes = [Box.from_workload(w, max_n=w.n + 301, box_id=k, seed=99) for k, w in enumerate(wbs)]
+    for b in boxes:
+        b.set_launch(*shape)
     bt = Batch(boxes)
     stats = bt.step(300, counter0=0)
     for k, w in enumerate(wbs):
