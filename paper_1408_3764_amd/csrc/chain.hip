@@ -47,8 +47,8 @@ __device__ __forceinline__ void head_of(const DevBox& B, uint64_t ctr, int64_t n
     H.idx = -1;
     if (H.type != GCMC_MOVE_INSERT && n > 0) {
         H.idx = pick_index(H.u, n);
-        H.rec = B.pos[H.idx];
-        if (H.type == GCMC_MOVE_DELETE) H.rlast = B.pos[n - 1];
+        H.rec = gload(B.pos + H.idx);
+        if (H.type == GCMC_MOVE_DELETE) H.rlast = gload(B.pos + (n - 1));
     }
 }
 
@@ -236,8 +236,8 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                     }
                     if (!in) c = cl0;
                     const int kc = k < cap ? k : cap - 1;
-                    cnt[r] = in ? B.count[c] : 0;
-                    e[r] = B.ent[(size_t)(uint32_t)c * (uint32_t)cap + kc];
+                    cnt[r] = in ? gload(B.count + c) : 0;
+                    e[r] = gload(B.ent + ((size_t)(uint32_t)c * (uint32_t)cap + kc));
                     kk[r] = k;
                     tt[r] = in ? t : -1;
                     which[r] = w;
@@ -348,31 +348,31 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 const int32_t id_last = swap ? meta_low(elast.w) : -1;
                 if (tid == 0) {
                     if (swap) {
-                        B.ent[loc] = elast;
-                        B.pos[id_last].w = pack_meta(meta_species(elast.w), (int32_t)loc);
+                        gstore(B.ent + loc, elast);
+                        gstore_w(B.pos + id_last, pack_meta(meta_species(elast.w), (int32_t)loc));
                     }
-                    if (removes) B.count[c0] = cnt0 - 1;
+                    if (removes) gstore(B.count + c0, cnt0 - 1);
                     if (T.type == GCMC_MOVE_DISPLACE) {
                         if (!two) {
-                            B.ent[loc] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)T.idx));
-                            B.pos[T.idx] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], T.meta);
+                            gstore(B.ent + loc, make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)T.idx)));
+                            gstore(B.pos + T.idx, make_double4(T.p[1][0], T.p[1][1], T.p[1][2], T.meta));
                         } else {
                             const int64_t nl = c1 * cap + cnt1;
-                            B.ent[nl] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)T.idx));
-                            B.count[c1] = cnt1 + 1;
-                            B.pos[T.idx] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)nl));
+                            gstore(B.ent + nl, make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)T.idx)));
+                            gstore(B.count + c1, cnt1 + 1);
+                            gstore(B.pos + T.idx, make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(0, (int32_t)nl)));
                         }
                     } else if (T.type == GCMC_MOVE_INSERT) {
                         const int64_t nl = c0 * cap + cnt0;
-                        B.ent[nl] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(0, (int32_t)N));
-                        B.count[c0] = cnt0 + 1;
-                        B.pos[N] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(0, (int32_t)nl));
+                        gstore(B.ent + nl, make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(0, (int32_t)N)));
+                        gstore(B.count + c0, cnt0 + 1);
+                        gstore(B.pos + N, make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(0, (int32_t)nl)));
                     } else if (T.idx != N - 1) {
                         // particle N-1 takes index idx
                         double4 r = H.rlast;
                         if (id_last == (int32_t)(N - 1)) r.w = pack_meta(meta_species(r.w), (int32_t)loc);
-                        B.pos[T.idx] = r;
-                        B.ent[meta_low(r.w)].w = pack_meta(meta_species(r.w), (int32_t)T.idx);
+                        gstore(B.pos + T.idx, r);
+                        gstore_w(B.ent + (meta_low(r.w)), pack_meta(meta_species(r.w), (int32_t)T.idx));
                     }
                 }
                 if (T.type == GCMC_MOVE_DISPLACE && two && cnt1 + 1 > maxc) maxc = cnt1 + 1;
@@ -405,11 +405,11 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                     const int64_t i2 = pick_index(Hn.u, N);
                     if (N != n_old || Hn.idx < 0 || i2 != Hn.idx || i2 == touched0 || i2 == touched1) {
                         Hn.idx = i2;
-                        Hn.rec = B.pos[i2];
+                        Hn.rec = gload(B.pos + i2);
                     }
                     if (Hn.type == GCMC_MOVE_DELETE &&
                         (N != n_old || N - 1 == touched0 || N - 1 == touched1))
-                        Hn.rlast = B.pos[N - 1];
+                        Hn.rlast = gload(B.pos + (N - 1));
                 } else {
                     Hn.idx = -1;
                 }

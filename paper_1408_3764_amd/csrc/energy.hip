@@ -61,9 +61,9 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
     const int k = threadIdx.x & (G - 1);
     double ei = 0.0;
     if (c < B.ncells) {
-        const int32_t cnt = B.count[c];
+        const int32_t cnt = gload(B.count + c);
         const bool own = k < cnt;
-        const double4 me = B.ent[c * B.cap + (own ? k : 0)];
+        const double4 me = gload(B.ent + (c * B.cap + (own ? k : 0)));
         const int32_t myid = own ? meta_low(me.w) : -1;
         const int sa = meta_species(me.w);
         int32_t cx, cy, cz;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
         if (cnt > 0) {
             for (int t = 0; t < B.nstencil; ++t) {
                 const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
-                const int32_t nc = B.count[nb];
+                const int32_t nc = gload(B.count + nb);
                 const double4* ne = B.ent + nb * B.cap;
                 for (int j = 0; j < nc; ++j) {
                     const double4 o = ne[j];
@@ -103,13 +103,13 @@ __global__ __launch_bounds__(kBlk) void k_total_allpairs(const DevBox* __restric
     const int64_t n = B.st->n;
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const bool own = i < n;
-    const double4 me = B.pos[own ? i : 0];
+    const double4 me = gload(B.pos + (own ? i : 0));
     const int sa = meta_species(me.w);
     double ei = 0.0;
     for (int64_t j0 = 0; j0 < n; j0 += kBlk) {
         const int64_t j = j0 + threadIdx.x;
         __syncthreads();
-        tile[threadIdx.x] = B.pos[j < n ? j : 0];
+        tile[threadIdx.x] = gload(B.pos + (j < n ? j : 0));
         __syncthreads();
         const int lim = (n - j0) < kBlk ? (int)(n - j0) : kBlk;
         for (int q = 0; q < lim; ++q) {
@@ -166,7 +166,7 @@ __device__ __forceinline__ void ap_chunk_sums(const DevBox& B, const APTrial& T,
     sb = 0.0;
     for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
         if (j == T.idx) continue;
-        const double4 o = B.pos[j];
+        const double4 o = gload(B.pos + j);
         int q = 0;
         if (mix) q = T.sp * B.ns + meta_species(o.w);
         const double r2a = dist2(B, T.p[0][0], T.p[0][1], T.p[0][2], o.x, o.y, o.z);
@@ -196,7 +196,7 @@ __device__ __forceinline__ APTrial ap_trial_from_move(const DevBox& B, const gcm
         return T;
     }
     T.idx = mv.index;
-    const double4 pi = B.pos[T.idx];
+    const double4 pi = gload(B.pos + T.idx);
     T.sp = meta_species(pi.w);
     T.p[0][0] = pi.x; T.p[0][1] = pi.y; T.p[0][2] = pi.z;
     if (mv.type == GCMC_MOVE_DISPLACE) {
@@ -293,7 +293,7 @@ __device__ __forceinline__ APTrial ap_trial_from_draws(const DevBox& B, const U8
     int64_t i = (int64_t)floor(u.u[2] * (double)n);
     if (i > n - 1) i = n - 1;
     T.idx = i;
-    const double4 pi = B.pos[i];
+    const double4 pi = gload(B.pos + i);
     T.p[0][0] = pi.x; T.p[0][1] = pi.y; T.p[0][2] = pi.z;
     if (T.type == GCMC_MOVE_DISPLACE) {
         T.npos = 2;
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kBlk) void k_ap_chain_decide(const DevBox* __restri
         ch->pair_evals += others * T.npos;
         if (ok) {
             int32_t mc = st->maxcount;
-            const double4 rec = (T.idx >= 0) ? B.pos[T.idx] : make_double4(0, 0, 0, 0);
+            const double4 rec = (T.idx >= 0) ? gload(B.pos + T.idx) : make_double4(0, 0, 0, 0);
             const int e = commit_ap(B, T, rec, n, mc);
             if (e != GCMC_OK) {
                 ch->att[T.type] -= 1;
@@ -454,51 +454,51 @@ __device__ int commit_ap(const DevBox& B, const APTrial& T, const double4& rec, 
         return ((int64_t)cz * B.M[1] + cy) * B.M[0] + cx;
     };
     auto remove = [&](int64_t c, int64_t loc) {
-        const int32_t nc = B.count[c];
+        const int32_t nc = gload(B.count + c);
         const int64_t last = c * cap + nc - 1;
         if (loc != last) {
-            const double4 e = B.ent[last];
-            B.ent[loc] = e;
-            B.pos[meta_low(e.w)].w = pack_meta(meta_species(e.w), (int32_t)loc);
+            const double4 e = gload(B.ent + last);
+            gstore(B.ent + loc, e);
+            gstore_w(B.pos + (meta_low(e.w)), pack_meta(meta_species(e.w), (int32_t)loc));
         }
-        B.count[c] = nc - 1;
+        gstore(B.count + c, nc - 1);
     };
     if (T.type == GCMC_MOVE_DISPLACE) {
         const int64_t c0 = cell_of(T.p[0]), c1 = cell_of(T.p[1]);
         const int64_t loc = meta_low(rec.w);
         if (c0 == c1) {
-            B.ent[loc] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)T.idx));
-            B.pos[T.idx] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], rec.w);
+            gstore(B.ent + loc, make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)T.idx)));
+            gstore(B.pos + T.idx, make_double4(T.p[1][0], T.p[1][1], T.p[1][2], rec.w));
             return GCMC_OK;
         }
-        const int32_t nc = B.count[c1];
+        const int32_t nc = gload(B.count + c1);
         if (nc >= cap) return GCMC_ERR_CELL_OVERFLOW;
         remove(c0, loc);
         const int64_t nl = c1 * cap + nc;
-        B.ent[nl] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)T.idx));
-        B.count[c1] = nc + 1;
-        B.pos[T.idx] = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)nl));
+        gstore(B.ent + nl, make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)T.idx)));
+        gstore(B.count + c1, nc + 1);
+        gstore(B.pos + T.idx, make_double4(T.p[1][0], T.p[1][1], T.p[1][2], pack_meta(T.sp, (int32_t)nl)));
         if (nc + 1 > maxc) maxc = nc + 1;
         return GCMC_OK;
     }
     if (T.type == GCMC_MOVE_INSERT) {
         if (n >= B.max_n) return GCMC_ERR_CAPACITY;
         const int64_t c0 = cell_of(T.p[0]);
-        const int32_t nc = B.count[c0];
+        const int32_t nc = gload(B.count + c0);
         if (nc >= cap) return GCMC_ERR_CELL_OVERFLOW;
         const int64_t nl = c0 * cap + nc;
-        B.ent[nl] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)n));
-        B.count[c0] = nc + 1;
-        B.pos[n] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)nl));
+        gstore(B.ent + nl, make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)n)));
+        gstore(B.count + c0, nc + 1);
+        gstore(B.pos + n, make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)nl)));
         if (nc + 1 > maxc) maxc = nc + 1;
         return GCMC_OK;
     }
     const int64_t c0 = cell_of(T.p[0]);
     remove(c0, meta_low(rec.w));
     if (T.idx != n - 1) {
-        const double4 last = B.pos[n - 1];
-        B.pos[T.idx] = last;
-        B.ent[meta_low(last.w)].w = pack_meta(meta_species(last.w), (int32_t)T.idx);
+        const double4 last = gload(B.pos + (n - 1));
+        gstore(B.pos + T.idx, last);
+        gstore_w(B.ent + (meta_low(last.w)), pack_meta(meta_species(last.w), (int32_t)T.idx));
     }
     return GCMC_OK;
 }
@@ -527,9 +527,9 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
     bool own = false;
     int32_t myid = -1;
     if (c < B.ncells) {
-        const int32_t cnt = B.count[c];
+        const int32_t cnt = gload(B.count + c);
         own = k < cnt;
-        const double4 me = B.ent[c * B.cap + (own ? k : 0)];
+        const double4 me = gload(B.ent + (c * B.cap + (own ? k : 0)));
         myid = own ? meta_low(me.w) : -1;
         sa = meta_species(me.w);
         int32_t cx, cy, cz;
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
         if (cnt > 0) {
             for (int t = 0; t < B.nstencil; ++t) {
                 const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
-                const int32_t nc = B.count[nb];
+                const int32_t nc = gload(B.count + nb);
                 const double4* ne = B.ent + nb * B.cap;
                 for (int j = 0; j < nc; ++j) {
                     const double4 o = ne[j];

@@ -76,6 +76,28 @@ __device__ __forceinline__ T* unip(T* p) {
     return (T*)(uintptr_t)uni64((int64_t)(uintptr_t)p);
 }
 
+// Accesses through the box's arrays as global-memory (address space 1)
+// operations.  The pointers reach the kernels inside a descriptor, so the
+// compiler would otherwise issue flat_* accesses, and a flat access also
+// counts against the LDS wait counter: every LDS wait after it would wait for
+// the memory operation as well.
+typedef double gcmc_d4v __attribute__((ext_vector_type(4)));
+#define GCMC_GLOBAL_AS __attribute__((address_space(1)))
+
+__device__ __forceinline__ double4 gload(const double4* p) {
+    const gcmc_d4v v = *(const GCMC_GLOBAL_AS gcmc_d4v*)p;
+    return make_double4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore(double4* p, const double4& v) {
+    const gcmc_d4v w = {v.x, v.y, v.z, v.w};
+    *(GCMC_GLOBAL_AS gcmc_d4v*)p = w;
+}
+__device__ __forceinline__ void gstore_w(double4* p, double w) {   // the fourth component only
+    *((GCMC_GLOBAL_AS double*)p + 3) = w;
+}
+__device__ __forceinline__ int32_t gload(const int32_t* p) { return *(const GCMC_GLOBAL_AS int32_t*)p; }
+__device__ __forceinline__ void gstore(int32_t* p, int32_t v) { *(GCMC_GLOBAL_AS int32_t*)p = v; }
+
 // ------------------------------------------------------------------ packing
 __host__ __device__ __forceinline__ double pack_meta(int32_t species, int32_t low) {
     uint64_t v = ((uint64_t)(uint32_t)species << 32) | (uint64_t)(uint32_t)low;
@@ -225,6 +247,37 @@ __device__ __forceinline__ double wave_sum_uniform(double v) {
     v += dpp_move<0x124>(v);   // row_ror:4
     v += dpp_move<0x128>(v);   // row_ror:8
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Integer sum and maximum over the wavefront with the same DPP pattern,
+// returned identically to every lane (no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_i32(int32_t v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ int32_t wave_sum_i32_uniform(int32_t v) {
+    v += dpp_i32<0xB1>(v);
+    v += dpp_i32<0x4E>(v);
+    v += dpp_i32<0x124>(v);
+    v += dpp_i32<0x128>(v);
+    return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+           (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+}
+
+__device__ __forceinline__ int32_t wave_max_i32_uniform(int32_t v) {
+    int32_t o = dpp_i32<0xB1>(v);
+    v = o > v ? o : v;
+    o = dpp_i32<0x4E>(v);
+    v = o > v ? o : v;
+    o = dpp_i32<0x124>(v);
+    v = o > v ? o : v;
+    o = dpp_i32<0x128>(v);
+    v = o > v ? o : v;
+    const int32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const int32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    const int32_t ab = a > b ? a : b, cd = c > d ? c : d;
+    return ab > cd ? ab : cd;
 }
 
 __device__ __forceinline__ int32_t wave_max_i(int32_t v) {

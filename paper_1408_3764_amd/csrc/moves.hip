@@ -99,8 +99,8 @@ __global__ __launch_bounds__(256) void k_neighbors(const DevBox* __restrict__ bo
         for (int s = threadIdx.x; s < NS; s += blockDim.x) {
             const int t = s >> lg, k = s & gmask;
             const int64_t c = stencil_cell(B, tab[t], T.c[0][0], T.c[0][1], T.c[0][2]);
-            if (k < B.count[c] && k < B.cap) {
-                const int32_t id = meta_low(B.ent[c * B.cap + k].w);
+            if (k < gload(B.count + c) && k < B.cap) {
+                const int32_t id = meta_low(gload(B.ent + (c * B.cap + k)).w);
                 if (id != ex) {
                     const int32_t at = atomicAdd(&fill, 1);
                     if (at < max_ids) ids[m * max_ids + at] = id;

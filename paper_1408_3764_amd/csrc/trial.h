@@ -109,8 +109,8 @@ __device__ __forceinline__ void eval_trial(const DevBox& B, const uint32_t* tab,
             const int32_t cz = w ? T.c[1][2] : T.c[0][2];
             const int64_t c = stencil_cell(B, tab[t], cx, cy, cz);
             const int kc = k < B.cap ? k : B.cap - 1;
-            cnt[r] = in ? B.count[c] : 0;
-            e[r] = B.ent[c * B.cap + kc];
+            cnt[r] = in ? gload(B.count + c) : 0;
+            e[r] = gload(B.ent + (c * B.cap + kc));
             kk[r] = k;
             which[r] = w;
         }
@@ -162,14 +162,14 @@ __device__ __forceinline__ void eval_trial(const DevBox& B, const uint32_t* tab,
 // Remove the entry at `loc` of cell `c`: the cell's last entry takes its place
 // (Sec. 3.2.5) and that particle's back-pointer follows.
 __device__ __forceinline__ void remove_entry(const DevBox& B, int64_t c, int64_t loc) {
-    const int32_t nc = B.count[c];
+    const int32_t nc = gload(B.count + c);
     const int64_t last = c * B.cap + nc - 1;
     if (loc != last) {
-        const double4 e = B.ent[last];
-        B.ent[loc] = e;
-        B.pos[meta_low(e.w)].w = pack_meta(meta_species(e.w), (int32_t)loc);
+        const double4 e = gload(B.ent + last);
+        gstore(B.ent + loc, e);
+        gstore_w(B.pos + (meta_low(e.w)), pack_meta(meta_species(e.w), (int32_t)loc));
     }
-    B.count[c] = nc - 1;
+    gstore(B.count + c, nc - 1);
 }
 
 // Apply an accepted trial (one thread).  Returns GCMC_OK, or an error with
@@ -180,28 +180,28 @@ __device__ int commit_trial(const DevBox& B, const Trial& T, int64_t n, int32_t&
         const int64_t loc = meta_low(T.meta);
         const double4 np = make_double4(T.p[1][0], T.p[1][1], T.p[1][2], 0.0);
         if (T.same) {
-            B.ent[loc] = make_double4(np.x, np.y, np.z, pack_meta(T.sp, (int32_t)T.idx));
-            B.pos[T.idx] = make_double4(np.x, np.y, np.z, T.meta);
+            gstore(B.ent + loc, make_double4(np.x, np.y, np.z, pack_meta(T.sp, (int32_t)T.idx)));
+            gstore(B.pos + T.idx, make_double4(np.x, np.y, np.z, T.meta));
             return GCMC_OK;
         }
-        const int32_t nc = B.count[T.cl[1]];
+        const int32_t nc = gload(B.count + (T.cl[1]));
         if (nc >= cap) return GCMC_ERR_CELL_OVERFLOW;
         remove_entry(B, T.cl[0], loc);
         const int64_t nl = T.cl[1] * cap + nc;
-        B.ent[nl] = make_double4(np.x, np.y, np.z, pack_meta(T.sp, (int32_t)T.idx));
-        B.count[T.cl[1]] = nc + 1;
-        B.pos[T.idx] = make_double4(np.x, np.y, np.z, pack_meta(T.sp, (int32_t)nl));
+        gstore(B.ent + nl, make_double4(np.x, np.y, np.z, pack_meta(T.sp, (int32_t)T.idx)));
+        gstore(B.count + (T.cl[1]), nc + 1);
+        gstore(B.pos + T.idx, make_double4(np.x, np.y, np.z, pack_meta(T.sp, (int32_t)nl)));
         if (nc + 1 > maxc) maxc = nc + 1;
         return GCMC_OK;
     }
     if (T.type == GCMC_MOVE_INSERT) {
         if (n >= B.max_n) return GCMC_ERR_CAPACITY;
-        const int32_t nc = B.count[T.cl[0]];
+        const int32_t nc = gload(B.count + (T.cl[0]));
         if (nc >= cap) return GCMC_ERR_CELL_OVERFLOW;
         const int64_t nl = T.cl[0] * cap + nc;
-        B.ent[nl] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)n));
-        B.count[T.cl[0]] = nc + 1;
-        B.pos[n] = make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)nl));
+        gstore(B.ent + nl, make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)n)));
+        gstore(B.count + (T.cl[0]), nc + 1);
+        gstore(B.pos + n, make_double4(T.p[0][0], T.p[0][1], T.p[0][2], pack_meta(T.sp, (int32_t)nl)));
         if (nc + 1 > maxc) maxc = nc + 1;
         return GCMC_OK;
     }
@@ -209,10 +209,10 @@ __device__ int commit_trial(const DevBox& B, const Trial& T, int64_t n, int32_t&
     const int64_t loc = meta_low(T.meta);
     remove_entry(B, T.cl[0], loc);
     if (T.idx != n - 1) {
-        const double4 last = B.pos[n - 1];
-        B.pos[T.idx] = last;
+        const double4 last = gload(B.pos + (n - 1));
+        gstore(B.pos + T.idx, last);
         const int64_t l2 = meta_low(last.w);
-        B.ent[l2].w = pack_meta(meta_species(last.w), (int32_t)T.idx);
+        gstore_w(B.ent + l2, pack_meta(meta_species(last.w), (int32_t)T.idx));
     }
     return GCMC_OK;
 }
@@ -236,7 +236,7 @@ __device__ __forceinline__ bool trial_from_move(const DevBox& B, const gcmc_move
     if (mv.type != GCMC_MOVE_DISPLACE && mv.type != GCMC_MOVE_DELETE) return false;
     if (mv.index < 0 || mv.index >= n) return false;
     T.idx = mv.index;
-    const double4 pi = B.pos[T.idx];
+    const double4 pi = gload(B.pos + T.idx);
     T.meta = pi.w;
     T.sp = meta_species(pi.w);
     T.p[0][0] = pi.x; T.p[0][1] = pi.y; T.p[0][2] = pi.z;
