@@ -4,7 +4,11 @@
 //
 // A round takes the next W moves.  Wavefront w evaluates move m + w against
 // the state at the start of the round:
-//   * its Philox draws, type, pick (with the round's N) and trial positions;
+//   * its Philox draws, type and trial positions.  A displacement or deletion
+//     picks floor(u N), which moves with N: the wavefront also computes the
+//     draws of the earlier moves of the round, so it knows how many insertions
+//     and deletions precede its move, and evaluates the pick at the N expected
+//     at its commit from the chain's running acceptance rates;
 //   * the counters of its stencil cells (one lane per cell, both stencils of a
 //     displacement that leaves its cell: at most 64 cells), an in-wave prefix
 //     sum of the counters, an owner table in LDS mapping each flattened
@@ -13,12 +17,16 @@
 //   * the pair sums, reduced across the wavefront, and ln A.
 // Wavefront 0 then walks the round's moves in order.  A move's evaluation is
 // used only if nothing it read has changed since the round started: its pick
-// recomputed with the current N is the one it evaluated, the particle record
+// at the current N is the one it evaluated, the particle record
 // it read was not touched by an earlier commit of the round, and no cell
 // modified by an earlier commit lies in one of its stencils.  Then the tail
 // correction and the acceptance prefactor are taken at the current N, the
 // Metropolis test is applied and an accepted move is committed (stores only;
-// the records it needs came back with its evaluation).  The first move that
+// the records it needs came back with its evaluation).  N moves by at most one
+// per move, so the records of particles N_round - W .. N_round + W - 1 (what a
+// deletion moves into the freed index) and the prefactors for those N are
+// prepared in LDS at the start of the round, in parallel with the evaluations,
+// and kept current by the commits.  The first move that
 // fails the check ends the round and is evaluated again in the next one, so
 // every move is decided on exactly the state the sequential chain would have.
 #include "trial.h"
@@ -28,9 +36,9 @@ namespace gcmc {
 constexpr int kSpecOwn = 4096;   // flattened candidates per wavefront (owner table bytes)
 
 struct SpecRec {
-    double dUp, lnA, u2, lpref;
+    double dUp, lnA, u2, pad0;
     double p0[3], p1[3];
-    double4 rec, rlast, elast;
+    double4 rec, elast;
     int64_t idx;
     int32_t type, flags, two, pad;
     int32_t c0[3], c1[3];
@@ -48,15 +56,6 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
     v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
     v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
     return v;
-}
-
-__device__ __forceinline__ int32_t wave_max_u(int32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const int32_t o = __shfl_xor(v, off, kWave);
-        v = o > v ? o : v;
-    }
-    return __builtin_amdgcn_readfirstlane(v);
 }
 
 __device__ __forceinline__ int spec_type(const DevBox& B, const U8& u) {
@@ -87,13 +86,34 @@ __device__ __forceinline__ bool in_stencil(const DevBox& B, int32_t x, int32_t y
     return in;
 }
 
-// One wavefront evaluates move ctr against the current state.
+// Wavefront k evaluates move ctr_round + k against the current state.
 template <int CR>
 __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, const int32_t* offs, uint8_t* own,
-                                          uint64_t ctr, int64_t N, bool no_full, SpecRec* out) {
+                                          uint64_t ctr_round, int k, int64_t N, bool no_full, double a_ins,
+                                          double a_del, SpecRec* out) {
     const int lane = threadIdx.x & (kWave - 1);
-    const U8 u = move_uniforms_lanes(B.seed, ctr, B.box_id);
+    // draws of the round's moves: lane 4j + b computes Philox block b of move ctr_round + j
+    double ua, ub;
+    {
+        const uint64_t c = ctr_round + (uint64_t)(lane >> 2);
+        uint32_t c0 = (uint32_t)c, c1 = (uint32_t)(c >> 32), c2 = B.box_id, c3 = (uint32_t)(lane & 3);
+        philox_block(c0, c1, c2, c3, (uint32_t)B.seed, (uint32_t)(B.seed >> 32));
+        ua = to_unit(c0, c1);
+        ub = to_unit(c2, c3);
+    }
+    U8 u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        u.u[2 * q] = read_lane(ua, 4 * k + q);
+        u.u[2 * q + 1] = read_lane(ub, 4 * k + q);
+    }
     const int type = __builtin_amdgcn_readfirstlane(spec_type(B, u));
+    // insertions (I) and deletions (D) among the earlier moves of the round: N at this
+    // move's commit lies in [N - D, N + I]
+    const int tj = (ua < B.p_disp) ? GCMC_MOVE_DISPLACE : ((ub < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
+    const bool earlier = (lane & 3) == 0 && (lane >> 2) < k;
+    const int64_t D = __popcll(__ballot(earlier && tj == GCMC_MOVE_DELETE));
+    const int64_t I = __popcll(__ballot(earlier && tj == GCMC_MOVE_INSERT));
     if (type != GCMC_MOVE_INSERT && N == 0) {
         if (lane == 0) {
             out->type = type;
@@ -105,15 +125,18 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
         return;
     }
     int64_t idx = -1;
-    double4 rec = make_double4(0, 0, 0, 0), rlast = make_double4(0, 0, 0, 0);
+    double4 rec = make_double4(0, 0, 0, 0);
     double p0[3], p1[3];
     if (type == GCMC_MOVE_INSERT) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) p0[a] = wrap_into_box(B.L[a] * u.u[4 + a], B.L[a]);
     } else {
-        idx = spec_pick(u.u[2], N);
-        rec = B.pos[idx];
-        if (type == GCMC_MOVE_DELETE) rlast = B.pos[N - 1];
+        // the pick at the N expected at commit from the running acceptance rates
+        const int64_t n_lo = (N - D) > 1 ? (N - D) : 1, n_hi = N + I;
+        int64_t n_c = (int64_t)floor((double)N + (double)I * a_ins - (double)D * a_del + 0.5);
+        n_c = uni64(n_c < n_lo ? n_lo : (n_c > n_hi ? n_hi : n_c));
+        idx = spec_pick(u.u[2], n_c);
+        rec = gload(B.pos + idx);
         p0[0] = rec.x; p0[1] = rec.y; p0[2] = rec.z;
     }
     int32_t c0[3], c1[3];
@@ -160,7 +183,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
             cell = (int32_t)stencil_cell(B, tab[t], wh ? c1[0] : c0[0], wh ? c1[1] : c0[1], wh ? c1[2] : c0[2]);
         }
     }
-    const int32_t cnt = cell_lane ? B.count[cell] : 0;
+    const int32_t cnt = cell_lane ? gload(B.count + cell) : 0;
     const int32_t incl = wave_incl_scan(cnt);
     const int32_t pre = incl - cnt;
     const int32_t total = __builtin_amdgcn_readlane(incl, 63);
@@ -172,14 +195,14 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     const int32_t cnt0 = __builtin_amdgcn_readlane(cnt, tc);
     const int32_t cnt1 = __builtin_amdgcn_readlane(cnt, tc1);
     // ---- owner of each flattened candidate
-    const int kmax = wave_max_u(cnt);
+    const int kmax = wave_max_i32_uniform(cnt);
     for (int k = 0; k < kmax; ++k)
         if (k < cnt) own[pre + k] = (uint8_t)lane;
     const int32_t cellbase = cell * B.cap - pre;   // record index of flattened candidate q: q + cellbase[owner]
     __builtin_amdgcn_wave_barrier();
     // last entry of the old centre cell (removal by swap-with-last)
     double4 elast = make_double4(0, 0, 0, 0);
-    if (cnt0 > 0) elast = B.ent[(size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)];
+    if (cnt0 > 0) elast = gload(B.ent + ((size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)));
     // ---- candidates
     const int32_t excl = (int32_t)idx;
     double sa = 0.0, sb = 0.0;
@@ -196,7 +219,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
             const int j = ok[r] ? own[q] : 0;
             const int32_t cb = __shfl(cellbase, j, kWave);
             wsel[r] = j >= nst ? 1 : 0;
-            e[r] = B.ent[(size_t)(uint32_t)(ok[r] ? cb + q : cl0 * B.cap)];
+            e[r] = gload(B.ent + (size_t)(uint32_t)(ok[r] ? cb + q : cl0 * B.cap));
         }
 #pragma unroll
         for (int r = 0; r < CR; ++r) {
@@ -224,27 +247,19 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     const double eb = (type == GCMC_MOVE_DISPLACE) ? wave_sum_uniform(sb) : 0.0;
     const double dUp = (type == GCMC_MOVE_DISPLACE) ? (eb - ea) : ((type == GCMC_MOVE_INSERT) ? ea : -ea);
     // work counters of this evaluation (wave sums)
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        n_cand += __shfl_xor(n_cand, off, kWave);
-        n_eval += __shfl_xor(n_eval, off, kWave);
-        n_in += __shfl_xor(n_in, off, kWave);
-    }
+    n_cand = wave_sum_i32_uniform(n_cand);
+    n_eval = wave_sum_i32_uniform(n_eval);
+    n_in = wave_sum_i32_uniform(n_in);
     const double lnA = log(u.u[3]);
-    double lpref = 0.0;
-    if (type == GCMC_MOVE_INSERT) lpref = log(B.V / (B.lambda3 * (double)(N + 1)));
-    else if (type == GCMC_MOVE_DELETE) lpref = log((B.lambda3 * (double)N) / B.V);
     if (lane == 0) {
         out->dUp = dUp;
         out->lnA = lnA;
-        out->lpref = lpref;
         out->u2 = u.u[2];
         out->type = type;
         out->flags = 0;
         out->two = two;
         out->idx = idx;
         out->rec = rec;
-        out->rlast = rlast;
         out->elast = elast;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -271,8 +286,11 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     __shared__ int32_t offs[64];
     __shared__ SpecRec recs[W];
     __shared__ uint8_t own[W][kSpecOwn];
+    __shared__ double4 top[2 * W];              // records of particles base .. base + 2W - 1
+    __shared__ double lp_ins[2 * W], lp_del[2 * W];   // acceptance prefactors at N = base + t
     __shared__ int64_t sh_state[4];       // N, moves done, error, error move
     __shared__ double sh_u;
+    __shared__ double sh_acc[2];
     __shared__ int32_t sh_maxc;
     const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
     const DevBox B = hot_copy(boxes[blockIdx.x]);
@@ -307,14 +325,32 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         err_move = (int64_t)ctr0;
     }
     int64_t m = 0;
+    double a_ins = 0.5, a_del = 0.5;   // running acceptance of insertions and deletions
     while (err == GCMC_OK && m < n_moves) {
+        const int64_t base = N - W;
+        // ------------------------------------------------ this wavefront's share of the round tables
+        const int64_t topj = base + wv;
+        double4 tv = make_double4(0, 0, 0, 0);
+        if (topj >= 0) tv = gload(B.pos + topj);
+        {
+            const int64_t n = base + wv + (lane >= 3 ? W : 0);
+            double x = 1.0;
+            if (lane == 1 || lane == 3) x = B.V / (B.lambda3 * (double)(n + 1));
+            if (lane == 2 || lane == 4) x = (B.lambda3 * (double)n) / B.V;
+            const double lx = log(x);
+            if (lane == 1) lp_ins[wv] = lx;
+            if (lane == 2) lp_del[wv] = lx;
+            if (lane == 3) lp_ins[wv + W] = lx;
+            if (lane == 4) lp_del[wv + W] = lx;
+        }
         // ------------------------------------------------ evaluate W moves
-        if (m + wv < n_moves) spec_eval<CR>(B, tab, offs, own[wv], ctr0 + (uint64_t)(m + wv), N, no_full, &recs[wv]);
+        if (m + wv < n_moves)
+            spec_eval<CR>(B, tab, offs, own[wv], ctr0 + (uint64_t)m, wv, N, no_full, a_ins, a_del, &recs[wv]);
+        if (topj >= 0 && lane == 0) top[wv] = tv;
         __syncthreads();
         // ------------------------------------------------ in-order commit
         if (wv == 0) {
-            const int64_t n_round = N;
-            int32_t modcell = -1, touched = -1;   // lane-held lists of this round
+            int32_t modx = 0, mody = 0, modz = 0, touched = -1;   // lane-held lists of this round
             int nmod = 0, ntouch = 0;
             int k = 0;
             const int kend = (n_moves - m) < W ? (int)(n_moves - m) : W;
@@ -337,19 +373,16 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 }
                 const int64_t idx = R.idx;
                 if (type != GCMC_MOVE_INSERT) {
-                    if (N != n_round && spec_pick(R.u2, N) != idx) break;
+                    if (spec_pick(R.u2, N) != idx) break;
                     if (__ballot(lane < ntouch && touched == (int32_t)idx) != 0) break;
                 }
                 // a cell changed by an earlier commit of this round inside one of its stencils
                 int32_t cc[3] = {R.c0[0], R.c0[1], R.c0[2]};
                 int32_t cn[3] = {R.c1[0], R.c1[1], R.c1[2]};
                 bool hit = false;
-                if (lane < nmod) {
-                    const int32_t mx = modcell % B.M[0];
-                    const int32_t my = (modcell / B.M[0]) % B.M[1];
-                    const int32_t mz = modcell / (B.M[0] * B.M[1]);
-                    hit = in_stencil(B, mx, my, mz, cc) || (type == GCMC_MOVE_DISPLACE && in_stencil(B, mx, my, mz, cn));
-                }
+                if (lane < nmod)
+                    hit = in_stencil(B, modx, mody, modz, cc) ||
+                          (type == GCMC_MOVE_DISPLACE && in_stencil(B, modx, mody, modz, cn));
                 if (__ballot(hit) != 0) break;
                 // ---- decide at the current N
                 const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
@@ -357,9 +390,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 const double dUt =
                     is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
                 const double dU = dUp + dUt;
-                double lpref = R.lpref;
-                if (!is_disp && N != n_round)
-                    lpref = is_ins ? log(B.V / (B.lambda3 * (double)(N + 1))) : log((B.lambda3 * (double)N) / B.V);
+                const double lpref = is_disp ? 0.0 : (is_ins ? lp_ins[N - base] : lp_del[N - base]);
                 const double arg = is_disp ? -(B.beta * dU)
                                            : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
                 const bool ok = __builtin_amdgcn_readfirstlane((dU == dU && R.lnA < arg) ? 1 : 0) != 0;
@@ -386,49 +417,61 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     const bool swap = removes && loc != last;
                     const int32_t id_last = swap ? meta_low(R.elast.w) : -1;
                     // the record of particle N-1 as of now (kept as scalars so that it stays in registers)
-                    double rlx = R.rlast.x, rly = R.rlast.y, rlz = R.rlast.z, rlw = R.rlast.w;
-                    if (type == GCMC_MOVE_DELETE && idx != N - 1) {
-                        const bool stale = (N != n_round) ||
-                                           (__ballot(lane < ntouch && touched == (int32_t)(N - 1)) != 0);
-                        if (stale) {
-                            // this wavefront's own earlier commit stores must have landed
-                            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-                            const double4 v = B.pos[N - 1];
-                            rlx = v.x; rly = v.y; rlz = v.z; rlw = v.w;
-                        }
+                    double rlx = 0.0, rly = 0.0, rlz = 0.0, rlw = 0.0;
+                    if (type == GCMC_MOVE_DELETE) {
+                        const double4 v = top[N - 1 - base];
+                        rlx = v.x; rly = v.y; rlz = v.z; rlw = v.w;
                     }
                     if (lane == 0) {
+                        // every store to pos[j] for j in the round's window is mirrored in top[]
                         if (swap) {
-                            B.ent[loc] = R.elast;
-                            B.pos[id_last].w = pack_meta(meta_species(R.elast.w), (int32_t)loc);
+                            gstore(B.ent + loc, R.elast);
+                            const double w = pack_meta(meta_species(R.elast.w), (int32_t)loc);
+                            gstore_w(B.pos + id_last, w);
+                            const int64_t t = (int64_t)id_last - base;
+                            if (t >= 0 && t < 2 * W) top[t].w = w;
                         }
-                        if (removes) B.count[c0] = cnt0 - 1;
+                        if (removes) gstore(B.count + c0, cnt0 - 1);
+                        double4 nr;
+                        int64_t j = -1;
                         if (is_disp) {
                             if (!two) {
-                                B.ent[loc] = make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)idx));
-                                B.pos[idx] = make_double4(R.p1[0], R.p1[1], R.p1[2], R.rec.w);
+                                gstore(B.ent + loc, make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)idx)));
+                                nr = make_double4(R.p1[0], R.p1[1], R.p1[2], R.rec.w);
                             } else {
                                 const int64_t nl = c1 * cap + cnt1;
-                                B.ent[nl] = make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)idx));
-                                B.count[c1] = cnt1 + 1;
-                                B.pos[idx] = make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)nl));
+                                gstore(B.ent + nl, make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)idx)));
+                                gstore(B.count + c1, cnt1 + 1);
+                                nr = make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)nl));
                             }
+                            j = idx;
                         } else if (is_ins) {
                             const int64_t nl = c0 * cap + cnt0;
-                            B.ent[nl] = make_double4(R.p0[0], R.p0[1], R.p0[2], pack_meta(0, (int32_t)N));
-                            B.count[c0] = cnt0 + 1;
-                            B.pos[N] = make_double4(R.p0[0], R.p0[1], R.p0[2], pack_meta(0, (int32_t)nl));
+                            gstore(B.ent + nl, make_double4(R.p0[0], R.p0[1], R.p0[2], pack_meta(0, (int32_t)N)));
+                            gstore(B.count + c0, cnt0 + 1);
+                            nr = make_double4(R.p0[0], R.p0[1], R.p0[2], pack_meta(0, (int32_t)nl));
+                            j = N;
                         } else if (idx != N - 1) {
                             if (id_last == (int32_t)(N - 1)) rlw = pack_meta(meta_species(rlw), (int32_t)loc);
-                            B.pos[idx] = make_double4(rlx, rly, rlz, rlw);
-                            B.ent[meta_low(rlw)].w = pack_meta(meta_species(rlw), (int32_t)idx);
+                            nr = make_double4(rlx, rly, rlz, rlw);
+                            gstore_w(B.ent + meta_low(rlw), pack_meta(meta_species(rlw), (int32_t)idx));
+                            j = idx;
+                        }
+                        if (j >= 0) {
+                            gstore(B.pos + j, nr);
+                            const int64_t t = j - base;
+                            if (t >= 0 && t < 2 * W) top[t] = nr;
                         }
                     }
                     // what later moves of this round must not have read
-                    if (lane == nmod) modcell = (int32_t)c0;
+                    if (lane == nmod) {
+                        modx = R.c0[0]; mody = R.c0[1]; modz = R.c0[2];
+                    }
                     nmod += 1;
                     if (is_disp && two) {
-                        if (lane == nmod) modcell = (int32_t)c1;
+                        if (lane == nmod) {
+                            modx = R.c1[0]; mody = R.c1[1]; modz = R.c1[2];
+                        }
                         nmod += 1;
                     }
                     if (lane == ntouch) touched = is_ins ? (int32_t)N : (int32_t)idx;
@@ -480,6 +523,8 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 sh_state[3] = err_move;
                 sh_u = U;
                 sh_maxc = maxc;
+                sh_acc[0] = ((double)acc1 + 1.0) / ((double)att1 + 2.0);
+                sh_acc[1] = ((double)acc2 + 1.0) / ((double)att2 + 2.0);
             }
         }
         __syncthreads();   // commit stores done and visible; the new state published
@@ -489,6 +534,8 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         err_move = sh_state[3];
         U = sh_u;
         maxc = sh_maxc;
+        a_ins = sh_acc[0];
+        a_del = sh_acc[1];
     }
     if (tid == 0) {
         st->n = N;
