@@ -65,8 +65,10 @@ def kernel_source_hash(kernel):
 def measured_traffic(kernel, shape, workload, moves_per_launch):
     """HBM bytes per launch from the committed counter summaries under profiles/:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the same kernel, launch shape
-    and workload, each scaled by what the counter reads for a copy of known size.
-    None when no record matches or the kernel's sources changed since."""
+    and workload, each scaled by what the counter reads for a copy of known size,
+    per move times the moves of this launch; also the ratio of the measured bytes
+    to the algorithmic bytes of the profiled launch.  None when no record matches
+    or the kernel's sources changed since."""
     import glob
     import re
     want = kernel_source_hash(kernel)
@@ -76,10 +78,10 @@ def measured_traffic(kernel, shape, workload, moves_per_launch):
                 r = json.loads(m.group(1))
                 if (r["kernel"] == kernel and tuple(r["launch"]) == tuple(shape) and r["workload"] == workload
                         and r["source_hash"] == want):
-                    per_move = (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"]) * 1024.0 \
-                        / r["moves_per_launch"]
-                    return per_move * moves_per_launch, os.path.relpath(path, ROOT)
-    return None, None
+                    measured = (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"]) * 1024.0
+                    return (measured * moves_per_launch / r["moves_per_launch"], os.path.relpath(path, ROOT),
+                            measured / r["alg_bytes"])
+    return None, None, None
 
 
 def workload_by_name(name):
@@ -197,7 +199,7 @@ def main():
     log("timed %d x %d moves: %.3fs wall, launch avg %.2f ms, %.0f moves/s, %.3g pair evals/s" %
         (args.steps, mps, wall, 1e3 * avg_launch_s, moves / wall, pair_evals / wall))
     kname = "k_chain_spec" if shape[1] == 0 else "k_chain"
-    traffic, traffic_src = measured_traffic(kname, shape, wb.name, mps)
+    traffic, traffic_src, traffic_ratio = measured_traffic(kname, shape, wb.name, mps)
     acc = np.sum([s["accepts"] for s in stats_all], axis=0)
     att = np.sum([s["attempts"] for s in stats_all], axis=0)
 
@@ -225,7 +227,8 @@ def main():
         "us_per_move": 1e6 * wall / moves,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_source": traffic_src, "alg_bytes_per_launch": bytes_per_launch,
+                     "traffic_source": traffic_src, "traffic_over_alg_bytes": traffic_ratio,
+                     "alg_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": 1e3 * avg_launch_s},
     }
 

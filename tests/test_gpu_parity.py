@@ -288,11 +288,22 @@ def test_speculative_dense_conflicts():
         assert compare_chain_logs(glog, olog, wb.beta, "dense speculative") == 3000
 
 
-def test_chain_resume_split_equals_whole(c1):
+# the per-move kernel (the box's default launch) and the speculative kernel
+KERNELS = [None, (8, 0)]
+
+
+def _launch(b, shape):
+    if shape:
+        b.set_launch(*shape)
+    return b
+
+
+@pytest.mark.parametrize("shape", KERNELS)
+def test_chain_resume_split_equals_whole(c1, shape):
     """Counter-based draws: two calls of 400 + 600 moves = one call of 1,000."""
-    a = _box(c1, max_n=c1.n + 1001)
+    a = _launch(_box(c1, max_n=c1.n + 1001), shape)
     a.step(1000, counter0=0)
-    b = _box(c1, max_n=c1.n + 1001)
+    b = _launch(_box(c1, max_n=c1.n + 1001), shape)
     b.step(400, counter0=0)
     b.step(600, counter0=400)
     pa, _ = a.particles()
@@ -300,9 +311,10 @@ def test_chain_resume_split_equals_whole(c1):
     assert np.array_equal(pa, pb)
 
 
-def test_chain_deterministic(c1):
-    a = _box(c1, max_n=c1.n + 1001)
-    b = _box(c1, max_n=c1.n + 1001)
+@pytest.mark.parametrize("shape", KERNELS)
+def test_chain_deterministic(c1, shape):
+    a = _launch(_box(c1, max_n=c1.n + 1001), shape)
+    b = _launch(_box(c1, max_n=c1.n + 1001), shape)
     sa, la = a.step(1000, log=True)
     sb, lb = b.step(1000, log=True)
     assert la.tobytes() == lb.tobytes()
@@ -344,13 +356,15 @@ def test_host_driven_commit_matches_chain():
     assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(opos, wb.L, wb.rc))
 
 
-def test_ideal_gas_on_gpu():
+@pytest.mark.parametrize("shape", KERNELS)
+def test_ideal_gas_on_gpu(shape):
     """eps = 0: N is Poisson with mean V exp(beta mu)."""
     from paper_1408_3764_amd.box import Box
     L, beta, mu = 6.0, 1.0 / 1.3, -0.4
     mean = L ** 3 * math.exp(beta * mu)
     # an empty box sizes its cells for nothing: give the cells room for ~160 particles
     b = Box(np.zeros((0, 3)), [L] * 3, 2.5, beta=beta, mu=mu, eps=0.0, max_n=2000, seed=77, cell_cap=64)
+    _launch(b, shape)
     st, _ = b.step(50_000, counter0=0)
     assert int(st["error"]) == 0
     ns = []
@@ -363,19 +377,43 @@ def test_ideal_gas_on_gpu():
     assert abs(ns.mean() - mean) < 5 * se + 0.01 * mean, (ns.mean(), mean)
 
 
+def test_speculative_matches_per_move_under_churn():
+    """Ideal gas: every insertion and deletion changes N, and most are accepted.
+    The speculative kernel must leave exactly the per-move kernel's particle
+    array (order included) and cells after 20,000 moves."""
+    from paper_1408_3764_amd.box import Box
+    out = []
+    for shape in ((4, 4), (8, 0), (16, 0)):
+        b = Box(np.zeros((0, 3)), [6.0] * 3, 2.5, beta=1 / 1.3, mu=-0.4, eps=0.0, max_n=2000, seed=5,
+                cell_cap=64)
+        b.set_launch(*shape)
+        st, log = b.step(20_000, counter0=0, log=True)
+        assert int(st["error"]) == 0
+        out.append((b.particles()[0], b.cells(), log))
+    count0, ids0 = out[0][1][1], out[0][1][2]
+    valid = np.arange(ids0.shape[1])[None, :] < count0[:, None]
+    for pos, cells, log in out[1:]:
+        assert np.array_equal(pos, out[0][0])
+        assert np.array_equal(cells[1], count0)
+        assert np.array_equal(np.where(valid, cells[2], -1), np.where(valid, ids0, -1))
+        assert np.array_equal(log["accepted"], out[0][2]["accepted"])
+        assert np.array_equal(log["index"], out[0][2]["index"])
+
+
 # -------------------------------------------------------- error handling
-def test_overflow_latches_and_resumes():
+@pytest.mark.parametrize("shape", KERNELS)
+def test_overflow_latches_and_resumes(shape):
     """A cell over capacity stops the chain before the move; rebuilding with a
     larger capacity and resuming at the stop gives the uninterrupted chain."""
     M = 20_000
     # a sparse start (about 2 per cell) under a high chemical potential: cells fill up
     wb = workloads.random_box(1000, 20.0, rc=2.5, T=1.2, mu=10.0, seed=31)
-    ref = _box(wb, max_n=wb.n + M + 1, cell_cap=64)
+    ref = _launch(_box(wb, max_n=wb.n + M + 1, cell_cap=64), shape)
     ref.step(M, counter0=0)
     assert ref.status() == 0
     maxc0 = int(_box(wb, max_n=wb.n + 1).cells()[1].max())
     assert int(ref.cells()[1].max()) > maxc0
-    b2 = _box(wb, max_n=wb.n + M + 1, cell_cap=maxc0)   # no headroom: the first growth overflows
+    b2 = _launch(_box(wb, max_n=wb.n + M + 1, cell_cap=maxc0), shape)   # no headroom: the first growth overflows
     st, _ = b2.step(M, counter0=0)
     assert int(st["error"]) == 3
     stop = int(st["error_move"])
@@ -389,9 +427,10 @@ def test_overflow_latches_and_resumes():
     assert np.array_equal(b2.particles()[0], ref.particles()[0])
 
 
-def test_capacity_error():
+@pytest.mark.parametrize("shape", KERNELS)
+def test_capacity_error(shape):
     from paper_1408_3764_amd.box import Box
-    b = Box(np.zeros((0, 3)), [8.0] * 3, 2.5, mu=5.0, max_n=5, seed=1)
+    b = _launch(Box(np.zeros((0, 3)), [8.0] * 3, 2.5, mu=5.0, max_n=5, seed=1), shape)
     st, _ = b.step(500)
     assert int(st["error"]) == 4 and int(st["n"]) == 5
 
