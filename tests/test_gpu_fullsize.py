@@ -230,7 +230,7 @@ def test_autograd_function():
     U.backward()
     p = _params(w)
     t = oracle.total_energy(w.pos, p, species=w.species)
-    assert float(U) == pytest.approx(t["U_pair"] + t["U_tail"], rel=1e-11)
+    assert float(U.detach()) == pytest.approx(t["U_pair"] + t["U_tail"], rel=1e-11)
     g, de, ds = oracle.gradients(w.pos, p, species=w.species)
     assert np.allclose(pos.grad.cpu().numpy(), g, rtol=1e-7, atol=1e-9 * np.abs(g).max())
     assert np.allclose(E.grad.cpu().numpy(), de, rtol=1e-7)
