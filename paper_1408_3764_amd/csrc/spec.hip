@@ -422,6 +422,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                         const double4 v = top[N - 1 - base];
                         rlx = v.x; rly = v.y; rlz = v.z; rlw = v.w;
                     }
+                    const int32_t rl_cell = __builtin_amdgcn_readfirstlane(meta_low(rlw) / cap);
                     if (lane == 0) {
                         // every store to pos[j] for j in the round's window is mirrored in top[]
                         if (swap) {
@@ -468,6 +469,20 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                         modx = R.c0[0]; mody = R.c0[1]; modz = R.c0[2];
                     }
                     nmod += 1;
+                    // a deletion that frees an inner index rewrites the id of particle N-1 in that
+                    // particle's cell: that cell counts as modified too (a later removal from it
+                    // would otherwise copy the stale id with the cell's last entry)
+                    if (type == GCMC_MOVE_DELETE && idx != N - 1 && id_last != (int32_t)(N - 1)) {
+                        const int32_t cx = rl_cell;
+                        if (cx != (int32_t)c0) {
+                            if (lane == nmod) {
+                                modx = cx % B.M[0];
+                                mody = (cx / B.M[0]) % B.M[1];
+                                modz = cx / (B.M[0] * B.M[1]);
+                            }
+                            nmod += 1;
+                        }
+                    }
                     if (is_disp && two) {
                         if (lane == nmod) {
                             modx = R.c1[0]; mody = R.c1[1]; modz = R.c1[2];
@@ -572,12 +587,13 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
 using spec_fn = void (*)(const DevBox*, const int32_t*, int64_t, uint64_t, gcmc_stats*, gcmc_log*);
 
 struct SpecCfg {
+    int key;   // the waves value of gcmc_box_set_launch that selects it
     int w;
     spec_fn f;
 };
 
 static const SpecCfg kSpecCfgs[] = {
-    {4, k_chain_spec<4, 8>}, {8, k_chain_spec<8, 8>}, {16, k_chain_spec<16, 4>},
+    {4, 4, k_chain_spec<4, 8>}, {8, 8, k_chain_spec<8, 8>}, {16, 16, k_chain_spec<16, 4>},
 };
 
 // The speculative kernel handles one species, stencils of at most 32 cells
@@ -589,14 +605,14 @@ bool spec_supported(const DevBox& hb) {
 
 bool spec_cfg_exists(int waves) {
     for (const SpecCfg& c : kSpecCfgs)
-        if (c.w == waves) return true;
+        if (c.key == waves) return true;
     return false;
 }
 
 int launch_chain_spec(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
                       uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s) {
     for (const SpecCfg& c : kSpecCfgs) {
-        if (c.w == waves) {
+        if (c.key == waves) {
             hipLaunchKernelGGL(c.f, dim3(n_boxes), dim3(kWave * c.w), 0, s, d_boxes, d_order, n_moves, ctr0, stats,
                                log);
             return 0;

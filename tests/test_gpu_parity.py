@@ -400,6 +400,34 @@ def test_speculative_matches_per_move_under_churn():
         assert np.array_equal(log["index"], out[0][2]["index"])
 
 
+def test_speculative_deletion_relabel_invalidates():
+    """A deletion moves particle N-1 into the freed index and rewrites its id in
+    its cell.  That cell counts as modified: a later move of the same round that
+    removes a particle from it (with the relabelled particle as the cell's last
+    entry) must be evaluated again.  Ideal gas of about 400 particles in 125
+    cells (27-cell stencils), many accepted deletions and insertions: the
+    speculative kernels must leave the per-move kernel's particle array and
+    cells exactly."""
+    from paper_1408_3764_amd.box import Box
+    L, beta = 12.5, 1.0
+    mu = math.log(400.0 / L ** 3)
+    rng = np.random.default_rng(9)
+    start = rng.random((400, 3)) * L
+    out = []
+    for shape in ((4, 4), (8, 0), (16, 0)):
+        b = Box(start, [L] * 3, 2.5, beta=beta, mu=mu, eps=0.0, max_n=4000, seed=21, cell_cap=24)
+        b.set_launch(*shape)
+        st, _ = b.step(150_000, counter0=0)
+        assert int(st["error"]) == 0
+        out.append((b.particles()[0], b.cells()))
+    count0, ids0 = out[0][1][1], out[0][1][2]
+    valid = np.arange(ids0.shape[1])[None, :] < count0[:, None]
+    for pos, cells in out[1:]:
+        assert np.array_equal(pos, out[0][0])
+        assert np.array_equal(cells[1], count0)
+        assert np.array_equal(np.where(valid, cells[2], -1), np.where(valid, ids0, -1))
+
+
 # -------------------------------------------------------- error handling
 @pytest.mark.parametrize("shape", KERNELS)
 def test_overflow_latches_and_resumes(shape):
