@@ -48,7 +48,8 @@ def alg_bytes(stats, nstencil):
 # rocprofv3 counters is used only while these files are unchanged.
 KERNEL_SOURCES = {
     "k_chain": ["chain.hip", "trial.h", "gcmc_internal.h"],
-    "k_chain_spec": ["spec.hip", "trial.h", "gcmc_internal.h"],
+    "k_chain_spec": ["spec.hip", "spec_eval.h", "trial.h", "gcmc_internal.h"],
+    "k_chain_async": ["async.hip", "spec_eval.h", "trial.h", "gcmc_internal.h"],
 }
 
 
@@ -84,6 +85,72 @@ def measured_traffic(kernel, shape, workload, moves_per_launch):
     return None, None, None
 
 
+def stencil_candidates(count, span):
+    """Sum over cells c of count[c] x (particles in the stencil of c): the pair
+    distances a full-stencil total-energy pass evaluates (self pairs included)."""
+    import numpy as np
+    tot = np.zeros_like(count, dtype=np.int64)
+    sx, sy, sz = span     # stencil cells per axis (2k + 1, or the whole axis)
+    for dz in range(-(sz // 2), sz - sz // 2):
+        for dy in range(-(sy // 2), sy - sy // 2):
+            for dx in range(-(sx // 2), sx - sx // 2):
+                tot += np.roll(count, (dz, dy, dx), axis=(0, 1, 2))
+    return int((count.astype(np.int64) * tot).sum())
+
+
+def extra_configs(Box, tune, stream):
+    """The small box's 1,000-move chain and the binary mixture's forward and
+    backward passes (the parity workloads, timed with HIP events)."""
+    import numpy as np
+    import torch
+    from paper_1408_3764_amd import workloads
+    res = {}
+    sw = workloads.small()
+    sb = Box.from_workload(sw, max_n=sw.n + 12_000)
+    sb.set_launch(*tune.chain_shape(sb))
+    sb.step(1000, counter0=0)
+    torch.cuda.synchronize()
+    times = []
+    for k in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sb.step(1000, counter0=1000 * (k + 1))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    res["small"] = {"workload": sw.name, "moves_per_launch": 1000, "launch_ms_median": float(np.median(times)),
+                    "moves_per_s": 1000 / (float(np.median(times)) / 1e3)}
+    sb.close()
+    log("small box: %.0f moves/s (median of 5 launches of 1,000 moves)" % res["small"]["moves_per_s"])
+    mw = workloads.mixture()
+    mb = Box.from_workload(mw)
+    info = mb.info()
+    _, count, _ = mb.cells()
+    m = info["cell_m"]
+    pairs = stencil_candidates(count.reshape(m[2], m[1], m[0]), info["span"])
+    mb.total_energy_device()
+    mb.backward_device(mw.n)
+    torch.cuda.synchronize()
+    fw, bw = [], []
+    for k in range(5):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        mb.total_energy_device()
+        e1.record(stream)
+        mb.backward_device(mw.n)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        fw.append(e0.elapsed_time(e1))
+        bw.append(e1.elapsed_time(e2))
+    f, b = float(np.median(fw)), float(np.median(bw))
+    res["mixture"] = {"workload": mw.name, "n": mw.n, "forward_ms_median": f, "backward_ms_median": b,
+                      "pair_distances": pairs, "pair_distances_per_s_forward": pairs / (f / 1e3),
+                      "pair_distances_per_s_backward": pairs / (b / 1e3)}
+    mb.close()
+    log("mixture N=%d: forward %.3f ms, backward %.3f ms, %.3g pair distances per pass" % (mw.n, f, b, pairs))
+    return res
+
+
 def workload_by_name(name):
     from paper_1408_3764_amd import workloads
     return {"slab": workloads.slab, "large": workloads.large, "small": workloads.small}[name]()
@@ -112,10 +179,11 @@ def main():
     ap.add_argument("--workload", default="slab", choices=["slab", "large", "small"])
     ap.add_argument("--moves-per-step", type=int, default=0, help="0: the workload's move count")
     ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--rows", type=int, default=0, help="with --waves: rows per wavefront, 0 = speculative kernel")
+    ap.add_argument("--rows", type=int, default=0, help="with --waves: rows per wavefront; 0 = speculative rounds, -1 = pipelined kernel")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the small-box chain and the mixture forward/backward")
     ap.add_argument("--no-allpairs", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="heuristic launch shape instead of timing them")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -198,7 +266,7 @@ def main():
     achieved = bytes_per_launch / avg_launch_s / 1e9
     log("timed %d x %d moves: %.3fs wall, launch avg %.2f ms, %.0f moves/s, %.3g pair evals/s" %
         (args.steps, mps, wall, 1e3 * avg_launch_s, moves / wall, pair_evals / wall))
-    kname = "k_chain_spec" if shape[1] == 0 else "k_chain"
+    kname = {0: "k_chain_spec", -1: "k_chain_async"}.get(shape[1], "k_chain")
     traffic, traffic_src, traffic_ratio = measured_traffic(kname, shape, wb.name, mps)
     acc = np.sum([s["accepts"] for s in stats_all], axis=0)
     att = np.sum([s["attempts"] for s in stats_all], axis=0)
@@ -299,6 +367,9 @@ def main():
         bt.close()
         for b in boxes:
             b.close()
+
+    if not args.no_extra:
+        out.update(extra_configs(Box, tune, stream))
 
     if not args.no_cpu:
         n_cpu, dt, olog = run_cpu_baseline(wb, args.cpu_budget, 20000)

@@ -46,7 +46,8 @@ enum {
     GCMC_ERR_CAPACITY = 4,      /* an insertion would exceed max_n */
     GCMC_ERR_HIP = 5,           /* a HIP runtime call failed */
     GCMC_ERR_POISONED = 6,      /* the box holds a latched device error */
-    GCMC_ERR_UNSUPPORTED = 7    /* valid but not implemented (e.g. a chain over a mixture) */
+    GCMC_ERR_UNSUPPORTED = 7,   /* valid but not implemented (e.g. a chain over a mixture) */
+    GCMC_ERR_INTERNAL = 8       /* a wait inside the pipelined chain kernel exceeded its bound (latched) */
 };
 
 enum { GCMC_MOVE_DISPLACE = 0, GCMC_MOVE_INSERT = 1, GCMC_MOVE_DELETE = 2 };
@@ -204,7 +205,11 @@ int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair,
  * one per wavefront, against the round's starting state and committed in
  * order, each only if nothing it read has changed since (the same chain, move
  * for move); needs one species, at most 32 stencil cells and
- * 2 x stencil cells x cell_cap <= 4096, else GCMC_ERR_UNSUPPORTED. */
+ * 2 x stencil cells x cell_cap <= 4096, else GCMC_ERR_UNSUPPORTED.  rows = -1:
+ * pipelined, one wavefront decides the moves in order while waves - 1 (3 or
+ * 7) wavefronts evaluate the moves ahead of it; an evaluation is used only if
+ * no decision since it read memory changed what it read (the same chain, move
+ * for move); the same limits plus at most 1024 cells per axis. */
 int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows);
 
 /* Run n_moves moves of the Markov chain of Algorithm 1 on the device in one

@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(HERE, "libgcmc.so")
 GCMC_OK = 0
 ERRORS = {
     1: "GCMC_ERR_INVALID_ARG", 2: "GCMC_ERR_OOM", 3: "GCMC_ERR_CELL_OVERFLOW", 4: "GCMC_ERR_CAPACITY",
-    5: "GCMC_ERR_HIP", 6: "GCMC_ERR_POISONED", 7: "GCMC_ERR_UNSUPPORTED",
+    5: "GCMC_ERR_HIP", 6: "GCMC_ERR_POISONED", 7: "GCMC_ERR_UNSUPPORTED", 8: "GCMC_ERR_INTERNAL",
 }
 GCMC_ERR_INVALID_ARG, GCMC_ERR_OOM, GCMC_ERR_CELL_OVERFLOW, GCMC_ERR_CAPACITY = 1, 2, 3, 4
-GCMC_ERR_HIP, GCMC_ERR_POISONED, GCMC_ERR_UNSUPPORTED = 5, 6, 7
+GCMC_ERR_HIP, GCMC_ERR_POISONED, GCMC_ERR_UNSUPPORTED, GCMC_ERR_INTERNAL = 5, 6, 7, 8
 DISPLACE, INSERT, DELETE = 0, 1, 2
 COUNTER_CONTINUE = 0xFFFFFFFFFFFFFFFF
 MAX_SPECIES = 4

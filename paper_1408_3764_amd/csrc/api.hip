@@ -26,6 +26,11 @@ int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows) {
         if (!spec_supported(box->d))
             return set_error(GCMC_ERR_UNSUPPORTED, "speculative rounds need one species, <= 32 stencil cells "
                                                    "and 2 x stencil x cell_cap <= 4096");
+    } else if (rows == -1) {
+        if (!async_cfg_exists(waves)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported pipeline width");
+        if (!async_supported(box->d))
+            return set_error(GCMC_ERR_UNSUPPORTED, "the pipelined chain needs one species, <= 32 stencil cells, "
+                                                   "2 x stencil x cell_cap <= 4096 and <= 1024 cells per axis");
     } else if (!chain_cfg_exists(waves, rows)) {
         return set_error(GCMC_ERR_INVALID_ARG, "unsupported waves x rows");
     }
@@ -79,11 +84,14 @@ int gcmc_step(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_s
     if (!box || n_moves < 0) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
     if (box->d.ns != 1) return set_error(GCMC_ERR_UNSUPPORTED, "the chain supports one species");
     int r;
-    if (box->rows == 0 && spec_supported(box->d))
+    if (box->rows == -1 && async_supported(box->d))
+        r = launch_chain_async(box->d_desc, nullptr, 1, box->waves, n_moves, counter0, d_stats, d_log,
+                               (hipStream_t)stream);
+    else if (box->rows == 0 && spec_supported(box->d))
         r = launch_chain_spec(box->d_desc, nullptr, 1, box->waves, n_moves, counter0, d_stats, d_log,
                               (hipStream_t)stream);
     else
-        r = launch_chain(box->d_desc, nullptr, 1, box->waves, box->rows ? box->rows : 4, n_moves, counter0,
+        r = launch_chain(box->d_desc, nullptr, 1, box->waves, box->rows > 0 ? box->rows : 4, n_moves, counter0,
                          d_stats, d_log, (hipStream_t)stream);
     if (r) return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
     GCMC_HIP(hipGetLastError());
@@ -213,14 +221,18 @@ int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gc
         GCMC_HIP(hipStreamSynchronize(s));
     }
     const gcmc_box* b0 = bt->boxes[0];
-    bool spec = b0->rows == 0;
+    bool spec = b0->rows == 0, pipe = b0->rows == -1;
     for (int32_t q = 0; q < bt->n && spec; ++q) spec = spec_supported(bt->boxes[q]->d);
+    for (int32_t q = 0; q < bt->n && pipe; ++q) pipe = async_supported(bt->boxes[q]->d);
     int r;
-    if (spec)
+    if (pipe)
+        r = launch_chain_async(bt->d_descs, bt->d_order, bt->n, b0->waves, moves_per_box, counter0, d_stats,
+                               nullptr, s);
+    else if (spec)
         r = launch_chain_spec(bt->d_descs, bt->d_order, bt->n, b0->waves, moves_per_box, counter0, d_stats, nullptr,
                               s);
     else
-        r = launch_chain(bt->d_descs, bt->d_order, bt->n, b0->waves, b0->rows ? b0->rows : 4, moves_per_box,
+        r = launch_chain(bt->d_descs, bt->d_order, bt->n, b0->waves, b0->rows > 0 ? b0->rows : 4, moves_per_box,
                          counter0, d_stats, nullptr, s);
     if (r) return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
     GCMC_HIP(hipGetLastError());

@@ -346,6 +346,10 @@ bool chain_cfg_exists(int waves, int rows);
 // spec.hip
 bool spec_supported(const DevBox& hb);
 bool spec_cfg_exists(int waves);
+bool async_supported(const DevBox& hb);
+bool async_cfg_exists(int waves);
+int launch_chain_async(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
+                       uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 int launch_chain_spec(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
                       uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 int launch_delta(const DevBox* d_box, bool mix, int64_t n_moves, const gcmc_move* moves, double* dp, double* dt,

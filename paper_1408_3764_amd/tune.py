@@ -18,6 +18,9 @@ SHAPES = [(1, 8), (2, 8), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4)]
 # rows = 0: the speculative kernel, W consecutive moves evaluated at once and
 # committed in order (one species, stencils of at most 32 cells)
 SPEC_SHAPES = [(4, 0), (8, 0), (16, 0)]
+# rows = -1: the pipelined kernel, one committer and waves - 1 evaluator wavefronts
+# (the same limits, plus at most 1024 cells per axis)
+ASYNC_SHAPES = [(4, -1), (8, -1)]
 SPEC_OWN = 4096   # flattened candidates a speculative wavefront can hold
 CACHE_ENV = "GCMC_TUNE_CACHE"
 
@@ -37,6 +40,10 @@ def spec_supported(box):
     info = box.info()
     nst = info["span"][0] * info["span"][1] * info["span"][2]
     return info["n_species"] == 1 and nst <= 32 and 2 * nst * info["cell_cap"] <= SPEC_OWN
+
+
+def async_supported(box):
+    return spec_supported(box) and max(box.info()["cell_m"]) <= 1024
 
 
 def chain_shape(box):
@@ -75,7 +82,7 @@ def autotune_live(box, n_moves=3000, shapes=None):
     import torch
     from ._lib import COUNTER_CONTINUE
     if shapes is None:
-        shapes = SHAPES + (SPEC_SHAPES if spec_supported(box) else [])
+        shapes = SHAPES + (SPEC_SHAPES if spec_supported(box) else []) + (ASYNC_SHAPES if async_supported(box) else [])
     timings = {}
     best = None
     for w, r in shapes:

@@ -53,7 +53,7 @@ def _chain_check(wb, n_moves, shape=None):
     return b, k
 
 
-@pytest.mark.parametrize("shape", [None, (4, 4), (16, 0)])
+@pytest.mark.parametrize("shape", [None, (4, 4), (16, 0), (8, -1)])
 def test_large_chain_matches_oracle(large, shape):
     """N=262,144, rc=3.0: 300 moves, bit-exact decisions (per-move and speculative kernels)."""
     _, k = _chain_check(large, 300, shape)
@@ -114,7 +114,7 @@ def test_large_total_energy_sampled(large):
     assert cell["U_tail"] == pytest.approx(oracle.tail_energy([large.n], p), rel=1e-13)
 
 
-@pytest.mark.parametrize("shape", [None, (4, 4), (16, 0)])
+@pytest.mark.parametrize("shape", [None, (4, 4), (16, 0), (8, -1)])
 def test_slab_chain_matches_oracle(slab, shape):
     """The 1.5M-particle slab: 150 moves, bit-exact decisions (per-move and speculative kernels)."""
     _, k = _chain_check(slab, 150, shape)

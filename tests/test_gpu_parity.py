@@ -168,7 +168,8 @@ def test_delta_energy_c1_and_small_cells(c1):
         assert np.allclose(gt, rt, rtol=1e-12)
 
 
-@pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (4, 8), (8, 4), (4, 0), (8, 0), (16, 0)])
+@pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (4, 8), (8, 4), (4, 0), (8, 0), (16, 0), (4, -1),
+                                        (8, -1)])
 def test_chain_launch_shapes_agree(c1, waves, rows):
     """Every launch shape gives the oracle's chain (the tuner may pick any)."""
     p = _params(c1)
@@ -257,8 +258,8 @@ def test_chain_parity_c1(c1):
     assert acc[0] > 0 and acc[1] > 0 and acc[2] > 0
 
 
-@pytest.mark.parametrize("width", [8, 16])
-def test_speculative_chain_parity_c1(c1, width):
+@pytest.mark.parametrize("width,rows", [(8, 0), (16, 0), (8, -1)])
+def test_speculative_chain_parity_c1(c1, width, rows):
     """Speculative rounds (W moves evaluated at once, committed in order) give the
     sequential chain: 1,000 moves, same decisions and final configuration."""
     p = _params(c1)
@@ -266,7 +267,7 @@ def test_speculative_chain_parity_c1(c1, width):
     opos, oU, olog = oracle.chain(c1.pos, c1.n_moves, p, seed=c1.seed, max_n=c1.n + 1001,
                                   U0=t0["U_pair"] + t0["U_tail"])
     b = _box(c1, max_n=c1.n + 1001)
-    b.set_launch(width, 0)
+    b.set_launch(width, rows)
     b.total_energy()
     stats, glog = b.step(c1.n_moves, counter0=0, log=True)
     assert compare_chain_logs(glog, olog, c1.beta, "speculative C1") == c1.n_moves
@@ -281,15 +282,15 @@ def test_speculative_dense_conflicts():
     wb = workloads.random_box(300, 8.0, rc=2.5, T=1.2, mu=2.0, seed=77)
     p = _params(wb)
     _, _, olog = oracle.chain(wb.pos, 3000, p, seed=wb.seed, max_n=wb.n + 3001)
-    for width in (4, 16):
+    for width, rows in ((4, 0), (16, 0), (8, -1)):
         b = _box(wb, max_n=wb.n + 3001)
-        b.set_launch(width, 0)
+        b.set_launch(width, rows)
         _, glog = b.step(3000, counter0=0, log=True)
         assert compare_chain_logs(glog, olog, wb.beta, "dense speculative") == 3000
 
 
 # the per-move kernel (the box's default launch) and the speculative kernel
-KERNELS = [None, (8, 0)]
+KERNELS = [None, (8, 0), (8, -1)]
 
 
 def _launch(b, shape):
@@ -383,7 +384,7 @@ def test_speculative_matches_per_move_under_churn():
     array (order included) and cells after 20,000 moves."""
     from paper_1408_3764_amd.box import Box
     out = []
-    for shape in ((4, 4), (8, 0), (16, 0)):
+    for shape in ((4, 4), (8, 0), (16, 0), (8, -1)):
         b = Box(np.zeros((0, 3)), [6.0] * 3, 2.5, beta=1 / 1.3, mu=-0.4, eps=0.0, max_n=2000, seed=5,
                 cell_cap=64)
         b.set_launch(*shape)
@@ -414,7 +415,7 @@ def test_speculative_deletion_relabel_invalidates():
     rng = np.random.default_rng(9)
     start = rng.random((400, 3)) * L
     out = []
-    for shape in ((4, 4), (8, 0), (16, 0)):
+    for shape in ((4, 4), (8, 0), (16, 0), (8, -1), (4, -1)):
         b = Box(start, [L] * 3, 2.5, beta=beta, mu=mu, eps=0.0, max_n=4000, seed=21, cell_cap=24)
         b.set_launch(*shape)
         st, _ = b.step(150_000, counter0=0)
@@ -523,7 +524,7 @@ def test_backward_single_species(c1):
 
 
 # ------------------------------------------------------------------ batch
-@pytest.mark.parametrize("shape", [(2, 8), (8, 0)])
+@pytest.mark.parametrize("shape", [(2, 8), (8, 0), (4, -1)])
 def test_batch_matches_single_boxes(shape):
     from paper_1408_3764_amd.box import Batch, Box
     sizes = [130, 400, 900, 260, 1500]
