@@ -3,7 +3,7 @@
 // (the same chain as Algorithm 1, move for move).
 //
 // Evaluator e takes moves e, e + E, e + 2E, ... of the launch.  It starts
-// move j once the committer is fewer than kAhead moves away, reading a
+// move j once the committer is fewer than AHEAD moves away, reading a
 // snapshot of the chain first: the number of decisions whose stores are
 // complete (its epoch), the number of decided moves C and the current N.  It
 // evaluates j against memory as it finds it (spec_eval: the pick at the N
@@ -21,8 +21,8 @@
 // the move is decided and committed as in the round-based kernel.
 //
 // Deletions move particle N-1 into the freed index: the committer keeps the
-// records of particles mb .. mb + 63 in its lanes (mb follows N) together with
-// the acceptance prefactors for those N, and updates them with every store.
+// records of particles mb .. mb + 63 in LDS (mb follows N) together with the
+// acceptance prefactors for those N, and updates them with every store.
 // Every wait is bounded; a wait that exceeds its bound ends the launch with
 // GCMC_ERR_INTERNAL latched in the box.
 #include "spec_eval.h"
@@ -30,7 +30,9 @@
 namespace gcmc {
 
 constexpr int kSlots = 16;        // evaluated moves held ahead of the committer (slot = move mod kSlots)
-constexpr int kAhead = 14;        // an evaluator starts a move only this close to the committer
+// AHEAD (template): an evaluator starts a move only this close to the committer
+// (at most kSlots - 2).  Farther ahead, the pick at the N expected at the
+// decision misses more often.
 constexpr int kLogLen = 64;       // decisions kept for validation
 constexpr int kWin = 64;          // committer lanes holding particle records mb .. mb + 63
 constexpr int32_t kSpinCap = 1 << 26;
@@ -50,6 +52,9 @@ struct AsyncShared {
     int32_t stop;
     int32_t pad;
     double acc[2];                 // running acceptance of insertions, deletions
+    // the committer's window: records of particles mb .. mb + 63, prefactors at N = mb + t
+    double4 wrec[kWin];
+    double wlpi[kWin], wlpd[kWin];
 };
 
 __device__ __forceinline__ int32_t lds_load(const int32_t* p) {
@@ -58,11 +63,22 @@ __device__ __forceinline__ int32_t lds_load(const int32_t* p) {
 __device__ __forceinline__ uint64_t lds_load64(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void lds_store(int32_t* p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Publish a flag after this wavefront's earlier LDS accesses.  The fence is
+// limited to LDS: a workgroup-scope release of all memory would first wait for
+// every outstanding global store (the committer's stores of the move just
+// decided), which only the store-visibility counter needs.
+__device__ __forceinline__ void lds_publish(int32_t* p, int32_t v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void lds_store64(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ void lds_publish64(uint64_t* p, uint64_t v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Publish the store-visibility counter: every global store issued before it is complete.
+__device__ __forceinline__ void publish_visible(int32_t* p, int32_t v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ int32_t pack_cell(int32_t x, int32_t y, int32_t z) { return x | (y << 10) | (z << 20); }
@@ -72,30 +88,30 @@ __device__ __forceinline__ bool logged_in_stencil(const DevBox& B, int32_t pc, c
     return pc >= 0 && in_stencil(B, pc & 0x3FF, (pc >> 10) & 0x3FF, pc >> 20, c);
 }
 
-// Particle records mb .. mb + 63 (one per lane) and the prefactors at N = mb + lane.
-struct Window {
-    int64_t mb;
-    double4 r;
-    double lpi, lpd;
-};
-
-__device__ __forceinline__ void window_fill(const DevBox& B, Window& w, int64_t mb, int64_t N, int lane,
-                                            bool keep_upper) {
-    // keep_upper: the old window started 32 below: lanes 0..31 take its lanes 32..63
+// Fill the window with particles mb .. mb + 63 (one lane each): `from` holds
+// the old window's records for lanes whose index it covered (shift = new mb - old mb).
+__device__ __forceinline__ void window_fill(const DevBox& B, AsyncShared& S, int64_t mb, int64_t old_mb, int64_t N,
+                                            int lane) {
     const int64_t j = mb + lane;
-    const double x = __shfl(w.r.x, lane + 32, kWave), y = __shfl(w.r.y, lane + 32, kWave);
-    const double z = __shfl(w.r.z, lane + 32, kWave), m = __shfl(w.r.w, lane + 32, kWave);
+    const int64_t o = j - old_mb;   // lane of the old window that held particle j
     double4 nr = make_double4(0, 0, 0, 0);
-    if (keep_upper && lane < 32) nr = make_double4(x, y, z, m);
+    if (old_mb >= 0 && o >= 0 && o < kWin) nr = S.wrec[o];
     else if (j < N) nr = gload(B.pos + j);
-    w.r = nr;
-    w.mb = mb;
     const double n = (double)j;
-    w.lpi = log(B.V / (B.lambda3 * (n + 1.0)));
-    w.lpd = j >= 1 ? log((B.lambda3 * n) / B.V) : 0.0;
+    const double lpi = log(B.V / (B.lambda3 * (n + 1.0)));
+    const double lpd = j >= 1 ? log((B.lambda3 * n) / B.V) : 0.0;
+    // every lane has read the old window before any lane writes the new one
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+    S.wrec[lane] = nr;
+    S.wlpi[lane] = lpi;
+    S.wlpd[lane] = lpd;
+    // wait for the loads here: loads and stores share one counter, and a load still
+    // pending in the decision loop would make later waits wait for its stores too
+    __builtin_amdgcn_s_waitcnt(0);
 }
 
-template <int E, int CR>
+template <int E, int CR, int AHEAD>
 __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __restrict__ boxes,
                                                                 const int32_t* __restrict__ order, int64_t n_moves,
                                                                 uint64_t ctr0, gcmc_stats* stats, gcmc_log* trace) {
@@ -155,10 +171,10 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             }
             if (target < 0) {
                 const int32_t C = uni((int32_t)(lds_load64(&S.cn) >> 32));
-                if (jn >= n_moves || jn - C >= kAhead) {
+                if (jn >= n_moves || jn - C >= AHEAD) {
                     __builtin_amdgcn_s_sleep(2);
                     if (++spins > kSpinCap) {
-                        if (lane == 0) lds_store(&S.stop, 1);
+                        if (lane == 0) lds_publish(&S.stop, 1);
                         break;
                     }
                     continue;
@@ -178,13 +194,15 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             if (lane == 0) {
                 S.slot_move[s] = target;
                 S.slot_epoch[s] = vis;
-                lds_store(&S.slot_state[s], SLOT_READY);
+                lds_publish(&S.slot_state[s], SLOT_READY);
             }
         }
         return;
     }
 
     // ====================================================== committer
+    // the committer is the chain's critical path: it issues before the evaluators sharing its SIMD
+    __builtin_amdgcn_s_setprio(3);
     int64_t N = N0;
     double U = unid(st->u_pair);
     int32_t maxc = uni(st->maxcount);
@@ -199,31 +217,19 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
     int64_t att0 = 0, att1 = 0, att2 = 0, acc0 = 0, acc1 = 0, acc2 = 0;
     double sum_n = 0.0, sum_u = 0.0;
     int64_t stencils = 0, cand = 0, evals = 0, incut = 0;
-    Window W;
-    W.r = make_double4(0, 0, 0, 0);
-    window_fill(B, W, N - 32 > 0 ? N - 32 : 0, N, lane, false);
+    int64_t mb = N - 32 > 0 ? N - 32 : 0;
+    window_fill(B, S, mb, -1, N, lane);
     int32_t vis_pub = 0;
     int64_t j = 0;
     for (; err == GCMC_OK && j < n_moves; ++j) {
         // keep N - 1 and N inside the window
-        if (N - W.mb < 8 && W.mb > 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // stores below the window are complete
-            const int64_t nb = W.mb - 32 > 0 ? W.mb - 32 : 0;
-            // lane t of the new window is lane t - off of the old one, or below it
-            const int off = (int)(W.mb - nb);
-            const int src = lane - off > 0 ? lane - off : 0;
-            const double x = __shfl(W.r.x, src, kWave), y = __shfl(W.r.y, src, kWave);
-            const double z = __shfl(W.r.z, src, kWave), m = __shfl(W.r.w, src, kWave);
-            const int64_t jj = nb + lane;
-            double4 nr = make_double4(x, y, z, m);
-            if (jj < W.mb) nr = gload(B.pos + jj);
-            W.r = nr;
-            W.mb = nb;
-            const double n = (double)jj;
-            W.lpi = log(B.V / (B.lambda3 * (n + 1.0)));
-            W.lpd = jj >= 1 ? log((B.lambda3 * n) / B.V) : 0.0;
-        } else if (N - W.mb > kWin - 8) {
-            window_fill(B, W, W.mb + 32, N, lane, true);
+        if ((N - mb < 8 && mb > 0) || N - mb > kWin - 8) {
+            // the new window's particles below the old one come from memory: the
+            // committer's stores to them must be complete first
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            const int64_t nb = (N - mb < 8) ? (mb - 32 > 0 ? mb - 32 : 0) : mb + 32;
+            window_fill(B, S, nb, mb, N, lane);
+            mb = nb;
         }
         const int s = (int)(j % kSlots);
         // ---- the evaluation of move j
@@ -276,9 +282,9 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             vis_pub = (int32_t)j;
             if (lane == 0) {
-                lds_store(&S.vis, vis_pub);
-                lds_store(&S.slot_state[s], SLOT_REDO);
-                lds_store(&S.redo, (int32_t)j);
+                publish_visible(&S.vis, vis_pub);
+                lds_publish(&S.slot_state[s], SLOT_REDO);
+                lds_publish(&S.redo, (int32_t)j);
             }
             spins = 0;
             while (!(uni(lds_load(&S.slot_state[s])) == SLOT_READY)) {
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             err_move = (int64_t)ctr;
             break;
         }
-        const SpecRec& R = S.rec[s];
+        const SpecRec R = S.rec[s];   // the whole record in one batch of LDS reads
         // the decision's log entry: nothing modified until shown otherwise
         int32_t lc0 = -1, lc1 = -1, lc2 = -1, li0 = -1, li1 = -1, li2 = -1;
         if (type != GCMC_MOVE_INSERT && N == 0) {
@@ -313,8 +319,8 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             const double dUp = R.dUp;
             const double dUt = is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
             const double dU = dUp + dUt;
-            const int wl = (int)(N - W.mb);
-            const double lpref = is_disp ? 0.0 : (is_ins ? read_lane(W.lpi, wl) : read_lane(W.lpd, wl));
+            const int wl = (int)(N - mb);
+            const double lpref = is_disp ? 0.0 : (is_ins ? S.wlpi[wl] : S.wlpd[wl]);
             const double arg = is_disp ? -(B.beta * dU)
                                        : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
             const bool ok = __builtin_amdgcn_readfirstlane((dU == dU && R.lnA < arg) ? 1 : 0) != 0;
@@ -343,9 +349,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
                 // the record of particle N-1 as of now
                 double4 rl = make_double4(0.0, 0.0, 0.0, 0.0);
                 if (type == GCMC_MOVE_DELETE) {
-                    const int t = (int)(N - 1 - W.mb);
-                    rl = make_double4(read_lane(W.r.x, t), read_lane(W.r.y, t), read_lane(W.r.z, t),
-                                      read_lane(W.r.w, t));
+                    rl = S.wrec[N - 1 - mb];
                 }
                 const int32_t rl_cell = __builtin_amdgcn_readfirstlane(meta_low(rl.w) / cap);
                 if (swap) {
@@ -354,7 +358,8 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
                         gstore(B.ent + loc, R.elast);
                         gstore_w(B.pos + id_last, w);
                     }
-                    if ((int64_t)lane == (int64_t)id_last - W.mb) W.r.w = w;
+                    const int64_t t = (int64_t)id_last - mb;
+                    if (lane == 0 && t >= 0 && t < kWin) S.wrec[t].w = w;
                 }
                 if (removes && lane == 0) gstore(B.count + c0, cnt0 - 1);
                 double4 nr = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -388,7 +393,8 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
                 }
                 if (jp >= 0) {
                     if (lane == 0) gstore(B.pos + jp, nr);
-                    if ((int64_t)lane == jp - W.mb) W.r = nr;
+                    const int64_t t = jp - mb;
+                    if (lane == 0 && t >= 0 && t < kWin) S.wrec[t] = nr;
                 }
                 // the log entry: cells modified, particle records rewritten
                 lc0 = pack_cell(R.c0[0], R.c0[1], R.c0[2]);
@@ -431,8 +437,8 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             const int q = (int)(j % kLogLen);
             S.log_cell[q][0] = lc0; S.log_cell[q][1] = lc1; S.log_cell[q][2] = lc2;
             S.log_id[q][0] = li0; S.log_id[q][1] = li1; S.log_id[q][2] = li2;
-            lds_store(&S.slot_state[s], SLOT_FREE);
-            lds_store64(&S.cn, ((uint64_t)(j + 1) << 32) | (uint64_t)(uint32_t)N);
+            lds_publish(&S.slot_state[s], SLOT_FREE);
+            lds_publish64(&S.cn, ((uint64_t)(j + 1) << 32) | (uint64_t)(uint32_t)N);
         }
         // completed stores are published now and then (and always before asking for a move again)
         const int s1 = (int)((j + 1) % kSlots);
@@ -443,11 +449,11 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             if (lane == 0) {
                 S.acc[0] = ((double)acc1 + 1.0) / ((double)att1 + 2.0);
                 S.acc[1] = ((double)acc2 + 1.0) / ((double)att2 + 2.0);
-                lds_store(&S.vis, vis_pub);
+                publish_visible(&S.vis, vis_pub);
             }
         }
     }
-    if (lane == 0) lds_store(&S.stop, 1);
+    if (lane == 0) lds_publish(&S.stop, 1);
     if (lane == 0) {
         st->n = N;
         st->u_pair = U;
@@ -483,13 +489,14 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
 using async_fn = void (*)(const DevBox*, const int32_t*, int64_t, uint64_t, gcmc_stats*, gcmc_log*);
 
 struct AsyncCfg {
+    int key;     // the waves value of gcmc_box_set_launch that selects it
     int waves;   // evaluators + the committer
     async_fn f;
 };
 
 static const AsyncCfg kAsyncCfgs[] = {
-    {4, k_chain_async<3, 8>},
-    {8, k_chain_async<7, 8>},
+    {4, 4, k_chain_async<3, 8, 4>},
+    {8, 8, k_chain_async<7, 8, 4>},
 };
 
 // Cells are logged packed in 10 bits per axis.
@@ -499,7 +506,7 @@ bool async_supported(const DevBox& hb) {
 
 bool async_cfg_exists(int waves) {
     for (const AsyncCfg& c : kAsyncCfgs)
-        if (c.waves == waves) return true;
+        if (c.key == waves) return true;
     return false;
 }
 
@@ -507,7 +514,7 @@ int launch_chain_async(const DevBox* d_boxes, const int32_t* d_order, int n_boxe
                        uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s) {
     if (n_moves >= ((int64_t)1 << 31)) return -1;
     for (const AsyncCfg& c : kAsyncCfgs) {
-        if (c.waves == waves) {
+        if (c.key == waves) {
             hipLaunchKernelGGL(c.f, dim3(n_boxes), dim3(kWave * c.waves), 0, s, d_boxes, d_order, n_moves, ctr0,
                                stats, log);
             return 0;
