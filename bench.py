@@ -131,23 +131,30 @@ def extra_configs(Box, tune, stream):
     mb.total_energy_device()
     mb.backward_device(mw.n)
     torch.cuda.synchronize()
-    fw, bw = [], []
+    from paper_1408_3764_amd import _lib
+    vout = torch.empty(2, dtype=torch.float64, device="cuda")
+    fw, bw, vw = [], [], []
     for k in range(5):
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
         e0.record(stream)
         mb.total_energy_device()
         e1.record(stream)
         mb.backward_device(mw.n)
         e2.record(stream)
+        _lib.gcmc_virial(mb.handle, vout, mb.stream)
+        e3.record(stream)
         torch.cuda.synchronize()
         fw.append(e0.elapsed_time(e1))
         bw.append(e1.elapsed_time(e2))
-    f, b = float(np.median(fw)), float(np.median(bw))
+        vw.append(e2.elapsed_time(e3))
+    f, b, v = float(np.median(fw)), float(np.median(bw)), float(np.median(vw))
     res["mixture"] = {"workload": mw.name, "n": mw.n, "forward_ms_median": f, "backward_ms_median": b,
-                      "pair_distances": pairs, "pair_distances_per_s_forward": pairs / (f / 1e3),
+                      "virial_ms_median": v, "pair_distances": pairs,
+                      "pair_distances_per_s_forward": pairs / (f / 1e3),
                       "pair_distances_per_s_backward": pairs / (b / 1e3)}
     mb.close()
-    log("mixture N=%d: forward %.3f ms, backward %.3f ms, %.3g pair distances per pass" % (mw.n, f, b, pairs))
+    log("mixture N=%d: forward %.3f ms, backward %.3f ms, virial %.3f ms, %.3g pair distances per pass" %
+        (mw.n, f, b, v, pairs))
     return res
 
 

@@ -247,6 +247,17 @@ int gcmc_total_energy(gcmc_box* box, int32_t all_pairs, double* d_U, double* d_e
  * outputs may be NULL. */
 int gcmc_backward(gcmc_box* box, double* d_grad, double* d_deps, double* d_dsig, void* stream);
 
+/* Pressure from the virial of the pair forces (Eq. 1 differentiated, as in
+ * gcmc_backward; the running averages of the chain are in gcmc_stats).
+ * d_out[0] = W = sum over pairs inside the cutoff of -r du/dr
+ *              = sum 24 eps_ab [2 (sigma_ab/r)^12 - (sigma_ab/r)^6],
+ * d_out[1] = P = N k_B T / V + W / (3 V) + P_tail, where P_tail is the
+ * pressure of the full potential beyond r_c (the counterpart of U_tail):
+ * (16 pi / (3 V^2)) sum_ab N_a N_b eps_ab sigma_ab^3 [(2/3)(sigma_ab/r_c)^9
+ * - (sigma_ab/r_c)^3].  Cell-list sums in a fixed order; d_out is device
+ * memory, written on `stream`. */
+int gcmc_virial(gcmc_box* box, double* d_out, void* stream);
+
 /* ------------------------------------------------------------- batches */
 
 /* Group existing single-species boxes (all must stay alive) so that

@@ -102,6 +102,9 @@ def lib():
         L.oracle_neighbor_ids.restype = C.c_int64
         L.oracle_particle_gradient.argtypes = [C.c_int64, dp, dp, dp, ip, C.c_int64, pp, dp]
         L.oracle_gradients.argtypes = [C.c_int64, dp, dp, dp, ip, pp, dp, dp, dp, dp, dp]
+        L.oracle_tail_pressure.argtypes = [lp, pp]
+        L.oracle_tail_pressure.restype = C.c_double
+        L.oracle_virial.argtypes = [C.c_int64, dp, dp, dp, ip, pp, dp]
         _lib = L
     return _lib
 
@@ -282,3 +285,17 @@ def gradients(pos, p, species=None, positions=True):
         lib().oracle_gradients(n, _d(x), _d(y), _d(z), _i(sp), C.byref(p), None, None, None, _d(de), _d(ds))
         g = None
     return g, de.reshape(ns, ns), ds.reshape(ns, ns)
+
+
+def virial(pos, p, species=None):
+    """Pair virial and pressure: {"W", "sumabs", "P_tail", "P"} (P = N/(beta V) + W/(3V) + P_tail)."""
+    x, y, z = (_f64(pos[:, a]) for a in range(3))
+    sp = None if species is None else np.ascontiguousarray(species, dtype=np.int32)
+    out = np.zeros(4)
+    lib().oracle_virial(len(x), _d(x), _d(y), _d(z), _i(sp), C.byref(p), _d(out))
+    return {"W": float(out[0]), "sumabs": float(out[1]), "P_tail": float(out[2]), "P": float(out[3])}
+
+
+def tail_pressure(counts, p):
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    return float(lib().oracle_tail_pressure(_l(c), C.byref(p)))

@@ -624,3 +624,66 @@ void oracle_gradients(int64_t n, const double* x, const double* y, const double*
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pressure from the virial of the pair forces of Eq. (1).                  */
+/*   w(r) = -r du/dr = 24 eps [2 (sigma/r)^12 - (sigma/r)^6]  (r < r_c)     */
+/*   W    = sum over pairs i < j of w(r_ij)                                 */
+/*   P    = N / (beta V) + W / (3 V) + P_tail                               */
+/* P_tail is the pressure of the full potential beyond r_c, the counterpart */
+/* of the energy tail correction:                                           */
+/*   P_tail = -(2 pi / 3) sum_ab rho_a rho_b int_rc^inf r^3 u'_ab(r) dr     */
+/*          = (16 pi / (3 V^2)) sum_ab N_a N_b eps_ab sigma_ab^3            */
+/*            [(2/3) (sigma_ab/r_c)^9 - (sigma_ab/r_c)^3].                  */
+/* out[0] = W, out[1] = sum |w| (tolerance scale), out[2] = P_tail,         */
+/* out[3] = P.  Plain all-pairs loop, compensated sums.                     */
+/* ------------------------------------------------------------------------ */
+static double pair_w(const oracle_params* p, int32_t a, int32_t b, double r2)
+{
+    int ns = p->ns;
+    double eps = p->eps[a * ns + b], sigma = p->sigma[a * ns + b];
+    if (!(r2 < p->rc * p->rc) || eps == 0.0)
+        return 0.0;
+    if (r2 == 0.0)
+        return INFINITY;
+    double sr2 = (sigma * sigma) / r2;
+    double sr6 = sr2 * sr2 * sr2;
+    return 24.0 * eps * (2.0 * (sr6 * sr6) - sr6);
+}
+
+double oracle_tail_pressure(const int64_t* counts, const oracle_params* p)
+{
+    double V = box_volume(p);
+    double s = 0.0;
+    for (int a = 0; a < p->ns; ++a) {
+        for (int b = 0; b < p->ns; ++b) {
+            double eps = p->eps[a * p->ns + b], sig = p->sigma[a * p->ns + b];
+            double q = sig / p->rc;
+            double q3 = q * q * q;
+            s += (double)counts[a] * (double)counts[b] * eps * sig * sig * sig * ((2.0 / 3.0) * q3 * q3 * q3 - q3);
+        }
+    }
+    return (16.0 * M_PI / (3.0 * V * V)) * s;
+}
+
+void oracle_virial(int64_t n, const double* x, const double* y, const double* z, const int32_t* sp,
+                   const oracle_params* p, double out[4])
+{
+    nsum s = {0, 0}, a = {0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            double r2 = oracle_dist2(p->L, x[i], y[i], z[i], x[j], y[j], z[j]);
+            double w = pair_w(p, sp ? sp[i] : 0, sp ? sp[j] : 0, r2);
+            nsum_add(&s, w);
+            nsum_add(&a, fabs(w));
+        }
+    }
+    int64_t counts[ORACLE_MAX_SPECIES] = {0};
+    for (int64_t i = 0; i < n; ++i)
+        counts[sp ? sp[i] : 0] += 1;
+    double V = box_volume(p);
+    out[0] = nsum_get(&s);
+    out[1] = nsum_get(&a);
+    out[2] = oracle_tail_pressure(counts, p);
+    out[3] = (double)n / (p->beta * V) + out[0] / (3.0 * V) + out[2];
+}

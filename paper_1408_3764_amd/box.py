@@ -146,6 +146,13 @@ class Box:
             out["d_sigma"] = ds.view(self.ns, self.ns).cpu().numpy()
         return out
 
+    def virial(self):
+        """{"W": pair virial, "P": pressure with the ideal and tail terms}."""
+        out = torch.zeros(2, dtype=torch.float64, device=self.device)
+        _lib.gcmc_virial(self.handle, out, self.stream)
+        v = out.cpu().numpy()
+        return {"W": float(v[0]), "P": float(v[1])}
+
     # ----------------------------------------------------------- inspection
     @property
     def n(self):

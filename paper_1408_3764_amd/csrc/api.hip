@@ -136,6 +136,20 @@ int gcmc_total_energy(gcmc_box* box, int32_t all_pairs, double* d_U, double* d_e
     return GCMC_OK;
 }
 
+int gcmc_virial(gcmc_box* box, double* d_out, void* stream) {
+    if (!box || !d_out) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    BoxState h;
+    int rc = poisoned_check(box, s, &h);
+    if (rc) return rc;
+    if ((rc = ensure_scratch(box, total_partials_needed(box->d, h.maxcount, false, h.n)))) return rc;
+    const int r = launch_virial(box->d, box->d_desc, h.maxcount, box->scratch, box->scratch_len, d_out, s);
+    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
+    if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
+    GCMC_HIP(hipGetLastError());
+    return GCMC_OK;
+}
+
 int gcmc_backward(gcmc_box* box, double* d_grad, double* d_deps, double* d_dsig, void* stream) {
     if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
     hipStream_t s = (hipStream_t)stream;

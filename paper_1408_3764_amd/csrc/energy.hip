@@ -47,7 +47,8 @@ __device__ __forceinline__ void cell_coords(const DevBox& B, int64_t c, int32_t&
 
 // ------------------------------------------------------ cell-list total
 // Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
-template <bool MIX>
+// VIR: the pair virial -r du/dr in place of the pair energy (pressure).
+template <bool MIX, bool VIR = false>
 __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__ boxp, int lg, double* e_out,
                                                        double* partial) {
     __shared__ uint32_t tab[kMaxStencil];
@@ -77,12 +78,9 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
                     const double4 o = ne[j];
                     if (own && meta_low(o.w) != myid) {
                         const double r2 = dist2(B, me.x, me.y, me.z, o.x, o.y, o.z);
-                        if (MIX) {
-                            const int q = sa * B.ns + meta_species(o.w);
-                            ei += lj_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q]);
-                        } else {
-                            ei += lj_from_r2(r2, B.rc2, B.eps4[0], B.sig2[0]);
-                        }
+                        const int q = MIX ? sa * B.ns + meta_species(o.w) : 0;
+                        ei += VIR ? lj_virial_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q])
+                                  : lj_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q]);
                     }
                 }
             }
@@ -148,6 +146,37 @@ __global__ __launch_bounds__(kBlk) void k_total_finish(const DevBox* __restrict_
         U[0] = up;
         U[1] = ut;
         if (B.st->error == GCMC_OK) B.st->u_pair = up;
+    }
+}
+
+// The virial W = sum over pairs inside the cutoff of -r du/dr (half the sum of
+// the per-particle sums, in a fixed order) and the pressure
+// P = N / (beta V) + W / (3V) + P_tail, P_tail the pressure of the full potential
+// beyond r_c: (16 pi / (3 V^2)) sum_ab N_a N_b eps_ab sigma_ab^3 [(2/3) q^9 - q^3],
+// q = sigma_ab / r_c.
+__global__ __launch_bounds__(kBlk) void k_virial_finish(const DevBox* __restrict__ boxp, const double* partial,
+                                                         int64_t np, double* out) {
+    __shared__ double red[kBlk / kWave];
+    const DevBox& B = *boxp;
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < np; q += kBlk) s += partial[q];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        const double W = 0.5 * s;
+        const double rc = sqrt(B.rc2);
+        double pt = 0.0;
+        for (int a = 0; a < B.ns; ++a)
+            for (int b = 0; b < B.ns; ++b) {
+                const int k = a * B.ns + b;
+                const double sig = sqrt(B.sig2[k]);
+                const double q3 = (sig / rc) * (sig / rc) * (sig / rc);
+                const double eps = 0.25 * B.eps4[k];
+                pt += (double)B.st->nsp[a] * (double)B.st->nsp[b] * eps * (sig * sig * sig) *
+                      ((2.0 / 3.0) * (q3 * q3 * q3) - q3);
+            }
+        pt *= 16.0 * M_PI / (3.0 * B.V * B.V);
+        out[0] = W;
+        out[1] = (double)B.st->n / (B.beta * B.V) + W / (3.0 * B.V) + pt;
     }
 }
 
@@ -644,6 +673,23 @@ int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_p
             hipLaunchKernelGGL(k_total_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, e_out, partial);
     }
     hipLaunchKernelGGL(k_total_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, U);
+    return 0;
+}
+
+int launch_virial(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* partial, int64_t partial_len,
+                  double* out, hipStream_t s) {
+    const int lg = maxc <= 1 ? 0 : 32 - __builtin_clz((unsigned)(maxc - 1));
+    if (lg > 8) return -2;
+    const int cpb = kBlk >> lg;
+    const int64_t nb = (hb.ncells + cpb - 1) / cpb;
+    if (nb > partial_len) return -1;
+    if (hb.ns > 1)
+        hipLaunchKernelGGL((k_total_cells<true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, nullptr,
+                           partial);
+    else
+        hipLaunchKernelGGL((k_total_cells<false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, nullptr,
+                           partial);
+    hipLaunchKernelGGL(k_virial_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, out);
     return 0;
 }
 

@@ -208,6 +208,16 @@ __device__ __forceinline__ double lj_from_r2(double r2, double rc2, double eps4,
     return eps4 * (s6 * s6 - s6);
 }
 
+// Pair virial -r du/dr of the truncated potential inside the cutoff:
+// 24 eps [2 (sigma/r)^12 - (sigma/r)^6] (eps4 = 4 eps).
+__device__ __forceinline__ double lj_virial_from_r2(double r2, double rc2, double eps4, double sig2) {
+    if (!(r2 < rc2) || eps4 == 0.0) return 0.0;
+    if (r2 == 0.0) return __builtin_inf();
+    const double sr2 = sig2 / r2;
+    const double s6 = sr2 * sr2 * sr2;
+    return 6.0 * eps4 * (2.0 * (s6 * s6) - s6);
+}
+
 __device__ __forceinline__ double dist2(const DevBox& B, double px, double py, double pz, double qx, double qy,
                                         double qz) {
     const double dx = nearest_image(qx - px, B.L[0], B.hL[0]);
@@ -362,6 +372,8 @@ void launch_neighbors(const DevBox* d_box, const double* pts, const int32_t* exc
 int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_pairs, double* e_out,
                  double* partial, int64_t partial_len, double* U, hipStream_t s, int64_t n);
 int64_t total_partials_needed(const DevBox& hb, int32_t maxc, bool all_pairs, int64_t n);
+int launch_virial(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* partial, int64_t partial_len,
+                  double* out, hipStream_t s);
 int64_t grad_partials_needed(const DevBox& hb, int32_t maxc);
 int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* grad, double* partial, double* deps,
                 double* dsig, hipStream_t s);

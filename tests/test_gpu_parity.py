@@ -225,6 +225,23 @@ def test_total_energy_parity(case):
         assert np.allclose(got["e"], ref["e"], rtol=0, atol=1e-10 * max(1.0, np.abs(ref["e"]).max()))
 
 
+@pytest.mark.parametrize("case", list(SMALL_CASES) + ["mixture"])
+def test_virial_parity(case):
+    """Pair virial and pressure against the oracle's all-pairs sums."""
+    if case == "mixture":
+        eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+        wb = workloads.random_box(400, 11.0, rc=3.0, seed=6, species_counts=[200, 200], eps=eps, sigma=sig)
+        ref = oracle.virial(wb.pos, _params(wb), species=wb.species)
+    else:
+        c = SMALL_CASES[case]
+        wb = workloads.random_box(c["n"], c["L"], seed=c["seed"])
+        ref = oracle.virial(wb.pos, _params(wb))
+    got = _box(wb).virial()
+    V = float(np.prod(wb.L))
+    assert abs(got["W"] - ref["W"]) <= 1e-10 * ref["sumabs"]
+    assert abs(got["P"] - ref["P"]) <= 1e-10 * (abs(ref["P"]) + ref["sumabs"] / (3 * V))
+
+
 def test_total_energy_c1(c1):
     p = _params(c1)
     ref = oracle.total_energy(c1.pos, p)

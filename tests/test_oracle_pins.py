@@ -439,3 +439,76 @@ def test_gradient_finite_differences(orc):
         want_s = ds[a, c] + (ds[c, a] if a != c else 0.0)
         assert fd_e == pytest.approx(want_e, rel=1e-6)
         assert fd_s == pytest.approx(want_s, rel=1e-5)
+
+
+# --------------------------------------------------------------------------
+# Virial and pressure: the tail against quadrature of its definition, the
+# pair virial against the derivative of U_pair under uniform scaling
+# --------------------------------------------------------------------------
+def test_tail_pressure_vs_quadrature(orc):
+    """P_tail = -(2 pi/3) sum_ab rho_a rho_b int_rc^inf r^3 u_ab'(r) dr, with u'
+    taken by central differences of the potential (one and two species)."""
+    from scipy.integrate import quad
+
+    def u(r, e, s):
+        return 4.0 * e * ((s / r) ** 12 - (s / r) ** 6)
+
+    def du(r, e, s):
+        h = 1e-5 * r
+        return (u(r + h, e, s) - u(r - h, e, s)) / (2 * h)
+
+    L = np.array([13.0, 14.0, 15.0])
+    V = float((L[0] * L[1]) * L[2])
+    for rc in (2.5, 3.0):
+        p = orc.make_params(L, rc)
+        integ, _ = quad(lambda r: r ** 3 * du(r, 1.0, 1.0), rc, np.inf, epsabs=0, epsrel=1e-12)
+        N = 1234
+        ref = -(2.0 * math.pi / 3.0) * (N / V) ** 2 * integ
+        assert orc.tail_pressure([N], p) == pytest.approx(ref, rel=1e-8)
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    p = orc.make_params(L, 3.0, eps=eps, sigma=sig)
+    counts = [700, 300]
+    ref = 0.0
+    for a in range(2):
+        for b in range(2):
+            integ, _ = quad(lambda r: r ** 3 * du(r, eps[a, b], sig[a, b]), 3.0, np.inf, epsabs=0, epsrel=1e-12)
+            ref += -(2.0 * math.pi / 3.0) * counts[a] * counts[b] / V ** 2 * integ
+    assert orc.tail_pressure(counts, p) == pytest.approx(ref, rel=1e-8)
+
+
+@pytest.mark.parametrize("mixture", [False, True])
+def test_virial_is_scaling_derivative(orc, mixture):
+    """W = sum r u'(r) with the sign of -dU_pair/d lambda at lambda = 1 when every
+    position and the box are scaled by lambda (no pair near the cutoff)."""
+    if mixture:
+        eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+        b = workloads.random_box(160, 8.5, seed=43, species_counts=[80, 80], eps=eps, sigma=sig)
+        rc, sp = 3.0, b.species
+    else:
+        eps, sig = 1.0, 1.0
+        b = workloads.random_box(200, 8.0, seed=44)
+        rc, sp = 2.5, None
+    d = b.pos[:, None, :] - b.pos[None, :, :]
+    d -= b.L * np.round(d / b.L)
+    r = np.sqrt((d * d).sum(axis=2))
+    assert not np.any(np.abs(r[np.triu_indices(b.n, 1)] - rc) < 1e-5 * rc)
+    h = 1e-6
+
+    def U(lam):
+        q = orc.make_params(np.asarray(b.L) * lam, rc, eps=eps, sigma=sig)
+        return orc.total_energy(b.pos * lam, q, species=sp)["U_pair"]
+
+    p = orc.make_params(b.L, rc, eps=eps, sigma=sig)
+    v = orc.virial(b.pos, p, species=sp)
+    fd = (U(1 + h) - U(1 - h)) / (2 * h)
+    assert abs(v["W"] + fd) <= 1e-6 * v["sumabs"]
+    assert v["sumabs"] > 0
+
+
+def test_virial_ideal_gas(orc):
+    b = workloads.random_box(100, 7.0, seed=45)
+    p = orc.make_params(b.L, 2.5, eps=0.0, beta=1 / 1.7)
+    v = orc.virial(b.pos, p)
+    V = float(np.prod(b.L))
+    assert v["W"] == 0.0 and v["P_tail"] == 0.0
+    assert v["P"] == pytest.approx(100 * 1.7 / V, rel=1e-15)
