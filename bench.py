@@ -158,6 +158,58 @@ def extra_configs(Box, tune, stream):
     return res
 
 
+def cell_size_sweep():
+    """Traditional cells (side >= rc) against microcells of about rc/2 and rc/3
+    (Sec. 3.3), whose stencils of 2k+1 cells per axis drop the cells beyond the
+    cutoff, on the small, large and slab workloads: for each cell size and each
+    launch shape that applies, moves/s of one chain (median of 3 launches after
+    a warmup launch) and the candidates read per move."""
+    import numpy as np
+    import torch
+    from paper_1408_3764_amd import tune
+    from paper_1408_3764_amd.box import Box
+    from paper_1408_3764_amd._lib import COUNTER_CONTINUE
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, mps in (("small", 1000), ("large", 10_000), ("slab", 10_000)):
+        wb = workload_by_name(name)
+        base = None
+        rows = []
+        for f in (1, 2, 3):
+            kw = {} if f == 1 else {"cell_m": [f * m for m in base]}
+            b = Box.from_workload(wb, max_n=wb.n + 20 * mps + 1000, **kw)
+            info = b.info()
+            base = base or info["cell_m"]
+            shapes = ([(8, 0)] if tune.spec_supported(b) else []) + [(4, 4), (8, 2), (8, 4)]
+            for shape in shapes:
+                b.set_launch(*shape)
+                b.step(mps, counter0=COUNTER_CONTINUE)
+                torch.cuda.synchronize()
+                ts, cand = [], 0
+                for _ in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    st, _ = b.step(mps, counter0=COUNTER_CONTINUE)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    if int(st["error"]) != 0:
+                        raise SystemExit("chain error %d in the cell sweep" % int(st["error"]))
+                    ts.append(e0.elapsed_time(e1))
+                    cand += int(st["candidates"])
+                med = float(np.median(ts))
+                r = {"cell_m": info["cell_m"], "cell_side": [float(wb.L[a] / info["cell_m"][a]) for a in range(3)],
+                     "stencil_cells": info["n_stencil"], "stencil_block": int(np.prod(info["span"])),
+                     "cell_cap": info["cell_cap"], "launch": list(shape), "moves_per_s": mps / (med / 1e3),
+                     "candidates_per_move": cand / (3 * mps)}
+                rows.append(r)
+                log("%s cells %s (stencil %d of %d) launch %dx%d: %.0f moves/s, %.1f candidates/move" %
+                    (name, info["cell_m"], r["stencil_cells"], r["stencil_block"], shape[0], shape[1],
+                     r["moves_per_s"], r["candidates_per_move"]))
+            b.close()
+        out[wb.name] = rows
+    return out
+
+
 def workload_by_name(name):
     from paper_1408_3764_amd import workloads
     return {"slab": workloads.slab, "large": workloads.large, "small": workloads.small}[name]()
@@ -193,6 +245,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the small-box chain and the mixture forward/backward")
     ap.add_argument("--no-allpairs", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="heuristic launch shape instead of timing them")
+    ap.add_argument("--cell-sweep", action="store_true",
+                    help="only compare traditional cells with pruned microcells on the small, large and slab boxes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (reference for the traffic counters)")
     args = ap.parse_args()
@@ -205,6 +259,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 8, "launches": 3}))
+        return
+    if args.cell_sweep:
+        print(json.dumps({"cell_sweep": cell_size_sweep()}))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path here (one box's chain is a "
@@ -226,7 +283,7 @@ def main():
     total_moves = mps * (args.steps + args.warmup) + 40_000   # + the moves the tuner runs
     box = Box.from_workload(wb, max_n=wb.n + total_moves + 1)
     info = box.info()
-    nst = info["span"][0] * info["span"][1] * info["span"][2]
+    nst = info["n_stencil"]
     U0 = box.total_energy()
     tuning = None
     if args.waves:

@@ -68,8 +68,11 @@ typedef struct gcmc_batch gcmc_batch;
  *                (symmetric, already mixed).
  *   max_n        particle capacity (insertions beyond it are GCMC_ERR_CAPACITY).
  *   cell_m       cells per axis, 0 = the paper's rule M = max(3, floor(L/rc))
- *                (Sec. 3.2.2); a larger M gives cells smaller than rc and a
- *                wider stencil of 2k+1 cells, k = ceil(rc M / L).
+ *                (Sec. 3.2.2); a larger M gives cells smaller than rc (the
+ *                microcells of Sec. 3.3) and a wider stencil of 2k+1 cells per
+ *                axis, k = ceil(rc M / L), from which the cells farther than rc
+ *                from the centre cell are dropped (Sec. 5 names this pruning as
+ *                future work).  At most 1024 stencil cells are kept.
  *   cell_cap     per-cell capacity, 0 = automatic.
  *   seed, box_id Philox4x32-10 key and the third counter word of the move stream. */
 typedef struct {
@@ -144,6 +147,10 @@ typedef struct {
     int64_t n_cells;
     int64_t max_n;
     double inv_s[3];     /* M_a / L_a */
+    int32_t n_stencil;   /* stencil cells kept: the span_x x span_y x span_z block less
+                            the cells whose closest point to the centre cell lies
+                            beyond rc (dropped only on axes not covered whole) */
+    int32_t pad;
 } gcmc_box_info;
 
 /* ---------------------------------------------------------------- boxes */

@@ -100,6 +100,8 @@ def lib():
         L.oracle_neighbor_ids.argtypes = [C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int64,
                                           dp, C.c_double, ip, lp, C.c_int64]
         L.oracle_neighbor_ids.restype = C.c_int64
+        L.oracle_stencil_count.argtypes = [dp, C.c_double, ip]
+        L.oracle_stencil_count.restype = C.c_int32
         L.oracle_particle_gradient.argtypes = [C.c_int64, dp, dp, dp, ip, C.c_int64, pp, dp]
         L.oracle_gradients.argtypes = [C.c_int64, dp, dp, dp, ip, pp, dp, dp, dp, dp, dp]
         L.oracle_tail_pressure.argtypes = [lp, pp]
@@ -243,6 +245,13 @@ def grid(L, rc, req_m=None):
     span = np.zeros(3, dtype=np.int32)
     lib().oracle_grid(_d(Lx), float(rc), _i(rq), _i(M), _d(invS), _i(k), _i(span))
     return {"M": M, "invS": invS, "k": k, "span": span}
+
+
+def stencil_count(L, rc, req_m=None):
+    """Stencil cells kept after dropping those beyond the cutoff."""
+    Lx = _f64(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+    rq = np.zeros(3, dtype=np.int32) if req_m is None else np.ascontiguousarray(req_m, dtype=np.int32)
+    return int(lib().oracle_stencil_count(_d(Lx), float(rc), _i(rq)))
 
 
 def cell_of(pos, L, rc, req_m=None):

@@ -495,8 +495,61 @@ static int in_axis_stencil(int32_t c, int32_t c0, int32_t k, int32_t M)
     return 0;
 }
 
-/* Sorted ids j != exclude of the particles whose cell lies in the stencil of
- * the cell of (px,py,pz).  Returns the number of ids (writes at most max_out). */
+/* Pruning of the stencil (the paper's conclusions name dropping the cells
+ * beyond the cutoff as future work): along an axis, cells whose indices differ
+ * by a (wrapped) |t| have |t| - 1 whole cells of side L/M between them when
+ * |t| >= 2, so no two of their points are closer than that gap.  A stencil cell
+ * is dropped when the squared gaps, summed over the axes the stencil does not
+ * cover whole, exceed rc^2 (1 + 1e-9) -- the relative margin keeps a cell whose
+ * gap equals rc up to the rounding of the cell assignment.  Covered axes add
+ * no gap (their offsets are not relative to the centre cell). */
+static double axis_gap(int32_t at, double L, int32_t M)
+{
+    return at >= 2 ? (double)(at - 1) * (L / (double)M) : 0.0;
+}
+
+static int gap_beyond_cutoff(double gap2, double rc)
+{
+    return gap2 > rc * rc * (1.0 + 1e-9);
+}
+
+/* |t| of the offset t in [-k, k] with (c0 + t) mod M == c on an axis the
+ * stencil does not cover whole, else -1. */
+static int32_t axis_offset(int32_t c, int32_t c0, int32_t k, int32_t M)
+{
+    for (int32_t t = -k; t <= k; ++t)
+        if (((c0 + t) % M + M) % M == c)
+            return t < 0 ? -t : t;
+    return -1;
+}
+
+/* Number of stencil cells kept for the grid of (L, rc, req_m). */
+int32_t oracle_stencil_count(const double L[3], double rc, const int32_t req_m[3])
+{
+    int32_t M[3], k[3], span[3];
+    double invS[3];
+    oracle_grid(L, rc, req_m, M, invS, k, span);
+    int32_t kept = 0;
+    for (int32_t i = 0; i < span[0]; ++i)
+        for (int32_t j = 0; j < span[1]; ++j)
+            for (int32_t l = 0; l < span[2]; ++l) {
+                int32_t off[3] = {i - k[0], j - k[1], l - k[2]};
+                double gap2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    if (2 * k[a] + 1 >= M[a])
+                        continue;
+                    double g = axis_gap(off[a] < 0 ? -off[a] : off[a], L[a], M[a]);
+                    gap2 += g * g;
+                }
+                if (!gap_beyond_cutoff(gap2, rc))
+                    ++kept;
+            }
+    return kept;
+}
+
+/* Sorted ids j != exclude of the particles whose cell lies in the (pruned)
+ * stencil of the cell of (px,py,pz).  Returns the number of ids (writes at
+ * most max_out). */
 int64_t oracle_neighbor_ids(int64_t n, const double* x, const double* y, const double* z,
                             double px, double py, double pz, int64_t exclude,
                             const double L[3], double rc, const int32_t req_m[3],
@@ -515,6 +568,16 @@ int64_t oracle_neighbor_ids(int64_t n, const double* x, const double* y, const d
         int ok = 1;
         for (int a = 0; a < 3 && ok; ++a)
             ok = in_axis_stencil(cj[a], c0[a], k[a], M[a]);
+        if (ok) {
+            double gap2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                if (2 * k[a] + 1 >= M[a])
+                    continue;
+                double g = axis_gap(axis_offset(cj[a], c0[a], k[a], M[a]), L[a], M[a]);
+                gap2 += g * g;
+            }
+            ok = !gap_beyond_cutoff(gap2, rc);
+        }
         if (ok) {
             if (cnt < max_out)
                 out[cnt] = j;

@@ -59,6 +59,7 @@ class BoxInfo(C.Structure):
     _fields_ = [
         ("cell_m", C.c_int32 * 3), ("span", C.c_int32 * 3), ("cell_cap", C.c_int32), ("n_species", C.c_int32),
         ("n_cells", C.c_int64), ("max_n", C.c_int64), ("inv_s", C.c_double * 3),
+        ("n_stencil", C.c_int32), ("pad", C.c_int32),
     ]
 
 

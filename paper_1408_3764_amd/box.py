@@ -88,7 +88,7 @@ class Box:
     def info(self):
         i = _lib.gcmc_box_get_info(self.handle)
         return {"cell_m": list(i.cell_m), "span": list(i.span), "cell_cap": i.cell_cap, "n_species": i.n_species,
-                "n_cells": i.n_cells, "max_n": i.max_n, "inv_s": list(i.inv_s)}
+                "n_cells": i.n_cells, "max_n": i.max_n, "inv_s": list(i.inv_s), "n_stencil": i.n_stencil}
 
     def set_launch(self, waves, rows):
         _lib.gcmc_box_set_launch(self.handle, waves, rows)

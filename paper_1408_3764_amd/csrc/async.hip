@@ -130,9 +130,9 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
     const int32_t err0 = uni(st->error);
     const bool no_full = !(B.full[0] | B.full[1] | B.full[2]);
     for (int t = tid; t < B.nstencil; t += blockDim.x) {
-        const int sx = B.span[0], sy = B.span[1];
-        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
-        tab[t] = (uint32_t)tx | ((uint32_t)ty << 10) | ((uint32_t)tz << 20);
+        const uint32_t pk = gload(B.stab + t);
+        const int tx = pk & 0x3FF, ty = (pk >> 10) & 0x3FF, tz = pk >> 20;
+        tab[t] = pk;
         if (t < 64) offs[t] = ((tz - B.k[2]) * B.M[1] + (ty - B.k[1])) * B.M[0] + (tx - B.k[0]);
     }
     for (int t = tid; t < kSlots; t += blockDim.x) {

@@ -10,7 +10,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <string>
+#include <vector>
 
 #include "gcmc_internal.h"
 
@@ -190,7 +192,33 @@ static int validate_desc(const gcmc_box_desc* d, int64_t n) {
 
 // Cells per axis (the paper's rule, or the caller's larger count), the
 // stencil half-width and extent.
-static int setup_grid(DevBox& B, const gcmc_box_desc* d) {
+// Stencil slots kept for this grid.  On an axis the stencil does not cover
+// whole, slot coordinate t stands for the cell offset d = t - k; the closest
+// points of the centre cell and a cell at offset d along that axis are
+// max(0, |d| - 1) cells of side S = L / M apart (0 on a covered axis).  A slot
+// whose squared gap summed over the axes exceeds rc^2 by a relative 1e-9 holds
+// no partner within the cutoff and is dropped (the margin keeps cells whose gap
+// is rc up to rounding of the cell assignment).  Slots stay in x-fastest order.
+static void stencil_slots(const DevBox& B, double rc, std::vector<uint32_t>& slots) {
+    slots.clear();
+    const double lim = (rc * rc) * (1.0 + 1e-9);
+    for (int tz = 0; tz < B.span[2]; ++tz)
+        for (int ty = 0; ty < B.span[1]; ++ty)
+            for (int tx = 0; tx < B.span[0]; ++tx) {
+                const int t[3] = {tx, ty, tz};
+                double g2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    if (B.full[a]) continue;
+                    const int d = std::abs(t[a] - B.k[a]);
+                    const double g = d > 1 ? (double)(d - 1) * (B.L[a] / (double)B.M[a]) : 0.0;
+                    g2 += g * g;
+                }
+                if (g2 > lim) continue;
+                slots.push_back((uint32_t)tx | ((uint32_t)ty << 10) | ((uint32_t)tz << 20));
+            }
+}
+
+static int setup_grid(DevBox& B, const gcmc_box_desc* d, std::vector<uint32_t>& slots) {
     for (int a = 0; a < 3; ++a) {
         int64_t m = (int64_t)floor(d->L[a] / d->rc);
         if (m < 3) m = 3;
@@ -207,7 +235,10 @@ static int setup_grid(DevBox& B, const gcmc_box_desc* d) {
         B.hL[a] = 0.5 * d->L[a];
     }
     B.ncells = (int64_t)B.M[0] * B.M[1] * B.M[2];
-    B.nstencil = B.span[0] * B.span[1] * B.span[2];
+    if ((int64_t)B.span[0] * B.span[1] * B.span[2] > 64 * kMaxStencil)
+        return set_error(GCMC_ERR_INVALID_ARG, "stencil larger than 1024 cells: use fewer, larger cells");
+    stencil_slots(B, d->rc, slots);
+    B.nstencil = (int32_t)slots.size();
     if (B.nstencil > kMaxStencil)
         return set_error(GCMC_ERR_INVALID_ARG, "stencil larger than 1024 cells: use fewer, larger cells");
     return GCMC_OK;
@@ -311,6 +342,7 @@ static void free_box(gcmc_box* box) {
     if (box->d.ent) (void)hipFree(box->d.ent);
     if (box->d.count) (void)hipFree(box->d.count);
     if (box->d.st) (void)hipFree(box->d.st);
+    if (box->d.stab) (void)hipFree((void*)box->d.stab);
     if (box->d_desc) (void)hipFree(box->d_desc);
     if (box->scratch) (void)hipFree(box->scratch);
     if (box->ap_chain) (void)hipFree(box->ap_chain);
@@ -338,11 +370,22 @@ int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* 
     box->waves = 4;
     box->rows = 4;
     DevBox& B = box->d;
-    if ((rc = setup_grid(B, desc))) {
+    std::vector<uint32_t> slots;
+    if ((rc = setup_grid(B, desc, slots))) {
         free_box(box);
         return rc;
     }
     setup_params(B, desc);
+    uint32_t* d_stab = nullptr;
+    if (hipMalloc(&d_stab, slots.size() * sizeof(uint32_t)) != hipSuccess) {
+        free_box(box);
+        return set_error(GCMC_ERR_OOM, "box allocation failed");
+    }
+    B.stab = d_stab;
+    if (hipMemcpy(d_stab, slots.data(), slots.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        free_box(box);
+        return set_error(GCMC_ERR_HIP, "stencil upload failed");
+    }
     if (hipMalloc(&B.pos, (size_t)B.max_n * sizeof(double4)) != hipSuccess ||
         hipMalloc(&B.count, (size_t)B.ncells * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&B.st, sizeof(BoxState)) != hipSuccess || hipMalloc(&box->d_desc, sizeof(DevBox)) != hipSuccess) {
@@ -402,6 +445,8 @@ int gcmc_box_get_info(const gcmc_box* box, gcmc_box_info* info) {
     info->n_species = box->d.ns;
     info->n_cells = box->d.ncells;
     info->max_n = box->d.max_n;
+    info->n_stencil = box->d.nstencil;
+    info->pad = 0;
     return GCMC_OK;
 }
 

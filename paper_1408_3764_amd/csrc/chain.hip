@@ -52,13 +52,6 @@ __device__ __forceinline__ void head_of(const DevBox& B, uint64_t ctr, int64_t n
     }
 }
 
-__device__ __forceinline__ int centre_slot(const DevBox& B, const int32_t* c) {
-    const int tx = B.full[0] ? c[0] : B.k[0];
-    const int ty = B.full[1] ? c[1] : B.k[1];
-    const int tz = B.full[2] ? c[2] : B.k[2];
-    return (tz * B.span[1] + ty) * B.span[0] + tx;
-}
-
 // Cell of position w of the trial, made wave-uniform (the positions are the
 // same in every lane; saying so keeps the stencil arithmetic scalar).
 __device__ __forceinline__ void locate_uniform(const DevBox& B, Trial& T, int w) {
@@ -75,8 +68,8 @@ __device__ __forceinline__ bool interior(const DevBox& B, const int32_t* c) {
     return ok;
 }
 
-// Packed per-row slot description: k | t << 10 | which << 21 | valid << 22.
-constexpr int kSlotT = 10, kSlotW = 21, kSlotV = 22;
+// Packed per-row slot description: k | which << 21 | valid << 22.
+constexpr int kSlotW = 21, kSlotV = 22;
 
 template <int W, int R>
 __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ boxes,
@@ -108,12 +101,11 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
     const int cap = B.cap;
     const int M0 = B.M[0], M01 = B.M[0] * B.M[1];
     const bool no_full = !(B.full[0] | B.full[1] | B.full[2]);
-    const int tcen_fast = (B.k[2] * B.span[1] + B.k[1]) * B.span[0] + B.k[0];
     int64_t m = 0;
     int ev = 0;
     int64_t stencils = 0;
     Work wk;
-    build_stencil(B, tab);
+    load_stencil(B, tab);
     __syncthreads();
 
     // per-lane slot table for the current occupancy level
@@ -192,15 +184,13 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                     const int dy = (int)((pk >> 10) & 0x3FF) - B.k[1];
                     const int dz = (int)(pk >> 20) - B.k[2];
                     soff[r] = dz * M01 + dy * M0 + dx;
-                    sk[r] = (k & 0x3FF) | (t << kSlotT) | (w << kSlotW) | ((s < 2 * NS ? 1 : 0) << kSlotV);
+                    sk[r] = (k & 0x3FF) | (w << kSlotW) | ((s < 2 * NS ? 1 : 0) << kSlotV);
                 }
             }
             const bool fast = __builtin_amdgcn_readfirstlane(
                                   (fast_ok && interior(B, T.c[0]) && (!two || interior(B, T.c[1]))) ? 1 : 0) != 0;
             const int buf = ev & 1;
             const int32_t excl = (int32_t)T.idx;
-            const int tc0 = fast ? tcen_fast : centre_slot(B, T.c[0]);
-            const int tc1 = two ? (fast ? tcen_fast : centre_slot(B, T.c[1])) : -1;
             const int32_t cl0 = (int32_t)T.cl[0], cl1 = (int32_t)T.cl[1];
             double sa = 0.0, sb = 0.0;
             Head Hn;
@@ -209,25 +199,24 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
             // -------------------------------------- gather + evaluate passes
             for (int base = 0; base < total; base += kWave * W * R) {
                 double4 e[R];
-                int32_t cnt[R], kk[R], tt[R], which[R];
+                int32_t cnt[R], kk[R], cc[R], which[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     int32_t c;
                     bool in;
-                    int k, t, w;
+                    int k, w;
                     if (fast) {
                         const int32_t pk = sk[r];
                         w = (pk >> kSlotW) & 1;
                         in = ((pk >> kSlotV) & 1) && (two || !w);
                         k = pk & 0x3FF;
-                        t = (pk >> kSlotT) & 0x7FF;
                         c = (w ? cl1 : cl0) + soff[r];
                     } else {
                         const int s = base + r * kWave * W + tid;
                         in = s < total;
                         w = (two && s >= NS) ? 1 : 0;
                         const int q = in ? s - w * NS : 0;
-                        t = q >> lg;
+                        const int t = q >> lg;
                         k = q & gmask;
                         const int32_t cx = w ? T.c[1][0] : T.c[0][0];
                         const int32_t cy = w ? T.c[1][1] : T.c[0][1];
@@ -239,7 +228,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                     cnt[r] = in ? gload(B.count + c) : 0;
                     e[r] = gload(B.ent + ((size_t)(uint32_t)c * (uint32_t)cap + kc));
                     kk[r] = k;
-                    tt[r] = in ? t : -1;
+                    cc[r] = in ? c : -1;
                     which[r] = w;
                 }
                 if (!have_next) {
@@ -255,8 +244,8 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 int nv = 0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int tcen = which[r] ? tc1 : tc0;
-                    if (tt[r] == tcen) {
+                    // the centre cell appears once in a stencil: found by its index
+                    if (cc[r] == (which[r] ? cl1 : cl0)) {
                         if (kk[r] == 0) sh_cnt[buf][which[r]] = cnt[r];
                         if (which[r] == 0 && kk[r] == cnt[r] - 1) sh_last[buf] = e[r];
                     }

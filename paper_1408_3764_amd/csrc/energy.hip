@@ -30,14 +30,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
-__device__ __forceinline__ void build_stencil_tab(const DevBox& B, uint32_t* tab) {
-    const int sx = B.span[0], sy = B.span[1];
-    for (int t = threadIdx.x; t < B.nstencil; t += blockDim.x) {
-        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
-        tab[t] = (uint32_t)tx | ((uint32_t)ty << 10) | ((uint32_t)tz << 20);
-    }
-}
-
 __device__ __forceinline__ void cell_coords(const DevBox& B, int64_t c, int32_t& cx, int32_t& cy, int32_t& cz) {
     cx = (int32_t)(c % B.M[0]);
     const int64_t r = c / B.M[0];
@@ -54,7 +46,7 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
     const DevBox& B = *boxp;
-    build_stencil_tab(B, tab);
+    load_stencil(B, tab);
     __syncthreads();
     const int G = 1 << lg;
     const int cells_per_blk = kBlk >> lg;
@@ -542,7 +534,7 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
     const DevBox& B = *boxp;
-    build_stencil_tab(B, tab);
+    load_stencil(B, tab);
     __syncthreads();
     const int64_t n = B.st->n;
     const int G = 1 << lg;

@@ -14,7 +14,7 @@ namespace gcmc {
 
 constexpr int kWave = 64;
 constexpr int kMaxSpecies = GCMC_MAX_SPECIES;
-constexpr int kMaxStencil = 1024;   // stencil cells kept in LDS (span_x * span_y * span_z)
+constexpr int kMaxStencil = 1024;   // stencil cells kept in LDS
 
 // Device-resident mutable state of one box.
 struct BoxState {
@@ -55,7 +55,8 @@ struct DevBox {
     double tailK[kMaxSpecies * kMaxSpecies];  // (8 pi / 3V) eps sigma^3 (q^9/3 - q^3), q = sigma / rc
     uint64_t seed;
     uint32_t box_id;
-    int32_t nstencil;    // span_x * span_y * span_z
+    int32_t nstencil;    // stencil cells kept (at most span_x * span_y * span_z)
+    const uint32_t* stab;   // the kept stencil slots, packed tx | ty << 10 | tz << 20 (device)
 };
 
 // ------------------------------------------------------- uniform values
@@ -96,6 +97,7 @@ __device__ __forceinline__ void gstore_w(double4* p, double w) {   // the fourth
     *((GCMC_GLOBAL_AS double*)p + 3) = w;
 }
 __device__ __forceinline__ int32_t gload(const int32_t* p) { return *(const GCMC_GLOBAL_AS int32_t*)p; }
+__device__ __forceinline__ uint32_t gload(const uint32_t* p) { return *(const GCMC_GLOBAL_AS uint32_t*)p; }
 __device__ __forceinline__ void gstore(int32_t* p, int32_t v) { *(GCMC_GLOBAL_AS int32_t*)p = v; }
 
 // ------------------------------------------------------------------ packing
@@ -182,6 +184,12 @@ __device__ __forceinline__ double wrap_into_box(double x, double L) {
 __device__ __forceinline__ int32_t axis_cell(double x, double invS, int32_t M) {
     int32_t c = (int32_t)floor(x * invS);
     return c > M - 1 ? M - 1 : (c < 0 ? 0 : c);
+}
+
+// The box's stencil slots into LDS (all threads of the block take part; the
+// caller synchronises before use).
+__device__ __forceinline__ void load_stencil(const DevBox& B, uint32_t* tab) {
+    for (int t = threadIdx.x; t < B.nstencil; t += blockDim.x) tab[t] = gload(B.stab + t);
 }
 
 // Linear cell index of a stencil slot t around centre cell (cx, cy, cz).

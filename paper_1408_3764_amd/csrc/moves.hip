@@ -11,7 +11,7 @@ __global__ __launch_bounds__(kWave* W) void k_delta(const DevBox* __restrict__ b
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[2 * W];
     const DevBox& B = *boxp;
-    build_stencil(B, tab);
+    load_stencil(B, tab);
     __syncthreads();
     const int64_t n = B.st->n;
     int64_t nsp[kMaxSpecies];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_neighbors(const DevBox* __restrict__ bo
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ int32_t fill;
     const DevBox& B = *boxp;
-    build_stencil(B, tab);
+    load_stencil(B, tab);
     const int lg = log2_ceil(B.st->maxcount);
     const int NS = B.nstencil << lg;
     const int gmask = (1 << lg) - 1;

@@ -69,9 +69,9 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     double sum_n = 0.0, sum_u = 0.0;
     int64_t stencils = 0, cand = 0, evals = 0, incut = 0;
     for (int t = tid; t < B.nstencil; t += blockDim.x) {
-        const int sx = B.span[0], sy = B.span[1];
-        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
-        tab[t] = (uint32_t)tx | ((uint32_t)ty << 10) | ((uint32_t)tz << 20);
+        const uint32_t pk = gload(B.stab + t);
+        const int tx = pk & 0x3FF, ty = (pk >> 10) & 0x3FF, tz = pk >> 20;
+        tab[t] = pk;
         if (t < 64) offs[t] = ((tz - B.k[2]) * B.M[1] + (ty - B.k[1])) * B.M[0] + (tx - B.k[0]);
     }
     __syncthreads();

@@ -167,11 +167,9 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     const int32_t incl = wave_incl_scan(cnt);
     const int32_t pre = incl - cnt;
     const int32_t total = __builtin_amdgcn_readlane(incl, 63);
-    const int tc = ((B.full[2] ? c0[2] : B.k[2]) * B.span[1] + (B.full[1] ? c0[1] : B.k[1])) * B.span[0] +
-                   (B.full[0] ? c0[0] : B.k[0]);
-    const int tc1 = two ? nst + ((B.full[2] ? c1[2] : B.k[2]) * B.span[1] + (B.full[1] ? c1[1] : B.k[1])) * B.span[0] +
-                              (B.full[0] ? c1[0] : B.k[0])
-                        : tc;
+    // lanes of the two centre cells (each appears once in its stencil)
+    const int tc = (int)__builtin_ctzll(__ballot(cell_lane && !wh && cell == cl0));
+    const int tc1 = two ? (int)__builtin_ctzll(__ballot(cell_lane && wh && cell == cl1)) : tc;
     const int32_t cnt0 = __builtin_amdgcn_readlane(cnt, tc);
     const int32_t cnt1 = __builtin_amdgcn_readlane(cnt, tc1);
     // ---- owner of each flattened candidate

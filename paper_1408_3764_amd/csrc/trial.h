@@ -39,15 +39,6 @@ __device__ __forceinline__ void locate(const DevBox& B, Trial& T, int w) {
     T.cl[w] = ((int64_t)T.c[w][2] * B.M[1] + T.c[w][1]) * B.M[0] + T.c[w][0];
 }
 
-// Stencil offsets (packed tx | ty << 10 | tz << 20) into LDS.
-__device__ __forceinline__ void build_stencil(const DevBox& B, uint32_t* tab) {
-    const int sx = B.span[0], sy = B.span[1];
-    for (int t = threadIdx.x; t < B.nstencil; t += blockDim.x) {
-        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
-        tab[t] = (uint32_t)tx | ((uint32_t)ty << 10) | ((uint32_t)tz << 20);
-    }
-}
-
 __device__ __forceinline__ int log2_ceil(int v) {
     return v <= 1 ? 0 : 32 - __clz(v - 1);
 }
@@ -288,6 +279,7 @@ __device__ __forceinline__ DevBox hot_copy(const DevBox& G) {
     B.seed = (uint64_t)uni64((int64_t)G.seed);
     B.box_id = (uint32_t)uni((int32_t)G.box_id);
     B.nstencil = uni(G.nstencil);
+    B.stab = unip(G.stab);
     return B;
 }
 

@@ -32,13 +32,13 @@ def _slots(box):
     g = 1
     while g < maxc:
         g *= 2
-    nst = info["span"][0] * info["span"][1] * info["span"][2]
+    nst = info["n_stencil"]
     return nst * g
 
 
 def spec_supported(box):
     info = box.info()
-    nst = info["span"][0] * info["span"][1] * info["span"][2]
+    nst = info["n_stencil"]
     return info["n_species"] == 1 and nst <= 32 and 2 * nst * info["cell_cap"] <= SPEC_OWN
 
 

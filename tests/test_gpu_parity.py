@@ -128,12 +128,17 @@ def test_neighbor_sets_bitexact(case):
         assert np.array_equal(got[k], np.sort(ref)), (k, q)
 
 
-def test_neighbor_sets_small_cells():
-    """Cells smaller than rc (k = 2, 5x5x5 stencil) give the oracle's sets too."""
+@pytest.mark.parametrize("req", [[8, 8, 8], [12, 12, 12], [13, 17, 21], [3, 9, 14]])
+def test_neighbor_sets_small_cells(req):
+    """Cells smaller than rc (k = 2 .. 5 per axis; the stencil less the cells
+    beyond the cutoff; one case covers x whole) give the oracle's sets, and
+    the library keeps the oracle's number of stencil cells."""
     wb = workloads.random_box(400, 11.0, seed=9)
-    req = np.array([8, 8, 8], dtype=np.int32)
+    req = np.array(req, dtype=np.int32)
     b = _box(wb, cell_m=req)
-    assert b.info()["span"] == [5, 5, 5]
+    g = oracle.grid(wb.L, wb.rc, req)
+    assert b.info()["span"] == list(g["span"])
+    assert b.info()["n_stencil"] == oracle.stencil_count(wb.L, wb.rc, req)
     got, cnt = b.neighbor_ids(wb.pos[:50], np.arange(50))
     for i in range(50):
         ref = oracle.neighbor_ids(wb.pos, wb.pos[i], wb.L, wb.rc, exclude=i, req_m=req)
@@ -161,7 +166,7 @@ def test_delta_energy_c1_and_small_cells(c1):
     rng = np.random.default_rng(7)
     moves = _random_moves(c1, rng, 400, c1.n)
     rp, rt, sa = _oracle_deltas(c1, p, moves)
-    for cm in (None, [16, 16, 16]):
+    for cm in (None, [16, 16, 16], [21, 21, 21], [24, 24, 24]):
         b = _box(c1, max_n=c1.n + 10, cell_m=cm)
         gp, gt = b.delta_energy(moves)
         assert_du(gp, rp, sa, "C1 cell_m=%s" % cm)
@@ -179,6 +184,45 @@ def test_chain_launch_shapes_agree(c1, waves, rows):
     b.set_launch(waves, rows)
     _, glog = b.step(300, counter0=0, log=True)
     assert compare_chain_logs(glog, olog, c1.beta) == 300
+
+
+@pytest.mark.parametrize("cm", [[16, 16, 16], [21, 21, 21], [24, 24, 24]])
+@pytest.mark.parametrize("waves,rows", [(4, 4), (8, 2)])
+def test_chain_microcells_agree(c1, cm, waves, rows):
+    """Microcells (k = 2, 3; pruned stencils of up to several hundred cells): the
+    chain kernel gives the oracle's chain, and the cell list it leaves behind
+    bins every particle where the oracle does."""
+    p = _params(c1)
+    opos, _, olog = oracle.chain(c1.pos, 300, p, seed=c1.seed, max_n=c1.n + 400, U0=0.0)
+    req = np.array(cm, dtype=np.int32)
+    b = _box(c1, max_n=c1.n + 400, cell_m=req)
+    assert b.info()["n_stencil"] == oracle.stencil_count(c1.L, c1.rc, req)
+    b.set_launch(waves, rows)
+    _, glog = b.step(300, counter0=0, log=True)
+    assert compare_chain_logs(glog, olog, c1.beta) == 300
+    gpos = b.particles()[0]
+    assert np.array_equal(gpos, opos)
+    cell_of, _, _ = b.cells()
+    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(gpos, c1.L, c1.rc, req))
+
+
+@pytest.mark.parametrize("cm", [[21, 21, 21], [24, 24, 24]])
+def test_total_energy_virial_backward_microcells(c1, cm):
+    """Cell-list total energy, virial and forces over a pruned microcell stencil."""
+    p = _params(c1)
+    req = np.array(cm, dtype=np.int32)
+    b = _box(c1, cell_m=req)
+    ref = oracle.total_energy(c1.pos, p, per_particle=True)
+    got = b.total_energy(per_particle=True)
+    assert abs(got["U_pair"] - ref["U_pair"]) <= 1e-10 * ref["sumabs"]
+    assert np.allclose(got["e"], ref["e"], rtol=0, atol=1e-10 * max(1.0, np.abs(ref["e"]).max()))
+    vref = oracle.virial(c1.pos, p)
+    v = b.virial()
+    assert abs(v["W"] - vref["W"]) <= 1e-10 * vref["sumabs"]
+    g = b.backward()["grad"]
+    for i in range(0, c1.n, 97):
+        gr = oracle.particle_gradient(c1.pos, i, p)
+        assert np.allclose(g[i], gr, rtol=1e-7, atol=1e-9 * max(1.0, np.abs(gr).max()))
 
 
 def test_delta_energy_mixture():

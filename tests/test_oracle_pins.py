@@ -241,8 +241,29 @@ def test_microcell_offset_example(orc, golden):
     ids = orc.neighbor_ids(cells, np.array(g["center"]) + 0.5, [L] * 3, 2.5, req_m=req)
     got = cells[ids] - 0.5
     lo, hi = np.array(g["first_cell"]), np.array(g["last_cell"])
-    assert len(ids) == g["cube"] ** 3
+    # The cube bounds the stencil; its cells with two offsets of 3 (two whole unit
+    # cells of gap on each of two axes: 2^2 + 2^2 = 8 > 2.5^2) are dropped: 3 axis
+    # pairs x 4 sign pairs x 5 offsets <= 2 on the third axis + 8 corners = 68.
+    assert len(ids) == g["cube"] ** 3 - 68
     assert np.all(got.min(axis=0) == lo) and np.all(got.max(axis=0) == hi)
+    assert orc.stencil_count([L] * 3, 2.5, req) == g["cube"] ** 3 - 68
+
+
+@pytest.mark.parametrize("m,kept", [(8, 27), (16, 125), (20, 251), (24, 275)])
+def test_pruned_stencil_counts(orc, m, kept):
+    """Kept stencil cells counted by hand, cubic box L = 30, rc = 3.5 (rc^2 = 12.25).
+
+    Along an axis the gap to a cell |d| cells away is (|d| - 1) S for |d| >= 2.
+    m = 8:  S = 3.75 >= rc, k = 1: no gaps, all 27 kept.
+    m = 16: S = 1.875, k = 2: at most three gaps of S, 3 S^2 = 10.55 <= 12.25: 125.
+    m = 20: S = 1.5, k = 3: squared gaps 2.25 (|d| = 2), 9 (|d| = 3).  Dropped:
+            two or three axes at |d| = 3 (>= 18): 3 axis pairs x 4 signs x 5 values
+            of the third offset + 8 corners = 68; one axis at 3 and both others at
+            2 (13.5): 3 x 2 x 4 = 24.  343 - 92 = 251.
+    m = 24: S = 1.25, k = 3: squared gaps 1.5625, 6.25.  Only two axes at |d| = 3
+            (>= 12.5) are dropped (3, 2, 2 gives 9.375): 343 - 68 = 275.
+    """
+    assert orc.stencil_count([30.0] * 3, 3.5, [m] * 3) == kept
 
 
 def test_paper_box_volumes(golden):
@@ -256,11 +277,16 @@ def test_paper_box_volumes(golden):
 # --------------------------------------------------------------------------
 # Cell list = all-pairs (brute force on tiny boxes, including points at faces)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("L,n,seed", [(7.4, 120, 1), (10.0, 300, 2), (12.7, 300, 3), ([7.6, 10.0, 12.7], 250, 4)])
-def test_cell_list_covers_cutoff(orc, L, n, seed):
+@pytest.mark.parametrize("L,n,seed,req", [(7.4, 120, 1, None), (10.0, 300, 2, None), (12.7, 300, 3, None),
+                                          ([7.6, 10.0, 12.7], 250, 4, None),
+                                          (10.0, 300, 5, [12, 12, 12]),     # k = 3, pruned stencil
+                                          (12.7, 300, 6, [13, 17, 21]),     # k = 2, 3, 5 per axis
+                                          ([7.6, 10.0, 12.7], 250, 7, [3, 9, 16])])   # x whole, pruned y, z
+def test_cell_list_covers_cutoff(orc, L, n, seed, req):
     b = workloads.random_box(n, L, seed=seed)
     pos = b.pos.copy()
-    g = orc.grid(b.L, 2.5)
+    req = None if req is None else np.array(req, dtype=np.int32)
+    g = orc.grid(b.L, 2.5, req)
     # push a few particles to within 1e-12 of cell faces
     rng = np.random.default_rng(seed)
     for i in range(0, n, 17):
@@ -270,7 +296,7 @@ def test_cell_list_covers_cutoff(orc, L, n, seed):
     p = orc.make_params(b.L, 2.5)
     rc2 = 2.5 * 2.5
     for i in range(0, n, 5):
-        ids = orc.neighbor_ids(pos, pos[i], b.L, 2.5, exclude=i)
+        ids = orc.neighbor_ids(pos, pos[i], b.L, 2.5, exclude=i, req_m=req)
         d = pos - pos[i]
         d -= b.L * np.round(d / b.L)
         r2 = (d * d).sum(axis=1)
