@@ -210,6 +210,74 @@ def cell_size_sweep():
     return out
 
 
+def paper_studies(sizes, cutoffs):
+    """The paper's size and cutoff studies (Sec. 4) on this GPU: moves/s of one
+    chain against N (density 0.67, rc = 2.5) and against the cutoff (87,296
+    particles in 128K sigma^3, rc = 2.5 ... 4.25), for the chain without a cell
+    list (all pairs), with traditional cells (the per-move kernel and, where it
+    applies, the speculative kernel) and with microcells of about rc/2."""
+    import numpy as np
+    import torch
+    from paper_1408_3764_amd import tune, workloads
+    from paper_1408_3764_amd.box import Box
+    from paper_1408_3764_amd._lib import COUNTER_CONTINUE
+    stream = torch.cuda.current_stream()
+
+    def rate(b, moves, all_pairs=False):
+        b.step(max(moves // 4, 1), counter0=COUNTER_CONTINUE, all_pairs=all_pairs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st, _ = b.step(moves, counter0=COUNTER_CONTINUE, all_pairs=all_pairs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if int(st["error"]) != 0:
+            raise SystemExit("chain error %d in the paper studies" % int(st["error"]))
+        return moves / (e0.elapsed_time(e1) / 1e3), int(st["candidates"]) / moves
+
+    def one(wb, moves):
+        r = {"n": wb.n, "rc": wb.rc}
+        b = Box.from_workload(wb, max_n=wb.n + 4 * moves + 1000)
+        r["cells"] = b.info()["cell_m"]
+        r["all_pairs"] = rate(b, max(moves // 8, 500), all_pairs=True)[0]
+        best = None
+        for shape in ((4, 4), (8, 4)):
+            b.set_launch(*shape)
+            v, c = rate(b, moves)
+            if best is None or v > best[0]:
+                best = (v, c, shape)
+        r["cells_per_move"], r["cells_candidates_per_move"], r["cells_per_move_launch"] = best[0], best[1], best[2]
+        r["cells_speculative"] = None
+        if tune.spec_supported(b):
+            b.set_launch(8, 0)
+            r["cells_speculative"] = rate(b, moves)[0]
+        base = r["cells"]
+        b.close()
+        b = Box.from_workload(wb, max_n=wb.n + 4 * moves + 1000, cell_m=[2 * m for m in base])
+        r["microcells"] = b.info()["cell_m"]
+        r["microcell_stencil"] = b.info()["n_stencil"]
+        best = None
+        for shape in ((4, 4), (8, 4)):
+            b.set_launch(*shape)
+            v, c = rate(b, moves)
+            if best is None or v > best[0]:
+                best = (v, c, shape)
+        r["microcells_per_move"], r["microcell_candidates_per_move"] = best[0], best[1]
+        b.close()
+        log("%s: all pairs %.0f, cells %.0f (%dx%d)%s, microcells %.0f moves/s" % (
+            wb.name, r["all_pairs"], r["cells_per_move"], best[2][0], best[2][1],
+            "" if r["cells_speculative"] is None else ", speculative %.0f" % r["cells_speculative"],
+            r["microcells_per_move"]))
+        return r
+
+    out = {"size_study": [], "cutoff_study": []}
+    for n in sizes:
+        out["size_study"].append(one(workloads.paper_size(n), 20_000))
+    for wb in workloads.paper_cutoff(cutoffs):
+        out["cutoff_study"].append(one(wb, 20_000))
+    return out
+
+
 def workload_by_name(name):
     from paper_1408_3764_amd import workloads
     return {"slab": workloads.slab, "large": workloads.large, "small": workloads.small}[name]()
@@ -247,6 +315,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="heuristic launch shape instead of timing them")
     ap.add_argument("--cell-sweep", action="store_true",
                     help="only compare traditional cells with pruned microcells on the small, large and slab boxes")
+    ap.add_argument("--paper-studies", action="store_true",
+                    help="only run the paper's size and cutoff studies (all pairs, cells, microcells)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (reference for the traffic counters)")
     args = ap.parse_args()
@@ -259,6 +329,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 8, "launches": 3}))
+        return
+    if args.paper_studies:
+        print(json.dumps(paper_studies([2 ** 9, 2 ** 12, 2 ** 15, 2 ** 18, 2 ** 20],
+                                        [2.5, 3.0, 3.5, 4.0, 4.25])))
         return
     if args.cell_sweep:
         print(json.dumps({"cell_sweep": cell_size_sweep()}))

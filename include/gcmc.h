@@ -174,6 +174,23 @@ int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream);
  * re-bin; used by the autograd wrapper between forward passes. */
 int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z, void* stream);
 
+/* Volume change (the cell-list rebuild and total energy that volume moves of
+ * the Gibbs ensemble need, proposed in the conclusions, Sec. 5): every
+ * coordinate is scaled by L'_a / L_a (x -> x * (L'_a / L_a), the ratio rounded
+ * once, kept in [0, L'_a)), the cell grid is rebuilt for the new edges by the
+ * box's rule (the cell_m given at create, else max(3, floor(L'/rc))), the
+ * tail-correction constants follow the new volume, the cell capacity grows by
+ * the creation rule if the densest new cell needs it, and particles are
+ * re-binned (same indices, species and move counter).  h_L: HOST array of the
+ * three new edges (> 0, rc <= L'_a / 2; else GCMC_ERR_INVALID_ARG and nothing
+ * changes).  d_U: DEVICE array of 4 doubles written with the cell-list
+ * U_pair and U_tail at the new volume, then at the old one; the box's running
+ * pair energy is reset to the new U_pair (as gcmc_total_energy does).  A box
+ * holding a latched error
+ * is refused (GCMC_ERR_POISONED).  Blocks the host until done; an allocation
+ * failure after the coordinates were scaled leaves the box unusable. */
+int gcmc_box_rescale(gcmc_box* box, const double* h_L, double* d_U, void* stream);
+
 /* Replace the force field: h_eps, h_sigma are HOST n_species^2 pair tables
  * (symmetric, eps >= 0, sigma > 0), as in gcmc_box_desc.  Blocks until work
  * already queued on the box is done. */
@@ -212,7 +229,7 @@ int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair,
  * one per wavefront, against the round's starting state and committed in
  * order, each only if nothing it read has changed since (the same chain, move
  * for move); needs one species, at most 32 stencil cells and
- * 2 x stencil cells x cell_cap <= 4096, else GCMC_ERR_UNSUPPORTED.  rows = -1:
+ * 2 x stencil cells x cell_cap <= 8192, else GCMC_ERR_UNSUPPORTED.  rows = -1:
  * pipelined, one wavefront decides the moves in order while waves - 1 (3 or
  * 7) wavefronts evaluate the moves ahead of it; an evaluation is used only if
  * no decision since it read memory changed what it read (the same chain, move

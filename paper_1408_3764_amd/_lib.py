@@ -30,7 +30,7 @@ MAX_SPECIES = 4
 # every symbol include/gcmc.h declares
 EXPORTS = [
     "gcmc_box_create", "gcmc_box_destroy", "gcmc_box_get_info", "gcmc_cell_build", "gcmc_set_positions",
-    "gcmc_set_params",
+    "gcmc_set_params", "gcmc_box_rescale",
     "gcmc_delta_energy", "gcmc_delta_energy_allpairs", "gcmc_commit", "gcmc_box_set_launch", "gcmc_step",
     "gcmc_step_allpairs", "gcmc_total_energy", "gcmc_backward", "gcmc_virial", "gcmc_batch_create",
     "gcmc_batch_destroy",
@@ -97,6 +97,7 @@ def lib():
         "gcmc_cell_build": [vp, i32, vp],
         "gcmc_set_positions": [vp, dp, dp, dp, vp],
         "gcmc_set_params": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "gcmc_box_rescale": [vp, C.POINTER(C.c_double), vp, vp],
         "gcmc_delta_energy": [vp, dp, i64, dp, dp, vp],
         "gcmc_delta_energy_allpairs": [vp, dp, i64, dp, dp, vp],
         "gcmc_commit": [vp, dp, dp, vp],
@@ -178,6 +179,11 @@ def gcmc_set_params(box, eps, sigma):
     s = np.ascontiguousarray(sigma, dtype=np.float64).reshape(-1)
     check(lib().gcmc_set_params(box, e.ctypes.data_as(C.POINTER(C.c_double)),
                                 s.ctypes.data_as(C.POINTER(C.c_double))))
+
+
+def gcmc_box_rescale(box, L_new, out, stream=None):
+    Lh = np.ascontiguousarray(np.broadcast_to(np.asarray(L_new, dtype=np.float64), (3,)))
+    check(lib().gcmc_box_rescale(box, Lh.ctypes.data_as(C.POINTER(C.c_double)), ptr(out), stream_handle(stream)))
 
 
 def gcmc_delta_energy(box, moves, n, dU_pair, dU_tail, stream=None):

@@ -207,6 +207,16 @@ class Box:
         z = _dev(pos[:, 2], torch.float64, self.device)
         _lib.gcmc_set_positions(self.handle, x, y, z, self.stream)
 
+    def rescale(self, L_new):
+        """Scale the box to edges L_new (coordinates scaled with it), rebuild the
+        cell list and return the cell-list energies {"U_pair", "U_tail"} at the
+        new volume and {"U_pair_old", "U_tail_old"} at the old one."""
+        out = torch.zeros(4, dtype=torch.float64, device=self.device)
+        _lib.gcmc_box_rescale(self.handle, L_new, out, self.stream)
+        self.L = np.broadcast_to(np.asarray(L_new, dtype=np.float64), (3,)).copy()
+        v = out.cpu().numpy()
+        return {"U_pair": float(v[0]), "U_tail": float(v[1]), "U_pair_old": float(v[2]), "U_tail_old": float(v[3])}
+
     def set_params(self, eps, sigma):
         _lib.gcmc_set_params(self.handle, np.asarray(eps, dtype=np.float64), np.asarray(sigma, dtype=np.float64))
 

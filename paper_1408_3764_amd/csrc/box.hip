@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <string>
 #include <vector>
@@ -123,6 +124,17 @@ __global__ void k_reset_state(BoxState* st, int64_t n, double u_pair, int keep_e
     }
 }
 
+// Affine rescaling of the particle coordinates, x_a -> x_a * r_a, kept in [0, L_a).
+__global__ void k_rescale(DevBox B, int64_t n, double rx, double ry, double rz, double Lx, double Ly, double Lz) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double4 p = B.pos[i];
+        p.x = wrap_into_box(p.x * rx, Lx);
+        p.y = wrap_into_box(p.y * ry, Ly);
+        p.z = wrap_into_box(p.z * rz, Lz);
+        B.pos[i] = p;
+    }
+}
+
 __global__ void k_clear_overflow(BoxState* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && st->error == GCMC_ERR_CELL_OVERFLOW) {
         st->error = GCMC_OK;
@@ -190,8 +202,6 @@ static int validate_desc(const gcmc_box_desc* d, int64_t n) {
     return GCMC_OK;
 }
 
-// Cells per axis (the paper's rule, or the caller's larger count), the
-// stencil half-width and extent.
 // Stencil slots kept for this grid.  On an axis the stencil does not cover
 // whole, slot coordinate t stands for the cell offset d = t - k; the closest
 // points of the centre cell and a cell at offset d along that axis are
@@ -218,6 +228,8 @@ static void stencil_slots(const DevBox& B, double rc, std::vector<uint32_t>& slo
             }
 }
 
+// Cells per axis (the paper's rule, or the caller's count), the stencil
+// half-width and extent, and the kept stencil slots.
 static int setup_grid(DevBox& B, const gcmc_box_desc* d, std::vector<uint32_t>& slots) {
     for (int a = 0; a < 3; ++a) {
         int64_t m = (int64_t)floor(d->L[a] / d->rc);
@@ -367,6 +379,11 @@ int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* 
     gcmc_box* box = new gcmc_box();
     memset(box, 0, sizeof(*box));
     GCMC_HIP(hipGetDevice(&box->device));
+    for (int a = 0; a < 3; ++a) box->req_m[a] = desc->cell_m[a];
+    for (int a = 0; a < desc->n_species * desc->n_species; ++a) {
+        box->h_eps[a] = desc->eps[a];
+        box->h_sig[a] = desc->sigma[a];
+    }
     box->waves = 4;
     box->rows = 4;
     DevBox& B = box->d;
@@ -523,7 +540,97 @@ int gcmc_set_params(gcmc_box* box, const double* h_eps, const double* h_sigma) {
     GCMC_HIP(hipDeviceSynchronize());
     setup_params(box->d, &d);
     box->d.rc2 = d.rc * d.rc;
+    for (int a = 0; a < ns * ns; ++a) {
+        box->h_eps[a] = h_eps[a];
+        box->h_sig[a] = h_sigma[a];
+    }
     return sync_desc(box);
+}
+
+int gcmc_box_rescale(gcmc_box* box, const double* h_L, double* d_U, void* stream) {
+    if (!box || !h_L || !d_U) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    DevBox& B = box->d;
+    const double rc = sqrt(B.rc2);
+    for (int a = 0; a < 3; ++a) {
+        if (!(h_L[a] > 0.0) || !std::isfinite(h_L[a])) return set_error(GCMC_ERR_INVALID_ARG, "box edges must be positive");
+        if (rc > 0.5 * h_L[a]) return set_error(GCMC_ERR_INVALID_ARG, "rc > L/2 breaks the minimum image");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    BoxState h;
+    int rc_ = read_state(box, &h, s);
+    if (rc_) return rc_;
+    if (h.error) return set_error(GCMC_ERR_POISONED, "box holds a latched error");
+    const int64_t old_cells = B.ncells;
+    // energies at the old volume
+    if ((rc_ = ensure_scratch(box, total_partials_needed(B, h.maxcount, false, h.n)))) return rc_;
+    int r = launch_total(B, box->d_desc, h.maxcount, false, nullptr, box->scratch, box->scratch_len, d_U + 2, s, h.n);
+    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
+    if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
+    // the new grid (the box's rule for cells per axis) and force-field constants
+    gcmc_box_desc d;
+    memset(&d, 0, sizeof d);
+    for (int a = 0; a < 3; ++a) {
+        d.L[a] = h_L[a];
+        d.cell_m[a] = box->req_m[a];
+    }
+    d.rc = rc;
+    d.beta = B.beta;
+    d.mu = B.mu;
+    d.lambda3 = B.lambda3;
+    d.max_disp = B.max_disp;
+    d.p_disp = B.p_disp;
+    d.n_species = B.ns;
+    d.eps = box->h_eps;
+    d.sigma = box->h_sig;
+    d.seed = B.seed;
+    d.box_id = B.box_id;
+    d.max_n = B.max_n;
+    DevBox N2 = B;
+    std::vector<uint32_t> slots;
+    if ((rc_ = setup_grid(N2, &d, slots))) return rc_;
+    setup_params(N2, &d);
+    N2.rc2 = B.rc2;
+    // From here on the box changes; a failure leaves it poisoned.
+    GCMC_HIP(hipStreamSynchronize(s));
+    uint32_t* d_stab = nullptr;
+    if (hipMalloc(&d_stab, slots.size() * sizeof(uint32_t)) != hipSuccess)
+        return set_error(GCMC_ERR_OOM, "stencil table allocation failed");
+    GCMC_HIP(hipMemcpy(d_stab, slots.data(), slots.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    (void)hipFree((void*)B.stab);
+    N2.stab = d_stab;
+    if (N2.ncells != B.ncells) {
+        (void)hipFree(B.count);
+        N2.count = nullptr;
+        if (hipMalloc(&N2.count, (size_t)N2.ncells * sizeof(int32_t)) != hipSuccess) {
+            B = N2;
+            return set_error(GCMC_ERR_OOM, "cell counter allocation failed");
+        }
+    }
+    if (h.n > 0)
+        k_rescale<<<grid_for(h.n), 256, 0, s>>>(B, h.n, h_L[0] / B.L[0], h_L[1] / B.L[1], h_L[2] / B.L[2], h_L[0],
+                                                h_L[1], h_L[2]);
+    B = N2;
+    // occupancy at the new grid; the capacity grows (by the creation rule) if the densest cell needs it
+    k_reset_state<<<1, 1, 0, s>>>(B.st, h.n, h.u_pair, 1);
+    k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
+    if (h.n > 0) k_count<<<grid_for(h.n), 256, 0, s>>>(B, h.n);
+    BoxState h2;
+    if ((rc_ = read_state(box, &h2, s))) return rc_;
+    const int32_t cap = h2.maxcount > B.cap ? auto_cap(h2.maxcount) : B.cap;
+    if (cap != B.cap || B.ncells != old_cells) {
+        if ((rc_ = alloc_cells(box, cap))) return rc_;
+    }
+    if ((rc_ = bin_particles(box, h.n, s, true, h.u_pair)) || (rc_ = read_state(box, &h2, s))) return rc_;
+    if (h2.error) return set_error(h2.error, "re-binning failed");
+    if ((rc_ = sync_desc(box))) return rc_;
+    // energies at the new volume (the running pair energy is reset to U_pair)
+    if ((rc_ = ensure_scratch(box, total_partials_needed(B, h2.maxcount, false, h.n)))) return rc_;
+    r = launch_total(B, box->d_desc, h2.maxcount, false, nullptr, box->scratch, box->scratch_len, d_U, s, h.n);
+    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
+    if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
+    GCMC_HIP(hipGetLastError());
+    GCMC_HIP(hipStreamSynchronize(s));
+    return GCMC_OK;
 }
 
 int gcmc_get_particles(gcmc_box* box, double* d_x, double* d_y, double* d_z, int32_t* d_species, int64_t* h_n,

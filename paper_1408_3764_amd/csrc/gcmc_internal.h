@@ -341,6 +341,9 @@ struct gcmc_box {
     void* ap_chain;          // all-pairs chain bookkeeping (device)
     int device;
     int waves, rows;         // launch shape of the move kernels
+    int32_t req_m[3];        // cells per axis asked for at create (0 = the paper's rule)
+    double h_eps[gcmc::kMaxSpecies * gcmc::kMaxSpecies];   // force-field tables as given (host)
+    double h_sig[gcmc::kMaxSpecies * gcmc::kMaxSpecies];
 };
 
 struct gcmc_batch {

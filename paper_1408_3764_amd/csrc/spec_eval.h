@@ -13,7 +13,7 @@
 
 namespace gcmc {
 
-constexpr int kSpecOwn = 4096;   // flattened candidates per wavefront (owner table bytes)
+constexpr int kSpecOwn = 8192;   // flattened candidates per wavefront (owner table bytes)
 
 struct SpecRec {
     double dUp, lnA, u2, pad0;

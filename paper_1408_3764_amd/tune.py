@@ -21,7 +21,7 @@ SPEC_SHAPES = [(4, 0), (8, 0), (16, 0)]
 # rows = -1: the pipelined kernel, one committer and waves - 1 evaluator wavefronts
 # (the same limits, plus at most 1024 cells per axis)
 ASYNC_SHAPES = [(4, -1), (8, -1)]
-SPEC_OWN = 4096   # flattened candidates a speculative wavefront can hold
+SPEC_OWN = 8192   # flattened candidates a speculative wavefront can hold
 CACHE_ENV = "GCMC_TUNE_CACHE"
 
 

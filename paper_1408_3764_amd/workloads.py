@@ -198,6 +198,27 @@ def slab(seed=BASE_SEED + 2, n_total=1_500_000, rho_l=0.8, rho_v=0.02):
                name="slab 1:1:4 N=%d rho_l=0.8 rho_v=0.02 rc=2.5" % n_total)
 
 
+def paper_size(n, seed=BASE_SEED + 5):
+    """The paper's size study (Sec. 4): N particles at density 0.67, rc = 2.5,
+    30 % displacements and 35 % each insertions and deletions.  The paper states
+    no temperature or chemical potential for it: T* = 1.2, mu* = -3 are taken."""
+    b = cubic_box(n, 0.67, 1.2, 2.5, seed, name="size study N=%d rho=0.67 rc=2.5" % n)
+    b.p_disp = 0.3
+    return b
+
+
+def paper_cutoff(rcs, seed=BASE_SEED + 6, n=87_296, volume=131_072.0):
+    """The paper's cutoff study (Sec. 4): one configuration of 87,296 particles in
+    a cube of 128K sigma^3 (density 0.666), the same move mix and state as the
+    size study, one box per cutoff in rcs."""
+    L = float(np.cbrt(volume))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Lv = np.array([L, L, L])
+    pos, _ = rsa_place(n, Lv, rng)
+    return [Box(pos=pos, L=Lv.copy(), rc=float(rc), beta=1.0 / 1.2, mu=-3.0, p_disp=0.3, seed=seed,
+                name="cutoff study N=%d V=%g rc=%g" % (n, volume, rc)) for rc in rcs]
+
+
 def batched(seed=BASE_SEED + 3, n_boxes=512, n_min=128, n_max=32768) -> List[Box]:
     rng = np.random.Generator(np.random.PCG64(seed))
     ln = rng.uniform(math.log(n_min), math.log(n_max), n_boxes)
