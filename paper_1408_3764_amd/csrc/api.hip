@@ -130,7 +130,6 @@ int gcmc_total_energy(gcmc_box* box, int32_t all_pairs, double* d_U, double* d_e
     if ((rc = ensure_scratch(box, need))) return rc;
     const int r = launch_total(box->d, box->d_desc, h.maxcount, all_pairs != 0, d_e, box->scratch, box->scratch_len,
                                d_U, s, h.n);
-    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
     if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
@@ -143,8 +142,7 @@ int gcmc_virial(gcmc_box* box, double* d_out, void* stream) {
     int rc = poisoned_check(box, s, &h);
     if (rc) return rc;
     if ((rc = ensure_scratch(box, total_partials_needed(box->d, h.maxcount, false, h.n)))) return rc;
-    const int r = launch_virial(box->d, box->d_desc, h.maxcount, box->scratch, box->scratch_len, d_out, s);
-    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
+    const int r = launch_virial(box->d, box->d_desc, h.maxcount, box->scratch, box->scratch_len, d_out, s, h.n);
     if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
@@ -156,9 +154,8 @@ int gcmc_backward(gcmc_box* box, double* d_grad, double* d_deps, double* d_dsig,
     BoxState h;
     int rc = poisoned_check(box, s, &h);
     if (rc) return rc;
-    if ((rc = ensure_scratch(box, grad_partials_needed(box->d, h.maxcount)))) return rc;
-    const int r = launch_grad(box->d, box->d_desc, h.maxcount, d_grad, box->scratch, d_deps, d_dsig, s);
-    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
+    if ((rc = ensure_scratch(box, grad_partials_needed(box->d, h.maxcount, h.n)))) return rc;
+    const int r = launch_grad(box->d, box->d_desc, h.maxcount, d_grad, box->scratch, d_deps, d_dsig, s, h.n);
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }

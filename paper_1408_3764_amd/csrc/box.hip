@@ -564,7 +564,6 @@ int gcmc_box_rescale(gcmc_box* box, const double* h_L, double* d_U, void* stream
     // energies at the old volume
     if ((rc_ = ensure_scratch(box, total_partials_needed(B, h.maxcount, false, h.n)))) return rc_;
     int r = launch_total(B, box->d_desc, h.maxcount, false, nullptr, box->scratch, box->scratch_len, d_U + 2, s, h.n);
-    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
     if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
     // the new grid (the box's rule for cells per axis) and force-field constants
     gcmc_box_desc d;
@@ -626,7 +625,6 @@ int gcmc_box_rescale(gcmc_box* box, const double* h_L, double* d_U, void* stream
     // energies at the new volume (the running pair energy is reset to U_pair)
     if ((rc_ = ensure_scratch(box, total_partials_needed(B, h2.maxcount, false, h.n)))) return rc_;
     r = launch_total(B, box->d_desc, h2.maxcount, false, nullptr, box->scratch, box->scratch_len, d_U, s, h.n);
-    if (r == -2) return set_error(GCMC_ERR_UNSUPPORTED, "cells hold more than 256 particles");
     if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
     GCMC_HIP(hipGetLastError());
     GCMC_HIP(hipStreamSynchronize(s));

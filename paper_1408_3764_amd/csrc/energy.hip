@@ -1,13 +1,14 @@
 // Total energy, the all-pairs (no cell list) energy path, and the gradient.
 //
-// Total energy over the cell list: G = the power of two at or above the
-// largest cell count; a workgroup of 256 lanes covers 256/G cells, lane k of a
-// cell owns that cell's k-th particle, and all lanes of a cell walk the same
-// stencil cells together, so each candidate entry is one 32-byte load shared
-// by the G lanes of its group.  e_i is summed per lane, U_pair = (1/2) sum e_i
-// (Sec. 3.1.1 computes each unique pair once; here each pair is met from both
-// ends, which needs no atomics), workgroup partials are summed by one more
-// workgroup in a fixed order.
+// Total energy over the cell list: one lane per particle, the particles taken
+// in cell-major order (cell by cell, slot by slot: the order comes from an
+// exclusive scan of the cell counters), so no lane idles on an empty slot and
+// the lanes of one wavefront belong to a few consecutive cells.  Each lane
+// walks the stencil of its own cell and sums its pair energies e_i in stencil
+// order, candidate order; U_pair = (1/2) sum e_i (Sec. 3.1.1 computes each
+// unique pair once; here each pair is met from both ends, which needs no
+// atomics), workgroup partials are summed by one more workgroup in a fixed
+// order.
 //
 // The all-pairs path (Algorithms 3 and 4 without a cell list) streams the
 // particle records in chunks, one chunk per workgroup, with the same
@@ -37,47 +38,122 @@ __device__ __forceinline__ void cell_coords(const DevBox& B, int64_t c, int32_t&
     cz = (int32_t)(r / B.M[1]);
 }
 
+// ------------------------------------------------ particles in cell order
+// home[off[c] + k] = c * cap + k for k < count[c]: the cell entry of every
+// particle, cell by cell.  off is the exclusive scan of the counters, taken in
+// blocks of kScanCells cells (bsum: the blocks' totals, then their exclusive
+// scan), so the order is a function of the configuration alone.
+constexpr int kScanPer = 4;
+constexpr int kScanCells = kBlk * kScanPer;
+
+__global__ __launch_bounds__(kBlk) void k_scan_cells(const int32_t* __restrict__ count, int64_t ncells,
+                                                      int32_t* off, int32_t* bsum) {
+    __shared__ int32_t sh[kBlk];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanCells + (int64_t)tid * kScanPer;
+    int32_t v[kScanPer];
+    int32_t tot = 0;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        v[u] = base + u < ncells ? count[base + u] : 0;
+        tot += v[u];
+    }
+    sh[tid] = tot;
+    __syncthreads();
+    for (int d = 1; d < kBlk; d <<= 1) {
+        const int32_t t = tid >= d ? sh[tid - d] : 0;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    int32_t run = sh[tid] - tot;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        if (base + u < ncells) off[base + u] = run;
+        run += v[u];
+    }
+    if (tid == kBlk - 1) bsum[blockIdx.x] = sh[tid];
+}
+
+// Exclusive scan of the block totals, in place (one workgroup; each thread
+// takes a contiguous run of blocks).
+__global__ __launch_bounds__(kBlk) void k_scan_sums(int32_t* bsum, int64_t nb) {
+    __shared__ int32_t sh[kBlk];
+    const int tid = threadIdx.x;
+    const int64_t per = (nb + kBlk - 1) / kBlk;
+    const int64_t b0 = (int64_t)tid * per;
+    int32_t tot = 0;
+    for (int64_t b = b0; b < b0 + per && b < nb; ++b) tot += bsum[b];
+    sh[tid] = tot;
+    __syncthreads();
+    for (int d = 1; d < kBlk; d <<= 1) {
+        const int32_t t = tid >= d ? sh[tid - d] : 0;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    int32_t run = sh[tid] - tot;
+    for (int64_t b = b0; b < b0 + per && b < nb; ++b) {
+        const int32_t t = bsum[b];
+        bsum[b] = run;
+        run += t;
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_home_order(DevBox B, const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ bsum, int32_t* home, int64_t n) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < B.ncells;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = (int64_t)off[c] + bsum[c / kScanCells];
+        const int32_t cnt = B.count[c] < B.cap ? B.count[c] : B.cap;
+        for (int32_t k = 0; k < cnt && o + k < n; ++k) home[o + k] = (int32_t)(c * B.cap + k);
+    }
+}
+
 // ------------------------------------------------------ cell-list total
+constexpr int kUnroll = 4;   // candidate records requested together
+
 // Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
 // VIR: the pair virial -r du/dr in place of the pair energy (pressure).
 template <bool MIX, bool VIR = false>
-__global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__ boxp, int lg, double* e_out,
-                                                       double* partial) {
+__global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__ boxp, const int32_t* __restrict__ home,
+                                                       int64_t n, double* e_out, double* partial) {
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
     const DevBox& B = *boxp;
     load_stencil(B, tab);
     __syncthreads();
-    const int G = 1 << lg;
-    const int cells_per_blk = kBlk >> lg;
-    const int64_t c = (int64_t)blockIdx.x * cells_per_blk + (threadIdx.x >> lg);
-    const int k = threadIdx.x & (G - 1);
+    const int64_t h = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     double ei = 0.0;
-    if (c < B.ncells) {
-        const int32_t cnt = gload(B.count + c);
-        const bool own = k < cnt;
-        const double4 me = gload(B.ent + (c * B.cap + (own ? k : 0)));
-        const int32_t myid = own ? meta_low(me.w) : -1;
+    if (h < n) {
+        int32_t slot = home[h];
+        if (slot < 0 || (int64_t)slot >= B.ncells * B.cap) slot = 0;   // counters and N disagree: stay in bounds
+        const int64_t c = slot / B.cap;
+        const double4 me = gload(B.ent + slot);
+        const int32_t myid = meta_low(me.w);
         const int sa = meta_species(me.w);
         int32_t cx, cy, cz;
         cell_coords(B, c, cx, cy, cz);
-        if (cnt > 0) {
-            for (int t = 0; t < B.nstencil; ++t) {
-                const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
-                const int32_t nc = gload(B.count + nb);
-                const double4* ne = B.ent + nb * B.cap;
-                for (int j = 0; j < nc; ++j) {
-                    const double4 o = ne[j];
-                    if (own && meta_low(o.w) != myid) {
-                        const double r2 = dist2(B, me.x, me.y, me.z, o.x, o.y, o.z);
-                        const int q = MIX ? sa * B.ns + meta_species(o.w) : 0;
+        for (int t = 0; t < B.nstencil; ++t) {
+            const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
+            const int32_t nc = gload(B.count + nb);
+            const double4* ne = B.ent + nb * B.cap;
+            for (int j = 0; j < nc; j += kUnroll) {
+                double4 o[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) o[u] = gload(ne + (j + u < nc ? j + u : j));
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (j + u < nc && meta_low(o[u].w) != myid) {
+                        const double r2 = dist2(B, me.x, me.y, me.z, o[u].x, o[u].y, o[u].z);
+                        const int q = MIX ? sa * B.ns + meta_species(o[u].w) : 0;
                         ei += VIR ? lj_virial_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q])
                                   : lj_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q]);
                     }
                 }
             }
         }
-        if (own && e_out) e_out[myid] = ei;
+        if (e_out) e_out[myid] = ei;
     }
     const double s = block_sum(ei, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -527,73 +603,74 @@ __device__ int commit_ap(const DevBox& B, const APTrial& T, const double4& rec, 
 // ------------------------------------------------------------- gradient
 // Per particle: dU/dr_i = sum_j (24 eps / r^2)(2 s12 - s6) d_ij, written by
 // particle id; parameter partials per block: [0, ns^2) d eps, [ns^2, 2 ns^2)
-// d sigma, each pair met twice contributing half from each end.
+// d sigma, each pair met twice contributing half from each end.  One lane per
+// particle in cell order, as the total energy.
 template <bool MIX>
-__global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ boxp, int lg, double* grad,
-                                                      double* partial) {
+__global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ boxp, const int32_t* __restrict__ home,
+                                                      int64_t n, double* grad, double* partial) {
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
     const DevBox& B = *boxp;
     load_stencil(B, tab);
     __syncthreads();
-    const int64_t n = B.st->n;
-    const int G = 1 << lg;
-    const int cells_per_blk = kBlk >> lg;
-    const int64_t c = (int64_t)blockIdx.x * cells_per_blk + (threadIdx.x >> lg);
-    const int k = threadIdx.x & (G - 1);
+    const int64_t h = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const int ns = B.ns;
     double gx = 0.0, gy = 0.0, gz = 0.0;
     double de[kMaxSpecies] = {0, 0, 0, 0}, ds[kMaxSpecies] = {0, 0, 0, 0};
     int sa = 0;
-    bool own = false;
-    int32_t myid = -1;
-    if (c < B.ncells) {
-        const int32_t cnt = gload(B.count + c);
-        own = k < cnt;
-        const double4 me = gload(B.ent + (c * B.cap + (own ? k : 0)));
-        myid = own ? meta_low(me.w) : -1;
+    const bool own = h < n;
+    if (own) {
+        int32_t slot = home[h];
+        if (slot < 0 || (int64_t)slot >= B.ncells * B.cap) slot = 0;   // counters and N disagree: stay in bounds
+        const int64_t c = slot / B.cap;
+        const double4 me = gload(B.ent + slot);
+        const int32_t myid = meta_low(me.w);
         sa = meta_species(me.w);
         int32_t cx, cy, cz;
         cell_coords(B, c, cx, cy, cz);
-        if (cnt > 0) {
-            for (int t = 0; t < B.nstencil; ++t) {
-                const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
-                const int32_t nc = gload(B.count + nb);
-                const double4* ne = B.ent + nb * B.cap;
-                for (int j = 0; j < nc; ++j) {
-                    const double4 o = ne[j];
-                    if (!own || meta_low(o.w) == myid) continue;
-                    const double dx = nearest_image(o.x - me.x, B.L[0], B.hL[0]);
-                    const double dy = nearest_image(o.y - me.y, B.L[1], B.hL[1]);
-                    const double dz = nearest_image(o.z - me.z, B.L[2], B.hL[2]);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (!(r2 < B.rc2) || r2 == 0.0) continue;
-                    const int sb = meta_species(o.w);
-                    const int q = MIX ? sa * ns + sb : 0;
-                    const double eps4 = B.eps4[q], sig2 = B.sig2[q];
-                    const double sr2 = sig2 / r2;
-                    const double s6 = sr2 * sr2 * sr2;
-                    const double s12 = s6 * s6;
-                    const double coef = (6.0 * eps4 / r2) * (2.0 * s12 - s6);
-                    gx += coef * dx;
-                    gy += coef * dy;
-                    gz += coef * dz;
-                    const double t_e = 0.5 * 4.0 * (s12 - s6);
-                    const double t_s = 0.5 * (eps4 / sqrt(sig2)) * (12.0 * s12 - 6.0 * s6);
-                    if (MIX) {
-                        for (int b = 0; b < kMaxSpecies; ++b)
-                            if (b == sb) {
-                                de[b] += t_e;
-                                ds[b] += t_s;
-                            }
-                    } else {
-                        de[0] += t_e;
-                        ds[0] += t_s;
-                    }
+        for (int t = 0; t < B.nstencil; ++t) {
+            const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
+            const int32_t nc = gload(B.count + nb);
+            const double4* ne = B.ent + nb * B.cap;
+            for (int j = 0; j < nc; j += kUnroll) {
+              double4 ob[kUnroll];
+#pragma unroll
+              for (int u = 0; u < kUnroll; ++u) ob[u] = gload(ne + (j + u < nc ? j + u : j));
+#pragma unroll
+              for (int u = 0; u < kUnroll; ++u) {
+                const double4& o = ob[u];
+                if (j + u >= nc || meta_low(o.w) == myid) continue;
+                const double dx = nearest_image(o.x - me.x, B.L[0], B.hL[0]);
+                const double dy = nearest_image(o.y - me.y, B.L[1], B.hL[1]);
+                const double dz = nearest_image(o.z - me.z, B.L[2], B.hL[2]);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (!(r2 < B.rc2) || r2 == 0.0) continue;
+                const int sb = meta_species(o.w);
+                const int q = MIX ? sa * ns + sb : 0;
+                const double eps4 = B.eps4[q], sig2 = B.sig2[q];
+                const double sr2 = sig2 / r2;
+                const double s6 = sr2 * sr2 * sr2;
+                const double s12 = s6 * s6;
+                const double coef = (6.0 * eps4 / r2) * (2.0 * s12 - s6);
+                gx += coef * dx;
+                gy += coef * dy;
+                gz += coef * dz;
+                const double t_e = 0.5 * 4.0 * (s12 - s6);
+                const double t_s = 0.5 * (eps4 / sqrt(sig2)) * (12.0 * s12 - 6.0 * s6);
+                if (MIX) {
+                    for (int b = 0; b < kMaxSpecies; ++b)
+                        if (b == sb) {
+                            de[b] += t_e;
+                            ds[b] += t_s;
+                        }
+                } else {
+                    de[0] += t_e;
+                    ds[0] += t_s;
                 }
+              }
             }
         }
-        if (own && grad) {
+        if (grad) {
             grad[myid] = gx;
             grad[n + myid] = gy;
             grad[2 * n + myid] = gz;
@@ -641,8 +718,32 @@ __global__ __launch_bounds__(kBlk) void k_grad_finish(const DevBox* __restrict__
 }
 
 // ------------------------------------------------------------ launchers
+// Scratch layout of a cell-list pass (in doubles): the block partials (times
+// `stride` doubles per block), then, as int32, the particles in cell order
+// (n), the cell offsets (ncells) and the scan-block totals.
+static int64_t cell_pass_blocks(int64_t n) { return n > 0 ? (n + kBlk - 1) / kBlk : 1; }
+static int64_t scan_blocks(const DevBox& hb) { return (hb.ncells + kScanCells - 1) / kScanCells; }
+static int64_t cell_pass_doubles(const DevBox& hb, int64_t n, int64_t stride) {
+    const int64_t ints = n + hb.ncells + scan_blocks(hb);
+    return cell_pass_blocks(n) * stride + (ints + 1) / 2 + 1;
+}
+
+// The particles in cell order into the scratch after `partial_doubles`.
+static int32_t* cell_order(const DevBox& hb, int64_t n, double* scratch, int64_t partial_doubles, hipStream_t s) {
+    int32_t* home = reinterpret_cast<int32_t*>(scratch + partial_doubles);
+    int32_t* off = home + n;
+    int32_t* bsum = off + hb.ncells;
+    const int64_t nsb = scan_blocks(hb);
+    hipLaunchKernelGGL(k_scan_cells, dim3((unsigned)nsb), dim3(kBlk), 0, s, hb.count, hb.ncells, off, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlk), 0, s, bsum, nsb);
+    const int64_t g = (hb.ncells + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL(k_home_order, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(kBlk), 0, s, hb, off, bsum, home, n);
+    return home;
+}
+
 int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_pairs, double* e_out,
                  double* partial, int64_t partial_len, double* U, hipStream_t s, int64_t n) {
+    (void)maxc;
     const bool mix = hb.ns > 1;
     int64_t nb;
     if (all_pairs) {
@@ -654,59 +755,56 @@ int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_p
         else
             hipLaunchKernelGGL(k_total_allpairs<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, e_out, partial);
     } else {
-        int lg = maxc <= 1 ? 0 : 32 - __builtin_clz((unsigned)(maxc - 1));
-        if (lg > 8) return -2;
-        const int cpb = kBlk >> lg;
-        nb = (hb.ncells + cpb - 1) / cpb;
-        if (nb > partial_len) return -1;
+        nb = cell_pass_blocks(n);
+        if (cell_pass_doubles(hb, n, 1) > partial_len) return -1;
+        const int32_t* home = cell_order(hb, n, partial, nb, s);
         if (mix)
-            hipLaunchKernelGGL(k_total_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, e_out, partial);
+            hipLaunchKernelGGL(k_total_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, e_out,
+                               partial);
         else
-            hipLaunchKernelGGL(k_total_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, e_out, partial);
+            hipLaunchKernelGGL(k_total_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, e_out,
+                               partial);
     }
     hipLaunchKernelGGL(k_total_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, U);
     return 0;
 }
 
 int launch_virial(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* partial, int64_t partial_len,
-                  double* out, hipStream_t s) {
-    const int lg = maxc <= 1 ? 0 : 32 - __builtin_clz((unsigned)(maxc - 1));
-    if (lg > 8) return -2;
-    const int cpb = kBlk >> lg;
-    const int64_t nb = (hb.ncells + cpb - 1) / cpb;
-    if (nb > partial_len) return -1;
+                  double* out, hipStream_t s, int64_t n) {
+    (void)maxc;
+    const int64_t nb = cell_pass_blocks(n);
+    if (cell_pass_doubles(hb, n, 1) > partial_len) return -1;
+    const int32_t* home = cell_order(hb, n, partial, nb, s);
     if (hb.ns > 1)
-        hipLaunchKernelGGL((k_total_cells<true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, nullptr,
-                           partial);
+        hipLaunchKernelGGL((k_total_cells<true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
+                           nullptr, partial);
     else
-        hipLaunchKernelGGL((k_total_cells<false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, nullptr,
-                           partial);
+        hipLaunchKernelGGL((k_total_cells<false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
+                           nullptr, partial);
     hipLaunchKernelGGL(k_virial_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, out);
     return 0;
 }
 
 int64_t total_partials_needed(const DevBox& hb, int32_t maxc, bool all_pairs, int64_t n) {
+    (void)maxc;
     if (all_pairs) return (n + kBlk - 1) / kBlk + 1;
-    int lg = maxc <= 1 ? 0 : 32 - __builtin_clz((unsigned)(maxc - 1));
-    if (lg > 8) lg = 8;
-    const int cpb = kBlk >> lg;
-    return (hb.ncells + cpb - 1) / cpb + 1;
+    return cell_pass_doubles(hb, n, 1);
 }
 
-int64_t grad_partials_needed(const DevBox& hb, int32_t maxc) {
-    return total_partials_needed(hb, maxc, false, 0) * 2 * kMaxSpecies * kMaxSpecies;
+int64_t grad_partials_needed(const DevBox& hb, int32_t maxc, int64_t n) {
+    (void)maxc;
+    return cell_pass_doubles(hb, n, 2 * kMaxSpecies * kMaxSpecies);
 }
 
 int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* grad, double* partial, double* deps,
-                double* dsig, hipStream_t s) {
-    int lg = maxc <= 1 ? 0 : 32 - __builtin_clz((unsigned)(maxc - 1));
-    if (lg > 8) return -2;
-    const int cpb = kBlk >> lg;
-    const int64_t nb = (hb.ncells + cpb - 1) / cpb;
+                double* dsig, hipStream_t s, int64_t n) {
+    (void)maxc;
+    const int64_t nb = cell_pass_blocks(n);
+    const int32_t* home = cell_order(hb, n, partial, nb * 2 * kMaxSpecies * kMaxSpecies, s);
     if (hb.ns > 1)
-        hipLaunchKernelGGL(k_grad_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, grad, partial);
+        hipLaunchKernelGGL(k_grad_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad, partial);
     else
-        hipLaunchKernelGGL(k_grad_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, lg, grad, partial);
+        hipLaunchKernelGGL(k_grad_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad, partial);
     if (deps || dsig)
         hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, deps, dsig);
     return 0;

@@ -384,10 +384,10 @@ int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_p
                  double* partial, int64_t partial_len, double* U, hipStream_t s, int64_t n);
 int64_t total_partials_needed(const DevBox& hb, int32_t maxc, bool all_pairs, int64_t n);
 int launch_virial(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* partial, int64_t partial_len,
-                  double* out, hipStream_t s);
-int64_t grad_partials_needed(const DevBox& hb, int32_t maxc);
+                  double* out, hipStream_t s, int64_t n);
+int64_t grad_partials_needed(const DevBox& hb, int32_t maxc, int64_t n);
 int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* grad, double* partial, double* deps,
-                double* dsig, hipStream_t s);
+                double* dsig, hipStream_t s, int64_t n);
 int64_t ap_chunk_len();
 int launch_delta_allpairs(const DevBox* d_box, int64_t n, const gcmc_move* moves, int64_t n_moves, double* scratch,
                           double* dp, double* dt, hipStream_t s);
