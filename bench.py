@@ -475,7 +475,7 @@ def main():
         bt = Batch(boxes)
         # time the shapes that fit a batch (one workgroup per box) and keep the fastest
         btimes = {}
-        for bshape in ((1, 8), (2, 8), (4, 4), (4, 2), (4, 0), (8, 0)):
+        for bshape in ((1, 8), (2, 8), (4, 4), (4, 2), (2, 0), (4, 0), (8, 0)):
             for b in boxes:
                 b.set_launch(*bshape)
             bt.step(50, counter0=COUNTER_CONTINUE)

@@ -225,7 +225,7 @@ int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair,
 /* Launch shape of the chain kernels (the autotuner's choice).  rows > 0: one
  * move at a time, `waves` wavefronts per workgroup and `rows` candidate slots
  * per lane per pass (1x8, 2x8, 4x2, 4x4, 4x8, 8x2, 8x4).  rows = 0:
- * speculative rounds, `waves` (4, 8 or 16) consecutive moves evaluated at once,
+ * speculative rounds, `waves` (2, 4, 8 or 16) consecutive moves evaluated at once,
  * one per wavefront, against the round's starting state and committed in
  * order, each only if nothing it read has changed since (the same chain, move
  * for move); needs one species, at most 32 stencil cells and

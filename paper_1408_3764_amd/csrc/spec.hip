@@ -348,7 +348,8 @@ struct SpecCfg {
 };
 
 static const SpecCfg kSpecCfgs[] = {
-    {4, 4, k_chain_spec<4, 8>}, {8, 8, k_chain_spec<8, 8>}, {16, 16, k_chain_spec<16, 4>},
+    {2, 2, k_chain_spec<2, 8>}, {4, 4, k_chain_spec<4, 8>}, {8, 8, k_chain_spec<8, 8>},
+    {16, 16, k_chain_spec<16, 4>},
 };
 
 // The speculative kernel handles one species, stencils of at most 32 cells

@@ -17,7 +17,7 @@ import time
 SHAPES = [(1, 8), (2, 8), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4)]
 # rows = 0: the speculative kernel, W consecutive moves evaluated at once and
 # committed in order (one species, stencils of at most 32 cells)
-SPEC_SHAPES = [(4, 0), (8, 0), (16, 0)]
+SPEC_SHAPES = [(2, 0), (4, 0), (8, 0), (16, 0)]
 # rows = -1: the pipelined kernel, one committer and waves - 1 evaluator wavefronts
 # (the same limits, plus at most 1024 cells per axis)
 ASYNC_SHAPES = [(4, -1), (8, -1)]

@@ -173,8 +173,8 @@ def test_delta_energy_c1_and_small_cells(c1):
         assert np.allclose(gt, rt, rtol=1e-12)
 
 
-@pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (4, 8), (8, 4), (4, 0), (8, 0), (16, 0), (4, -1),
-                                        (8, -1)])
+@pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (4, 8), (8, 4), (2, 0), (4, 0), (8, 0), (16, 0),
+                                        (4, -1), (8, -1)])
 def test_chain_launch_shapes_agree(c1, waves, rows):
     """Every launch shape gives the oracle's chain (the tuner may pick any)."""
     p = _params(c1)
