@@ -113,6 +113,33 @@ __global__ __launch_bounds__(kBlk) void k_home_order(DevBox B, const int32_t* __
 // ------------------------------------------------------ cell-list total
 constexpr int kUnroll = 4;   // candidate records requested together
 
+// Constants of a cell pass held in registers for the whole kernel (read once
+// from the descriptor: the compiler would otherwise reload them from memory
+// inside the candidate loop), the species tables in LDS.
+struct PassConst {
+    double L[3], hL[3], rc2, e4, s2;
+};
+
+__device__ __forceinline__ PassConst pass_const(const DevBox& B) {
+    PassConst c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c.L[a] = unid(B.L[a]);
+        c.hL[a] = unid(B.hL[a]);
+    }
+    c.rc2 = unid(B.rc2);
+    c.e4 = unid(B.eps4[0]);
+    c.s2 = unid(B.sig2[0]);
+    return c;
+}
+
+__device__ __forceinline__ void load_species_tables(const DevBox& B, double* e4, double* s2) {
+    if (threadIdx.x < kMaxSpecies * kMaxSpecies) {
+        e4[threadIdx.x] = B.eps4[threadIdx.x];
+        s2[threadIdx.x] = B.sig2[threadIdx.x];
+    }
+}
+
 // Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
 // VIR: the pair virial -r du/dr in place of the pair energy (pressure).
 template <bool MIX, bool VIR = false>
@@ -120,8 +147,11 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
                                                        int64_t n, double* e_out, double* partial) {
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
+    __shared__ double te4[kMaxSpecies * kMaxSpecies], ts2[kMaxSpecies * kMaxSpecies];
     const DevBox& B = *boxp;
     load_stencil(B, tab);
+    load_species_tables(B, te4, ts2);
+    const PassConst K = pass_const(B);
     __syncthreads();
     const int64_t h = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     double ei = 0.0;
@@ -132,6 +162,7 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
         const double4 me = gload(B.ent + slot);
         const int32_t myid = meta_low(me.w);
         const int sa = meta_species(me.w);
+        const int ns = uni(B.ns);
         int32_t cx, cy, cz;
         cell_coords(B, c, cx, cy, cz);
         for (int t = 0; t < B.nstencil; ++t) {
@@ -145,10 +176,13 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     if (j + u < nc && meta_low(o[u].w) != myid) {
-                        const double r2 = dist2(B, me.x, me.y, me.z, o[u].x, o[u].y, o[u].z);
-                        const int q = MIX ? sa * B.ns + meta_species(o[u].w) : 0;
-                        ei += VIR ? lj_virial_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q])
-                                  : lj_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q]);
+                        const double dx = nearest_image(o[u].x - me.x, K.L[0], K.hL[0]);
+                        const double dy = nearest_image(o[u].y - me.y, K.L[1], K.hL[1]);
+                        const double dz = nearest_image(o[u].z - me.z, K.L[2], K.hL[2]);
+                        const double r2 = (dx * dx + dy * dy) + dz * dz;
+                        const int q = MIX ? sa * ns + meta_species(o[u].w) : 0;
+                        const double e4 = MIX ? te4[q] : K.e4, s2 = MIX ? ts2[q] : K.s2;
+                        ei += VIR ? lj_virial_from_r2(r2, K.rc2, e4, s2) : lj_from_r2(r2, K.rc2, e4, s2);
                     }
                 }
             }
@@ -610,11 +644,14 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
                                                       int64_t n, double* grad, double* partial) {
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
+    __shared__ double te4[kMaxSpecies * kMaxSpecies], ts2[kMaxSpecies * kMaxSpecies];
     const DevBox& B = *boxp;
     load_stencil(B, tab);
+    load_species_tables(B, te4, ts2);
+    const PassConst K = pass_const(B);
     __syncthreads();
     const int64_t h = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    const int ns = B.ns;
+    const int ns = uni(B.ns);
     double gx = 0.0, gy = 0.0, gz = 0.0;
     double de[kMaxSpecies] = {0, 0, 0, 0}, ds[kMaxSpecies] = {0, 0, 0, 0};
     int sa = 0;
@@ -640,14 +677,14 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
               for (int u = 0; u < kUnroll; ++u) {
                 const double4& o = ob[u];
                 if (j + u >= nc || meta_low(o.w) == myid) continue;
-                const double dx = nearest_image(o.x - me.x, B.L[0], B.hL[0]);
-                const double dy = nearest_image(o.y - me.y, B.L[1], B.hL[1]);
-                const double dz = nearest_image(o.z - me.z, B.L[2], B.hL[2]);
+                const double dx = nearest_image(o.x - me.x, K.L[0], K.hL[0]);
+                const double dy = nearest_image(o.y - me.y, K.L[1], K.hL[1]);
+                const double dz = nearest_image(o.z - me.z, K.L[2], K.hL[2]);
                 const double r2 = (dx * dx + dy * dy) + dz * dz;
-                if (!(r2 < B.rc2) || r2 == 0.0) continue;
+                if (!(r2 < K.rc2) || r2 == 0.0) continue;
                 const int sb = meta_species(o.w);
                 const int q = MIX ? sa * ns + sb : 0;
-                const double eps4 = B.eps4[q], sig2 = B.sig2[q];
+                const double eps4 = MIX ? te4[q] : K.e4, sig2 = MIX ? ts2[q] : K.s2;
                 const double sr2 = sig2 / r2;
                 const double s6 = sr2 * sr2 * sr2;
                 const double s12 = s6 * s6;
