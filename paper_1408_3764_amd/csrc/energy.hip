@@ -31,6 +31,43 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
+// Constants of an energy pass held in registers for the whole kernel (read
+// once from the descriptor: the compiler would otherwise reload them from
+// memory inside the candidate loop), the species tables in LDS.
+struct PassConst {
+    double L[3], hL[3], rc2, e4, s2;
+};
+
+__device__ __forceinline__ PassConst pass_const(const DevBox& B) {
+    PassConst c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c.L[a] = unid(B.L[a]);
+        c.hL[a] = unid(B.hL[a]);
+    }
+    c.rc2 = unid(B.rc2);
+    c.e4 = unid(B.eps4[0]);
+    c.s2 = unid(B.sig2[0]);
+    return c;
+}
+
+// Squared minimum-image distance with the pass constants (the same
+// operations, in the same order, as dist2).
+__device__ __forceinline__ double pass_dist2(const PassConst& K, double px, double py, double pz, double qx, double qy,
+                                             double qz) {
+    const double dx = nearest_image(qx - px, K.L[0], K.hL[0]);
+    const double dy = nearest_image(qy - py, K.L[1], K.hL[1]);
+    const double dz = nearest_image(qz - pz, K.L[2], K.hL[2]);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ void load_species_tables(const DevBox& B, double* e4, double* s2) {
+    if (threadIdx.x < kMaxSpecies * kMaxSpecies) {
+        e4[threadIdx.x] = B.eps4[threadIdx.x];
+        s2[threadIdx.x] = B.sig2[threadIdx.x];
+    }
+}
+
 __device__ __forceinline__ void cell_coords(const DevBox& B, int64_t c, int32_t& cx, int32_t& cy, int32_t& cz) {
     cx = (int32_t)(c % B.M[0]);
     const int64_t r = c / B.M[0];
@@ -113,32 +150,6 @@ __global__ __launch_bounds__(kBlk) void k_home_order(DevBox B, const int32_t* __
 // ------------------------------------------------------ cell-list total
 constexpr int kUnroll = 4;   // candidate records requested together
 
-// Constants of a cell pass held in registers for the whole kernel (read once
-// from the descriptor: the compiler would otherwise reload them from memory
-// inside the candidate loop), the species tables in LDS.
-struct PassConst {
-    double L[3], hL[3], rc2, e4, s2;
-};
-
-__device__ __forceinline__ PassConst pass_const(const DevBox& B) {
-    PassConst c;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        c.L[a] = unid(B.L[a]);
-        c.hL[a] = unid(B.hL[a]);
-    }
-    c.rc2 = unid(B.rc2);
-    c.e4 = unid(B.eps4[0]);
-    c.s2 = unid(B.sig2[0]);
-    return c;
-}
-
-__device__ __forceinline__ void load_species_tables(const DevBox& B, double* e4, double* s2) {
-    if (threadIdx.x < kMaxSpecies * kMaxSpecies) {
-        e4[threadIdx.x] = B.eps4[threadIdx.x];
-        s2[threadIdx.x] = B.sig2[threadIdx.x];
-    }
-}
 
 // Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
 // VIR: the pair virial -r du/dr in place of the pair energy (pressure).
@@ -200,6 +211,8 @@ __global__ __launch_bounds__(kBlk) void k_total_allpairs(const DevBox* __restric
     __shared__ double4 tile[kBlk];
     __shared__ double red[kBlk / kWave];
     const DevBox& B = *boxp;
+    const PassConst K = pass_const(B);
+    const int ns = uni(B.ns);
     const int64_t n = B.st->n;
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const bool own = i < n;
@@ -215,12 +228,12 @@ __global__ __launch_bounds__(kBlk) void k_total_allpairs(const DevBox* __restric
         for (int q = 0; q < lim; ++q) {
             const double4 o = tile[q];
             if (own && j0 + q != i) {
-                const double r2 = dist2(B, me.x, me.y, me.z, o.x, o.y, o.z);
+                const double r2 = pass_dist2(K, me.x, me.y, me.z, o.x, o.y, o.z);
                 if (MIX) {
-                    const int qq = sa * B.ns + meta_species(o.w);
-                    ei += lj_from_r2(r2, B.rc2, B.eps4[qq], B.sig2[qq]);
+                    const int qq = sa * ns + meta_species(o.w);
+                    ei += lj_from_r2(r2, K.rc2, B.eps4[qq], B.sig2[qq]);
                 } else {
-                    ei += lj_from_r2(r2, B.rc2, B.eps4[0], B.sig2[0]);
+                    ei += lj_from_r2(r2, K.rc2, K.e4, K.s2);
                 }
             }
         }
@@ -295,16 +308,19 @@ __device__ __forceinline__ void ap_chunk_sums(const DevBox& B, const APTrial& T,
                                               int64_t j1, bool mix, double& sa, double& sb) {
     sa = 0.0;
     sb = 0.0;
+    const PassConst K = pass_const(B);
+    const int ns = uni(B.ns);
     for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
         if (j == T.idx) continue;
         const double4 o = gload(B.pos + j);
         int q = 0;
-        if (mix) q = T.sp * B.ns + meta_species(o.w);
-        const double r2a = dist2(B, T.p[0][0], T.p[0][1], T.p[0][2], o.x, o.y, o.z);
-        sa += lj_from_r2(r2a, B.rc2, B.eps4[q], B.sig2[q]);
+        if (mix) q = T.sp * ns + meta_species(o.w);
+        const double e4 = mix ? B.eps4[q] : K.e4, s2 = mix ? B.sig2[q] : K.s2;
+        const double r2a = pass_dist2(K, T.p[0][0], T.p[0][1], T.p[0][2], o.x, o.y, o.z);
+        sa += lj_from_r2(r2a, K.rc2, e4, s2);
         if (T.npos == 2) {
-            const double r2b = dist2(B, T.p[1][0], T.p[1][1], T.p[1][2], o.x, o.y, o.z);
-            sb += lj_from_r2(r2b, B.rc2, B.eps4[q], B.sig2[q]);
+            const double r2b = pass_dist2(K, T.p[1][0], T.p[1][1], T.p[1][2], o.x, o.y, o.z);
+            sb += lj_from_r2(r2b, K.rc2, e4, s2);
         }
     }
 }
