@@ -355,21 +355,26 @@ def main():
     log("workload %s: N=%d generated in %.1fs" % (wb.name, wb.n, time.perf_counter() - t))
     mps = args.moves_per_step or wb.n_moves
     total_moves = mps * (args.steps + args.warmup) + 40_000   # + the moves the tuner runs
-    box = Box.from_workload(wb, max_n=wb.n + total_moves + 1)
-    info = box.info()
-    nst = info["n_stencil"]
-    U0 = box.total_energy()
+    cell_m = None
     tuning = None
     if args.waves:
+        box = Box.from_workload(wb, max_n=wb.n + total_moves + 1)
         box.set_launch(args.waves, args.rows)
         shape = (args.waves, args.rows)
     elif args.no_tune:
+        box = Box.from_workload(wb, max_n=wb.n + total_moves + 1)
         shape = tune.chain_shape(box)
         box.set_launch(*shape)
     else:
-        # time every launch shape on this machine (the chain continues on its device counter)
-        shape, tuning = tune.autotune_live(box)
-        log("tuned launch %dx%d: %s" % (shape[0], shape[1], {k: round(v * 1e3, 2) for k, v in tuning.items()}))
+        # cell size (the paper's cells, or twice as many per axis) and launch shape, every
+        # candidate timed on its own box (the chain continues on the device counter)
+        box, cell_m, shape, tuning = tune.autotune_cells(
+            lambda cm: Box.from_workload(wb, max_n=wb.n + total_moves + 1, cell_m=cm))
+        log("tuned cells %s, launch %dx%d: %s" % (box.info()["cell_m"], shape[0], shape[1],
+                                                   {k: round(v * 1e3, 2) for k, v in tuning.items()}))
+    info = box.info()
+    nst = info["n_stencil"]
+    U0 = box.total_energy()
     log("box: cells %s cap %d stencil %d, launch %dx%d, U0=%.6f" % (info["cell_m"], info["cell_cap"], nst,
                                                                      shape[0], shape[1], U0["U_pair"]))
     from paper_1408_3764_amd._lib import COUNTER_CONTINUE
@@ -512,7 +517,7 @@ def main():
     if not args.no_cpu:
         n_cpu, dt, olog = run_cpu_baseline(wb, args.cpu_budget, 20000)
         # the same moves on the GPU, for a parity check of the timed chain
-        pb = Box.from_workload(wb, max_n=wb.n + n_cpu + 1)
+        pb = Box.from_workload(wb, max_n=wb.n + n_cpu + 1, cell_m=cell_m)
         pb.set_launch(*shape)
         _, glog = pb.step(n_cpu, counter0=0, log=True)
         same = bool(np.array_equal(glog["type"], olog["type"]) and np.array_equal(glog["accepted"], olog["accepted"])

@@ -102,6 +102,39 @@ def autotune_live(box, n_moves=3000, shapes=None):
     return best[1], timings
 
 
+def autotune_cells(make_box, factors=(1, 2), n_moves=3000):
+    """Cell size and launch shape together.  make_box(cell_m) builds the box:
+    cell_m None gives the paper's cells (side >= rc, 27-cell stencils); factor
+    f > 1 asks for f times as many cells per axis (microcells, whose stencils
+    drop the cells beyond the cutoff).  Every launch shape that applies is
+    timed on each box with autotune_live (its chain continues on the device
+    counter); the fastest box is returned open with its shape set and the
+    others are closed.  Returns (box, cell_m or None, shape, timings keyed
+    "MxMxM/WxR")."""
+    best = None
+    base = None
+    timings = {}
+    for f in factors:
+        cm = None if f == 1 else [f * m for m in base]
+        b = make_box(cm)
+        info = b.info()
+        if base is None:
+            base = info["cell_m"]
+        shape, t = autotune_live(b, n_moves=n_moves)
+        grid = "x".join(str(m) for m in info["cell_m"])
+        for k, v in t.items():
+            timings["%s/%s" % (grid, k)] = v
+        dt = t["%dx%d" % shape]
+        if best is None or dt < best[0]:
+            if best is not None:
+                best[1].close()
+            best = (dt, b, cm, shape)
+        else:
+            b.close()
+    best[1].set_launch(*best[3])
+    return best[1], best[2], best[3], timings
+
+
 def autotune_chain(make_box, n_moves=2000, shapes=SHAPES, key=None):
     """Time each launch shape on a fresh box from make_box() and return the fastest.
     Every shape runs the same chain (counter-based draws), so the comparison is
