@@ -503,10 +503,15 @@ def main():
         torch.cuda.synchronize()
         db = time.perf_counter() - tb
         bmoves = 1000 * len(boxes)
+        b_alg = float(sum(alg_bytes(bst[k], boxes[k].info()["n_stencil"]) for k in range(len(boxes))))
+        b_ms = e0.elapsed_time(e1)
         out["batched"] = {"boxes": len(boxes), "moves_per_box": 1000, "moves_per_s": bmoves / db,
                           "pair_evals_per_s": float(np.sum(bst["pair_evals"])) / db,
-                          "launch_ms": e0.elapsed_time(e1), "launch": {"waves": bshape[0], "rows": bshape[1]},
-                          "errors": int(np.count_nonzero(bst["error"]))}
+                          "launch_ms": b_ms, "launch": {"waves": bshape[0], "rows": bshape[1]},
+                          "errors": int(np.count_nonzero(bst["error"])),
+                          "roofline": {"bound": "hbm", "alg_bytes_per_launch": b_alg,
+                                       "achieved": b_alg / (b_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": b_alg / (b_ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
         bt.close()
         for b in boxes:
             b.close()
