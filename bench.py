@@ -512,6 +512,30 @@ def main():
                           "roofline": {"bound": "hbm", "alg_bytes_per_launch": b_alg,
                                        "achieved": b_alg / (b_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": b_alg / (b_ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
+        # the same 1,000 moves per box as ten 100-move launches captured in one HIP graph
+        # (device-side move counters), replayed once to warm up and once timed
+        from paper_1408_3764_amd import _lib
+        from paper_1408_3764_amd._lib import STATS_DTYPE
+        gs = torch.cuda.Stream()
+        gst = torch.zeros(len(boxes) * STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs):
+            for _ in range(10):
+                _lib.gcmc_batch_step(bt.handle, 100, COUNTER_CONTINUE, gst, gs)
+        graph.replay()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()
+        graph.replay()
+        g1.record()
+        torch.cuda.synchronize()
+        g_ms = g0.elapsed_time(g1)
+        gstats = np.frombuffer(gst.cpu().numpy().tobytes(), dtype=STATS_DTYPE)
+        out["batched"]["graph"] = {"launches": 10, "moves_per_launch": 100, "replay_ms": g_ms,
+                                   "moves_per_s": bmoves / (g_ms / 1e3),
+                                   "errors": int(np.count_nonzero(gstats["error"]))}
+        log("batched: one launch of 1,000 moves/box %.3f ms; graph of 10 x 100 moves/box %.3f ms" % (b_ms, g_ms))
         bt.close()
         for b in boxes:
             b.close()
