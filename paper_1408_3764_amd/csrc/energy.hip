@@ -153,6 +153,55 @@ constexpr int kUnroll = 4;   // candidate records requested together
 
 // Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
 // VIR: the pair virial -r du/dr in place of the pair energy (pressure).
+// Does the stencil of cell (cx, cy, cz) stay clear of the periodic wrap with room
+// to spare?  Then every candidate lies within (k + 1) S < L/2 of the home
+// particle along each axis (at least 2k + 3 cells per axis: half a cell of
+// margin, far above the rounding of the cell assignment), and the minimum
+// image of a coordinate difference is the difference itself, bit for bit.
+__device__ __forceinline__ bool stencil_inside(const DevBox& B, int32_t cx, int32_t cy, int32_t cz) {
+    const int32_t c[3] = {cx, cy, cz};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        in = in && B.M[a] >= 2 * B.k[a] + 3 && c[a] >= B.k[a] && c[a] <= B.M[a] - 1 - B.k[a];
+    return in;
+}
+
+__device__ __forceinline__ double image_diff(double d, double L, double hL, bool wrap) {
+    return wrap ? nearest_image(d, L, hL) : d;
+}
+
+// e_i of one home particle over its stencil (WRAP: apply the minimum image).
+template <bool MIX, bool VIR, bool WRAP>
+__device__ __forceinline__ double home_energy(const DevBox& B, const PassConst& K, const uint32_t* tab,
+                                              const double* te4, const double* ts2, const double4& me, int32_t myid,
+                                              int sa, int ns, int32_t cx, int32_t cy, int32_t cz) {
+    double ei = 0.0;
+    for (int t = 0; t < B.nstencil; ++t) {
+        const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
+        const int32_t nc = gload(B.count + nb);
+        const double4* ne = B.ent + nb * B.cap;
+        for (int j = 0; j < nc; j += kUnroll) {
+            double4 o[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) o[u] = gload(ne + (j + u < nc ? j + u : j));
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (j + u < nc && meta_low(o[u].w) != myid) {
+                    const double dx = image_diff(o[u].x - me.x, K.L[0], K.hL[0], WRAP);
+                    const double dy = image_diff(o[u].y - me.y, K.L[1], K.hL[1], WRAP);
+                    const double dz = image_diff(o[u].z - me.z, K.L[2], K.hL[2], WRAP);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    const int q = MIX ? sa * ns + meta_species(o[u].w) : 0;
+                    const double e4 = MIX ? te4[q] : K.e4, s2 = MIX ? ts2[q] : K.s2;
+                    ei += VIR ? lj_virial_from_r2(r2, K.rc2, e4, s2) : lj_from_r2(r2, K.rc2, e4, s2);
+                }
+            }
+        }
+    }
+    return ei;
+}
+
 template <bool MIX, bool VIR = false>
 __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__ boxp, const int32_t* __restrict__ home,
                                                        int64_t n, double* e_out, double* partial) {
@@ -176,28 +225,11 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
         const int ns = uni(B.ns);
         int32_t cx, cy, cz;
         cell_coords(B, c, cx, cy, cz);
-        for (int t = 0; t < B.nstencil; ++t) {
-            const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
-            const int32_t nc = gload(B.count + nb);
-            const double4* ne = B.ent + nb * B.cap;
-            for (int j = 0; j < nc; j += kUnroll) {
-                double4 o[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) o[u] = gload(ne + (j + u < nc ? j + u : j));
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (j + u < nc && meta_low(o[u].w) != myid) {
-                        const double dx = nearest_image(o[u].x - me.x, K.L[0], K.hL[0]);
-                        const double dy = nearest_image(o[u].y - me.y, K.L[1], K.hL[1]);
-                        const double dz = nearest_image(o[u].z - me.z, K.L[2], K.hL[2]);
-                        const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        const int q = MIX ? sa * ns + meta_species(o[u].w) : 0;
-                        const double e4 = MIX ? te4[q] : K.e4, s2 = MIX ? ts2[q] : K.s2;
-                        ei += VIR ? lj_virial_from_r2(r2, K.rc2, e4, s2) : lj_from_r2(r2, K.rc2, e4, s2);
-                    }
-                }
-            }
-        }
+        // the wrap is skipped when no lane of the wavefront needs it
+        if (__ballot(!stencil_inside(B, cx, cy, cz)) != 0)
+            ei = home_energy<MIX, VIR, true>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz);
+        else
+            ei = home_energy<MIX, VIR, false>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz);
         if (e_out) e_out[myid] = ei;
     }
     const double s = block_sum(ei, red);
@@ -655,6 +687,62 @@ __device__ int commit_ap(const DevBox& B, const APTrial& T, const double4& rec, 
 // particle id; parameter partials per block: [0, ns^2) d eps, [ns^2, 2 ns^2)
 // d sigma, each pair met twice contributing half from each end.  One lane per
 // particle in cell order, as the total energy.
+struct GradAcc {
+    double gx, gy, gz;
+    double de[kMaxSpecies], ds[kMaxSpecies];
+};
+
+// Force and parameter-derivative sums of one home particle over its stencil
+// (WRAP: apply the minimum image).
+template <bool MIX, bool WRAP>
+__device__ __forceinline__ void home_gradient(const DevBox& B, const PassConst& K, const uint32_t* tab,
+                                              const double* te4, const double* ts2, const double4& me, int32_t myid,
+                                              int sa, int ns, int32_t cx, int32_t cy, int32_t cz, GradAcc& A) {
+    for (int t = 0; t < B.nstencil; ++t) {
+        const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
+        const int32_t nc = gload(B.count + nb);
+        const double4* ne = B.ent + nb * B.cap;
+        for (int j = 0; j < nc; j += kUnroll) {
+            double4 ob[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) ob[u] = gload(ne + (j + u < nc ? j + u : j));
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const double4& o = ob[u];
+                if (j + u >= nc || meta_low(o.w) == myid) continue;
+                const double dx = image_diff(o.x - me.x, K.L[0], K.hL[0], WRAP);
+                const double dy = image_diff(o.y - me.y, K.L[1], K.hL[1], WRAP);
+                const double dz = image_diff(o.z - me.z, K.L[2], K.hL[2], WRAP);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (!(r2 < K.rc2) || r2 == 0.0) continue;
+                const int sb = meta_species(o.w);
+                const int q = MIX ? sa * ns + sb : 0;
+                const double eps4 = MIX ? te4[q] : K.e4, sig2 = MIX ? ts2[q] : K.s2;
+                const double sr2 = sig2 / r2;
+                const double s6 = sr2 * sr2 * sr2;
+                const double s12 = s6 * s6;
+                const double coef = (6.0 * eps4 / r2) * (2.0 * s12 - s6);
+                A.gx += coef * dx;
+                A.gy += coef * dy;
+                A.gz += coef * dz;
+                const double t_e = 0.5 * 4.0 * (s12 - s6);
+                const double t_s = 0.5 * (eps4 / sqrt(sig2)) * (12.0 * s12 - 6.0 * s6);
+                if (MIX) {
+#pragma unroll
+                    for (int b = 0; b < kMaxSpecies; ++b)
+                        if (b == sb) {
+                            A.de[b] += t_e;
+                            A.ds[b] += t_s;
+                        }
+                } else {
+                    A.de[0] += t_e;
+                    A.ds[0] += t_s;
+                }
+            }
+        }
+    }
+}
+
 template <bool MIX>
 __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ boxp, const int32_t* __restrict__ home,
                                                       int64_t n, double* grad, double* partial) {
@@ -668,8 +756,10 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
     __syncthreads();
     const int64_t h = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const int ns = uni(B.ns);
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    double de[kMaxSpecies] = {0, 0, 0, 0}, ds[kMaxSpecies] = {0, 0, 0, 0};
+    GradAcc A;
+    A.gx = A.gy = A.gz = 0.0;
+#pragma unroll
+    for (int b = 0; b < kMaxSpecies; ++b) A.de[b] = A.ds[b] = 0.0;
     int sa = 0;
     const bool own = h < n;
     if (own) {
@@ -681,60 +771,21 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
         sa = meta_species(me.w);
         int32_t cx, cy, cz;
         cell_coords(B, c, cx, cy, cz);
-        for (int t = 0; t < B.nstencil; ++t) {
-            const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
-            const int32_t nc = gload(B.count + nb);
-            const double4* ne = B.ent + nb * B.cap;
-            for (int j = 0; j < nc; j += kUnroll) {
-              double4 ob[kUnroll];
-#pragma unroll
-              for (int u = 0; u < kUnroll; ++u) ob[u] = gload(ne + (j + u < nc ? j + u : j));
-#pragma unroll
-              for (int u = 0; u < kUnroll; ++u) {
-                const double4& o = ob[u];
-                if (j + u >= nc || meta_low(o.w) == myid) continue;
-                const double dx = nearest_image(o.x - me.x, K.L[0], K.hL[0]);
-                const double dy = nearest_image(o.y - me.y, K.L[1], K.hL[1]);
-                const double dz = nearest_image(o.z - me.z, K.L[2], K.hL[2]);
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                if (!(r2 < K.rc2) || r2 == 0.0) continue;
-                const int sb = meta_species(o.w);
-                const int q = MIX ? sa * ns + sb : 0;
-                const double eps4 = MIX ? te4[q] : K.e4, sig2 = MIX ? ts2[q] : K.s2;
-                const double sr2 = sig2 / r2;
-                const double s6 = sr2 * sr2 * sr2;
-                const double s12 = s6 * s6;
-                const double coef = (6.0 * eps4 / r2) * (2.0 * s12 - s6);
-                gx += coef * dx;
-                gy += coef * dy;
-                gz += coef * dz;
-                const double t_e = 0.5 * 4.0 * (s12 - s6);
-                const double t_s = 0.5 * (eps4 / sqrt(sig2)) * (12.0 * s12 - 6.0 * s6);
-                if (MIX) {
-                    for (int b = 0; b < kMaxSpecies; ++b)
-                        if (b == sb) {
-                            de[b] += t_e;
-                            ds[b] += t_s;
-                        }
-                } else {
-                    de[0] += t_e;
-                    ds[0] += t_s;
-                }
-              }
-            }
-        }
+        // (one loop for every wavefront: a second, wrap-free copy as in the energy pass costs
+        // more in registers than it saves here)
+        home_gradient<MIX, true>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz, A);
         if (grad) {
-            grad[myid] = gx;
-            grad[n + myid] = gy;
-            grad[2 * n + myid] = gz;
+            grad[myid] = A.gx;
+            grad[n + myid] = A.gy;
+            grad[2 * n + myid] = A.gz;
         }
     }
     // parameter partials: entry (a, b) gets the lanes with own species a
     for (int a = 0; a < ns; ++a) {
         for (int b = 0; b < ns; ++b) {
             const bool mine = own && sa == a;
-            const double ve = block_sum(mine ? de[b] : 0.0, red);
-            const double vs = block_sum(mine ? ds[b] : 0.0, red);
+            const double ve = block_sum(mine ? A.de[b] : 0.0, red);
+            const double vs = block_sum(mine ? A.ds[b] : 0.0, red);
             if (threadIdx.x == 0) {
                 partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + a * ns + b] = ve;
                 partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + kMaxSpecies * kMaxSpecies + a * ns + b] =
