@@ -784,8 +784,15 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
     for (int a = 0; a < ns; ++a) {
         for (int b = 0; b < ns; ++b) {
             const bool mine = own && sa == a;
-            const double ve = block_sum(mine ? A.de[b] : 0.0, red);
-            const double vs = block_sum(mine ? A.ds[b] : 0.0, red);
+            double le = 0.0, ls = 0.0;   // A.de[b], A.ds[b] read with static indices (registers, not scratch)
+#pragma unroll
+            for (int q = 0; q < kMaxSpecies; ++q)
+                if (q == b) {
+                    le = A.de[q];
+                    ls = A.ds[q];
+                }
+            const double ve = block_sum(mine ? le : 0.0, red);
+            const double vs = block_sum(mine ? ls : 0.0, red);
             if (threadIdx.x == 0) {
                 partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + a * ns + b] = ve;
                 partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + kMaxSpecies * kMaxSpecies + a * ns + b] =
