@@ -121,12 +121,14 @@ def test_slab_chain_matches_oracle(slab, shape):
     assert k == 150
 
 
-def test_batched_sample_matches_oracle():
-    """512 boxes advanced together (the benchmark's launch); six boxes checked move for move."""
+@pytest.mark.parametrize("bshape", [None, (4, 0)])
+def test_batched_sample_matches_oracle(bshape):
+    """512 boxes advanced together in one launch (the per-move heuristic shape, and the
+    speculative 4x0 the benchmark's tuner picks); six boxes checked move for move."""
     from paper_1408_3764_amd.box import Batch, Box
     wbs = workloads.batched()
     boxes = [Box.from_workload(w, max_n=w.n + 1001, box_id=k) for k, w in enumerate(wbs)]
-    shape = tune.batch_shape(boxes)
+    shape = bshape or tune.batch_shape(boxes)
     for b in boxes:
         b.set_launch(*shape)
     bt = Batch(boxes)
