@@ -351,7 +351,6 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
                 if (type == GCMC_MOVE_DELETE) {
                     rl = S.wrec[N - 1 - mb];
                 }
-                const int32_t rl_cell = __builtin_amdgcn_readfirstlane(meta_low(rl.w) / cap);
                 if (swap) {
                     const double w = pack_meta(meta_species(R.elast.w), (int32_t)loc);
                     if (lane == 0) {
@@ -399,8 +398,14 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
                 // the log entry: cells modified, particle records rewritten
                 lc0 = pack_cell(R.c0[0], R.c0[1], R.c0[2]);
                 if (is_disp && two) lc1 = pack_cell(R.c1[0], R.c1[1], R.c1[2]);
-                if (type == GCMC_MOVE_DELETE && idx != N - 1 && id_last != (int32_t)(N - 1) && rl_cell != (int32_t)c0)
-                    lc2 = pack_cell(rl_cell % B.M[0], (rl_cell / B.M[0]) % B.M[1], rl_cell / (B.M[0] * B.M[1]));
+                if (type == GCMC_MOVE_DELETE && idx != N - 1 && id_last != (int32_t)(N - 1)) {
+                    // the relabelled particle's cell, from its position (every record lives in the
+                    // cell of its position)
+                    const int32_t rx = spec_axis_cell(rl.x, B.invS[0], B.M[0]);
+                    const int32_t ry = spec_axis_cell(rl.y, B.invS[1], B.M[1]);
+                    const int32_t rz = spec_axis_cell(rl.z, B.invS[2], B.M[2]);
+                    if ((rz * B.M[1] + ry) * B.M[0] + rx != (int32_t)c0) lc2 = pack_cell(rx, ry, rz);
+                }
                 li0 = is_ins ? (int32_t)N : (int32_t)idx;
                 li1 = swap ? id_last : -1;
                 li2 = (type == GCMC_MOVE_DELETE) ? (int32_t)(N - 1) : -1;

@@ -177,7 +177,6 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                         const double4 v = top[N - 1 - base];
                         rlx = v.x; rly = v.y; rlz = v.z; rlw = v.w;
                     }
-                    const int32_t rl_cell = __builtin_amdgcn_readfirstlane(meta_low(rlw) / cap);
                     if (lane == 0) {
                         // every store to pos[j] for j in the round's window is mirrored in top[]
                         if (swap) {
@@ -228,12 +227,15 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     // particle's cell: that cell counts as modified too (a later removal from it
                     // would otherwise copy the stale id with the cell's last entry)
                     if (type == GCMC_MOVE_DELETE && idx != N - 1 && id_last != (int32_t)(N - 1)) {
-                        const int32_t cx = rl_cell;
-                        if (cx != (int32_t)c0) {
+                        // its cell from its position (every record lives in the cell of its position)
+                        const int32_t rx = spec_axis_cell(rlx, B.invS[0], B.M[0]);
+                        const int32_t ry = spec_axis_cell(rly, B.invS[1], B.M[1]);
+                        const int32_t rz = spec_axis_cell(rlz, B.invS[2], B.M[2]);
+                        if ((rz * B.M[1] + ry) * B.M[0] + rx != (int32_t)c0) {
                             if (lane == nmod) {
-                                modx = cx % B.M[0];
-                                mody = (cx / B.M[0]) % B.M[1];
-                                modz = cx / (B.M[0] * B.M[1]);
+                                modx = rx;
+                                mody = ry;
+                                modz = rz;
                             }
                             nmod += 1;
                         }
