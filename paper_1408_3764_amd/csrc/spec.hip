@@ -165,10 +165,11 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                         err_move = (int64_t)ctr;
                         break;
                     }
-                    const int64_t loc = meta_low(R.rec.w);
-                    const int64_t c0 = R.cl0, c1 = R.cl1;
+                    // slot and cell indices fit 32 bits (cells x capacity < 2^31 for this kernel)
+                    const int32_t loc = meta_low(R.rec.w);
+                    const int32_t c0 = R.cl0, c1 = R.cl1;
                     const bool removes = (type == GCMC_MOVE_DELETE) || (is_disp && two);
-                    const int64_t last = c0 * cap + cnt0 - 1;
+                    const int32_t last = c0 * cap + cnt0 - 1;
                     const bool swap = removes && loc != last;
                     const int32_t id_last = swap ? meta_low(R.elast.w) : -1;
                     // the record of particle N-1 as of now (kept as scalars so that it stays in registers)
@@ -194,14 +195,14 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                                 gstore(B.ent + loc, make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)idx)));
                                 nr = make_double4(R.p1[0], R.p1[1], R.p1[2], R.rec.w);
                             } else {
-                                const int64_t nl = c1 * cap + cnt1;
+                                const int32_t nl = c1 * cap + cnt1;
                                 gstore(B.ent + nl, make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)idx)));
                                 gstore(B.count + c1, cnt1 + 1);
                                 nr = make_double4(R.p1[0], R.p1[1], R.p1[2], pack_meta(0, (int32_t)nl));
                             }
                             j = idx;
                         } else if (is_ins) {
-                            const int64_t nl = c0 * cap + cnt0;
+                            const int32_t nl = c0 * cap + cnt0;
                             gstore(B.ent + nl, make_double4(R.p0[0], R.p0[1], R.p0[2], pack_meta(0, (int32_t)N)));
                             gstore(B.count + c0, cnt0 + 1);
                             nr = make_double4(R.p0[0], R.p0[1], R.p0[2], pack_meta(0, (int32_t)nl));
