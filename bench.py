@@ -443,6 +443,30 @@ def main():
                      "avg_launch_ms": 1e3 * avg_launch_s},
     }
 
+    # the cell-list build of the same box (binning, Sec. 3.2.1): counters cleared, every particle
+    # claims a slot of its cell, cells ordered by particle id; algorithmic bytes per build: each
+    # record read (32 B) and written into its cell (32 B) with its back-pointer (8 B), and the
+    # counters cleared and incremented (8 B per cell)
+    n_now = box.n
+    box.cell_build()
+    torch.cuda.synchronize()
+    bts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        box.cell_build()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bts.append(e0.elapsed_time(e1))
+    b_ms = float(np.median(bts))
+    b_bytes = 72.0 * n_now + 8.0 * info["n_cells"]
+    out["cell_build"] = {"n": n_now, "cells": info["n_cells"], "ms_median": b_ms,
+                         "particles_per_s": n_now / (b_ms / 1e3),
+                         "roofline": {"bound": "hbm", "alg_bytes": b_bytes,
+                                      "achieved": b_bytes / (b_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": b_bytes / (b_ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
+    log("cell-list build of %d particles in %d cells: %.3f ms" % (n_now, info["n_cells"], b_ms))
+
     if not args.no_allpairs:
         # the paper's comparison of its cell list with the no-cell-list GPU code, on the
         # 262,144-particle box (rc = 3.0): the same chain through both paths

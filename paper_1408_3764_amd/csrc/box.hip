@@ -109,6 +109,49 @@ __global__ void k_sort_cells(DevBox B) {
     }
 }
 
+// Pass 3 with one wavefront per cell, for capacities up to 64: lane k holds the
+// cell's entry k; the ids are unique, so the entry's slot in id order is the
+// number of the cell's entries with a smaller id, and every entry is written
+// once, straight to its slot (the layout is the one the per-thread sort above
+// produces).  Species counts and the largest occupancy are kept per wavefront
+// over its cells and added once at the end.
+__global__ __launch_bounds__(256) void k_sort_cells_wave(DevBox B) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    const int ns = B.ns;
+    int64_t nsp[kMaxSpecies] = {0, 0, 0, 0};
+    int32_t maxc = 0;
+    for (int64_t c = wave0; c < B.ncells; c += nwaves) {
+        int32_t cnt = B.count[c];
+        cnt = __builtin_amdgcn_readfirstlane(cnt > B.cap ? B.cap : cnt);
+        if (cnt == 0) continue;
+        double4* e = B.ent + c * B.cap;
+        double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+        int32_t id = INT32_MAX;
+        if (lane < cnt) {
+            v = e[lane];
+            id = meta_low(v.w);
+        }
+        int32_t rank = 0;
+        for (int j = 0; j < cnt; ++j) rank += (__builtin_amdgcn_readlane(id, j) < id) ? 1 : 0;
+        // every lane's load has completed (the ranks read all ids) before any store below
+        if (lane < cnt) {
+            e[rank] = v;
+            B.pos[id].w = pack_meta(meta_species(v.w), (int32_t)(c * B.cap + rank));
+        }
+        const int sp = meta_species(v.w);
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; ++q) nsp[q] += __popcll(__ballot(lane < cnt && sp == q));
+        maxc = cnt > maxc ? cnt : maxc;
+    }
+    if (lane == 0) {
+        for (int q = 0; q < ns; ++q)
+            if (nsp[q]) atomicAdd((unsigned long long*)&B.st->nsp[q], (unsigned long long)nsp[q]);
+        if (maxc) atomicMax(&B.st->maxcount, maxc);
+    }
+}
+
 // keep_error: a rebuild keeps the latched error, its move and the move counter.
 __global__ void k_reset_state(BoxState* st, int64_t n, double u_pair, int keep_error) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -297,7 +340,12 @@ static int bin_particles(gcmc_box* box, int64_t n, hipStream_t s, bool keep_erro
     k_reset_state<<<1, 1, 0, s>>>(B.st, n, u_pair, keep_error ? 1 : 0);
     k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
     if (n > 0) k_bin<<<grid_for(n), 256, 0, s>>>(B, n);
-    k_sort_cells<<<grid_for(B.ncells), 256, 0, s>>>(B);
+    if (B.cap <= kWave) {
+        const int64_t blocks = std::min<int64_t>((B.ncells + 3) / 4, 4096);
+        k_sort_cells_wave<<<(unsigned)blocks, 256, 0, s>>>(B);
+    } else {
+        k_sort_cells<<<grid_for(B.ncells), 256, 0, s>>>(B);
+    }
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }
