@@ -57,14 +57,18 @@ __device__ __forceinline__ int64_t cell_of_point(const DevBox& B, double x, doub
     return ((int64_t)cz * B.M[1] + cy) * B.M[0] + cx;
 }
 
-// Pass 1: occupancy only (to size the cells).
+// Pass 1: occupancy only (to size the cells); the largest count is kept per
+// wavefront and published with one atomic.
 __global__ void k_count(DevBox B, int64_t n) {
+    int32_t mx = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double4 p = B.pos[i];
         const int64_t c = cell_of_point(B, p.x, p.y, p.z);
         const int32_t k = atomicAdd(&B.count[c], 1);
-        atomicMax(&B.st->maxcount, k + 1);
+        mx = k + 1 > mx ? k + 1 : mx;
     }
+    mx = wave_max_i32_uniform(mx);
+    if ((threadIdx.x & (kWave - 1)) == 0 && mx > 0) atomicMax(&B.st->maxcount, mx);
 }
 
 // Pass 2: claim a slot and write the cell entry.
