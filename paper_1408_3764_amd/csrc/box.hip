@@ -85,9 +85,12 @@ __global__ void k_bin(DevBox B, int64_t n) {
     }
 }
 
-// Pass 3: order each cell by particle id, set the back-pointers, and gather
-// the maximum occupancy and the species counts.
+// Pass 3 (capacities above 64): order each cell by particle id, set the
+// back-pointers, and gather the maximum occupancy and the species counts (kept
+// per thread, summed per wavefront, one atomic each).
 __global__ void k_sort_cells(DevBox B) {
+    int32_t nsp[kMaxSpecies] = {0, 0, 0, 0};
+    int32_t maxc = 0;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < B.ncells;
          c += (int64_t)gridDim.x * blockDim.x) {
         int32_t cnt = B.count[c];
@@ -106,11 +109,21 @@ __global__ void k_sort_cells(DevBox B) {
         for (int32_t a = 0; a < cnt; ++a) {
             const double4 v = e[a];
             const int32_t id = meta_low(v.w);
-            B.pos[id].w = pack_meta(meta_species(v.w), (int32_t)(c * B.cap + a));
-            atomicAdd((unsigned long long*)&B.st->nsp[meta_species(v.w)], 1ull);
+            const int sp = meta_species(v.w);
+            B.pos[id].w = pack_meta(sp, (int32_t)(c * B.cap + a));
+#pragma unroll
+            for (int q = 0; q < kMaxSpecies; ++q) nsp[q] += (sp == q) ? 1 : 0;
         }
-        if (cnt > 0) atomicMax(&B.st->maxcount, cnt);
+        maxc = cnt > maxc ? cnt : maxc;
     }
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int q = 0; q < kMaxSpecies; ++q) {
+        const int32_t t = wave_sum_i32_uniform(nsp[q]);
+        if (lane == 0 && t > 0) atomicAdd((unsigned long long*)&B.st->nsp[q], (unsigned long long)t);
+    }
+    maxc = wave_max_i32_uniform(maxc);
+    if (lane == 0 && maxc > 0) atomicMax(&B.st->maxcount, maxc);
 }
 
 // Pass 3 with one wavefront per cell, for capacities up to 64: lane k holds the

@@ -98,6 +98,24 @@ def test_cell_assignment_bitexact(case):
     assert b.info()["cell_m"] == list(g["M"]) and b.info()["span"] == list(g["span"])
 
 
+@pytest.mark.parametrize("cap", [0, 100])
+def test_cell_build_both_sort_paths(cap):
+    """The cell build orders entries with one wavefront per cell up to 64 slots per
+    cell and with one thread per cell above that; both give the oracle's cells,
+    id order inside each cell, and species counts (checked through U_tail)."""
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    wb = workloads.random_box(500, 11.0, rc=3.0, seed=12, species_counts=[250, 250], eps=eps, sigma=sig)
+    b = _box(wb, cell_cap=cap)
+    assert (b.info()["cell_cap"] > 64) == (cap == 100)
+    cell_of, count, ids = b.cells()
+    ref = oracle.cell_of(wb.pos, wb.L, wb.rc)
+    assert np.array_equal(cell_of.astype(np.int64), ref)
+    for cidx in np.nonzero(count)[0]:
+        assert ids[cidx, : count[cidx]].tolist() == sorted(np.nonzero(ref == cidx)[0].tolist())
+    t = oracle.total_energy(wb.pos, _params(wb), species=wb.species)
+    assert b.total_energy()["U_tail"] == pytest.approx(t["U_tail"], rel=1e-13)
+
+
 def test_cell_assignment_c1_exact_grid(c1):
     b = _box(c1)
     assert b.info()["cell_m"] == [8, 8, 8]
