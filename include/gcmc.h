@@ -47,7 +47,7 @@ enum {
     GCMC_ERR_HIP = 5,           /* a HIP runtime call failed */
     GCMC_ERR_POISONED = 6,      /* the box holds a latched device error */
     GCMC_ERR_UNSUPPORTED = 7,   /* valid but not implemented (e.g. a chain over a mixture) */
-    GCMC_ERR_INTERNAL = 8       /* a wait inside the pipelined chain kernel exceeded its bound (latched) */
+    GCMC_ERR_INTERNAL = 8       /* a wait inside a chain kernel (pipelined or speculative) exceeded its bound (latched) */
 };
 
 enum { GCMC_MOVE_DISPLACE = 0, GCMC_MOVE_INSERT = 1, GCMC_MOVE_DELETE = 2 };

@@ -15,7 +15,9 @@
 //     candidate to its cell, and then exactly the candidates' 32-byte records
 //     (one memory round trip for the counters, one for the records);
 //   * the pair sums, reduced across the wavefront, and ln A.
-// Wavefront 0 then walks the round's moves in order.  A move's evaluation is
+// Wavefront 0 then walks the round's moves in order, taking each as soon as
+// its wavefront has published it (a flag in LDS), while slower wavefronts may
+// still be evaluating.  A move's evaluation is
 // used only if nothing it read has changed since the round started: its pick
 // at the current N is the one it evaluated, the particle record
 // it read was not touched by an earlier commit of the round, and no cell
@@ -25,13 +27,18 @@
 // the records it needs came back with its evaluation).  N moves by at most one
 // per move, so the records of particles N_round - W .. N_round + W - 1 (what a
 // deletion moves into the freed index) and the prefactors for those N are
-// prepared in LDS at the start of the round, in parallel with the evaluations,
-// and kept current by the commits.  The first move that
+// prepared in LDS by wavefront 0 at the start of the round, and kept current by
+// the commits.  The check also covers commits whose stores land while a later
+// move is still reading: whatever a commit writes lies in a modified cell or a
+// touched particle record.  The first move that
 // fails the check ends the round and is evaluated again in the next one, so
 // every move is decided on exactly the state the sequential chain would have.
 #include "spec_eval.h"
 
 namespace gcmc {
+
+// Polls of a move's ready flag before the commit gives up with GCMC_ERR_INTERNAL.
+constexpr int32_t kSpecSpinCap = 1 << 26;
 
 template <int W, int CR>
 __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restrict__ boxes,
@@ -47,6 +54,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     __shared__ double sh_u;
     __shared__ double sh_acc[2];
     __shared__ int32_t sh_maxc;
+    __shared__ int32_t ready[W];                // round whose evaluation wavefront w has published
     const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
     const DevBox B = hot_copy(boxes[blockIdx.x]);
     const int tid = threadIdx.x;
@@ -74,44 +82,70 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         tab[t] = pk;
         if (t < 64) offs[t] = ((tz - B.k[2]) * B.M[1] + (ty - B.k[1])) * B.M[0] + (tx - B.k[0]);
     }
+    if (tid < W) ready[tid] = -1;
     __syncthreads();
     if (err == GCMC_OK && B.ns != 1) {
         err = GCMC_ERR_UNSUPPORTED;
         err_move = (int64_t)ctr0;
     }
     int64_t m = 0;
+    int32_t rnd = 0;                   // rounds begun
     double a_ins = 0.5, a_del = 0.5;   // running acceptance of insertions and deletions
     while (err == GCMC_OK && m < n_moves) {
         const int64_t base = N - W;
-        // ------------------------------------------------ this wavefront's share of the round tables
-        const int64_t topj = base + wv;
+        ++rnd;
+        // ------------------------------------------------ the round tables (wavefront 0 decides with them)
         double4 tv = make_double4(0, 0, 0, 0);
-        if (topj >= 0) tv = gload(B.pos + topj);
-        {
-            const int64_t n = base + wv + (lane >= 3 ? W : 0);
-            double x = 1.0;
-            if (lane == 1 || lane == 3) x = B.V / (B.lambda3 * (double)(n + 1));
-            if (lane == 2 || lane == 4) x = (B.lambda3 * (double)n) / B.V;
-            const double lx = log(x);
-            if (lane == 1) lp_ins[wv] = lx;
-            if (lane == 2) lp_del[wv] = lx;
-            if (lane == 3) lp_ins[wv + W] = lx;
-            if (lane == 4) lp_del[wv + W] = lx;
+        if (wv == 0) {
+            if (lane < W && base + lane >= 0) tv = gload(B.pos + base + lane);
+            // lanes 0 .. 2W-1: insertion prefactor at N = base + lane; lanes 2W .. 4W-1: deletion
+            // prefactor at N = base + lane - 2W
+            if (lane < 4 * W) {
+                const bool del = lane >= 2 * W;
+                const int64_t n = base + (del ? lane - 2 * W : lane);
+                const double x = del ? (B.lambda3 * (double)n) / B.V : B.V / (B.lambda3 * (double)(n + 1));
+                const double lx = log(x);
+                if (del) lp_del[lane - 2 * W] = lx;
+                else lp_ins[lane] = lx;
+            }
         }
         // ------------------------------------------------ evaluate W moves
         if (m + wv < n_moves)
             spec_eval<CR>(B, tab, offs, own[wv], ctr0 + (uint64_t)m, wv, N, no_full, a_ins, a_del, &recs[wv]);
-        if (topj >= 0 && lane == 0) top[wv] = tv;
-        __syncthreads();
+        if (wv != 0) {
+            // publish this move's record: wavefront 0 decides it as soon as its turn comes, while
+            // slower wavefronts still evaluate.  A commit may then store to memory that a later
+            // move of the round is still reading; such a move fails the in-order check (its
+            // stencil holds a modified cell, or its particle was touched) and is discarded.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            if (lane == 0) __hip_atomic_store(&ready[wv], rnd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         // ------------------------------------------------ in-order commit
         if (wv == 0) {
+            if (lane < W && base + lane >= 0) top[lane] = tv;
+            // this wavefront's own table and record writes, seen by all of its lanes
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local");
             int32_t modx = 0, mody = 0, modz = 0, touched = -1;   // lane-held lists of this round
             int nmod = 0, ntouch = 0;
             int k = 0;
             const int kend = (n_moves - m) < W ? (int)(n_moves - m) : W;
             for (; k < kend; ++k) {
-                const SpecRec& R = recs[k];
                 const uint64_t ctr = ctr0 + (uint64_t)(m + k);
+                if (k > 0) {
+                    // wait for wavefront k's evaluation (bounded: it publishes without waiting on anything)
+                    int32_t spins = 0;
+                    while (uni(__hip_atomic_load(&ready[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) != rnd) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > kSpecSpinCap) break;
+                    }
+                    if (spins > kSpecSpinCap) {
+                        err = GCMC_ERR_INTERNAL;
+                        err_move = (int64_t)ctr;
+                        break;
+                    }
+                }
+                const SpecRec& R = recs[k];
                 const int type = __builtin_amdgcn_readfirstlane(R.type);
                 // the empty-box rejection holds only while the box is still empty
                 if (R.flags & 1) {
