@@ -47,7 +47,7 @@ enum {
     GCMC_ERR_HIP = 5,           /* a HIP runtime call failed */
     GCMC_ERR_POISONED = 6,      /* the box holds a latched device error */
     GCMC_ERR_UNSUPPORTED = 7,   /* valid but not implemented (e.g. a chain over a mixture) */
-    GCMC_ERR_INTERNAL = 8       /* a wait inside a chain kernel (pipelined or speculative) exceeded its bound (latched) */
+    GCMC_ERR_INTERNAL = 8       /* a wait inside a chain kernel (pipelined or speculative) exceeded its bound (latched; a rebuild clears it) */
 };
 
 enum { GCMC_MOVE_DISPLACE = 0, GCMC_MOVE_INSERT = 1, GCMC_MOVE_DELETE = 2 };
@@ -166,8 +166,9 @@ int gcmc_box_destroy(gcmc_box* box);
 int gcmc_box_get_info(const gcmc_box* box, gcmc_box_info* h_info);
 
 /* Re-bin the current particles (Sec. 3.2.1), optionally with a new per-cell
- * capacity (new_cap > 0 reallocates).  Clears a latched cell-overflow error, so
- * a chain stopped by an overflow can resume at its error_move counter. */
+ * capacity (new_cap > 0 reallocates).  Clears a latched cell-overflow or
+ * wait-bound (GCMC_ERR_INTERNAL) error: both stop the chain before a move with
+ * every earlier move committed, so it can resume at its error_move counter. */
 int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream);
 
 /* Replace the positions of the current particles (same N and species) and
@@ -235,6 +236,17 @@ int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair,
  * no decision since it read memory changed what it read (the same chain, move
  * for move); the same limits plus at most 1024 cells per axis. */
 int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows);
+
+/* Bound on the in-kernel waits of the speculative and pipelined chains (a
+ * wavefront polling an LDS flag that another wavefront of its workgroup sets;
+ * no such wait depends on another workgroup or on the host).  polls > 0: a
+ * wait gives up after that many polls; 0: the default, 2^26 polls (seconds);
+ * < 0: every wait gives up at once, so a launch that reaches one stops there
+ * with GCMC_ERR_INTERNAL latched (the chain stops before the waiting move, as
+ * on a cell overflow, and gcmc_cell_build clears it).  For tests of that error path; the per-move chain has
+ * no such waits.  Blocks until work already queued on the box is done; batches
+ * take the value of each box. */
+int gcmc_box_set_wait_limit(gcmc_box* box, int32_t polls);
 
 /* Run n_moves moves of the Markov chain of Algorithm 1 on the device in one
  * persistent launch (Sec. 3.3.4: one kernel call for many moves): move m uses

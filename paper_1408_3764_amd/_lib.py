@@ -31,7 +31,7 @@ MAX_SPECIES = 4
 EXPORTS = [
     "gcmc_box_create", "gcmc_box_destroy", "gcmc_box_get_info", "gcmc_cell_build", "gcmc_set_positions",
     "gcmc_set_params", "gcmc_box_rescale",
-    "gcmc_delta_energy", "gcmc_delta_energy_allpairs", "gcmc_commit", "gcmc_box_set_launch", "gcmc_step",
+    "gcmc_delta_energy", "gcmc_delta_energy_allpairs", "gcmc_commit", "gcmc_box_set_launch", "gcmc_box_set_wait_limit", "gcmc_step",
     "gcmc_step_allpairs", "gcmc_total_energy", "gcmc_backward", "gcmc_virial", "gcmc_batch_create",
     "gcmc_batch_destroy",
     "gcmc_batch_step", "gcmc_get_particles", "gcmc_get_cells", "gcmc_neighbor_ids", "gcmc_export_state",
@@ -102,6 +102,7 @@ def lib():
         "gcmc_delta_energy_allpairs": [vp, dp, i64, dp, dp, vp],
         "gcmc_commit": [vp, dp, dp, vp],
         "gcmc_box_set_launch": [vp, i32, i32],
+        "gcmc_box_set_wait_limit": [vp, i32],
         "gcmc_step": [vp, i64, u64, dp, dp, vp],
         "gcmc_step_allpairs": [vp, i64, u64, dp, dp, vp],
         "gcmc_total_energy": [vp, i32, dp, dp, vp],
@@ -201,6 +202,10 @@ def gcmc_commit(box, move, dU_pair, stream=None):
 
 def gcmc_box_set_launch(box, waves, rows):
     check(lib().gcmc_box_set_launch(box, int(waves), int(rows)))
+
+
+def gcmc_box_set_wait_limit(box, polls):
+    check(lib().gcmc_box_set_wait_limit(box, int(polls)))
 
 
 def gcmc_step(box, n_moves, counter0, stats, log, stream=None):

@@ -93,6 +93,10 @@ class Box:
     def set_launch(self, waves, rows):
         _lib.gcmc_box_set_launch(self.handle, waves, rows)
 
+    def set_wait_limit(self, polls):
+        """Bound on the chain kernels' in-kernel waits (0: default; < 0: fail at once)."""
+        _lib.gcmc_box_set_wait_limit(self.handle, polls)
+
     # ----------------------------------------------------------------- moves
     def delta_energy(self, moves: np.ndarray, all_pairs=False):
         moves = np.asarray(moves, dtype=MOVE_DTYPE)

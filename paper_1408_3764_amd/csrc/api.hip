@@ -25,12 +25,12 @@ int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows) {
         if (!spec_cfg_exists(waves)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported speculative width");
         if (!spec_supported(box->d))
             return set_error(GCMC_ERR_UNSUPPORTED, "speculative rounds need one species, <= 32 stencil cells "
-                                                   "and 2 x stencil x cell_cap <= 4096");
+                                                   "and 2 x stencil x cell_cap <= 8192");
     } else if (rows == -1) {
         if (!async_cfg_exists(waves)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported pipeline width");
         if (!async_supported(box->d))
             return set_error(GCMC_ERR_UNSUPPORTED, "the pipelined chain needs one species, <= 32 stencil cells, "
-                                                   "2 x stencil x cell_cap <= 4096 and <= 1024 cells per axis");
+                                                   "2 x stencil x cell_cap <= 8192 and <= 1024 cells per axis");
     } else if (!chain_cfg_exists(waves, rows)) {
         return set_error(GCMC_ERR_INVALID_ARG, "unsupported waves x rows");
     }

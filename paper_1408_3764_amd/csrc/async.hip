@@ -35,7 +35,6 @@ constexpr int kSlots = 16;        // evaluated moves held ahead of the committer
 // decision misses more often.
 constexpr int kLogLen = 64;       // decisions kept for validation
 constexpr int kWin = 64;          // committer lanes holding particle records mb .. mb + 63
-constexpr int32_t kSpinCap = 1 << 26;
 
 enum { SLOT_FREE = 0, SLOT_READY = 1, SLOT_REDO = 2 };
 
@@ -129,6 +128,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
     const int64_t N0 = uni64(st->n);
     const int32_t err0 = uni(st->error);
     const bool no_full = !(B.full[0] | B.full[1] | B.full[2]);
+    const int32_t spin_cap = wait_bound(B.wait_limit);   // polls of a bounded wait
     for (int t = tid; t < B.nstencil; t += blockDim.x) {
         const uint32_t pk = gload(B.stab + t);
         const int tx = pk & 0x3FF, ty = (pk >> 10) & 0x3FF, tz = pk >> 20;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
                 const int32_t C = uni((int32_t)(lds_load64(&S.cn) >> 32));
                 if (jn >= n_moves || jn - C >= AHEAD) {
                     __builtin_amdgcn_s_sleep(2);
-                    if (++spins > kSpinCap) {
+                    if (++spins > spin_cap) {
                         if (lane == 0) lds_publish(&S.stop, 1);
                         break;
                     }
@@ -236,9 +236,9 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
         int32_t spins = 0;
         while (!(uni(lds_load(&S.slot_state[s])) == SLOT_READY && uni(S.slot_move[s]) == (int32_t)j)) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinCap) break;
+            if (++spins > spin_cap) break;
         }
-        if (spins > kSpinCap) {
+        if (spins > spin_cap) {
             err = GCMC_ERR_INTERNAL;
             err_move = (int64_t)(ctr0 + (uint64_t)j);
             break;
@@ -289,9 +289,9 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             spins = 0;
             while (!(uni(lds_load(&S.slot_state[s])) == SLOT_READY)) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > kSpinCap) break;
+                if (++spins > spin_cap) break;
             }
-            if (spins > kSpinCap) {
+            if (spins > spin_cap) {
                 err = GCMC_ERR_INTERNAL;
                 break;
             }

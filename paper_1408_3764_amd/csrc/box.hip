@@ -195,8 +195,10 @@ __global__ void k_rescale(DevBox B, int64_t n, double rx, double ry, double rz, 
     }
 }
 
+// Clear the latched errors a rebuild resolves (a cell overflow, a wait past its bound).
 __global__ void k_clear_overflow(BoxState* st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && st->error == GCMC_ERR_CELL_OVERFLOW) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 &&
+        (st->error == GCMC_ERR_CELL_OVERFLOW || st->error == GCMC_ERR_INTERNAL)) {
         st->error = GCMC_OK;
     }
 }
@@ -539,7 +541,9 @@ int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream) {
     BoxState h;
     int rc = read_state(box, &h, s);
     if (rc) return rc;
-    if (h.error && h.error != GCMC_ERR_CELL_OVERFLOW)
+    // a cell overflow and a wait past its bound both stop the chain before a move, every
+    // earlier move committed: the rebuilt box resumes there
+    if (h.error && h.error != GCMC_ERR_CELL_OVERFLOW && h.error != GCMC_ERR_INTERNAL)
         return set_error(GCMC_ERR_POISONED, "box holds a latched error that a rebuild does not clear");
     if (new_cap > 0 && new_cap != box->d.cap) {
         if ((rc = alloc_cells(box, new_cap))) return rc;
@@ -609,6 +613,13 @@ int gcmc_set_params(gcmc_box* box, const double* h_eps, const double* h_sigma) {
         box->h_eps[a] = h_eps[a];
         box->h_sig[a] = h_sigma[a];
     }
+    return sync_desc(box);
+}
+
+int gcmc_box_set_wait_limit(gcmc_box* box, int32_t polls) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    GCMC_HIP(hipDeviceSynchronize());
+    box->d.wait_limit = polls;
     return sync_desc(box);
 }
 

@@ -56,6 +56,7 @@ struct DevBox {
     uint64_t seed;
     uint32_t box_id;
     int32_t nstencil;    // stencil cells kept (at most span_x * span_y * span_z)
+    int32_t wait_limit;  // polls of an in-kernel wait before it fails: 0 the default bound, < 0 at once
     const uint32_t* stab;   // the kept stencil slots, packed tx | ty << 10 | tz << 20 (device)
 };
 
@@ -64,6 +65,13 @@ struct DevBox {
 // registers and, unlike a field loaded from the descriptor, is not reloaded
 // from memory inside loops.
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Polls of a bounded in-kernel wait (a flag another wavefront of the workgroup
+// sets) before the kernel gives up with GCMC_ERR_INTERNAL.
+constexpr int32_t kWaitPollsDefault = 1 << 26;
+__host__ __device__ __forceinline__ int32_t wait_bound(int32_t wait_limit) {
+    return wait_limit == 0 ? kWaitPollsDefault : wait_limit;
+}
 __device__ __forceinline__ int64_t uni64(int64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));

@@ -37,9 +37,6 @@
 
 namespace gcmc {
 
-// Polls of a move's ready flag before the commit gives up with GCMC_ERR_INTERNAL.
-constexpr int32_t kSpecSpinCap = 1 << 26;
-
 template <int W, int CR>
 __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restrict__ boxes,
                                                           const int32_t* __restrict__ order, int64_t n_moves,
@@ -71,6 +68,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     const double tk = B.tailK[0];
     const int cap = B.cap;
     const bool no_full = !(B.full[0] | B.full[1] | B.full[2]);
+    const int32_t spin_cap = wait_bound(B.wait_limit);
     // statistics (wavefront 0 keeps them)
     // (per-type counters as separate scalars: a dynamically indexed array would live in scratch)
     int64_t att0 = 0, att1 = 0, att2 = 0, acc0 = 0, acc1 = 0, acc2 = 0;
@@ -137,9 +135,9 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     int32_t spins = 0;
                     while (uni(__hip_atomic_load(&ready[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) != rnd) {
                         __builtin_amdgcn_s_sleep(1);
-                        if (++spins > kSpecSpinCap) break;
+                        if (++spins > spin_cap) break;
                     }
-                    if (spins > kSpecSpinCap) {
+                    if (spins > spin_cap) {
                         err = GCMC_ERR_INTERNAL;
                         err_move = (int64_t)ctr;
                         break;

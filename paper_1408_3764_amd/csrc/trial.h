@@ -279,6 +279,7 @@ __device__ __forceinline__ DevBox hot_copy(const DevBox& G) {
     B.seed = (uint64_t)uni64((int64_t)G.seed);
     B.box_id = (uint32_t)uni((int32_t)G.box_id);
     B.nstencil = uni(G.nstencil);
+    B.wait_limit = uni(G.wait_limit);
     B.stab = unip(G.stab);
     return B;
 }

@@ -543,6 +543,34 @@ def test_capacity_error(shape):
     assert int(st["error"]) == 4 and int(st["n"]) == 5
 
 
+@pytest.mark.parametrize("shape", [(8, 0), (8, -1)])
+def test_wait_error_latches_and_resumes(c1, shape):
+    """The speculative and pipelined chains wait on flags set by other wavefronts
+    of the workgroup, each wait bounded.  A negative wait limit (set from the
+    host) makes the first wait give up at once: the launch stops before the
+    waiting move with GCMC_ERR_INTERNAL latched and every wavefront exits.  After
+    a rebuild at the default limit, resuming at the stop gives the uninterrupted
+    chain."""
+    M = 3000
+    ref = _launch(_box(c1, max_n=c1.n + M + 1), shape)
+    ref.step(M, counter0=0)
+    assert ref.status() == 0
+    b = _launch(_box(c1, max_n=c1.n + M + 1), shape)
+    b.set_wait_limit(-1)
+    st, _ = b.step(M, counter0=0)
+    assert int(st["error"]) == 8
+    stop = int(st["error_move"])
+    assert 0 <= stop < M and int(st["moves_done"]) == stop
+    assert stop <= 1                      # the first wait comes at the first or second move
+    assert b.status() == 8
+    b.set_wait_limit(0)
+    b.cell_build()
+    assert b.status() == 0
+    st2, _ = b.step(M - stop, counter0=stop)
+    assert int(st2["error"]) == 0
+    assert np.array_equal(b.particles()[0], ref.particles()[0])
+
+
 def test_invalid_arguments():
     from paper_1408_3764_amd import _lib
     from paper_1408_3764_amd.box import Box
