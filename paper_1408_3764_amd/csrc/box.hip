@@ -196,7 +196,7 @@ __global__ void k_rescale(DevBox B, int64_t n, double rx, double ry, double rz, 
 }
 
 // Clear the latched errors a rebuild resolves (a cell overflow, a wait past its bound).
-__global__ void k_clear_overflow(BoxState* st) {
+__global__ void k_clear_rebuild_errors(BoxState* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0 &&
         (st->error == GCMC_ERR_CELL_OVERFLOW || st->error == GCMC_ERR_INTERNAL)) {
         st->error = GCMC_OK;
@@ -548,7 +548,7 @@ int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream) {
     if (new_cap > 0 && new_cap != box->d.cap) {
         if ((rc = alloc_cells(box, new_cap))) return rc;
     }
-    k_clear_overflow<<<1, 1, 0, s>>>(box->d.st);
+    k_clear_rebuild_errors<<<1, 1, 0, s>>>(box->d.st);
     // keep N, running energy and the error move counter; re-bin
     const int64_t n = h.n;
     if ((rc = bin_particles(box, n, s, true, h.u_pair))) return rc;
