@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     double a_ins = 0.5, a_del = 0.5;   // running acceptance of insertions and deletions
     while (err == GCMC_OK && m < n_moves) {
         const int64_t base = N - W;
-        ++rnd;
+        rnd = rnd == INT32_MAX ? 1 : rnd + 1;   // round numbers stay positive (a flag starts at -1)
         // ------------------------------------------------ the round tables (wavefront 0 decides with them)
         double4 tv = make_double4(0, 0, 0, 0);
         if (wv == 0) {
