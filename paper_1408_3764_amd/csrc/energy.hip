@@ -150,9 +150,6 @@ __global__ __launch_bounds__(kBlk) void k_home_order(DevBox B, const int32_t* __
 // ------------------------------------------------------ cell-list total
 constexpr int kUnroll = 4;   // candidate records requested together
 
-
-// Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
-// VIR: the pair virial -r du/dr in place of the pair energy (pressure).
 // Does the stencil of cell (cx, cy, cz) stay clear of the periodic wrap with room
 // to spare?  Then every candidate lies within (k + 1) S < L/2 of the home
 // particle along each axis (at least 2k + 3 cells per axis: half a cell of
@@ -172,66 +169,129 @@ __device__ __forceinline__ double image_diff(double d, double L, double hL, bool
 }
 
 // e_i of one home particle over its stencil (WRAP: apply the minimum image).
+// In-cutoff pairs wait in a per-wavefront ring in LDS until 64 are queued; then
+// every lane takes one and evaluates the Lennard-Jones term (about one
+// candidate in six lies inside the cutoff of a full stencil, so the pair
+// arithmetic runs at full lane occupancy instead of under a mostly empty mask)
+// and adds it to its home particle's accumulator with an LDS atomic.
+constexpr int kRing = 128;   // queued pairs per wavefront (at most 63 + 64 at a time)
+
+struct PairQueue {
+    double* r2;      // [kRing] squared distances
+    int32_t* meta;   // [kRing] home lane | species pair << 8
+    double* acc;     // [kWave] energy of each lane's home particle
+};
+
+template <bool MIX, bool VIR>
+__device__ __forceinline__ void drain_pairs(const PassConst& K, const double* te4, const double* ts2,
+                                            const PairQueue& Q, uint32_t head, uint32_t cnt, int lane) {
+    // the ring entries written by other lanes of this wavefront are visible to every lane
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+    if ((uint32_t)lane < cnt) {
+        const uint32_t e = (head + (uint32_t)lane) & (kRing - 1);
+        const double r2 = Q.r2[e];
+        const int32_t mt = Q.meta[e];
+        const int q = mt >> 8;
+        const double e4 = MIX ? te4[q] : K.e4, s2 = MIX ? ts2[q] : K.s2;
+        const double v = VIR ? lj_virial_from_r2(r2, K.rc2, e4, s2) : lj_from_r2(r2, K.rc2, e4, s2);
+        atomicAdd(&Q.acc[mt & (kWave - 1)], v);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+}
+
+// Energy (or pair virial) of each lane's home particle over its stencil.  Every
+// lane of the wavefront calls it (lanes without a home particle pass live =
+// false and have no candidates); the loops run to the wavefront's largest cell
+// count so that the queue is drained with all lanes active.
 template <bool MIX, bool VIR, bool WRAP>
 __device__ __forceinline__ double home_energy(const DevBox& B, const PassConst& K, const uint32_t* tab,
                                               const double* te4, const double* ts2, const double4& me, int32_t myid,
-                                              int sa, int ns, int32_t cx, int32_t cy, int32_t cz) {
-    double ei = 0.0;
+                                              int sa, int ns, int32_t cx, int32_t cy, int32_t cz, bool live,
+                                              const PairQueue& Q) {
+    const int lane = threadIdx.x & (kWave - 1);
+    Q.acc[lane] = 0.0;
+    uint32_t head = 0, tail = 0;   // wave-uniform positions in the ring
     for (int t = 0; t < B.nstencil; ++t) {
         const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
-        const int32_t nc = gload(B.count + nb);
+        const int32_t nc = live ? gload(B.count + nb) : 0;
+        const int32_t ncmax = wave_max_i32_uniform(nc);
         const double4* ne = B.ent + nb * B.cap;
-        for (int j = 0; j < nc; j += kUnroll) {
+        for (int j = 0; j < ncmax; j += kUnroll) {
             double4 o[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) o[u] = gload(ne + (j + u < nc ? j + u : j));
+            for (int u = 0; u < kUnroll; ++u) o[u] = gload(ne + (j + u < nc ? j + u : 0));
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
+                bool in = false;
+                double r2 = 0.0;
+                int q = 0;
                 if (j + u < nc && meta_low(o[u].w) != myid) {
                     const double dx = image_diff(o[u].x - me.x, K.L[0], K.hL[0], WRAP);
                     const double dy = image_diff(o[u].y - me.y, K.L[1], K.hL[1], WRAP);
                     const double dz = image_diff(o[u].z - me.z, K.L[2], K.hL[2], WRAP);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    const int q = MIX ? sa * ns + meta_species(o[u].w) : 0;
-                    const double e4 = MIX ? te4[q] : K.e4, s2 = MIX ? ts2[q] : K.s2;
-                    ei += VIR ? lj_virial_from_r2(r2, K.rc2, e4, s2) : lj_from_r2(r2, K.rc2, e4, s2);
+                    r2 = (dx * dx + dy * dy) + dz * dz;
+                    q = MIX ? sa * ns + meta_species(o[u].w) : 0;
+                    in = r2 < K.rc2 && (MIX ? te4[q] : K.e4) != 0.0;
+                }
+                const uint64_t m = __ballot(in);
+                if (in) {
+                    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    const uint32_t e = (tail + below) & (kRing - 1);
+                    Q.r2[e] = r2;
+                    Q.meta[e] = lane | (q << 8);
+                }
+                tail += (uint32_t)__builtin_popcountll(m);
+                if (tail - head >= (uint32_t)kWave) {
+                    drain_pairs<MIX, VIR>(K, te4, ts2, Q, head, kWave, lane);
+                    head += kWave;
                 }
             }
         }
     }
-    return ei;
+    if (tail != head) drain_pairs<MIX, VIR>(K, te4, ts2, Q, head, tail - head, lane);
+    return Q.acc[lane];
 }
 
+// Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
+// VIR: the pair virial -r du/dr in place of the pair energy (pressure).
 template <bool MIX, bool VIR = false>
 __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__ boxp, const int32_t* __restrict__ home,
                                                        int64_t n, double* e_out, double* partial) {
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
     __shared__ double te4[kMaxSpecies * kMaxSpecies], ts2[kMaxSpecies * kMaxSpecies];
+    __shared__ double q_r2[kBlk / kWave][kRing];
+    __shared__ int32_t q_meta[kBlk / kWave][kRing];
+    __shared__ double q_acc[kBlk];
     const DevBox& B = *boxp;
     load_stencil(B, tab);
     load_species_tables(B, te4, ts2);
     const PassConst K = pass_const(B);
     __syncthreads();
+    const int w = threadIdx.x / kWave;
+    const PairQueue Q{q_r2[w], q_meta[w], q_acc + w * kWave};
     const int64_t h = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    double ei = 0.0;
-    if (h < n) {
-        int32_t slot = home[h];
-        if (slot < 0 || (int64_t)slot >= B.ncells * B.cap) slot = 0;   // counters and N disagree: stay in bounds
-        const int64_t c = slot / B.cap;
-        const double4 me = gload(B.ent + slot);
-        const int32_t myid = meta_low(me.w);
-        const int sa = meta_species(me.w);
-        const int ns = uni(B.ns);
-        int32_t cx, cy, cz;
-        cell_coords(B, c, cx, cy, cz);
-        // the wrap is skipped when no lane of the wavefront needs it
-        if (__ballot(!stencil_inside(B, cx, cy, cz)) != 0)
-            ei = home_energy<MIX, VIR, true>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz);
-        else
-            ei = home_energy<MIX, VIR, false>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz);
-        if (e_out) e_out[myid] = ei;
-    }
+    const bool live = h < n;
+    int32_t slot = live ? home[h] : 0;
+    if (slot < 0 || (int64_t)slot >= B.ncells * B.cap) slot = 0;   // counters and N disagree: stay in bounds
+    const int64_t c = slot / B.cap;
+    const double4 me = gload(B.ent + slot);
+    const int32_t myid = meta_low(me.w);
+    const int sa = meta_species(me.w);
+    const int ns = uni(B.ns);
+    int32_t cx, cy, cz;
+    cell_coords(B, c, cx, cy, cz);
+    // the wrap is skipped when no lane of the wavefront needs it
+    double ei;
+    if (__ballot(live && !stencil_inside(B, cx, cy, cz)) != 0)
+        ei = home_energy<MIX, VIR, true>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz, live, Q);
+    else
+        ei = home_energy<MIX, VIR, false>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz, live, Q);
+    if (!live) ei = 0.0;
+    if (live && e_out) e_out[myid] = ei;
     const double s = block_sum(ei, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
