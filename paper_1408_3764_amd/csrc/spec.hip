@@ -69,10 +69,12 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     const int cap = B.cap;
     const bool no_full = !(B.full[0] | B.full[1] | B.full[2]);
     const int32_t spin_cap = wait_bound(B.wait_limit);
-    // statistics (wavefront 0 keeps them)
-    // (per-type counters as separate scalars: a dynamically indexed array would live in scratch)
-    int64_t att0 = 0, att1 = 0, att2 = 0, acc0 = 0, acc1 = 0, acc2 = 0;
+    // statistics (wavefront 0 keeps them): attempts and acceptances per move type as separate
+    // doubles (a dynamically indexed array would live in scratch; exact below 2^53), folded in
+    // once per round
+    double att0 = 0.0, att1 = 0.0, att2 = 0.0, acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     double sum_n = 0.0, sum_u = 0.0;
+    // per-lane sums over the moves lane j decided as move j of a round, added up at the end
     int64_t stencils = 0, cand = 0, evals = 0, incut = 0;
     for (int t = tid; t < B.nstencil; t += blockDim.x) {
         const uint32_t pk = gload(B.stab + t);
@@ -126,6 +128,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local");
             int32_t modx = 0, mody = 0, modz = 0, touched = -1;   // lane-held lists of this round
             int nmod = 0, ntouch = 0;
+            uint64_t okbits = 0;   // bit k: move k of the round accepted
             int k = 0;
             const int kend = (n_moves - m) < W ? (int)(n_moves - m) : W;
             for (; k < kend; ++k) {
@@ -148,7 +151,6 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 // the empty-box rejection holds only while the box is still empty
                 if (R.flags & 1) {
                     if (N != 0) break;
-                    att0 += type == 0; att1 += type == 1; att2 += type == 2;
                     if (trace && lane == 0) {
                         gcmc_log r;
                         r.type = type; r.index = -1; r.accepted = 0; r.flags = 1;
@@ -291,15 +293,10 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     }
                     if (is_disp && two && cnt1 + 1 > maxc) maxc = cnt1 + 1;
                     if (is_ins && cnt0 + 1 > maxc) maxc = cnt0 + 1;
-                    acc0 += type == 0; acc1 += type == 1; acc2 += type == 2;
+                    okbits |= 1ull << k;
                     N += is_ins ? 1 : (type == GCMC_MOVE_DELETE ? -1 : 0);
                     U += dUp;
                 }
-                att0 += type == 0; att1 += type == 1; att2 += type == 2;
-                stencils += two ? 2 : 1;
-                cand += R.cand;
-                evals += R.evals;
-                incut += R.incut;
                 if (trace && lane == 0) {
                     gcmc_log r;
                     r.type = type;
@@ -321,6 +318,25 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     break;
                 }
             }
+            // statistics of the k moves decided this round: lane j takes move j
+            {
+                const bool mine = lane < k;
+                const SpecRec& S = recs[mine ? lane : 0];
+                const int t = mine ? S.type : -1;
+                const bool a = ((okbits >> lane) & 1) != 0;
+                att0 += (double)__builtin_popcountll(__ballot(t == 0));
+                att1 += (double)__builtin_popcountll(__ballot(t == 1));
+                att2 += (double)__builtin_popcountll(__ballot(t == 2));
+                acc0 += (double)__builtin_popcountll(__ballot(a && t == 0));
+                acc1 += (double)__builtin_popcountll(__ballot(a && t == 1));
+                acc2 += (double)__builtin_popcountll(__ballot(a && t == 2));
+                if (mine && !(S.flags & 1)) {
+                    stencils += S.two ? 2 : 1;
+                    cand += S.cand;
+                    evals += S.evals;
+                    incut += S.incut;
+                }
+            }
             if (lane == 0) {
                 sh_state[0] = N;
                 sh_state[1] = m + k;
@@ -328,8 +344,8 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 sh_state[3] = err_move;
                 sh_u = U;
                 sh_maxc = maxc;
-                sh_acc[0] = ((double)acc1 + 1.0) / ((double)att1 + 2.0);
-                sh_acc[1] = ((double)acc2 + 1.0) / ((double)att2 + 2.0);
+                sh_acc[0] = (acc1 + 1.0) / (att1 + 2.0);
+                sh_acc[1] = (acc2 + 1.0) / (att2 + 2.0);
             }
         }
         __syncthreads();   // commit stores done and visible; the new state published
@@ -341,6 +357,14 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         maxc = sh_maxc;
         a_ins = sh_acc[0];
         a_del = sh_acc[1];
+    }
+    if (wv == 0) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            stencils += __shfl_xor(stencils, off, kWave);
+            cand += __shfl_xor(cand, off, kWave);
+            evals += __shfl_xor(evals, off, kWave);
+            incut += __shfl_xor(incut, off, kWave);
+        }
     }
     if (tid == 0) {
         st->n = N;
@@ -354,8 +378,8 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         }
         if (stats) {
             gcmc_stats o;
-            o.attempts[0] = att0; o.attempts[1] = att1; o.attempts[2] = att2;
-            o.accepts[0] = acc0; o.accepts[1] = acc1; o.accepts[2] = acc2;
+            o.attempts[0] = (int64_t)att0; o.attempts[1] = (int64_t)att1; o.attempts[2] = (int64_t)att2;
+            o.accepts[0] = (int64_t)acc0; o.accepts[1] = (int64_t)acc1; o.accepts[2] = (int64_t)acc2;
             o.n = N;
             o.moves_done = m;
             o.u_pair = U;
