@@ -344,6 +344,140 @@ def test_ideal_gas_displacements_all_accepted(orc):
     assert np.all(log["type"] == 0) and np.all(log["accepted"] == 1)
 
 
+# --------------------------------------------------------------------------
+# Algorithm 2 (a random particle, moved within a cube around it) and
+# Algorithm 1's move draws: the displacement proposal and the particle pick,
+# pinned by their distributions (uniform cube of half-width max_disp, each
+# axis its own draw, wrapped into [0, L); index uniform over 0 .. N-1).
+# --------------------------------------------------------------------------
+def _displacement_law_ok(d, half, n_sigma=5.0):
+    """d: (m, 3) minimum-image displacements.  Uniform on [-half, half)^3 with
+    independent axes: bounds, mean 0, variance half^2/3, Kolmogorov-Smirnov,
+    no correlation between axes.  Returns the list of failed checks."""
+    from scipy import stats
+    m = len(d)
+    bad = []
+    if not (np.all(d >= -half) and np.all(d < half)):
+        bad.append("bounds")
+    for a in range(3):
+        x = d[:, a]
+        if abs(x.mean()) > n_sigma * half / math.sqrt(3 * m):
+            bad.append("mean%d" % a)
+        # variance of a uniform on [-h, h): h^2/3; sd of the sample variance: h^2 sqrt(4/45 / m)
+        if abs(x.var() - half * half / 3) > n_sigma * half * half * math.sqrt(4.0 / 45.0 / m):
+            bad.append("var%d" % a)
+        if stats.kstest(x, stats.uniform(loc=-half, scale=2 * half).cdf).pvalue < 1e-6:
+            bad.append("ks%d" % a)
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        if abs(np.corrcoef(d[:, a], d[:, b])[0, 1]) > n_sigma / math.sqrt(m):
+            bad.append("corr%d%d" % (a, b))
+    return bad
+
+
+def _pick_law_ok(idx, n):
+    """idx: picks from N = n particles.  Uniform over 0 .. n-1 by chi-square,
+    and the last index drawn about as often as the others."""
+    from scipy import stats
+    bad = []
+    if idx.min() < 0 or idx.max() > n - 1:
+        bad.append("range")
+    cnt = np.bincount(idx, minlength=n)[:n]
+    if stats.chisquare(cnt).pvalue < 1e-6:
+        bad.append("chi2")
+    e = len(idx) / n
+    if abs(cnt[n - 1] - e) > 6 * math.sqrt(e):
+        bad.append("last")
+    return bad
+
+
+def _displacement_chain(orc, n=37, L=7.0, moves=30_000, half=0.3, seed=17):
+    """Ideal gas (eps = 0), displacements only: every move is accepted, so the
+    chain's positions follow from the log alone."""
+    b = workloads.random_box(n, L, seed=4)
+    p = orc.make_params(b.L, 2.5, eps=0.0, p_disp=1.0, max_disp=half)
+    fin, _, log = orc.chain(b.pos, moves, p, seed=seed)
+    assert np.all(log["type"] == 0) and np.all(log["accepted"] == 1)
+    pos = b.pos.copy()
+    d = np.zeros((moves, 3))
+    for m in range(moves):
+        i = int(log["index"][m])
+        new = np.array([log["x"][m], log["y"][m], log["z"][m]])
+        dd = new - pos[i]
+        d[m] = dd - b.L * np.round(dd / b.L)   # minimum image: |d| <= half << L/2
+        pos[i] = new
+    assert np.array_equal(pos, fin)
+    return b, p, log, d
+
+
+def test_displacement_proposal_is_a_uniform_cube(orc):
+    b, p, log, d = _displacement_chain(orc)
+    assert _displacement_law_ok(d, 0.3) == []
+    # every trial coordinate lies in [0, L)
+    for a, k in enumerate("xyz"):
+        assert np.all(log[k] >= 0.0) and np.all(log[k] < b.L[a])
+
+
+def test_displacement_wraps_across_the_boundary(orc):
+    """Particles next to a face: displacements that cross it re-enter at the
+    opposite face (trial coordinates stay in [0, L) and the minimum-image step
+    is still the uniform cube)."""
+    L = np.array([5.0, 5.0, 5.0])
+    pos = np.array([[0.05, 4.98, 2.5], [4.99, 0.01, 0.1], [0.1, 0.1, 4.95]])
+    p = orc.make_params(L, 2.4, eps=0.0, p_disp=1.0, max_disp=0.3)
+    _, _, log = orc.chain(pos, 20_000, p, seed=23)
+    cur = pos.copy()
+    d = np.zeros((len(log), 3))
+    crossed = 0
+    for m in range(len(log)):
+        i = int(log["index"][m])
+        new = np.array([log["x"][m], log["y"][m], log["z"][m]])
+        assert np.all(new >= 0.0) and np.all(new < L)
+        raw = new - cur[i]
+        crossed += int(np.any(np.abs(raw) > 2.5))
+        d[m] = raw - L * np.round(raw / L)
+        cur[i] = new
+    assert crossed > 100
+    assert _displacement_law_ok(d, 0.3) == []
+
+
+def test_particle_pick_is_uniform_including_the_last(orc):
+    _, _, log, _ = _displacement_chain(orc)
+    assert _pick_law_ok(log["index"].astype(np.int64), 37) == []
+
+
+def test_pick_uniform_while_n_changes(orc):
+    """Displacements and deletions of a grand-canonical ideal gas pick from the
+    N of the moment: (index + w) / N with w ~ U[0, 1) is then exactly uniform."""
+    from scipy import stats
+    p = orc.make_params([6.0] * 3, 2.5, eps=0.0, beta=1.0, mu=-0.5)
+    _, _, log = orc.chain(np.zeros((0, 3)), 120_000, p, seed=31, max_n=1000)
+    d = np.where(log["accepted"] == 1, np.where(log["type"] == 1, 1, np.where(log["type"] == 2, -1, 0)), 0)
+    n_before = np.concatenate([[0], np.cumsum(d)[:-1]])
+    sel = (log["type"] != 1) & ((log["flags"] & 1) == 0)
+    idx, nb = log["index"][sel].astype(np.float64), n_before[sel].astype(np.float64)
+    assert np.all(idx >= 0) and np.all(idx < nb)
+    w = np.random.default_rng(5).random(len(idx))
+    assert stats.kstest((idx + w) / nb, "uniform").pvalue > 1e-6
+    # the last particle is picked 1/N of the time
+    assert abs(np.mean(idx == nb - 1) - np.mean(1.0 / nb)) < 6 * math.sqrt(np.mean(1.0 / nb) / len(idx))
+
+
+def test_pick_and_displacement_checks_have_power(orc):
+    """The checks above reject the plausible misreadings, built here from the
+    same Philox draws: a one-sided step d u, one draw for all three axes, no
+    wrap (a coordinate leaves [0, L)), and a pick of floor(u (N - 1))."""
+    n, moves, half = 37, 30_000, 0.3
+    u = np.array([orc.move_draws(17, m) for m in range(moves)])
+    one_sided = half * u[:, 4:7]
+    one_draw = np.repeat((half * (2 * u[:, 4] - 1))[:, None], 3, axis=1)
+    assert _displacement_law_ok(one_sided, half) != []
+    assert _displacement_law_ok(one_draw, half) != []
+    assert _pick_law_ok(np.floor(u[:, 2] * (n - 1)).astype(np.int64), n) != []
+    assert _pick_law_ok(np.minimum(np.floor(u[:, 2] * n), n - 1).astype(np.int64), n) == []
+    x = np.full(moves, 0.1) + half * (2 * u[:, 4] - 1)   # unwrapped step from next to a face
+    assert np.any(x < 0.0)
+
+
 def test_chain_energy_bookkeeping(orc):
     """Running U (sum of accepted dU) equals the recomputed U_pair + U_tail after many moves."""
     b = workloads.random_box(200, 8.0, seed=21, T=1.2)
