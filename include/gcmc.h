@@ -107,7 +107,12 @@ typedef struct {
     int32_t pad;
 } gcmc_move;
 
-/* Chain statistics written by gcmc_step / gcmc_batch_step (device struct). */
+/* Chain statistics written by gcmc_step / gcmc_batch_step (device struct),
+ * one launch's worth.  The averages are the ensemble averages the paper's
+ * multi-move kernel keeps on the GPU (Sec. 3.3.4: average energy and average
+ * pressure), taken over the moves of the launch, each move counted with the
+ * state after it; the same sums accumulated over every launch since the box
+ * was created, imported or cleared are part of gcmc_checkpoint. */
 typedef struct {
     int64_t attempts[3];   /* per move type */
     int64_t accepts[3];
@@ -124,9 +129,40 @@ typedef struct {
     int64_t candidates;    /* candidate particle records read from those stencils */
     int64_t pair_evals;    /* pair distances evaluated (candidates x positions evaluated against them) */
     int64_t in_cutoff;     /* of those, pairs strictly inside the cutoff */
+    double w_pair;         /* running pair virial W after the last move (Sec. 3.1.2 updates the virial on
+                              every acceptance; set by gcmc_virial, kept current by the chain) */
+    double sum_w;          /* sum over processed moves of W after the move */
+    double sum_n2;         /* sum over processed moves of N^2 after the move */
+    double avg_n;          /* sum_n / moves_done (NaN if no move was processed) */
+    double avg_u;          /* sum_u / moves_done */
+    double avg_p;          /* average pressure N k_B T / V + W / (3V) + P_tail(N), with P_tail the
+                              pressure of the potential beyond rc (as gcmc_virial), averaged over the
+                              same moves: k_B T avg_n / V + (sum_w / moves) / (3V) + c (sum_n2 / moves) */
 } gcmc_stats;
 
-/* Optional per-move record of gcmc_step (64 bytes, device array of n_moves). */
+/* Checkpoint of a box (host struct): everything besides the particles that a
+ * chain needs to continue exactly where it stopped (Algorithm 1 periodically
+ * writes the system status to disk; Sec. 3.3.4 checkpoints every 10,000
+ * moves).  Cumulative sums cover every move since the box was created,
+ * imported or its averages cleared. */
+typedef struct {
+    int64_t n;             /* particles */
+    double u_pair;         /* running pair energy */
+    double w_pair;         /* running pair virial */
+    uint64_t counter;      /* device move counter: the next move GCMC_COUNTER_CONTINUE runs */
+    int64_t moves;         /* moves in the cumulative sums below */
+    int64_t attempts[3];   /* per move type */
+    int64_t accepts[3];
+    double sum_n;          /* sums over those moves of N, N^2, u_pair + u_tail and W after each move */
+    double sum_n2;
+    double sum_u;
+    double sum_w;
+    int32_t error;         /* latched GCMC_ERR_* (export only; import needs GCMC_OK) */
+    int32_t pad;
+    int64_t error_move;    /* move counter of the latched error, else -1 */
+} gcmc_checkpoint;
+
+/* Optional per-move record of gcmc_step (72 bytes, device array of n_moves). */
 typedef struct {
     int32_t type;      /* GCMC_MOVE_* */
     int32_t index;     /* particle index (displace/delete), new index N (insert), -1 if N == 0 */
@@ -136,6 +172,7 @@ typedef struct {
     double dU_tail;
     double x, y, z;    /* trial position */
     double arg;        /* log of the acceptance ratio */
+    double dW_pair;    /* change of the pair virial the move would make (applied on acceptance) */
 } gcmc_log;
 
 /* Geometry chosen at create (host struct). */
@@ -162,7 +199,10 @@ typedef struct {
  * overflow is reported here.  *out receives the box. */
 int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* d_y, const double* d_z,
                     const int32_t* d_species, int64_t n, void* stream, gcmc_box** out);
+/* Release a box (the device arrays of Sec. 3.2.1's cell list and the particle
+ * records).  Waits for the device first; the handle is invalid afterwards. */
 int gcmc_box_destroy(gcmc_box* box);
+/* The cell grid chosen at create (Sec. 3.2.2: cells per axis, stencil). */
 int gcmc_box_get_info(const gcmc_box* box, gcmc_box_info* h_info);
 
 /* Re-bin the current particles (Sec. 3.2.1), optionally with a new per-cell
@@ -171,9 +211,15 @@ int gcmc_box_get_info(const gcmc_box* box, gcmc_box_info* h_info);
  * every earlier move committed, so it can resume at its error_move counter. */
 int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream);
 
-/* Replace the positions of the current particles (same N and species) and
- * re-bin; used by the autograd wrapper between forward passes. */
-int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z, void* stream);
+/* Replace the positions of the current particles and re-bin (Sec. 3.2.1);
+ * used by the autograd wrapper between forward passes (Eq. 1 evaluated at new
+ * coordinates).  n must equal the box's N (else GCMC_ERR_INVALID_ARG and
+ * nothing changes): d_x, d_y, d_z hold n coordinates each, in [0, L).
+ * Species, the move counter and the cumulative sums are kept.  The running
+ * pair energy and virial no longer describe the configuration: both become
+ * NaN until gcmc_total_energy and gcmc_virial set them again. */
+int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z, int64_t n,
+                       void* stream);
 
 /* Volume change (the cell-list rebuild and total energy that volume moves of
  * the Gibbs ensemble need, proposed in the conclusions, Sec. 5): every
@@ -192,9 +238,11 @@ int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, cons
  * failure after the coordinates were scaled leaves the box unusable. */
 int gcmc_box_rescale(gcmc_box* box, const double* h_L, double* d_U, void* stream);
 
-/* Replace the force field: h_eps, h_sigma are HOST n_species^2 pair tables
- * (symmetric, eps >= 0, sigma > 0), as in gcmc_box_desc.  Blocks until work
- * already queued on the box is done. */
+/* Replace the force field (the eps_ab, sigma_ab of Eq. 1): h_eps, h_sigma are
+ * HOST n_species^2 pair tables (symmetric, eps >= 0, sigma > 0), as in
+ * gcmc_box_desc.  Blocks until work already queued on the box is done.  The
+ * running pair energy and virial become NaN until gcmc_total_energy and
+ * gcmc_virial set them for the new force field. */
 int gcmc_set_params(gcmc_box* box, const double* h_eps, const double* h_sigma);
 
 /* ------------------------------------------------------------ the moves */
@@ -205,23 +253,31 @@ int gcmc_set_params(gcmc_box* box, const double* h_eps, const double* h_sigma);
  * wavefront then workgroup reduction).  d_moves[n_moves] as gcmc_move;
  * d_dU_pair[n_moves] receives the pair part (displacement: new - old;
  * insertion: + energy at the point; deletion: - energy of the particle);
- * d_dU_tail[n_moves] (may be NULL) the tail-correction change. */
+ * d_dU_tail[n_moves] (may be NULL) the tail-correction change; d_dW_pair
+ * [n_moves] (may be NULL) the change of the pair virial W (the sum of
+ * 24 eps [2 (sigma/r)^12 - (sigma/r)^6] over pairs inside the cutoff), which
+ * Sec. 3.1.2 updates with the energy on acceptance.  A move with a bad index
+ * or species gives NaN. */
 int gcmc_delta_energy(gcmc_box* box, const gcmc_move* d_moves, int64_t n_moves, double* d_dU_pair,
-                      double* d_dU_tail, void* stream);
+                      double* d_dU_tail, double* d_dW_pair, void* stream);
 
 /* The same quantities over all N particles, without the cell list (the
  * no-cell-list path of Algorithms 3 and 4): many workgroups per move, partial
  * sums reduced by a second kernel in a fixed order. */
 int gcmc_delta_energy_allpairs(gcmc_box* box, const gcmc_move* d_moves, int64_t n_moves, double* d_dU_pair,
-                               double* d_dU_tail, void* stream);
+                               double* d_dU_tail, double* d_dW_pair, void* stream);
 
 /* Apply one accepted move (device gcmc_move) whose pair-energy change is
- * *d_dU_pair (as returned by gcmc_delta_energy): position write, N +- 1, the
- * running pair energy, and the
- * incremental cell update of Sec. 3.2.5 (remove from the old cell by swapping
- * in the cell's last entry, append to the new cell; nothing when the cell is
- * unchanged); a deletion moves particle N-1 to the freed index. */
-int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair, void* stream);
+ * *d_dU_pair and pair-virial change *d_dW_pair (as returned by
+ * gcmc_delta_energy): position write, N +- 1, the running pair energy and
+ * virial (an accepted move updates both, Sec. 3.1.2), and the incremental
+ * cell update of Sec. 3.2.5
+ * (remove from the old cell by swapping in the cell's last entry, append to
+ * the new cell; nothing when the cell is unchanged); a deletion moves particle
+ * N-1 to the freed index.  d_dW_pair may be NULL: the running virial then
+ * becomes NaN until gcmc_virial sets it. */
+int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair, const double* d_dW_pair,
+                void* stream);
 
 /* Launch shape of the chain kernels (the autotuner's choice).  rows > 0: one
  * move at a time, `waves` wavefronts per workgroup and `rows` candidate slots
@@ -291,15 +347,22 @@ int gcmc_backward(gcmc_box* box, double* d_grad, double* d_deps, double* d_dsig,
  * pressure of the full potential beyond r_c (the counterpart of U_tail):
  * (16 pi / (3 V^2)) sum_ab N_a N_b eps_ab sigma_ab^3 [(2/3)(sigma_ab/r_c)^9
  * - (sigma_ab/r_c)^3].  Cell-list sums in a fixed order; d_out is device
- * memory, written on `stream`. */
+ * memory, written on `stream`.  Also sets the running pair virial that the
+ * chain keeps current on every acceptance (Sec. 3.1.2) to W. */
 int gcmc_virial(gcmc_box* box, double* d_out, void* stream);
 
 /* ------------------------------------------------------------- batches */
 
 /* Group existing single-species boxes (all must stay alive) so that
- * gcmc_batch_step advances all of them in one persistent launch, one
- * workgroup per box, boxes ordered by decreasing N. */
+ * gcmc_batch_step advances all of them in one persistent launch: the paper's
+ * conclusions (Sec. 5) note that one microcell chain uses a single
+ * multiprocessor, leaving room to run many simulations on one GPU at once.
+ * One workgroup per box, boxes ordered by decreasing N; each box keeps its own
+ * launch shape (gcmc_box_set_launch), and boxes of different shapes go to
+ * separate launches on the same stream.  boxes[n_boxes] is a HOST array of
+ * handles, copied. */
 int gcmc_batch_create(gcmc_box* const* boxes, int32_t n_boxes, gcmc_batch** out);
+/* Release a batch (not its boxes). */
 int gcmc_batch_destroy(gcmc_batch* batch);
 /* Advance every box of the batch by moves_per_box moves (counter0 + m, the
  * box's own box_id and seed; GCMC_COUNTER_CONTINUE: each box's device
@@ -317,9 +380,10 @@ int gcmc_batch_step(gcmc_batch* batch, int64_t moves_per_box, uint64_t counter0,
 int gcmc_get_particles(gcmc_box* box, double* d_x, double* d_y, double* d_z, int32_t* d_species, int64_t* h_n,
                        void* stream);
 
-/* Copy the cell list out (blocks): d_cell_of[N] the cell of each particle,
- * d_count[n_cells], d_ids[n_cells * cell_cap] cell-major particle ids (entries
- * past a cell's count are unspecified).  Any pointer may be NULL. */
+/* Copy the cell list out (blocks), the ParticlesInCells arrays of Sec. 3.2.1:
+ * d_cell_of[N] the cell of each particle, d_count[n_cells] the per-cell
+ * counters, d_ids[n_cells * cell_cap] cell-major particle ids (entries past a
+ * cell's count are unspecified).  Any pointer may be NULL. */
 int gcmc_get_cells(gcmc_box* box, int32_t* d_cell_of, int32_t* d_count, int32_t* d_ids, void* stream);
 
 /* Neighbour candidates (the particles in the stencil cells of a point, the
@@ -330,18 +394,34 @@ int gcmc_get_cells(gcmc_box* box, int32_t* d_cell_of, int32_t* d_count, int32_t*
 int gcmc_neighbor_ids(gcmc_box* box, const double* d_points, const int32_t* d_exclude, int64_t n,
                       int32_t max_ids, int32_t* d_ids, int32_t* d_counts, void* stream);
 
-/* Checkpoint (blocks): N, running pair energy and latched error. */
-int gcmc_export_state(gcmc_box* box, int64_t* h_n, double* h_u_pair, int32_t* h_error);
-/* Restore N particles (device SoA, n <= max_n) and the running energy, then
- * re-bin; the Philox counter is the caller's, so resuming at counter c replays
- * the chain exactly. */
+/* Checkpoint (blocks after the work queued on `stream`): the periodic
+ * system-status dump of Algorithm 1, taken every so many moves (Sec. 3.3.4).
+ * h_ck receives N, the running energy and virial, the device move counter,
+ * the cumulative statistics and the latched error.  d_x, d_y, d_z, d_species
+ * (device, each may be NULL) receive the N particles; `capacity` is their
+ * length (GCMC_ERR_INVALID_ARG if a pointer is given and capacity < N). */
+int gcmc_export_state(gcmc_box* box, double* d_x, double* d_y, double* d_z, int32_t* d_species, int64_t capacity,
+                      gcmc_checkpoint* h_ck, void* stream);
+/* Restore a checkpoint into a box with the same geometry and force field:
+ * h_ck->n particles from device SoA arrays (d_species may be NULL for one
+ * species; n <= max_n), the running energy and virial, the move counter and
+ * the cumulative statistics, then re-bin (Sec. 3.2.1).  A chain continued
+ * with GCMC_COUNTER_CONTINUE is then the uninterrupted chain.  h_ck->error must
+ * be GCMC_OK (GCMC_ERR_INVALID_ARG otherwise). */
 int gcmc_import_state(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z,
-                      const int32_t* d_species, int64_t n, double u_pair, void* stream);
+                      const int32_t* d_species, const gcmc_checkpoint* h_ck, void* stream);
+/* Zero the cumulative statistics of the checkpoint (e.g. after equilibration);
+ * the running energy, virial and move counter are kept.  Enqueued on
+ * `stream`. */
+int gcmc_clear_averages(gcmc_box* box, void* stream);
 
-/* Block until the box's queued work is done; returns its latched error. */
+/* Block until the box's queued work is done; returns its latched error (a
+ * device error of the kind the paper's kernels would report to the host after
+ * a move: cell over capacity, N at max_n). */
 int gcmc_sync_status(gcmc_box* box);
 
-/* Message for the last error on the calling thread ("" if none). */
+/* Message for the last error on the calling thread ("" if none): the text
+ * behind the GCMC_ERR_* code of the call that failed last. */
 const char* gcmc_last_error(void);
 
 /* Library version string. */

@@ -55,7 +55,7 @@ LOG_DTYPE = np.dtype([
     ("type", np.int32), ("index", np.int32), ("accepted", np.int32), ("flags", np.int32),
     ("dU_pair", np.float64), ("dU_tail", np.float64), ("sumabs", np.float64),
     ("x", np.float64), ("y", np.float64), ("z", np.float64),
-    ("arg", np.float64), ("a", np.float64),
+    ("arg", np.float64), ("a", np.float64), ("dW_pair", np.float64), ("wsumabs", np.float64),
 ])
 
 _lib = None
@@ -91,8 +91,10 @@ def lib():
         L.oracle_accept_arg.restype = C.c_double
         L.oracle_accept.argtypes = [C.c_double, C.c_double, C.c_double]
         L.oracle_accept.restype = C.c_int32
-        L.oracle_chain.argtypes = [C.c_int64, dp, dp, dp, lp, dp, pp, C.c_uint64, C.c_uint32, C.c_uint64,
+        L.oracle_chain.argtypes = [C.c_int64, dp, dp, dp, lp, dp, dp, pp, C.c_uint64, C.c_uint32, C.c_uint64,
                                    C.c_int64, C.c_void_p]
+        L.oracle_position_virial.argtypes = [C.c_int64, dp, dp, dp, ip, C.c_double, C.c_double, C.c_double,
+                                             C.c_int32, C.c_int64, pp, dp]
         L.oracle_chain.restype = C.c_int
         L.oracle_grid.argtypes = [dp, C.c_double, ip, ip, dp, ip, ip]
         L.oracle_cell_of.argtypes = [C.c_double, C.c_double, C.c_double, ip, dp]
@@ -184,6 +186,16 @@ def position_energy(pos, p, point, exclude=-1, species=None, point_species=0):
     return float(out[0]), float(out[1])
 
 
+def position_virial(pos, p, point, exclude=-1, species=None, point_species=0):
+    """(sum_j w, sum_j |w|) of a particle at `point` with every particle but `exclude`."""
+    x, y, z = (_f64(pos[:, a]) for a in range(3))
+    sp = None if species is None else np.ascontiguousarray(species, dtype=np.int32)
+    out = np.zeros(2)
+    lib().oracle_position_virial(len(x), _d(x), _d(y), _d(z), _i(sp), float(point[0]), float(point[1]),
+                                 float(point[2]), int(point_species), int(exclude), C.byref(p), _d(out))
+    return float(out[0]), float(out[1])
+
+
 def total_energy(pos, p, species=None, per_particle=False):
     """Returns dict(U_pair, sumabs, U_tail[, e])."""
     x, y, z = (_f64(pos[:, a]) for a in range(3))
@@ -221,21 +233,26 @@ class ChainError(RuntimeError):
     pass
 
 
-def chain(pos, n_moves, p, seed, box=0, counter0=0, max_n=None, U0=0.0):
-    """Run the serial GCMC chain.  Returns (pos[n], U, log array)."""
+def chain(pos, n_moves, p, seed, box=0, counter0=0, max_n=None, U0=0.0, W0=None):
+    """Run the serial GCMC chain.  Returns (pos[n], U, log array), or with W0
+    given (the starting pair virial) (pos[n], U, W, log array)."""
     n0 = pos.shape[0]
     max_n = max_n if max_n is not None else n0 + n_moves + 1
     x = np.zeros(max_n); y = np.zeros(max_n); z = np.zeros(max_n)
     x[:n0], y[:n0], z[:n0] = pos[:, 0], pos[:, 1], pos[:, 2]
     n = C.c_int64(n0)
     U = C.c_double(U0)
+    W = C.c_double(0.0 if W0 is None else W0)
     log = np.zeros(int(n_moves), dtype=LOG_DTYPE)
-    rc = lib().oracle_chain(int(max_n), _d(x), _d(y), _d(z), C.byref(n), C.byref(U), C.byref(p), int(seed),
-                            int(box), int(counter0), int(n_moves), log.ctypes.data_as(C.c_void_p))
+    rc = lib().oracle_chain(int(max_n), _d(x), _d(y), _d(z), C.byref(n), C.byref(U), C.byref(W), C.byref(p),
+                            int(seed), int(box), int(counter0), int(n_moves), log.ctypes.data_as(C.c_void_p))
     if rc != 0:
         raise ChainError("oracle_chain returned %d" % rc)
     k = n.value
-    return np.stack([x[:k], y[:k], z[:k]], axis=1), U.value, log
+    pos_out = np.stack([x[:k], y[:k], z[:k]], axis=1)
+    if W0 is None:
+        return pos_out, U.value, log
+    return pos_out, U.value, W.value, log
 
 
 def grid(L, rc, req_m=None):

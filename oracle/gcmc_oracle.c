@@ -60,6 +60,8 @@ typedef struct {
     double x, y, z;    /* trial position (new position / insertion point / deleted particle) */
     double arg;        /* log of the acceptance ratio */
     double a;          /* the uniform A of the acceptance test */
+    double dW_pair;    /* change of the pair virial W the move would make */
+    double wsumabs;    /* sum of |w| over the terms of dW_pair (tolerance scale) */
 } oracle_log;
 
 /* ------------------------------------------------------------------------ */
@@ -201,6 +203,30 @@ void oracle_position_energy(int64_t n, const double* x, const double* y, const d
     out[1] = nsum_get(&a);
 }
 
+/* Pair virial w = -r du/dr of the truncated potential (Eq. 1 differentiated):
+ * 24 eps [2 (sigma/r)^12 - (sigma/r)^6] strictly inside the cutoff, else 0. */
+static double pair_w(const oracle_params* p, int32_t a, int32_t b, double r2);
+
+/* Virial of a particle of species ps at (px,py,pz) with every particle j
+ * except `exclude`: sum_j w(r_ij), the quantity an accepted move changes in
+ * the running pressure (Sec. 3.1.2).  out[1] = sum of |w|. */
+void oracle_position_virial(int64_t n, const double* x, const double* y, const double* z, const int32_t* sp,
+                            double px, double py, double pz, int32_t ps, int64_t exclude,
+                            const oracle_params* p, double out[2])
+{
+    nsum s = {0, 0}, a = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == exclude)
+            continue;
+        double r2 = oracle_dist2(p->L, px, py, pz, x[j], y[j], z[j]);
+        double w = pair_w(p, ps, sp ? sp[j] : 0, r2);
+        nsum_add(&s, w);
+        nsum_add(&a, fabs(w));
+    }
+    out[0] = nsum_get(&s);
+    out[1] = nsum_get(&a);
+}
+
 /* Total pair energy over the N(N-1)/2 unique pairs (Sec. 3.1.1), and the
  * per-particle energies e_i = sum_{j != i} u(r_ij) when e != NULL.
  * out[0] = U_pair, out[1] = sum over pairs of |u|, out[2] = U_tail. */
@@ -326,11 +352,13 @@ static double wrap_coord(double x, double L)
 /*   and are rejected when N == 0.  Displacement: x' = wrap(x + d (2u-1))   */
 /*   per axis.  Insertion: x = wrap(L u).  On accepted insertion the new    */
 /*   particle gets index N; on accepted deletion particle N-1 takes index i.*/
-/* State: x,y,z[max_n], *n, *U (total energy incl. tail, running).          */
+/* State: x,y,z[max_n], *n, *U (total energy incl. tail, running), *W (pair */
+/* virial, running; may be NULL).  Each move's virial change is computed    */
+/* like its energy change and applied on acceptance (Sec. 3.1.2).           */
 /* Returns 0, or -1 if an insertion would exceed max_n (an error, never a   */
 /* rejection), or -2 for an unsupported parameter set.                      */
 /* ------------------------------------------------------------------------ */
-int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, double* U_io,
+int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, double* U_io, double* W_io,
                  const oracle_params* p, uint64_t seed, uint32_t box, uint64_t counter0, int64_t n_moves,
                  oracle_log* log_out)
 {
@@ -338,6 +366,7 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
         return -2;
     int64_t n = *n_io;
     double U = *U_io;
+    double W = W_io ? *W_io : 0.0;
     for (int64_t m = 0; m < n_moves; ++m) {
         double u[8];
         oracle_move_draws(seed, counter0 + (uint64_t)m, box, u);
@@ -366,36 +395,46 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
             if (i > n - 1)
                 i = n - 1;
         }
-        double dUp = 0.0, dUt = 0.0, sabs = 0.0;
+        double dUp = 0.0, dUt = 0.0, sabs = 0.0, dWp = 0.0, wabs = 0.0;
         double nx = 0, ny = 0, nz = 0;
         if (type == 0) {
             nx = wrap_coord(x[i] + p->max_disp * (2.0 * u[4] - 1.0), p->L[0]);
             ny = wrap_coord(y[i] + p->max_disp * (2.0 * u[5] - 1.0), p->L[1]);
             nz = wrap_coord(z[i] + p->max_disp * (2.0 * u[6] - 1.0), p->L[2]);
-            double eo[2], en[2];
+            double eo[2], en[2], wo[2], wn[2];
             oracle_position_energy(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, eo);
             oracle_position_energy(n, x, y, z, NULL, nx, ny, nz, 0, i, p, en);
+            oracle_position_virial(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, wo);
+            oracle_position_virial(n, x, y, z, NULL, nx, ny, nz, 0, i, p, wn);
             dUp = en[0] - eo[0];
             sabs = en[1] + eo[1];
+            dWp = wn[0] - wo[0];
+            wabs = wn[1] + wo[1];
             rec.index = (int32_t)i;
         } else if (type == 1) {
             nx = wrap_coord(p->L[0] * u[4], p->L[0]);
             ny = wrap_coord(p->L[1] * u[5], p->L[1]);
             nz = wrap_coord(p->L[2] * u[6], p->L[2]);
-            double en[2];
+            double en[2], wn[2];
             oracle_position_energy(n, x, y, z, NULL, nx, ny, nz, 0, -1, p, en);
+            oracle_position_virial(n, x, y, z, NULL, nx, ny, nz, 0, -1, p, wn);
             int64_t counts[1] = {n};
             dUp = en[0];
             sabs = en[1];
+            dWp = wn[0];
+            wabs = wn[1];
             dUt = oracle_tail_delta(counts, 0, +1, p);
             rec.index = (int32_t)n;
         } else {
             nx = x[i]; ny = y[i]; nz = z[i];
-            double eo[2];
+            double eo[2], wo[2];
             oracle_position_energy(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, eo);
+            oracle_position_virial(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, wo);
             int64_t counts[1] = {n};
             dUp = -eo[0];
             sabs = eo[1];
+            dWp = -wo[0];
+            wabs = wo[1];
             dUt = oracle_tail_delta(counts, 0, -1, p);
             rec.index = (int32_t)i;
         }
@@ -405,6 +444,8 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
         rec.dU_pair = dUp;
         rec.dU_tail = dUt;
         rec.sumabs = sabs;
+        rec.dW_pair = dWp;
+        rec.wsumabs = wabs;
         rec.x = nx; rec.y = ny; rec.z = nz;
         rec.arg = arg;
         if (acc) {
@@ -414,6 +455,8 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
                 if (n >= max_n) {
                     *n_io = n;
                     *U_io = U;
+                    if (W_io)
+                        *W_io = W;
                     return -1;
                 }
                 x[n] = nx; y[n] = ny; z[n] = nz;
@@ -423,6 +466,7 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
                 n -= 1;
             }
             U += dU;
+            W += dWp;
         }
         rec.accepted = acc;
         if (log_out)
@@ -430,6 +474,8 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
     }
     *n_io = n;
     *U_io = U;
+    if (W_io)
+        *W_io = W;
     return 0;
 }
 

@@ -35,7 +35,7 @@ EXPORTS = [
     "gcmc_step_allpairs", "gcmc_total_energy", "gcmc_backward", "gcmc_virial", "gcmc_batch_create",
     "gcmc_batch_destroy",
     "gcmc_batch_step", "gcmc_get_particles", "gcmc_get_cells", "gcmc_neighbor_ids", "gcmc_export_state",
-    "gcmc_import_state", "gcmc_sync_status", "gcmc_last_error", "gcmc_version",
+    "gcmc_import_state", "gcmc_clear_averages", "gcmc_sync_status", "gcmc_last_error", "gcmc_version",
 ]
 
 
@@ -67,15 +67,27 @@ MOVE_DTYPE = np.dtype({"names": ["type", "index", "x", "y", "z", "species", "pad
                        "formats": [np.int32, np.int32, np.float64, np.float64, np.float64, np.int32, np.int32],
                        "offsets": [0, 4, 8, 16, 24, 32, 36], "itemsize": 40})
 STATS_DTYPE = np.dtype({"names": ["attempts", "accepts", "n", "moves_done", "u_pair", "u_tail", "sum_n", "sum_u",
-                                  "error", "pad", "error_move", "stencils", "candidates", "pair_evals", "in_cutoff"],
+                                  "error", "pad", "error_move", "stencils", "candidates", "pair_evals", "in_cutoff",
+                                  "w_pair", "sum_w", "sum_n2", "avg_n", "avg_u", "avg_p"],
                         "formats": [(np.int64, 3), (np.int64, 3), np.int64, np.int64, np.float64, np.float64,
                                     np.float64, np.float64, np.int32, np.int32, np.int64, np.int64, np.int64,
-                                    np.int64, np.int64],
-                        "offsets": [0, 24, 48, 56, 64, 72, 80, 88, 96, 100, 104, 112, 120, 128, 136],
-                        "itemsize": 144})
-LOG_DTYPE = np.dtype({"names": ["type", "index", "accepted", "flags", "dU_pair", "dU_tail", "x", "y", "z", "arg"],
-                      "formats": [np.int32] * 4 + [np.float64] * 6,
-                      "offsets": [0, 4, 8, 12, 16, 24, 32, 40, 48, 56], "itemsize": 64})
+                                    np.int64, np.int64] + [np.float64] * 6,
+                        "offsets": [0, 24, 48, 56, 64, 72, 80, 88, 96, 100, 104, 112, 120, 128, 136,
+                                    144, 152, 160, 168, 176, 184],
+                        "itemsize": 192})
+LOG_DTYPE = np.dtype({"names": ["type", "index", "accepted", "flags", "dU_pair", "dU_tail", "x", "y", "z", "arg",
+                                "dW_pair"],
+                      "formats": [np.int32] * 4 + [np.float64] * 7,
+                      "offsets": [0, 4, 8, 12, 16, 24, 32, 40, 48, 56, 64], "itemsize": 72})
+
+
+class Checkpoint(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("u_pair", C.c_double), ("w_pair", C.c_double), ("counter", C.c_uint64),
+        ("moves", C.c_int64), ("attempts", C.c_int64 * 3), ("accepts", C.c_int64 * 3),
+        ("sum_n", C.c_double), ("sum_n2", C.c_double), ("sum_u", C.c_double), ("sum_w", C.c_double),
+        ("error", C.c_int32), ("pad", C.c_int32), ("error_move", C.c_int64),
+    ]
 
 _lib = None
 
@@ -95,12 +107,12 @@ def lib():
         "gcmc_box_destroy": [vp],
         "gcmc_box_get_info": [vp, C.POINTER(BoxInfo)],
         "gcmc_cell_build": [vp, i32, vp],
-        "gcmc_set_positions": [vp, dp, dp, dp, vp],
+        "gcmc_set_positions": [vp, dp, dp, dp, i64, vp],
         "gcmc_set_params": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "gcmc_box_rescale": [vp, C.POINTER(C.c_double), vp, vp],
-        "gcmc_delta_energy": [vp, dp, i64, dp, dp, vp],
-        "gcmc_delta_energy_allpairs": [vp, dp, i64, dp, dp, vp],
-        "gcmc_commit": [vp, dp, dp, vp],
+        "gcmc_delta_energy": [vp, dp, i64, dp, dp, dp, vp],
+        "gcmc_delta_energy_allpairs": [vp, dp, i64, dp, dp, dp, vp],
+        "gcmc_commit": [vp, dp, dp, dp, vp],
         "gcmc_box_set_launch": [vp, i32, i32],
         "gcmc_box_set_wait_limit": [vp, i32],
         "gcmc_step": [vp, i64, u64, dp, dp, vp],
@@ -114,8 +126,9 @@ def lib():
         "gcmc_get_particles": [vp, dp, dp, dp, dp, C.POINTER(i64), vp],
         "gcmc_get_cells": [vp, dp, dp, dp, vp],
         "gcmc_neighbor_ids": [vp, dp, dp, i64, i32, dp, dp, vp],
-        "gcmc_export_state": [vp, C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(i32)],
-        "gcmc_import_state": [vp, dp, dp, dp, dp, i64, C.c_double, vp],
+        "gcmc_export_state": [vp, dp, dp, dp, dp, i64, C.POINTER(Checkpoint), vp],
+        "gcmc_import_state": [vp, dp, dp, dp, dp, C.POINTER(Checkpoint), vp],
+        "gcmc_clear_averages": [vp, vp],
         "gcmc_sync_status": [vp],
         "gcmc_last_error": [],
         "gcmc_version": [],
@@ -171,8 +184,8 @@ def gcmc_cell_build(box, new_cap=0, stream=None):
     check(lib().gcmc_cell_build(box, int(new_cap), stream_handle(stream)))
 
 
-def gcmc_set_positions(box, x, y, z, stream=None):
-    check(lib().gcmc_set_positions(box, ptr(x), ptr(y), ptr(z), stream_handle(stream)))
+def gcmc_set_positions(box, x, y, z, n, stream=None):
+    check(lib().gcmc_set_positions(box, ptr(x), ptr(y), ptr(z), int(n), stream_handle(stream)))
 
 
 def gcmc_set_params(box, eps, sigma):
@@ -187,17 +200,18 @@ def gcmc_box_rescale(box, L_new, out, stream=None):
     check(lib().gcmc_box_rescale(box, Lh.ctypes.data_as(C.POINTER(C.c_double)), ptr(out), stream_handle(stream)))
 
 
-def gcmc_delta_energy(box, moves, n, dU_pair, dU_tail, stream=None):
-    check(lib().gcmc_delta_energy(box, ptr(moves), int(n), ptr(dU_pair), ptr(dU_tail), stream_handle(stream)))
+def gcmc_delta_energy(box, moves, n, dU_pair, dU_tail, dW_pair=None, stream=None):
+    check(lib().gcmc_delta_energy(box, ptr(moves), int(n), ptr(dU_pair), ptr(dU_tail), ptr(dW_pair),
+                                  stream_handle(stream)))
 
 
-def gcmc_delta_energy_allpairs(box, moves, n, dU_pair, dU_tail, stream=None):
-    check(lib().gcmc_delta_energy_allpairs(box, ptr(moves), int(n), ptr(dU_pair), ptr(dU_tail),
+def gcmc_delta_energy_allpairs(box, moves, n, dU_pair, dU_tail, dW_pair=None, stream=None):
+    check(lib().gcmc_delta_energy_allpairs(box, ptr(moves), int(n), ptr(dU_pair), ptr(dU_tail), ptr(dW_pair),
                                            stream_handle(stream)))
 
 
-def gcmc_commit(box, move, dU_pair, stream=None):
-    check(lib().gcmc_commit(box, ptr(move), ptr(dU_pair), stream_handle(stream)))
+def gcmc_commit(box, move, dU_pair, dW_pair=None, stream=None):
+    check(lib().gcmc_commit(box, ptr(move), ptr(dU_pair), ptr(dW_pair), stream_handle(stream)))
 
 
 def gcmc_box_set_launch(box, waves, rows):
@@ -258,15 +272,20 @@ def gcmc_neighbor_ids(box, points, exclude, n, max_ids, ids, counts, stream=None
                                   stream_handle(stream)))
 
 
-def gcmc_export_state(box):
-    n, u, e = C.c_int64(), C.c_double(), C.c_int32()
-    check(lib().gcmc_export_state(box, C.byref(n), C.byref(u), C.byref(e)))
-    return n.value, u.value, e.value
-
-
-def gcmc_import_state(box, x, y, z, species, n, u_pair, stream=None):
-    check(lib().gcmc_import_state(box, ptr(x), ptr(y), ptr(z), ptr(species), int(n), float(u_pair),
+def gcmc_export_state(box, x=None, y=None, z=None, species=None, capacity=0, stream=None):
+    """Returns the Checkpoint struct; the particles go into the given device tensors."""
+    ck = Checkpoint()
+    check(lib().gcmc_export_state(box, ptr(x), ptr(y), ptr(z), ptr(species), int(capacity), C.byref(ck),
                                   stream_handle(stream)))
+    return ck
+
+
+def gcmc_import_state(box, x, y, z, species, ck, stream=None):
+    check(lib().gcmc_import_state(box, ptr(x), ptr(y), ptr(z), ptr(species), C.byref(ck), stream_handle(stream)))
+
+
+def gcmc_clear_averages(box, stream=None):
+    check(lib().gcmc_clear_averages(box, stream_handle(stream)))
 
 
 def gcmc_sync_status(box):

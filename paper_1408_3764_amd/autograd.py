@@ -26,11 +26,20 @@ class LJEnergy(torch.autograd.Function):
         U = box.total_energy_device()
         ctx.box = box
         ctx.n = pos.shape[0]
+        ctx.version = box.version
+        ctx.save_for_backward(pos.detach(), eps.detach(), sigma.detach())
         return U[0] + U[1]
 
     @staticmethod
     def backward(ctx, gU):
-        g, de, ds = ctx.box.backward_device(ctx.n)
+        box = ctx.box
+        if box.version != ctx.version:
+            # the box was changed after this forward (another forward, new parameters, moves):
+            # the gradient is taken at the saved inputs, put back into the box
+            pos, eps, sigma = ctx.saved_tensors
+            box.set_params(eps.cpu().numpy(), sigma.cpu().numpy())
+            box.set_positions_device(pos)
+        g, de, ds = box.backward_device(ctx.n)
         return gU * g, gU * de, gU * ds, None
 
 

@@ -65,6 +65,8 @@ class Box:
         sp = None if species is None else _dev(species, torch.int32, self.device)
         self.handle = _lib.gcmc_box_create(d, x, y, z, sp, n, stream)
         self.max_n = d.max_n
+        # bumped by every call that changes the configuration or the force field
+        self.version = 0
 
     @classmethod
     def from_workload(cls, wb, max_n=None, **kw):
@@ -98,21 +100,27 @@ class Box:
         _lib.gcmc_box_set_wait_limit(self.handle, polls)
 
     # ----------------------------------------------------------------- moves
-    def delta_energy(self, moves: np.ndarray, all_pairs=False):
+    def delta_energy(self, moves: np.ndarray, all_pairs=False, virial=False):
+        """(dU_pair, dU_tail[, dW_pair]) of each move against the current configuration."""
         moves = np.asarray(moves, dtype=MOVE_DTYPE)
         m = len(moves)
         dm = _struct_to_device(moves, self.device)
         dp = torch.empty(m, dtype=torch.float64, device=self.device)
         dt = torch.empty(m, dtype=torch.float64, device=self.device)
+        dw = torch.empty(m, dtype=torch.float64, device=self.device) if virial else None
         f = _lib.gcmc_delta_energy_allpairs if all_pairs else _lib.gcmc_delta_energy
-        f(self.handle, dm, m, dp, dt, self.stream)
+        f(self.handle, dm, m, dp, dt, dw, self.stream)
+        if virial:
+            return dp.cpu().numpy(), dt.cpu().numpy(), dw.cpu().numpy()
         return dp.cpu().numpy(), dt.cpu().numpy()
 
-    def commit(self, move, dU_pair):
+    def commit(self, move, dU_pair, dW_pair=None):
         mv = np.asarray([move], dtype=MOVE_DTYPE) if not isinstance(move, np.ndarray) else move.reshape(1)
         dm = _struct_to_device(mv, self.device)
         du = torch.tensor([float(dU_pair)], dtype=torch.float64, device=self.device)
-        _lib.gcmc_commit(self.handle, dm, du, self.stream)
+        dw = None if dW_pair is None else torch.tensor([float(dW_pair)], dtype=torch.float64, device=self.device)
+        _lib.gcmc_commit(self.handle, dm, du, dw, self.stream)
+        self.version += 1
         self.sync()
 
     def step(self, n_moves, counter0=0, log=False, all_pairs=False):
@@ -120,6 +128,7 @@ class Box:
         lg = torch.zeros(max(1, n_moves) * LOG_DTYPE.itemsize, dtype=torch.uint8, device=self.device) if log else None
         f = _lib.gcmc_step_allpairs if all_pairs else _lib.gcmc_step
         f(self.handle, n_moves, counter0, st, lg, self.stream)
+        self.version += 1
         stats = _struct_from_device(st, STATS_DTYPE)[0]
         lgs = _struct_from_device(lg, LOG_DTYPE)[:n_moves] if log else None
         return stats, lgs
@@ -151,7 +160,8 @@ class Box:
         return out
 
     def virial(self):
-        """{"W": pair virial, "P": pressure with the ideal and tail terms}."""
+        """{"W": pair virial, "P": pressure with the ideal and tail terms}; also sets the
+        running virial the chain keeps current."""
         out = torch.zeros(2, dtype=torch.float64, device=self.device)
         _lib.gcmc_virial(self.handle, out, self.stream)
         v = out.cpu().numpy()
@@ -160,7 +170,12 @@ class Box:
     # ----------------------------------------------------------- inspection
     @property
     def n(self):
-        return self.export_state()[0]
+        return int(_lib.gcmc_export_state(self.handle, stream=self.stream).n)
+
+    def checkpoint(self):
+        """The box's checkpoint fields (no particles) as a dict."""
+        ck = _lib.gcmc_export_state(self.handle, stream=self.stream)
+        return checkpoint_dict(ck)
 
     def particles(self):
         n = self.n
@@ -194,22 +209,41 @@ class Box:
         return [np.sort(ids[i, : min(cnt[i], max_ids)]) for i in range(m)], cnt[:m]
 
     def export_state(self):
-        return _lib.gcmc_export_state(self.handle)
+        """A complete checkpoint: (positions (N, 3), species (N,), checkpoint dict)."""
+        cap = max(self.max_n, 1)
+        x = torch.zeros(cap, dtype=torch.float64, device=self.device)
+        y, z = torch.zeros_like(x), torch.zeros_like(x)
+        sp = torch.zeros(cap, dtype=torch.int32, device=self.device)
+        ck = _lib.gcmc_export_state(self.handle, x, y, z, sp, cap, self.stream)
+        n = int(ck.n)
+        pos = torch.stack([x[:n], y[:n], z[:n]], dim=1).cpu().numpy()
+        return pos, sp[:n].cpu().numpy(), checkpoint_dict(ck)
 
-    def import_state(self, pos, u_pair, species=None):
+    def import_state(self, pos, ck, species=None):
+        """Restore a checkpoint taken by export_state (ck: its dict)."""
         pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+        if pos.shape[0] != int(ck["n"]):
+            raise ValueError("the checkpoint holds %d particles, pos has %d" % (int(ck["n"]), pos.shape[0]))
         x = _dev(pos[:, 0], torch.float64, self.device)
         y = _dev(pos[:, 1], torch.float64, self.device)
         z = _dev(pos[:, 2], torch.float64, self.device)
         sp = None if species is None else _dev(species, torch.int32, self.device)
-        _lib.gcmc_import_state(self.handle, x, y, z, sp, len(pos), u_pair, self.stream)
+        _lib.gcmc_import_state(self.handle, x, y, z, sp, checkpoint_struct(ck), self.stream)
+        self.version += 1
+
+    def clear_averages(self):
+        _lib.gcmc_clear_averages(self.handle, self.stream)
 
     def set_positions(self, pos):
-        pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+        pos = np.asarray(pos, dtype=np.float64)
+        n = self.n
+        if pos.shape != (n, 3):
+            raise ValueError("positions must have shape (%d, 3), got %s" % (n, pos.shape))
         x = _dev(pos[:, 0], torch.float64, self.device)
         y = _dev(pos[:, 1], torch.float64, self.device)
         z = _dev(pos[:, 2], torch.float64, self.device)
-        _lib.gcmc_set_positions(self.handle, x, y, z, self.stream)
+        _lib.gcmc_set_positions(self.handle, x, y, z, n, self.stream)
+        self.version += 1
 
     def rescale(self, L_new):
         """Scale the box to edges L_new (coordinates scaled with it), rebuild the
@@ -217,17 +251,25 @@ class Box:
         new volume and {"U_pair_old", "U_tail_old"} at the old one."""
         out = torch.zeros(4, dtype=torch.float64, device=self.device)
         _lib.gcmc_box_rescale(self.handle, L_new, out, self.stream)
+        self.version += 1
         self.L = np.broadcast_to(np.asarray(L_new, dtype=np.float64), (3,)).copy()
         v = out.cpu().numpy()
         return {"U_pair": float(v[0]), "U_tail": float(v[1]), "U_pair_old": float(v[2]), "U_tail_old": float(v[3])}
 
     def set_params(self, eps, sigma):
         _lib.gcmc_set_params(self.handle, np.asarray(eps, dtype=np.float64), np.asarray(sigma, dtype=np.float64))
+        self.version += 1
 
-    def set_positions_device(self, pos: torch.Tensor):
-        """pos: (N, 3) float64 device tensor with the current N."""
+    def set_positions_device(self, pos: torch.Tensor, n=None):
+        """pos: (N, 3) float64 device tensor with the current N (n: that N, if the caller knows it)."""
+        n = self.n if n is None else int(n)
+        if tuple(pos.shape) != (n, 3):
+            raise ValueError("positions must have shape (%d, 3), got %s" % (n, tuple(pos.shape)))
+        if pos.dtype != torch.float64 or not pos.is_cuda:
+            raise TypeError("positions must be a float64 device tensor")
         x, y, z = (pos[:, a].contiguous() for a in range(3))
-        _lib.gcmc_set_positions(self.handle, x, y, z, self.stream)
+        _lib.gcmc_set_positions(self.handle, x, y, z, n, self.stream)
+        self.version += 1
 
     def total_energy_device(self, all_pairs=False):
         """(U_pair, U_tail) as a device tensor, no host synchronisation."""
@@ -253,6 +295,26 @@ class Box:
 
     def status(self):
         return _lib.gcmc_sync_status(self.handle)
+
+
+def checkpoint_dict(ck) -> dict:
+    return {"n": int(ck.n), "u_pair": float(ck.u_pair), "w_pair": float(ck.w_pair), "counter": int(ck.counter),
+            "moves": int(ck.moves), "attempts": [int(v) for v in ck.attempts],
+            "accepts": [int(v) for v in ck.accepts], "sum_n": float(ck.sum_n), "sum_n2": float(ck.sum_n2),
+            "sum_u": float(ck.sum_u), "sum_w": float(ck.sum_w), "error": int(ck.error),
+            "error_move": int(ck.error_move)}
+
+
+def checkpoint_struct(d: dict):
+    ck = _lib.Checkpoint()
+    for k in ("n", "counter", "moves", "error", "error_move"):
+        setattr(ck, k, int(d[k]))
+    for k in ("u_pair", "w_pair", "sum_n", "sum_n2", "sum_u", "sum_w"):
+        setattr(ck, k, float(d[k]))
+    for t in range(3):
+        ck.attempts[t] = int(d["attempts"][t])
+        ck.accepts[t] = int(d["accepts"][t])
+    return ck
 
 
 class Batch:

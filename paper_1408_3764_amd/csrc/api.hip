@@ -40,18 +40,18 @@ int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows) {
 }
 
 int gcmc_delta_energy(gcmc_box* box, const gcmc_move* d_moves, int64_t n_moves, double* d_dU_pair,
-                      double* d_dU_tail, void* stream) {
+                      double* d_dU_tail, double* d_dW_pair, void* stream) {
     if (!box || (n_moves > 0 && (!d_moves || !d_dU_pair)) || n_moves < 0)
         return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
     if (n_moves == 0) return GCMC_OK;
     hipStream_t s = (hipStream_t)stream;
-    launch_delta(box->d_desc, box->d.ns > 1, n_moves, d_moves, d_dU_pair, d_dU_tail, s);
+    launch_delta(box->d_desc, box->d.ns > 1, n_moves, d_moves, d_dU_pair, d_dU_tail, d_dW_pair, s);
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }
 
 int gcmc_delta_energy_allpairs(gcmc_box* box, const gcmc_move* d_moves, int64_t n_moves, double* d_dU_pair,
-                               double* d_dU_tail, void* stream) {
+                               double* d_dU_tail, double* d_dW_pair, void* stream) {
     if (!box || (n_moves > 0 && (!d_moves || !d_dU_pair)) || n_moves < 0)
         return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
     if (n_moves == 0) return GCMC_OK;
@@ -63,18 +63,19 @@ int gcmc_delta_energy_allpairs(gcmc_box* box, const gcmc_move* d_moves, int64_t 
     const int64_t nch = std::max<int64_t>(1, (h.n + chunk - 1) / chunk);
     for (int64_t m0 = 0; m0 < n_moves; m0 += 65535) {
         const int64_t nm = std::min<int64_t>(65535, n_moves - m0);
-        if ((rc = ensure_scratch(box, nm * nch * 2))) return rc;
+        if ((rc = ensure_scratch(box, nm * nch * 4))) return rc;
         if (launch_delta_allpairs(box->d_desc, h.n, d_moves + m0, nm, box->scratch, d_dU_pair + m0,
-                                  d_dU_tail ? d_dU_tail + m0 : nullptr, s))
+                                  d_dU_tail ? d_dU_tail + m0 : nullptr, d_dW_pair ? d_dW_pair + m0 : nullptr, s))
             return set_error(GCMC_ERR_INVALID_ARG, "too many moves");
         GCMC_HIP(hipGetLastError());
     }
     return GCMC_OK;
 }
 
-int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair, void* stream) {
+int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair, const double* d_dW_pair,
+                void* stream) {
     if (!box || !d_move || !d_dU_pair) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
-    launch_commit(box->d_desc, d_move, d_dU_pair, (hipStream_t)stream);
+    launch_commit(box->d_desc, d_move, d_dU_pair, d_dW_pair, (hipStream_t)stream);
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }
@@ -111,11 +112,12 @@ int gcmc_step_allpairs(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_s
     }
     const int64_t chunk = ap_chunk_len();
     const int64_t nch = std::max<int64_t>(1, (box->d.max_n + chunk - 1) / chunk);
-    int rc = ensure_scratch(box, nch * 2);
+    int rc = ensure_scratch(box, nch * 4);
     if (rc) return rc;
-    launch_ap_chain_begin(box->ap_chain, counter0, s);
+    launch_ap_chain_begin(box->d_desc, box->ap_chain, counter0, s);
     for (int64_t m = 0; m < n_moves; ++m) launch_ap_chain_move(box->d_desc, box->ap_chain, nch, box->scratch, d_log, s);
-    if (d_stats) launch_ap_chain_end(box->d_desc, box->ap_chain, d_stats, s);
+    // the end also folds the launch into the box's cumulative statistics and counter
+    launch_ap_chain_end(box->d_desc, box->ap_chain, d_stats, s);
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }
@@ -156,6 +158,7 @@ int gcmc_backward(gcmc_box* box, double* d_grad, double* d_deps, double* d_dsig,
     if (rc) return rc;
     if ((rc = ensure_scratch(box, grad_partials_needed(box->d, h.maxcount, h.n)))) return rc;
     const int r = launch_grad(box->d, box->d_desc, h.maxcount, d_grad, box->scratch, d_deps, d_dsig, s, h.n);
+    if (r) return set_error(GCMC_ERR_INVALID_ARG, "scratch too small");
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }
@@ -254,5 +257,6 @@ int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gc
 
 static_assert(sizeof(gcmc_box_desc) == 128, "gcmc_box_desc layout");
 static_assert(sizeof(gcmc_move) == 40, "gcmc_move layout");
-static_assert(sizeof(gcmc_stats) == 144, "gcmc_stats layout");
-static_assert(sizeof(gcmc_log) == 64, "gcmc_log layout");
+static_assert(sizeof(gcmc_stats) == 192, "gcmc_stats layout");
+static_assert(sizeof(gcmc_log) == 72, "gcmc_log layout");
+static_assert(sizeof(gcmc_checkpoint) == 136, "gcmc_checkpoint layout");

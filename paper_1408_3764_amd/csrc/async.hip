@@ -205,6 +205,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
     __builtin_amdgcn_s_setprio(3);
     int64_t N = N0;
     double U = unid(st->u_pair);
+    double Wvir = unid(st->w_pair);
     int32_t maxc = uni(st->maxcount);
     int32_t err = err0;
     int64_t err_move = uni64(st->error_move);
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
     const double tk = B.tailK[0];
     const int cap = B.cap;
     int64_t att0 = 0, att1 = 0, att2 = 0, acc0 = 0, acc1 = 0, acc2 = 0;
-    double sum_n = 0.0, sum_u = 0.0;
+    double sum_n = 0.0, sum_u = 0.0, sum_n2 = 0.0, sum_w = 0.0;
     int64_t stencils = 0, cand = 0, evals = 0, incut = 0;
     int64_t mb = N - 32 > 0 ? N - 32 : 0;
     window_fill(B, S, mb, -1, N, lane);
@@ -309,10 +310,11 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             if (trace && lane == 0) {
                 gcmc_log r;
                 r.type = type; r.index = -1; r.accepted = 0; r.flags = 1;
-                r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0;
+                r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0; r.dW_pair = 0.0;
                 trace[(size_t)bi * n_moves + j] = r;
             }
             sum_u += U;
+            sum_w += Wvir;
         } else {
             const int64_t idx = R.idx;
             const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
@@ -414,6 +416,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
                 acc0 += type == 0; acc1 += type == 1; acc2 += type == 2;
                 N += is_ins ? 1 : (type == GCMC_MOVE_DELETE ? -1 : 0);
                 U += dUp;
+                Wvir += R.dWp;
             }
             att0 += type == 0; att1 += type == 1; att2 += type == 2;
             stencils += two ? 2 : 1;
@@ -432,10 +435,13 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
                 r.y = is_disp ? R.p1[1] : R.p0[1];
                 r.z = is_disp ? R.p1[2] : R.p0[2];
                 r.arg = arg;
+                r.dW_pair = R.dWp;
                 trace[(size_t)bi * n_moves + j] = r;
             }
             sum_n += (double)N;
+            sum_n2 += (double)N * (double)N;
             sum_u += U + tk * (double)N * (double)N;
+            sum_w += Wvir;
         }
         // publish the decision: its log entry, the free slot, the decided count and N
         if (lane == 0) {
@@ -462,6 +468,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
     if (lane == 0) {
         st->n = N;
         st->u_pair = U;
+        st->w_pair = Wvir;
         st->maxcount = maxc;
         st->nsp[0] = N;
         st->counter = (int64_t)(ctr0 + (uint64_t)j);
@@ -469,25 +476,15 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             st->error = err;
             st->error_move = err_move;
         }
-        if (stats) {
-            gcmc_stats o;
-            o.attempts[0] = att0; o.attempts[1] = att1; o.attempts[2] = att2;
-            o.accepts[0] = acc0; o.accepts[1] = acc1; o.accepts[2] = acc2;
-            o.n = N;
-            o.moves_done = j;
-            o.u_pair = U;
-            o.u_tail = tk * (double)N * (double)N;
-            o.sum_n = sum_n;
-            o.sum_u = sum_u;
-            o.error = st->error;
-            o.pad = 0;
-            o.error_move = st->error_move;
-            o.stencils = stencils;
-            o.candidates = cand;
-            o.pair_evals = evals;
-            o.in_cutoff = incut;
-            stats[bi] = o;
-        }
+        ChainSums L;
+        L.moves = j;
+        L.att[0] = att0; L.att[1] = att1; L.att[2] = att2;
+        L.acc[0] = acc0; L.acc[1] = acc1; L.acc[2] = acc2;
+        L.sum_n = sum_n;
+        L.sum_n2 = sum_n2;
+        L.sum_u = sum_u;
+        L.sum_w = sum_w;
+        finish_launch(B, st, L, N, U, Wvir, stencils, cand, evals, incut, stats ? stats + bi : nullptr);
     }
 }
 

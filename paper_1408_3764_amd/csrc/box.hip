@@ -169,18 +169,58 @@ __global__ __launch_bounds__(256) void k_sort_cells_wave(DevBox B) {
     }
 }
 
-// keep_error: a rebuild keeps the latched error, its move and the move counter.
-__global__ void k_reset_state(BoxState* st, int64_t n, double u_pair, int keep_error) {
+// keep: a rebuild keeps the latched error, its move, the move counter and the
+// cumulative statistics; otherwise (a new box) all of them start afresh.
+__global__ void k_reset_state(BoxState* st, int64_t n, double u_pair, double w_pair, int keep) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->n = n;
         st->u_pair = u_pair;
+        st->w_pair = w_pair;
         st->maxcount = 0;
-        if (!keep_error) {
+        if (!keep) {
             st->error = GCMC_OK;
             st->error_move = -1;
             st->counter = 0;
+            st->cum.moves = 0;
+            for (int t = 0; t < 3; ++t) st->cum.att[t] = st->cum.acc[t] = 0;
+            st->cum.sum_n = st->cum.sum_n2 = st->cum.sum_u = st->cum.sum_w = 0.0;
         }
         for (int s = 0; s < kMaxSpecies; ++s) st->nsp[s] = 0;
+    }
+}
+
+// Running energy and virial (a NaN marks a value no longer describing the configuration).
+__global__ void k_set_running(BoxState* st, double u_pair, double w_pair) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->u_pair = u_pair;
+        st->w_pair = w_pair;
+    }
+}
+
+// The chain part of a checkpoint: running energy and virial, move counter,
+// cumulative statistics.
+__global__ void k_apply_checkpoint(BoxState* st, gcmc_checkpoint ck) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->u_pair = ck.u_pair;
+        st->w_pair = ck.w_pair;
+        st->counter = (int64_t)ck.counter;
+        st->cum.moves = ck.moves;
+        for (int t = 0; t < 3; ++t) {
+            st->cum.att[t] = ck.attempts[t];
+            st->cum.acc[t] = ck.accepts[t];
+        }
+        st->cum.sum_n = ck.sum_n;
+        st->cum.sum_n2 = ck.sum_n2;
+        st->cum.sum_u = ck.sum_u;
+        st->cum.sum_w = ck.sum_w;
+    }
+}
+
+__global__ void k_clear_averages(BoxState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->cum.moves = 0;
+        for (int t = 0; t < 3; ++t) st->cum.att[t] = st->cum.acc[t] = 0;
+        st->cum.sum_n = st->cum.sum_n2 = st->cum.sum_u = st->cum.sum_w = 0.0;
     }
 }
 
@@ -309,6 +349,9 @@ static int setup_grid(DevBox& B, const gcmc_box_desc* d, std::vector<uint32_t>& 
         B.hL[a] = 0.5 * d->L[a];
     }
     B.ncells = (int64_t)B.M[0] * B.M[1] * B.M[2];
+    // cell slots c * cap + k are 32-bit indices (back-pointers, home slots)
+    if (d->cell_cap > 0 && B.ncells * (int64_t)d->cell_cap >= ((int64_t)1 << 31))
+        return set_error(GCMC_ERR_INVALID_ARG, "cells x cell_cap must stay below 2^31");
     if ((int64_t)B.span[0] * B.span[1] * B.span[2] > 64 * kMaxStencil)
         return set_error(GCMC_ERR_INVALID_ARG, "stencil larger than 1024 cells: use fewer, larger cells");
     stencil_slots(B, d->rc, slots);
@@ -332,10 +375,12 @@ static void setup_params(DevBox& B, const gcmc_box_desc* d) {
     B.box_id = d->box_id;
     B.max_n = d->max_n;
     const double pre = 8.0 * M_PI / (3.0 * B.V);
+    const double ppre = 16.0 * M_PI / (3.0 * B.V * B.V);
     for (int a = 0; a < kMaxSpecies * kMaxSpecies; ++a) {
         B.eps4[a] = 0.0;
         B.sig2[a] = 1.0;
         B.tailK[a] = 0.0;
+        B.ptailK[a] = 0.0;
     }
     for (int a = 0; a < ns; ++a)
         for (int b = 0; b < ns; ++b) {
@@ -344,6 +389,7 @@ static void setup_params(DevBox& B, const gcmc_box_desc* d) {
             B.sig2[a * ns + b] = s * s;
             const double q = s / d->rc, q3 = q * q * q;
             B.tailK[a * ns + b] = pre * e * (s * s * s) * (q3 * q3 * q3 / 3.0 - q3);
+            B.ptailK[a * ns + b] = ppre * e * (s * s * s) * ((2.0 / 3.0) * (q3 * q3 * q3) - q3);
         }
 }
 
@@ -354,9 +400,9 @@ static int auto_cap(int32_t maxcount) {
 }
 
 // Bin the first n particles of B.pos into a fresh cell array.
-static int bin_particles(gcmc_box* box, int64_t n, hipStream_t s, bool keep_error, double u_pair) {
+static int bin_particles(gcmc_box* box, int64_t n, hipStream_t s, bool keep, double u_pair, double w_pair) {
     DevBox& B = box->d;
-    k_reset_state<<<1, 1, 0, s>>>(B.st, n, u_pair, keep_error ? 1 : 0);
+    k_reset_state<<<1, 1, 0, s>>>(B.st, n, u_pair, w_pair, keep ? 1 : 0);
     k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
     if (n > 0) k_bin<<<grid_for(n), 256, 0, s>>>(B, n);
     if (B.cap <= kWave) {
@@ -371,6 +417,8 @@ static int bin_particles(gcmc_box* box, int64_t n, hipStream_t s, bool keep_erro
 
 static int alloc_cells(gcmc_box* box, int32_t cap) {
     DevBox& B = box->d;
+    if (B.ncells * (int64_t)cap >= ((int64_t)1 << 31))
+        return set_error(GCMC_ERR_INVALID_ARG, "cells x cell_cap must stay below 2^31");
     if (B.ent) {
         GCMC_HIP(hipFree(B.ent));
         B.ent = nullptr;
@@ -445,7 +493,6 @@ int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* 
     hipStream_t s = (hipStream_t)stream;
     gcmc_box* box = new gcmc_box();
     memset(box, 0, sizeof(*box));
-    GCMC_HIP(hipGetDevice(&box->device));
     for (int a = 0; a < 3; ++a) box->req_m[a] = desc->cell_m[a];
     for (int a = 0; a < desc->n_species * desc->n_species; ++a) {
         box->h_eps[a] = desc->eps[a];
@@ -458,6 +505,10 @@ int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* 
     if ((rc = setup_grid(B, desc, slots))) {
         free_box(box);
         return rc;
+    }
+    if (hipGetDevice(&box->device) != hipSuccess) {
+        free_box(box);
+        return set_error(GCMC_ERR_HIP, "no HIP device");
     }
     setup_params(B, desc);
     uint32_t* d_stab = nullptr;
@@ -477,7 +528,7 @@ int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* 
         return set_error(GCMC_ERR_OOM, "box allocation failed");
     }
     // upload and count occupancy to size the cells
-    k_reset_state<<<1, 1, 0, s>>>(B.st, n, 0.0, 0);
+    k_reset_state<<<1, 1, 0, s>>>(B.st, n, 0.0, 0.0, 0);
     if (n > 0) k_upload<<<grid_for(n), 256, 0, s>>>(B, d_x, d_y, d_z, d_species, n);
     k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
     if (n > 0) k_count<<<grid_for(n), 256, 0, s>>>(B, n);
@@ -495,7 +546,8 @@ int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* 
         free_box(box);
         return set_error(GCMC_ERR_CELL_OVERFLOW, "cell_cap smaller than the densest cell");
     }
-    if ((rc = alloc_cells(box, cap)) || (rc = bin_particles(box, n, s, false, 0.0)) || (rc = read_state(box, &h, s))) {
+    if ((rc = alloc_cells(box, cap)) || (rc = bin_particles(box, n, s, false, 0.0, 0.0)) ||
+        (rc = read_state(box, &h, s))) {
         free_box(box);
         return rc;
     }
@@ -551,20 +603,22 @@ int gcmc_cell_build(gcmc_box* box, int32_t new_cap, void* stream) {
     k_clear_rebuild_errors<<<1, 1, 0, s>>>(box->d.st);
     // keep N, running energy and the error move counter; re-bin
     const int64_t n = h.n;
-    if ((rc = bin_particles(box, n, s, true, h.u_pair))) return rc;
+    if ((rc = bin_particles(box, n, s, true, h.u_pair, h.w_pair))) return rc;
     if ((rc = read_state(box, &h, s))) return rc;
     if ((rc = sync_desc(box))) return rc;
     if (h.maxcount > box->d.cap) return set_error(GCMC_ERR_CELL_OVERFLOW, "cell_cap smaller than the densest cell");
     return GCMC_OK;
 }
 
-int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z, void* stream) {
-    if (!box || !d_x || !d_y || !d_z) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z, int64_t n,
+                       void* stream) {
+    if (!box || ((!d_x || !d_y || !d_z) && n > 0)) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     BoxState h;
     int rc = read_state(box, &h, s);
     if (rc) return rc;
     if (h.error) return set_error(GCMC_ERR_POISONED, "box holds a latched error");
+    if (n != h.n) return set_error(GCMC_ERR_INVALID_ARG, "n must equal the box's particle count");
     // species are kept: copy them out of the records first
     int32_t* sp = nullptr;
     if (h.n > 0) {
@@ -575,7 +629,9 @@ int gcmc_set_positions(gcmc_box* box, const double* d_x, const double* d_y, cons
     }
     if ((rc = read_state(box, &h, s))) return rc;
     if (h.error) return set_error(GCMC_ERR_INVALID_ARG, "coordinates must lie in [0, L)");
-    if ((rc = bin_particles(box, h.n, s, false, h.u_pair))) return rc;
+    // the running energy and virial no longer describe the configuration
+    const double nan = std::nan("");
+    if ((rc = bin_particles(box, h.n, s, true, nan, nan))) return rc;
     if ((rc = read_state(box, &h, s))) return rc;
     if (h.error) return set_error(h.error, "re-binning overflowed a cell; rebuild with a larger cell_cap");
     return GCMC_OK;
@@ -613,6 +669,10 @@ int gcmc_set_params(gcmc_box* box, const double* h_eps, const double* h_sigma) {
         box->h_eps[a] = h_eps[a];
         box->h_sig[a] = h_sigma[a];
     }
+    // the running energy and virial belong to the old force field
+    k_set_running<<<1, 1>>>(box->d.st, std::nan(""), std::nan(""));
+    GCMC_HIP(hipGetLastError());
+    GCMC_HIP(hipDeviceSynchronize());
     return sync_desc(box);
 }
 
@@ -686,7 +746,8 @@ int gcmc_box_rescale(gcmc_box* box, const double* h_L, double* d_U, void* stream
                                                 h_L[1], h_L[2]);
     B = N2;
     // occupancy at the new grid; the capacity grows (by the creation rule) if the densest cell needs it
-    k_reset_state<<<1, 1, 0, s>>>(B.st, h.n, h.u_pair, 1);
+    // the running virial is NaN until gcmc_virial sets it at the new volume
+    k_reset_state<<<1, 1, 0, s>>>(B.st, h.n, h.u_pair, std::nan(""), 1);
     k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
     if (h.n > 0) k_count<<<grid_for(h.n), 256, 0, s>>>(B, h.n);
     BoxState h2;
@@ -695,7 +756,8 @@ int gcmc_box_rescale(gcmc_box* box, const double* h_L, double* d_U, void* stream
     if (cap != B.cap || B.ncells != old_cells) {
         if ((rc_ = alloc_cells(box, cap))) return rc_;
     }
-    if ((rc_ = bin_particles(box, h.n, s, true, h.u_pair)) || (rc_ = read_state(box, &h2, s))) return rc_;
+    if ((rc_ = bin_particles(box, h.n, s, true, h.u_pair, std::nan(""))) || (rc_ = read_state(box, &h2, s)))
+        return rc_;
     if (h2.error) return set_error(h2.error, "re-binning failed");
     if ((rc_ = sync_desc(box))) return rc_;
     // energies at the new volume (the running pair energy is reset to U_pair)
@@ -730,32 +792,65 @@ int gcmc_get_cells(gcmc_box* box, int32_t* d_cell_of, int32_t* d_count, int32_t*
     return GCMC_OK;
 }
 
-int gcmc_export_state(gcmc_box* box, int64_t* h_n, double* h_u_pair, int32_t* h_error) {
-    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+int gcmc_export_state(gcmc_box* box, double* d_x, double* d_y, double* d_z, int32_t* d_species, int64_t capacity,
+                      gcmc_checkpoint* h_ck, void* stream) {
+    if (!box || !h_ck) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
     BoxState h;
-    GCMC_HIP(hipDeviceSynchronize());
-    GCMC_HIP(hipMemcpy(&h, box->d.st, sizeof(BoxState), hipMemcpyDeviceToHost));
-    if (h_n) *h_n = h.n;
-    if (h_u_pair) *h_u_pair = h.u_pair;
-    if (h_error) *h_error = h.error;
+    int rc = read_state(box, &h, s);
+    if (rc) return rc;
+    if ((d_x || d_y || d_z || d_species) && capacity < h.n)
+        return set_error(GCMC_ERR_INVALID_ARG, "particle arrays shorter than N");
+    if (h.n > 0 && (d_x || d_y || d_z || d_species)) {
+        k_get_particles<<<grid_for(h.n), 256, 0, s>>>(box->d, d_x, d_y, d_z, d_species);
+        GCMC_HIP(hipGetLastError());
+        GCMC_HIP(hipStreamSynchronize(s));
+    }
+    memset(h_ck, 0, sizeof(*h_ck));
+    h_ck->n = h.n;
+    h_ck->u_pair = h.u_pair;
+    h_ck->w_pair = h.w_pair;
+    h_ck->counter = (uint64_t)h.counter;
+    h_ck->moves = h.cum.moves;
+    for (int t = 0; t < 3; ++t) {
+        h_ck->attempts[t] = h.cum.att[t];
+        h_ck->accepts[t] = h.cum.acc[t];
+    }
+    h_ck->sum_n = h.cum.sum_n;
+    h_ck->sum_n2 = h.cum.sum_n2;
+    h_ck->sum_u = h.cum.sum_u;
+    h_ck->sum_w = h.cum.sum_w;
+    h_ck->error = h.error;
+    h_ck->error_move = h.error_move;
     return GCMC_OK;
 }
 
 int gcmc_import_state(gcmc_box* box, const double* d_x, const double* d_y, const double* d_z,
-                      const int32_t* d_species, int64_t n, double u_pair, void* stream) {
-    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+                      const int32_t* d_species, const gcmc_checkpoint* h_ck, void* stream) {
+    if (!box || !h_ck) return set_error(GCMC_ERR_INVALID_ARG, "NULL argument");
+    const int64_t n = h_ck->n;
     if (n < 0 || n > box->d.max_n) return set_error(GCMC_ERR_INVALID_ARG, "need 0 <= n <= max_n");
     if (n > 0 && (!d_x || !d_y || !d_z)) return set_error(GCMC_ERR_INVALID_ARG, "coordinate arrays are NULL");
+    if (h_ck->error != GCMC_OK) return set_error(GCMC_ERR_INVALID_ARG, "a checkpoint with a latched error");
     hipStream_t s = (hipStream_t)stream;
-    k_reset_state<<<1, 1, 0, s>>>(box->d.st, n, u_pair, 0);
+    k_reset_state<<<1, 1, 0, s>>>(box->d.st, n, h_ck->u_pair, h_ck->w_pair, 0);
     if (n > 0) k_upload<<<grid_for(n), 256, 0, s>>>(box->d, d_x, d_y, d_z, d_species, n);
     BoxState h;
     int rc = read_state(box, &h, s);
     if (rc) return rc;
     if (h.error) return set_error(GCMC_ERR_INVALID_ARG, "coordinates must lie in [0, L) and species in range");
-    if ((rc = bin_particles(box, n, s, false, u_pair))) return rc;
+    if ((rc = bin_particles(box, n, s, false, h_ck->u_pair, h_ck->w_pair))) return rc;
+    k_apply_checkpoint<<<1, 1, 0, s>>>(box->d.st, *h_ck);
+    GCMC_HIP(hipGetLastError());
     if ((rc = read_state(box, &h, s))) return rc;
     if (h.error) return set_error(h.error, "binning overflowed a cell; rebuild with a larger cell_cap");
+    return GCMC_OK;
+}
+
+int gcmc_clear_averages(gcmc_box* box, void* stream) {
+    if (!box) return set_error(GCMC_ERR_INVALID_ARG, "box is NULL");
+    k_clear_averages<<<1, 1, 0, (hipStream_t)stream>>>(box->d.st);
+    GCMC_HIP(hipGetLastError());
     return GCMC_OK;
 }
 

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                                                      const int32_t* __restrict__ order, int64_t n_moves,
                                                      uint64_t ctr0, gcmc_stats* stats, gcmc_log* trace) {
     __shared__ uint32_t tab[kMaxStencil];
-    __shared__ double red[2][2 * W];
+    __shared__ double red[2][4 * W];
     __shared__ int32_t sh_cnt[2][2];     // counters of the two centre cells, per buffer
     __shared__ double4 sh_last[2];       // last entry of the old centre cell, per buffer
     __shared__ int64_t wred[3][W];
@@ -92,11 +92,12 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
     if (ctr0 == GCMC_COUNTER_CONTINUE) ctr0 = (uint64_t)st->counter;
     int64_t N = st->n;
     double U = st->u_pair;
+    double Wvir = st->w_pair;
     int32_t maxc = st->maxcount;
     int32_t err = st->error;
     int64_t err_move = st->error_move;
     int64_t att[3] = {0, 0, 0}, acc_n[3] = {0, 0, 0};
-    double sum_n = 0.0, sum_u = 0.0;
+    double sum_n = 0.0, sum_u = 0.0, sum_n2 = 0.0, sum_w = 0.0;
     const double tk = B.tailK[0];
     const int cap = B.cap;
     const int M0 = B.M[0], M01 = B.M[0] * B.M[1];
@@ -128,10 +129,11 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 if (trace && tid == 0) {
                     gcmc_log r;
                     r.type = H.type; r.index = -1; r.accepted = 0; r.flags = 1;
-                    r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0;
+                    r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0; r.dW_pair = 0.0;
                     trace[(size_t)bi * n_moves + m] = r;
                 }
                 sum_u += U;
+                sum_w += Wvir;
                 if (m + 1 < n_moves) head_of(B, ctr + 1, N, H);
                 continue;
             }
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
             const int buf = ev & 1;
             const int32_t excl = (int32_t)T.idx;
             const int32_t cl0 = (int32_t)T.cl[0], cl1 = (int32_t)T.cl[1];
-            double sa = 0.0, sb = 0.0;
+            double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
             Head Hn;
             bool have_next = false;
             double lnA = 0.0, lpref = 0.0;
@@ -262,17 +264,17 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 for (int j = lane; j < nv; j += kWave) {
                     const double4 c4 = my[j];
                     if (T.npos == 1) {
-                        sa += pair_energy_w<false>(B, T.p[0], 0, c4, wk.incut);
+                        sa += pair_uw<false>(B, T.p[0], 0, c4, wk.incut, wa);
                         wk.evals += 1;
                     } else if (!two) {
-                        sa += pair_energy_w<false>(B, T.p[0], 0, c4, wk.incut);
-                        sb += pair_energy_w<false>(B, T.p[1], 0, c4, wk.incut);
+                        sa += pair_uw<false>(B, T.p[0], 0, c4, wk.incut, wa);
+                        sb += pair_uw<false>(B, T.p[1], 0, c4, wk.incut, wb);
                         wk.evals += 2;
                     } else if (c4.w != 0.0) {
-                        sb += pair_energy_w<false>(B, T.p[1], 0, c4, wk.incut);
+                        sb += pair_uw<false>(B, T.p[1], 0, c4, wk.incut, wb);
                         wk.evals += 1;
                     } else {
-                        sa += pair_energy_w<false>(B, T.p[0], 0, c4, wk.incut);
+                        sa += pair_uw<false>(B, T.p[0], 0, c4, wk.incut, wa);
                         wk.evals += 1;
                     }
                 }
@@ -283,25 +285,34 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
             // ----------------------------------------------------- reduce
             double ea = wave_sum_uniform(sa);
             double eb = (T.npos == 2) ? wave_sum_uniform(sb) : 0.0;
+            double va = wave_sum_uniform(wa);
+            double vb = (T.npos == 2) ? wave_sum_uniform(wb) : 0.0;
             if (W > 1) {
                 if (lane == 0) {
-                    red[buf][2 * wv] = ea;
-                    red[buf][2 * wv + 1] = eb;
+                    red[buf][4 * wv] = ea;
+                    red[buf][4 * wv + 1] = eb;
+                    red[buf][4 * wv + 2] = va;
+                    red[buf][4 * wv + 3] = vb;
                 }
                 __syncthreads();
-                double ta = 0.0, tb = 0.0;
+                double ta = 0.0, tb = 0.0, ua = 0.0, ub = 0.0;
 #pragma unroll
                 for (int v = 0; v < W; ++v) {
-                    ta += red[buf][2 * v];
-                    tb += red[buf][2 * v + 1];
+                    ta += red[buf][4 * v];
+                    tb += red[buf][4 * v + 1];
+                    ua += red[buf][4 * v + 2];
+                    ub += red[buf][4 * v + 3];
                 }
                 ea = ta;
                 eb = tb;
+                va = ua;
+                vb = ub;
             }
             // ----------------------------------------------------- decide
             // Accept iff ln A < ln(ratio) (Eqs. 3-5); the same test as A < min(1, ratio).
             const bool is_disp = T.type == GCMC_MOVE_DISPLACE, is_ins = T.type == GCMC_MOVE_INSERT;
             const double dUp = is_disp ? (eb - ea) : (is_ins ? ea : -ea);
+            const double dWp = is_disp ? (vb - va) : (is_ins ? va : -va);
             const double dUt = is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
             const double dU = dUp + dUt;
             const double arg = is_disp ? -(B.beta * dU)
@@ -371,6 +382,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 acc_n[T.type] += 1;
                 N += (T.type == GCMC_MOVE_INSERT) ? 1 : ((T.type == GCMC_MOVE_DELETE) ? -1 : 0);
                 U += dUp;
+                Wvir += dWp;
                 __syncthreads();   // commit stores complete and visible to the workgroup
             }
             if (trace && tid == 0) {
@@ -384,10 +396,13 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
                 const int w = (T.type == GCMC_MOVE_DISPLACE) ? 1 : 0;
                 r.x = T.p[w][0]; r.y = T.p[w][1]; r.z = T.p[w][2];
                 r.arg = arg;
+                r.dW_pair = dWp;
                 trace[(size_t)bi * n_moves + m] = r;
             }
             sum_n += (double)N;
+            sum_n2 += (double)N * (double)N;
             sum_u += U + tk * (double)N * (double)N;
+            sum_w += Wvir;
             // ------------------------------------- validate the prefetch
             if (m + 1 < n_moves) {
                 if (Hn.type != GCMC_MOVE_INSERT && N > 0) {
@@ -426,6 +441,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
     if (tid == 0) {
         st->n = N;
         st->u_pair = U;
+        st->w_pair = Wvir;
         st->maxcount = maxc;
         st->nsp[0] = N;
         st->counter = (int64_t)(ctr0 + (uint64_t)m);
@@ -433,30 +449,23 @@ __global__ __launch_bounds__(kWave* W) void k_chain(const DevBox* __restrict__ b
             st->error = err;
             st->error_move = err_move;
         }
-        if (stats) {
-            gcmc_stats o;
-            for (int t = 0; t < 3; ++t) {
-                o.attempts[t] = att[t];
-                o.accepts[t] = acc_n[t];
-            }
-            o.n = N;
-            o.moves_done = m;
-            o.u_pair = U;
-            o.u_tail = tk * (double)N * (double)N;
-            o.sum_n = sum_n;
-            o.sum_u = sum_u;
-            o.error = st->error;
-            o.pad = 0;
-            o.error_move = st->error_move;
-            o.stencils = stencils;
-            o.candidates = o.pair_evals = o.in_cutoff = 0;
-            for (int v = 0; v < W; ++v) {
-                o.candidates += wred[0][v];
-                o.pair_evals += wred[1][v];
-                o.in_cutoff += wred[2][v];
-            }
-            stats[bi] = o;
+        ChainSums L;
+        L.moves = m;
+        for (int t = 0; t < 3; ++t) {
+            L.att[t] = att[t];
+            L.acc[t] = acc_n[t];
         }
+        L.sum_n = sum_n;
+        L.sum_n2 = sum_n2;
+        L.sum_u = sum_u;
+        L.sum_w = sum_w;
+        int64_t c = 0, e = 0, q = 0;
+        for (int v = 0; v < W; ++v) {
+            c += wred[0][v];
+            e += wred[1][v];
+            q += wred[2][v];
+        }
+        finish_launch(B, st, L, N, U, Wvir, stencils, c, e, q, stats ? stats + bi : nullptr);
     }
 }
 

@@ -384,6 +384,7 @@ __global__ __launch_bounds__(kBlk) void k_virial_finish(const DevBox* __restrict
         pt *= 16.0 * M_PI / (3.0 * B.V * B.V);
         out[0] = W;
         out[1] = (double)B.st->n / (B.beta * B.V) + W / (3.0 * B.V) + pt;
+        if (B.st->error == GCMC_OK) B.st->w_pair = W;
     }
 }
 
@@ -397,9 +398,11 @@ struct APTrial {
 };
 
 __device__ __forceinline__ void ap_chunk_sums(const DevBox& B, const APTrial& T, int64_t n, int64_t j0,
-                                              int64_t j1, bool mix, double& sa, double& sb) {
+                                              int64_t j1, bool mix, double& sa, double& sb, double& wa, double& wb) {
     sa = 0.0;
     sb = 0.0;
+    wa = 0.0;
+    wb = 0.0;
     const PassConst K = pass_const(B);
     const int ns = uni(B.ns);
     for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
@@ -409,10 +412,10 @@ __device__ __forceinline__ void ap_chunk_sums(const DevBox& B, const APTrial& T,
         if (mix) q = T.sp * ns + meta_species(o.w);
         const double e4 = mix ? B.eps4[q] : K.e4, s2 = mix ? B.sig2[q] : K.s2;
         const double r2a = pass_dist2(K, T.p[0][0], T.p[0][1], T.p[0][2], o.x, o.y, o.z);
-        sa += lj_from_r2(r2a, K.rc2, e4, s2);
+        sa += lj_uw_from_r2(r2a, K.rc2, e4, s2, wa);
         if (T.npos == 2) {
             const double r2b = pass_dist2(K, T.p[1][0], T.p[1][1], T.p[1][2], o.x, o.y, o.z);
-            sb += lj_from_r2(r2b, K.rc2, e4, s2);
+            sb += lj_uw_from_r2(r2b, K.rc2, e4, s2, wb);
         }
     }
 }
@@ -445,7 +448,7 @@ __device__ __forceinline__ APTrial ap_trial_from_move(const DevBox& B, const gcm
     return T;
 }
 
-// grid (chunks, moves): scratch[(m * chunks + chunk) * 2 + {0,1}]
+// grid (chunks, moves): scratch[(m * chunks + chunk) * 4 + {0,1,2,3}] (energy old/new, virial old/new)
 __global__ __launch_bounds__(kBlk) void k_delta_ap_partial(const DevBox* __restrict__ boxp, const gcmc_move* moves,
                                                             int64_t chunk, double* scratch) {
     __shared__ double red[kBlk / kWave];
@@ -456,50 +459,65 @@ __global__ __launch_bounds__(kBlk) void k_delta_ap_partial(const DevBox* __restr
     const int64_t j0 = (int64_t)blockIdx.x * chunk;
     int64_t j1 = j0 + chunk;
     if (j1 > n) j1 = n;
-    double sa = 0.0, sb = 0.0;
-    if (T.valid) ap_chunk_sums(B, T, n, j0, j1, B.ns > 1, sa, sb);
+    double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
+    if (T.valid) ap_chunk_sums(B, T, n, j0, j1, B.ns > 1, sa, sb, wa, wb);
     sa = block_sum(sa, red);
     sb = block_sum(sb, red);
+    wa = block_sum(wa, red);
+    wb = block_sum(wb, red);
     if (threadIdx.x == 0) {
-        scratch[(m * gridDim.x + blockIdx.x) * 2] = sa;
-        scratch[(m * gridDim.x + blockIdx.x) * 2 + 1] = sb;
+        double* o = scratch + (m * gridDim.x + blockIdx.x) * 4;
+        o[0] = sa;
+        o[1] = sb;
+        o[2] = wa;
+        o[3] = wb;
     }
 }
 
 __global__ __launch_bounds__(kBlk) void k_delta_ap_finish(const DevBox* __restrict__ boxp, const gcmc_move* moves,
                                                            int64_t nchunks, const double* scratch, double* dU_pair,
-                                                           double* dU_tail) {
+                                                           double* dU_tail, double* dW_pair) {
     __shared__ double red[kBlk / kWave];
     const DevBox& B = *boxp;
     const int64_t n = B.st->n;
     const int64_t m = blockIdx.x;
     const APTrial T = ap_trial_from_move(B, moves[m], n);
-    double sa = 0.0, sb = 0.0;
+    double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
     for (int64_t q = threadIdx.x; q < nchunks; q += kBlk) {
-        sa += scratch[(m * nchunks + q) * 2];
-        sb += scratch[(m * nchunks + q) * 2 + 1];
+        const double* o = scratch + (m * nchunks + q) * 4;
+        sa += o[0];
+        sb += o[1];
+        wa += o[2];
+        wb += o[3];
     }
     sa = block_sum(sa, red);
     sb = block_sum(sb, red);
+    wa = block_sum(wa, red);
+    wb = block_sum(wb, red);
     if (threadIdx.x == 0) {
         int64_t nsp[kMaxSpecies];
         for (int s = 0; s < kMaxSpecies; ++s) nsp[s] = B.st->nsp[s];
-        double p, t;
+        double p, t, w;
         if (!T.valid) {
             p = __builtin_nan("");
             t = __builtin_nan("");
+            w = __builtin_nan("");
         } else if (T.type == GCMC_MOVE_DISPLACE) {
             p = sb - sa;
             t = 0.0;
+            w = wb - wa;
         } else if (T.type == GCMC_MOVE_INSERT) {
             p = sa;
             t = tail_change(B, nsp, T.sp, +1);
+            w = wa;
         } else {
             p = -sa;
             t = tail_change(B, nsp, T.sp, -1);
+            w = -wa;
         }
         dU_pair[m] = p;
         if (dU_tail) dU_tail[m] = t;
+        if (dW_pair) dW_pair[m] = w;
     }
 }
 
@@ -509,7 +527,7 @@ struct APChain {
     uint64_t counter;   // next move counter
     uint64_t ctr0;      // first counter of this call
     int64_t att[3], acc[3];
-    double sum_n, sum_u;
+    double sum_n, sum_u, sum_n2, sum_w;
     int64_t moves_done;
     int64_t candidates, pair_evals;
 };
@@ -553,13 +571,18 @@ __global__ __launch_bounds__(kBlk) void k_ap_chain_eval(const DevBox* __restrict
     const int64_t j0 = (int64_t)blockIdx.x * chunk;
     int64_t j1 = j0 + chunk;
     if (j1 > n) j1 = n;
-    double sa = 0.0, sb = 0.0;
-    if (T.valid) ap_chunk_sums(B, T, n, j0, j1, false, sa, sb);
+    double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
+    if (T.valid) ap_chunk_sums(B, T, n, j0, j1, false, sa, sb, wa, wb);
     sa = block_sum(sa, red);
     sb = block_sum(sb, red);
+    wa = block_sum(wa, red);
+    wb = block_sum(wb, red);
     if (threadIdx.x == 0) {
-        scratch[blockIdx.x * 2] = sa;
-        scratch[blockIdx.x * 2 + 1] = sb;
+        double* o = scratch + blockIdx.x * 4;
+        o[0] = sa;
+        o[1] = sb;
+        o[2] = wa;
+        o[3] = wb;
     }
 }
 
@@ -575,13 +598,17 @@ __global__ __launch_bounds__(kBlk) void k_ap_chain_decide(const DevBox* __restri
     const uint64_t ctr = ch->counter;
     const U8 u = move_uniforms(B.seed, ctr, B.box_id);
     const APTrial T = ap_trial_from_draws(B, u, n);
-    double sa = 0.0, sb = 0.0;
+    double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
     for (int64_t q = threadIdx.x; q < nchunks; q += kBlk) {
-        sa += scratch[q * 2];
-        sb += scratch[q * 2 + 1];
+        sa += scratch[q * 4];
+        sb += scratch[q * 4 + 1];
+        wa += scratch[q * 4 + 2];
+        wb += scratch[q * 4 + 3];
     }
     sa = block_sum(sa, red);
     sb = block_sum(sb, red);
+    wa = block_sum(wa, red);
+    wb = block_sum(wb, red);
     if (threadIdx.x != 0) return;
     const int64_t m = (int64_t)(ctr - ch->ctr0);
     const double tk = B.tailK[0];
@@ -593,23 +620,28 @@ __global__ __launch_bounds__(kBlk) void k_ap_chain_decide(const DevBox* __restri
     r.dU_pair = 0.0;
     r.dU_tail = 0.0;
     r.arg = 0.0;
+    r.dW_pair = 0.0;
     r.x = r.y = r.z = 0.0;
     int64_t n_after = n;
     if (!T.valid) {
         r.index = -1;
         r.flags = 1;
     } else {
-        double dUp, dUt;
+        double dUp, dUt, dWp;
         if (T.type == GCMC_MOVE_DISPLACE) {
             dUp = sb - sa;
             dUt = 0.0;
+            dWp = wb - wa;
         } else if (T.type == GCMC_MOVE_INSERT) {
             dUp = sa;
             dUt = tk * (2.0 * (double)n + 1.0);
+            dWp = wa;
         } else {
             dUp = -sa;
             dUt = tk * (1.0 - 2.0 * (double)n);
+            dWp = -wa;
         }
+        r.dW_pair = dWp;
         const double dU = dUp + dUt;
         const double arg = accept_log_ratio(B, T.type, dU, n);
         const bool ok = metropolis(arg, dU, u.u[3]);
@@ -637,23 +669,27 @@ __global__ __launch_bounds__(kBlk) void k_ap_chain_decide(const DevBox* __restri
             st->n = n_after;
             st->nsp[0] = n_after;
             st->u_pair += dUp;
+            st->w_pair += dWp;
             ch->acc[T.type] += 1;
             r.accepted = 1;
         }
     }
     if (log) log[m] = r;
     ch->sum_n += (double)n_after;
+    ch->sum_n2 += (double)n_after * (double)n_after;
     ch->sum_u += st->u_pair + tk * (double)n_after * (double)n_after;
+    ch->sum_w += st->w_pair;
     ch->moves_done = m + 1;
     ch->counter = ctr + 1;
 }
 
-__global__ void k_ap_chain_begin(APChain* ch, uint64_t ctr0) {
+__global__ void k_ap_chain_begin(const DevBox* __restrict__ boxp, APChain* ch, uint64_t ctr0) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (ctr0 == GCMC_COUNTER_CONTINUE) ctr0 = (uint64_t)boxp->st->counter;
         ch->counter = ctr0;
         ch->ctr0 = ctr0;
         for (int t = 0; t < 3; ++t) ch->att[t] = ch->acc[t] = 0;
-        ch->sum_n = ch->sum_u = 0.0;
+        ch->sum_n = ch->sum_u = ch->sum_n2 = ch->sum_w = 0.0;
         ch->moves_done = 0;
         ch->candidates = ch->pair_evals = 0;
     }
@@ -662,25 +698,20 @@ __global__ void k_ap_chain_begin(APChain* ch, uint64_t ctr0) {
 __global__ void k_ap_chain_end(const DevBox* __restrict__ boxp, const APChain* ch, gcmc_stats* stats) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const DevBox& B = *boxp;
-    gcmc_stats o;
+    ChainSums L;
+    L.moves = ch->moves_done;
     for (int t = 0; t < 3; ++t) {
-        o.attempts[t] = ch->att[t];
-        o.accepts[t] = ch->acc[t];
+        L.att[t] = ch->att[t];
+        L.acc[t] = ch->acc[t];
     }
-    o.n = B.st->n;
-    o.moves_done = ch->moves_done;
-    o.u_pair = B.st->u_pair;
-    o.u_tail = B.tailK[0] * (double)o.n * (double)o.n;
-    o.sum_n = ch->sum_n;
-    o.sum_u = ch->sum_u;
-    o.error = B.st->error;
-    o.pad = 0;
-    o.error_move = B.st->error_move;
-    o.stencils = ch->moves_done;
-    o.candidates = ch->candidates;
-    o.pair_evals = ch->pair_evals;
-    o.in_cutoff = -1;   // not counted on the all-pairs path
-    *stats = o;
+    L.sum_n = ch->sum_n;
+    L.sum_n2 = ch->sum_n2;
+    L.sum_u = ch->sum_u;
+    L.sum_w = ch->sum_w;
+    B.st->counter = (int64_t)ch->counter;
+    // in_cutoff is not counted on the all-pairs path (-1)
+    finish_launch(B, B.st, L, B.st->n, B.st->u_pair, B.st->w_pair, ch->moves_done, ch->candidates, ch->pair_evals,
+                  -1, stats);
 }
 
 // The all-pairs chain keeps the cell list up to date as well (same commit).
@@ -984,7 +1015,7 @@ int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* gra
 int64_t ap_chunk_len() { return 8 * kBlk; }
 
 int launch_delta_allpairs(const DevBox* d_box, int64_t n, const gcmc_move* moves, int64_t n_moves, double* scratch,
-                          double* dp, double* dt, hipStream_t s) {
+                          double* dp, double* dt, double* dw, hipStream_t s) {
     const int64_t chunk = ap_chunk_len();
     int64_t nch = (n + chunk - 1) / chunk;
     if (nch < 1) nch = 1;
@@ -992,14 +1023,14 @@ int launch_delta_allpairs(const DevBox* d_box, int64_t n, const gcmc_move* moves
     hipLaunchKernelGGL(k_delta_ap_partial, dim3((unsigned)nch, (unsigned)n_moves), dim3(kBlk), 0, s, d_box, moves,
                        chunk, scratch);
     hipLaunchKernelGGL(k_delta_ap_finish, dim3((unsigned)n_moves), dim3(kBlk), 0, s, d_box, moves, nch, scratch, dp,
-                       dt);
+                       dt, dw);
     return 0;
 }
 
 size_t ap_chain_state_bytes() { return sizeof(APChain); }
 
-void launch_ap_chain_begin(void* ch, uint64_t ctr0, hipStream_t s) {
-    hipLaunchKernelGGL(k_ap_chain_begin, dim3(1), dim3(64), 0, s, (APChain*)ch, ctr0);
+void launch_ap_chain_begin(const DevBox* d_box, void* ch, uint64_t ctr0, hipStream_t s) {
+    hipLaunchKernelGGL(k_ap_chain_begin, dim3(1), dim3(64), 0, s, d_box, (APChain*)ch, ctr0);
 }
 
 void launch_ap_chain_move(const DevBox* d_box, void* ch, int64_t nch, double* scratch, gcmc_log* log,

@@ -16,6 +16,14 @@ constexpr int kWave = 64;
 constexpr int kMaxSpecies = GCMC_MAX_SPECIES;
 constexpr int kMaxStencil = 1024;   // stencil cells kept in LDS
 
+// Sums of the chain statistics over many moves (per launch, or cumulative in
+// the box since it was created, imported or cleared).
+struct ChainSums {
+    int64_t moves;
+    int64_t att[3], acc[3];
+    double sum_n, sum_n2, sum_u, sum_w;   // N, N^2, u_pair + u_tail and W after each move
+};
+
 // Device-resident mutable state of one box.
 struct BoxState {
     int64_t n;            // particle count N
@@ -25,6 +33,8 @@ struct BoxState {
     int64_t error_move;   // move counter of the error, -1 if none
     int64_t nsp[kMaxSpecies];  // particles per species
     int64_t counter;      // move counter after the last move the chain ran
+    double w_pair;        // running pair virial
+    ChainSums cum;        // cumulative statistics (part of a checkpoint)
 };
 
 // Everything a kernel needs about one box (read-only during a launch).
@@ -53,6 +63,7 @@ struct DevBox {
     double eps4[kMaxSpecies * kMaxSpecies];   // 4 * eps_ab
     double sig2[kMaxSpecies * kMaxSpecies];   // sigma_ab^2
     double tailK[kMaxSpecies * kMaxSpecies];  // (8 pi / 3V) eps sigma^3 (q^9/3 - q^3), q = sigma / rc
+    double ptailK[kMaxSpecies * kMaxSpecies]; // (16 pi / 3V^2) eps sigma^3 ((2/3) q^9 - q^3): P_tail / (N_a N_b)
     uint64_t seed;
     uint32_t box_id;
     int32_t nstencil;    // stencil cells kept (at most span_x * span_y * span_z)
@@ -224,6 +235,21 @@ __device__ __forceinline__ double lj_from_r2(double r2, double rc2, double eps4,
     return eps4 * (s6 * s6 - s6);
 }
 
+// Pair energy u and pair virial w = -r du/dr together (the same s6, the same
+// cutoff decision): returns u, adds w to `w`.
+__device__ __forceinline__ double lj_uw_from_r2(double r2, double rc2, double eps4, double sig2, double& w) {
+    if (!(r2 < rc2) || eps4 == 0.0) return 0.0;
+    if (r2 == 0.0) {
+        w += __builtin_inf();
+        return __builtin_inf();
+    }
+    const double sr2 = sig2 / r2;
+    const double s6 = sr2 * sr2 * sr2;
+    const double s12 = s6 * s6;
+    w += 6.0 * eps4 * (2.0 * s12 - s6);
+    return eps4 * (s12 - s6);
+}
+
 // Pair virial -r du/dr of the truncated potential inside the cutoff:
 // 24 eps [2 (sigma/r)^12 - (sigma/r)^6] (eps4 = 4 eps).
 __device__ __forceinline__ double lj_virial_from_r2(double r2, double rc2, double eps4, double sig2) {
@@ -273,6 +299,19 @@ __device__ __forceinline__ double wave_sum_uniform(double v) {
     v += dpp_move<0x124>(v);   // row_ror:4
     v += dpp_move<0x128>(v);   // row_ror:8
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Sum over the wavefront kept in vector registers (every lane receives it):
+// the same DPP steps within rows of 16, then two cross-row exchanges.  For
+// sums that only one lane stores, so they take no scalar registers.
+__device__ __forceinline__ double wave_sum_vec(double v) {
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x124>(v);
+    v += dpp_move<0x128>(v);
+    v += __shfl_xor(v, 16, kWave);
+    v += __shfl_xor(v, 32, kWave);
+    return v;
 }
 
 // Integer sum and maximum over the wavefront with the same DPP pattern,
@@ -338,6 +377,53 @@ __device__ __forceinline__ double tail_change(const DevBox& B, const int64_t* ns
     return (double)(2 * sign) * acc + B.tailK[s * B.ns + s];
 }
 
+// End of a chain launch (one thread, single species): write the launch's
+// statistics with the averages of N, U and the pressure over its moves (the
+// averages Sec. 3.3.4 computes on the GPU), and fold the sums into the box's
+// cumulative statistics.  The caller has already stored N, U, W and the
+// counter into the box state.
+__device__ __forceinline__ void finish_launch(const DevBox& B, BoxState* st, const ChainSums& L, int64_t N, double U,
+                                              double W, int64_t stencils, int64_t cand, int64_t evals,
+                                              int64_t incut, gcmc_stats* out) {
+    ChainSums& c = st->cum;
+    c.moves += L.moves;
+    for (int t = 0; t < 3; ++t) {
+        c.att[t] += L.att[t];
+        c.acc[t] += L.acc[t];
+    }
+    c.sum_n += L.sum_n;
+    c.sum_n2 += L.sum_n2;
+    c.sum_u += L.sum_u;
+    c.sum_w += L.sum_w;
+    if (!out) return;
+    gcmc_stats o;
+    for (int t = 0; t < 3; ++t) {
+        o.attempts[t] = L.att[t];
+        o.accepts[t] = L.acc[t];
+    }
+    o.n = N;
+    o.moves_done = L.moves;
+    o.u_pair = U;
+    o.u_tail = B.tailK[0] * (double)N * (double)N;
+    o.sum_n = L.sum_n;
+    o.sum_u = L.sum_u;
+    o.error = st->error;
+    o.pad = 0;
+    o.error_move = st->error_move;
+    o.stencils = stencils;
+    o.candidates = cand;
+    o.pair_evals = evals;
+    o.in_cutoff = incut;
+    o.w_pair = W;
+    o.sum_w = L.sum_w;
+    o.sum_n2 = L.sum_n2;
+    const double inv = L.moves > 0 ? 1.0 / (double)L.moves : __builtin_nan("");
+    o.avg_n = L.sum_n * inv;
+    o.avg_u = L.sum_u * inv;
+    o.avg_p = o.avg_n / (B.beta * B.V) + (L.sum_w * inv) / (3.0 * B.V) + B.ptailK[0] * (L.sum_n2 * inv);
+    *out = o;
+}
+
 }  // namespace gcmc
 
 // ------------------------------------------------------------ host side
@@ -382,8 +468,8 @@ int launch_chain_async(const DevBox* d_boxes, const int32_t* d_order, int n_boxe
 int launch_chain_spec(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
                       uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 int launch_delta(const DevBox* d_box, bool mix, int64_t n_moves, const gcmc_move* moves, double* dp, double* dt,
-                 hipStream_t s);
-void launch_commit(const DevBox* d_box, const gcmc_move* move, const double* dU, hipStream_t s);
+                 double* dw, hipStream_t s);
+void launch_commit(const DevBox* d_box, const gcmc_move* move, const double* dU, const double* dW, hipStream_t s);
 void launch_neighbors(const DevBox* d_box, const double* pts, const int32_t* excl, int64_t n, int32_t max_ids,
                       int32_t* ids, int32_t* counts, hipStream_t s);
 
@@ -398,9 +484,9 @@ int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* gra
                 double* dsig, hipStream_t s, int64_t n);
 int64_t ap_chunk_len();
 int launch_delta_allpairs(const DevBox* d_box, int64_t n, const gcmc_move* moves, int64_t n_moves, double* scratch,
-                          double* dp, double* dt, hipStream_t s);
+                          double* dp, double* dt, double* dw, hipStream_t s);
 size_t ap_chain_state_bytes();
-void launch_ap_chain_begin(void* ch, uint64_t ctr0, hipStream_t s);
+void launch_ap_chain_begin(const DevBox* d_box, void* ch, uint64_t ctr0, hipStream_t s);
 void launch_ap_chain_move(const DevBox* d_box, void* ch, int64_t nch, double* scratch, gcmc_log* log,
                           hipStream_t s);
 void launch_ap_chain_end(const DevBox* d_box, const void* ch, gcmc_stats* stats, hipStream_t s);

@@ -7,9 +7,10 @@ namespace gcmc {
 
 template <int W, int R, bool MIX>
 __global__ __launch_bounds__(kWave* W) void k_delta(const DevBox* __restrict__ boxp, const gcmc_move* moves,
-                                                     int64_t n_moves, double* dU_pair, double* dU_tail) {
+                                                     int64_t n_moves, double* dU_pair, double* dU_tail,
+                                                     double* dW_pair) {
     __shared__ uint32_t tab[kMaxStencil];
-    __shared__ double red[2 * W];
+    __shared__ double red[4 * W];
     const DevBox& B = *boxp;
     load_stencil(B, tab);
     __syncthreads();
@@ -22,32 +23,38 @@ __global__ __launch_bounds__(kWave* W) void k_delta(const DevBox* __restrict__ b
         const gcmc_move mv = moves[m];
         Trial T;
         const bool ok = trial_from_move(B, mv, n, T);
-        double ea = 0.0, eb = 0.0;
+        double ea = 0.0, eb = 0.0, va = 0.0, vb = 0.0;
         Work wk;
-        if (ok) eval_trial<W, R, MIX>(B, tab, lg, T, ea, eb, red, wk);
+        if (ok) eval_trial<W, R, MIX>(B, tab, lg, T, ea, eb, va, vb, red, wk);
         __syncthreads();
         if (threadIdx.x == 0) {
-            double p, t;
+            double p, t, w;
             if (!ok) {
                 p = __builtin_nan("");
                 t = __builtin_nan("");
+                w = __builtin_nan("");
             } else if (T.type == GCMC_MOVE_DISPLACE) {
                 p = eb - ea;
                 t = 0.0;
+                w = vb - va;
             } else if (T.type == GCMC_MOVE_INSERT) {
                 p = ea;
                 t = tail_change(B, nsp, T.sp, +1);
+                w = va;
             } else {
                 p = -ea;
                 t = tail_change(B, nsp, T.sp, -1);
+                w = -va;
             }
             dU_pair[m] = p;
             if (dU_tail) dU_tail[m] = t;
+            if (dW_pair) dW_pair[m] = w;
         }
     }
 }
 
-__global__ void k_commit(const DevBox* __restrict__ boxp, const gcmc_move* move, const double* dU_pair) {
+__global__ void k_commit(const DevBox* __restrict__ boxp, const gcmc_move* move, const double* dU_pair,
+                         const double* dW_pair) {
     const DevBox& B = *boxp;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     BoxState* st = B.st;
@@ -76,6 +83,7 @@ __global__ void k_commit(const DevBox* __restrict__ boxp, const gcmc_move* move,
         st->nsp[T.sp] -= 1;
     }
     st->u_pair += *dU_pair;
+    st->w_pair = dW_pair ? st->w_pair + *dW_pair : __builtin_nan("");
 }
 
 // Candidate ids of points (the same slot mapping as eval_trial).
@@ -115,18 +123,18 @@ __global__ __launch_bounds__(256) void k_neighbors(const DevBox* __restrict__ bo
 
 // ---------------------------------------------------------- dispatch
 int launch_delta(const DevBox* d_box, bool mix, int64_t n_moves, const gcmc_move* moves, double* dp, double* dt,
-                 hipStream_t s) {
+                 double* dw, hipStream_t s) {
     const int64_t g64 = n_moves < 65536 ? n_moves : 65536;
     const int g = (int)(g64 < 1 ? 1 : g64);
     if (mix)
-        hipLaunchKernelGGL((k_delta<4, 4, true>), dim3(g), dim3(kWave * 4), 0, s, d_box, moves, n_moves, dp, dt);
+        hipLaunchKernelGGL((k_delta<4, 4, true>), dim3(g), dim3(kWave * 4), 0, s, d_box, moves, n_moves, dp, dt, dw);
     else
-        hipLaunchKernelGGL((k_delta<4, 4, false>), dim3(g), dim3(kWave * 4), 0, s, d_box, moves, n_moves, dp, dt);
+        hipLaunchKernelGGL((k_delta<4, 4, false>), dim3(g), dim3(kWave * 4), 0, s, d_box, moves, n_moves, dp, dt, dw);
     return 0;
 }
 
-void launch_commit(const DevBox* d_box, const gcmc_move* move, const double* dU, hipStream_t s) {
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, s, d_box, move, dU);
+void launch_commit(const DevBox* d_box, const gcmc_move* move, const double* dU, const double* dW, hipStream_t s) {
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, s, d_box, move, dU, dW);
 }
 
 void launch_neighbors(const DevBox* d_box, const double* pts, const int32_t* excl, int64_t n, int32_t max_ids,

@@ -37,6 +37,19 @@
 
 namespace gcmc {
 
+// Tail change and log acceptance ratio of a move decided at N particles
+// (Eqs. 3-5; the log prefactors for N come from the round's tables): one
+// routine for the decision and for the per-move log written after the round,
+// so both hold the same bits.
+__device__ __forceinline__ double spec_arg(const DevBox& B, int type, double dUp, int64_t N, int64_t base,
+                                           const double* lp_ins, const double* lp_del, double tk, double& dUt) {
+    const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
+    dUt = is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
+    const double dU = dUp + dUt;
+    const double lpref = is_disp ? 0.0 : (is_ins ? lp_ins[N - base] : lp_del[N - base]);
+    return is_disp ? -(B.beta * dU) : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
+}
+
 template <int W, int CR>
 __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restrict__ boxes,
                                                           const int32_t* __restrict__ order, int64_t n_moves,
@@ -48,10 +61,12 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     __shared__ double4 top[2 * W];              // records of particles base .. base + 2W - 1
     __shared__ double lp_ins[2 * W], lp_del[2 * W];   // acceptance prefactors at N = base + t
     __shared__ int64_t sh_state[4];       // N, moves done, error, error move
-    __shared__ double sh_u;
+    __shared__ double sh_u, sh_w;
     __shared__ double sh_acc[2];
     __shared__ int32_t sh_maxc;
     __shared__ int32_t ready[W];                // round whose evaluation wavefront w has published
+    __shared__ int64_t after_n[W];              // N, U and W after each move decided this round
+    __shared__ double after_u[W], after_w[W];
     const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
     const DevBox B = hot_copy(boxes[blockIdx.x]);
     const int tid = threadIdx.x;
@@ -62,6 +77,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     if (ctr0 == GCMC_COUNTER_CONTINUE) ctr0 = (uint64_t)st->counter;
     int64_t N = st->n;
     double U = st->u_pair;
+    double Wvir = st->w_pair;
     int32_t maxc = st->maxcount;
     int32_t err = st->error;
     int64_t err_move = st->error_move;
@@ -73,7 +89,8 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     // doubles (a dynamically indexed array would live in scratch; exact below 2^53), folded in
     // once per round
     double att0 = 0.0, att1 = 0.0, att2 = 0.0, acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    double sum_n = 0.0, sum_u = 0.0;
+    // per-lane sums over the moves lane j decided (N, N^2, U + U_tail, W after move j of a round)
+    double sum_n = 0.0, sum_u = 0.0, sum_n2 = 0.0, sum_w = 0.0;
     // per-lane sums over the moves lane j decided as move j of a round, added up at the end
     int64_t stencils = 0, cand = 0, evals = 0, incut = 0;
     for (int t = tid; t < B.nstencil; t += blockDim.x) {
@@ -151,13 +168,11 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 // the empty-box rejection holds only while the box is still empty
                 if (R.flags & 1) {
                     if (N != 0) break;
-                    if (trace && lane == 0) {
-                        gcmc_log r;
-                        r.type = type; r.index = -1; r.accepted = 0; r.flags = 1;
-                        r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0;
-                        trace[(size_t)bi * n_moves + m + k] = r;
+                    if (lane == 0) {
+                        after_n[k] = N;
+                        after_u[k] = U;
+                        after_w[k] = Wvir;
                     }
-                    sum_u += U;
                     continue;
                 }
                 const int64_t idx = R.idx;
@@ -176,16 +191,12 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 // ---- decide at the current N
                 const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
                 const double dUp = R.dUp;
-                const double dUt =
-                    is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
+                double dUt;
+                const double arg = spec_arg(B, type, dUp, N, base, lp_ins, lp_del, tk, dUt);
                 const double dU = dUp + dUt;
-                const double lpref = is_disp ? 0.0 : (is_ins ? lp_ins[N - base] : lp_del[N - base]);
-                const double arg = is_disp ? -(B.beta * dU)
-                                           : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
                 const bool ok = __builtin_amdgcn_readfirstlane((dU == dU && R.lnA < arg) ? 1 : 0) != 0;
                 const int two = R.two;
                 const int32_t cnt0 = R.cnt0, cnt1 = R.cnt1;
-                const int64_t n_old = N;
                 if (ok) {
                     int e = GCMC_OK;
                     if (is_ins) {
@@ -296,29 +307,22 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     okbits |= 1ull << k;
                     N += is_ins ? 1 : (type == GCMC_MOVE_DELETE ? -1 : 0);
                     U += dUp;
+                    Wvir += R.dWp;
                 }
-                if (trace && lane == 0) {
-                    gcmc_log r;
-                    r.type = type;
-                    r.index = is_ins ? (int32_t)n_old : (int32_t)idx;
-                    r.accepted = ok ? 1 : 0;
-                    r.flags = 0;
-                    r.dU_pair = dUp;
-                    r.dU_tail = dUt;
-                    r.x = is_disp ? R.p1[0] : R.p0[0];
-                    r.y = is_disp ? R.p1[1] : R.p0[1];
-                    r.z = is_disp ? R.p1[2] : R.p0[2];
-                    r.arg = arg;
-                    trace[(size_t)bi * n_moves + m + k] = r;
+                if (lane == 0) {
+                    after_n[k] = N;
+                    after_u[k] = U;
+                    after_w[k] = Wvir;
                 }
-                sum_n += (double)N;
-                sum_u += U + tk * (double)N * (double)N;
                 if (nmod > kWave - 2 || ntouch > kWave - 3) {
                     ++k;
                     break;
                 }
             }
-            // statistics of the k moves decided this round: lane j takes move j
+            // statistics of the k moves decided this round: lane j takes move j (the values
+            // lane 0 wrote above, seen by every lane of this wavefront)
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
             {
                 const bool mine = lane < k;
                 const SpecRec& S = recs[mine ? lane : 0];
@@ -336,6 +340,38 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     evals += S.evals;
                     incut += S.incut;
                 }
+                if (mine) {
+                    const double n = (double)after_n[lane];
+                    sum_n += n;
+                    sum_n2 += n * n;
+                    sum_u += after_u[lane] + tk * n * n;
+                    sum_w += after_w[lane];
+                }
+                // the per-move log, rebuilt from the evaluation, the decision and N after the move
+                if (trace && mine) {
+                    gcmc_log r;
+                    r.type = t;
+                    if (S.flags & 1) {
+                        r.index = -1; r.accepted = 0; r.flags = 1;
+                        r.dU_pair = 0.0; r.dU_tail = 0.0; r.x = r.y = r.z = 0.0; r.arg = 0.0; r.dW_pair = 0.0;
+                    } else {
+                        const int64_t dn = a ? (t == GCMC_MOVE_INSERT ? 1 : (t == GCMC_MOVE_DELETE ? -1 : 0)) : 0;
+                        const int64_t n_before = after_n[lane] - dn;
+                        double dUt;
+                        r.arg = spec_arg(B, t, S.dUp, n_before, base, lp_ins, lp_del, tk, dUt);
+                        r.index = t == GCMC_MOVE_INSERT ? (int32_t)n_before : (int32_t)S.idx;
+                        r.accepted = a ? 1 : 0;
+                        r.flags = 0;
+                        r.dU_pair = S.dUp;
+                        r.dU_tail = dUt;
+                        const bool dsp = t == GCMC_MOVE_DISPLACE;
+                        r.x = dsp ? S.p1[0] : S.p0[0];
+                        r.y = dsp ? S.p1[1] : S.p0[1];
+                        r.z = dsp ? S.p1[2] : S.p0[2];
+                        r.dW_pair = S.dWp;
+                    }
+                    trace[(size_t)bi * n_moves + m + lane] = r;
+                }
             }
             if (lane == 0) {
                 sh_state[0] = N;
@@ -343,6 +379,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 sh_state[2] = err;
                 sh_state[3] = err_move;
                 sh_u = U;
+                sh_w = Wvir;
                 sh_maxc = maxc;
                 sh_acc[0] = (acc1 + 1.0) / (att1 + 2.0);
                 sh_acc[1] = (acc2 + 1.0) / (att2 + 2.0);
@@ -354,6 +391,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         err = (int32_t)sh_state[2];
         err_move = sh_state[3];
         U = sh_u;
+        Wvir = sh_w;
         maxc = sh_maxc;
         a_ins = sh_acc[0];
         a_del = sh_acc[1];
@@ -365,10 +403,15 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
             evals += __shfl_xor(evals, off, kWave);
             incut += __shfl_xor(incut, off, kWave);
         }
+        sum_n = wave_sum_vec(sum_n);
+        sum_n2 = wave_sum_vec(sum_n2);
+        sum_u = wave_sum_vec(sum_u);
+        sum_w = wave_sum_vec(sum_w);
     }
     if (tid == 0) {
         st->n = N;
         st->u_pair = U;
+        st->w_pair = Wvir;
         st->maxcount = maxc;
         st->nsp[0] = N;
         st->counter = (int64_t)(ctr0 + (uint64_t)m);
@@ -376,25 +419,15 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
             st->error = err;
             st->error_move = err_move;
         }
-        if (stats) {
-            gcmc_stats o;
-            o.attempts[0] = (int64_t)att0; o.attempts[1] = (int64_t)att1; o.attempts[2] = (int64_t)att2;
-            o.accepts[0] = (int64_t)acc0; o.accepts[1] = (int64_t)acc1; o.accepts[2] = (int64_t)acc2;
-            o.n = N;
-            o.moves_done = m;
-            o.u_pair = U;
-            o.u_tail = tk * (double)N * (double)N;
-            o.sum_n = sum_n;
-            o.sum_u = sum_u;
-            o.error = st->error;
-            o.pad = 0;
-            o.error_move = st->error_move;
-            o.stencils = stencils;
-            o.candidates = cand;
-            o.pair_evals = evals;
-            o.in_cutoff = incut;
-            stats[bi] = o;
-        }
+        ChainSums L;
+        L.moves = m;
+        L.att[0] = (int64_t)att0; L.att[1] = (int64_t)att1; L.att[2] = (int64_t)att2;
+        L.acc[0] = (int64_t)acc0; L.acc[1] = (int64_t)acc1; L.acc[2] = (int64_t)acc2;
+        L.sum_n = sum_n;
+        L.sum_n2 = sum_n2;
+        L.sum_u = sum_u;
+        L.sum_w = sum_w;
+        finish_launch(B, st, L, N, U, Wvir, stencils, cand, evals, incut, stats ? stats + bi : nullptr);
     }
 }
 

@@ -16,7 +16,7 @@ namespace gcmc {
 constexpr int kSpecOwn = 8192;   // flattened candidates per wavefront (owner table bytes)
 
 struct SpecRec {
-    double dUp, lnA, u2, pad0;
+    double dUp, lnA, u2, dWp;   // pair energy change, ln A, pick draw, pair virial change
     double p0[3], p1[3];
     double4 rec, elast;
     int64_t idx;
@@ -183,7 +183,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     if (cnt0 > 0) elast = gload(B.ent + ((size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)));
     // ---- candidates
     const int32_t excl = (int32_t)idx;
-    double sa = 0.0, sb = 0.0;
+    double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
     int32_t n_cand = 0, n_eval = 0, n_in = 0;
     int64_t incut = 0;
     for (int base = 0; base < total; base += kWave * CR) {
@@ -204,17 +204,17 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
             if (ok[r] && meta_low(e[r].w) != excl) {
                 n_cand += 1;
                 if (type != GCMC_MOVE_DISPLACE) {
-                    sa += pair_energy_w<false>(B, p0, 0, e[r], incut);
+                    sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
                     n_eval += 1;
                 } else if (!two) {
-                    sa += pair_energy_w<false>(B, p0, 0, e[r], incut);
-                    sb += pair_energy_w<false>(B, p1, 0, e[r], incut);
+                    sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
+                    sb += pair_uw<false>(B, p1, 0, e[r], incut, wb);
                     n_eval += 2;
                 } else if (wsel[r]) {
-                    sb += pair_energy_w<false>(B, p1, 0, e[r], incut);
+                    sb += pair_uw<false>(B, p1, 0, e[r], incut, wb);
                     n_eval += 1;
                 } else {
-                    sa += pair_energy_w<false>(B, p0, 0, e[r], incut);
+                    sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
                     n_eval += 1;
                 }
             }
@@ -224,6 +224,9 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     const double ea = wave_sum_uniform(sa);
     const double eb = (type == GCMC_MOVE_DISPLACE) ? wave_sum_uniform(sb) : 0.0;
     const double dUp = (type == GCMC_MOVE_DISPLACE) ? (eb - ea) : ((type == GCMC_MOVE_INSERT) ? ea : -ea);
+    const double va = wave_sum_vec(wa);
+    const double vb = (type == GCMC_MOVE_DISPLACE) ? wave_sum_vec(wb) : 0.0;
+    const double dWp = (type == GCMC_MOVE_DISPLACE) ? (vb - va) : ((type == GCMC_MOVE_INSERT) ? va : -va);
     // work counters of this evaluation (wave sums)
     n_cand = wave_sum_i32_uniform(n_cand);
     n_eval = wave_sum_i32_uniform(n_eval);
@@ -231,6 +234,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     const double lnA = log(u.u[3]);
     if (lane == 0) {
         out->dUp = dUp;
+        out->dWp = dWp;
         out->lnA = lnA;
         out->u2 = u.u[2];
         out->type = type;

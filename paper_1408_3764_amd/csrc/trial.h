@@ -53,8 +53,6 @@ __device__ __forceinline__ double pair_energy(const DevBox& B, const double* p, 
     return lj_from_r2(r2, B.rc2, B.eps4[0], B.sig2[0]);
 }
 
-// Block-wide: ea = sum over candidates of u(p[0], .), eb = sum of u(p[1], .)
-// (eb only for displacements).  `red` holds 2*W doubles of LDS.
 // Per-lane work counters, summed over a whole launch.
 struct Work {
     int64_t cand = 0;   // candidate records read (valid slots)
@@ -74,16 +72,32 @@ __device__ __forceinline__ double pair_energy_w(const DevBox& B, const double* p
     return lj_from_r2(r2, B.rc2, B.eps4[0], B.sig2[0]);
 }
 
+// Pair energy and pair virial together (the virial added to `w`).
+template <bool MIX>
+__device__ __forceinline__ double pair_uw(const DevBox& B, const double* p, int sp, const double4& e, int64_t& incut,
+                                          double& w) {
+    const double r2 = dist2(B, p[0], p[1], p[2], e.x, e.y, e.z);
+    incut += (r2 < B.rc2) ? 1 : 0;
+    if (MIX) {
+        const int q = sp * B.ns + meta_species(e.w);
+        return lj_uw_from_r2(r2, B.rc2, B.eps4[q], B.sig2[q], w);
+    }
+    return lj_uw_from_r2(r2, B.rc2, B.eps4[0], B.sig2[0], w);
+}
+
+// Block-wide: ea = sum over candidates of u(p[0], .), eb = sum of u(p[1], .)
+// (eb only for displacements), va and vb the same sums of the pair virial.
+// `red` holds 4*W doubles of LDS.
 template <int W, int R, bool MIX>
 __device__ __forceinline__ void eval_trial(const DevBox& B, const uint32_t* tab, int lg, const Trial& T,
-                                           double& ea, double& eb, double* red, Work& wk) {
+                                           double& ea, double& eb, double& va, double& vb, double* red, Work& wk) {
     const int tid = threadIdx.x;
     const int NS = B.nstencil << lg;
     const int two = (T.npos == 2 && !T.same) ? 1 : 0;
     const int total = NS << two;
     const int gmask = (1 << lg) - 1;
     const int32_t excl = (int32_t)T.idx;
-    double sa = 0.0, sb = 0.0;
+    double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
     for (int base = 0; base < total; base += kWave * W * R) {
         double4 e[R];
         int32_t cnt[R], kk[R], which[R];
@@ -111,17 +125,17 @@ __device__ __forceinline__ void eval_trial(const DevBox& B, const uint32_t* tab,
             if (valid) {
                 wk.cand += 1;
                 if (T.npos == 1) {
-                    sa += pair_energy_w<MIX>(B, T.p[0], T.sp, e[r], wk.incut);
+                    sa += pair_uw<MIX>(B, T.p[0], T.sp, e[r], wk.incut, wa);
                     wk.evals += 1;
                 } else if (!two) {
-                    sa += pair_energy_w<MIX>(B, T.p[0], T.sp, e[r], wk.incut);
-                    sb += pair_energy_w<MIX>(B, T.p[1], T.sp, e[r], wk.incut);
+                    sa += pair_uw<MIX>(B, T.p[0], T.sp, e[r], wk.incut, wa);
+                    sb += pair_uw<MIX>(B, T.p[1], T.sp, e[r], wk.incut, wb);
                     wk.evals += 2;
                 } else if (which[r]) {
-                    sb += pair_energy_w<MIX>(B, T.p[1], T.sp, e[r], wk.incut);
+                    sb += pair_uw<MIX>(B, T.p[1], T.sp, e[r], wk.incut, wb);
                     wk.evals += 1;
                 } else {
-                    sa += pair_energy_w<MIX>(B, T.p[0], T.sp, e[r], wk.incut);
+                    sa += pair_uw<MIX>(B, T.p[0], T.sp, e[r], wk.incut, wa);
                     wk.evals += 1;
                 }
             }
@@ -129,25 +143,35 @@ __device__ __forceinline__ void eval_trial(const DevBox& B, const uint32_t* tab,
     }
     sa = wave_sum(sa);
     sb = wave_sum(sb);
+    wa = wave_sum(wa);
+    wb = wave_sum(wb);
     if (W == 1) {
         ea = sa;
         eb = sb;
+        va = wa;
+        vb = wb;
         return;
     }
     const int wv = tid / kWave;
     if ((tid & (kWave - 1)) == 0) {
-        red[2 * wv] = sa;
-        red[2 * wv + 1] = sb;
+        red[4 * wv] = sa;
+        red[4 * wv + 1] = sb;
+        red[4 * wv + 2] = wa;
+        red[4 * wv + 3] = wb;
     }
     __syncthreads();
-    double ta = 0.0, tb = 0.0;
+    double ta = 0.0, tb = 0.0, ua = 0.0, ub = 0.0;
 #pragma unroll
     for (int v = 0; v < W; ++v) {
-        ta += red[2 * v];
-        tb += red[2 * v + 1];
+        ta += red[4 * v];
+        tb += red[4 * v + 1];
+        ua += red[4 * v + 2];
+        ub += red[4 * v + 3];
     }
     ea = ta;
     eb = tb;
+    va = ua;
+    vb = ub;
 }
 
 // Remove the entry at `loc` of cell `c`: the cell's last entry takes its place
@@ -276,6 +300,7 @@ __device__ __forceinline__ DevBox hot_copy(const DevBox& G) {
     B.eps4[0] = unid(G.eps4[0]);
     B.sig2[0] = unid(G.sig2[0]);
     B.tailK[0] = unid(G.tailK[0]);
+    B.ptailK[0] = unid(G.ptailK[0]);
     B.seed = (uint64_t)uni64((int64_t)G.seed);
     B.box_id = (uint32_t)uni((int32_t)G.box_id);
     B.nstencil = uni(G.nstencil);

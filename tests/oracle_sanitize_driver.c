@@ -71,8 +71,9 @@ int main(void)
 
     /* the chain (single species), then gradients and virial of a two-species mixture */
     int64_t nc = n;
-    double U = tot[0] + tot[2];
-    int rc = oracle_chain(max_n, x, y, z, &nc, &U, &p, 99, 0, 0, moves, lg);
+    double U = tot[0] + tot[2], Wr = 0.0, pv[2];
+    oracle_position_virial(n, x, y, z, NULL, x[0], y[0], z[0], 0, 0, &p, pv);
+    int rc = oracle_chain(max_n, x, y, z, &nc, &U, &Wr, &p, 99, 0, 0, moves, lg);
     if (rc != 0)
         return 3;
     p.ns = 2;

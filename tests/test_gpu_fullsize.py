@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_1408_3764_amd import tune, workloads
-from tests.helpers import DU_REL, assert_du, compare_chain_logs
+from tests.helpers import DU_REL, assert_du, chain_parity, compare_chain_logs
 
 pytestmark = pytest.mark.gpu
 
@@ -41,23 +41,22 @@ def mixture():
 
 
 def _chain_check(wb, n_moves, shape=None):
+    """n_moves of the chain from the workload's configuration, move for move
+    against the oracle (a near-tie resyncs from the oracle's state), then the
+    final configuration bit for bit."""
     p = _params(wb)
     b = _box(wb, max_n=wb.n + n_moves + 1)
     b.set_launch(*(shape or tune.chain_shape(b)))
-    _, glog = b.step(n_moves, counter0=0, log=True)
-    opos, _, olog = oracle.chain(wb.pos, n_moves, p, seed=wb.seed, max_n=wb.n + n_moves + 1)
-    k = compare_chain_logs(glog, olog, wb.beta, wb.name)
-    if k == n_moves:
-        gpos, _ = b.particles()
-        assert np.array_equal(gpos, opos)
-    return b, k
+    r = chain_parity(b, oracle, wb.pos, p, wb.seed, n_moves, wb.beta, wb.n + n_moves + 1, wb.name, U0=0.0)
+    gpos, _ = b.particles()
+    assert np.array_equal(gpos, r["opos"])
+    return b, r
 
 
 @pytest.mark.parametrize("shape", [None, (4, 4), (16, 0), (8, -1)])
 def test_large_chain_matches_oracle(large, shape):
     """N=262,144, rc=3.0: 300 moves, bit-exact decisions (per-move and speculative kernels)."""
-    _, k = _chain_check(large, 300, shape)
-    assert k == 300
+    _chain_check(large, 300, shape)
 
 
 def test_large_deltas_cell_and_allpairs(large):
@@ -117,14 +116,14 @@ def test_large_total_energy_sampled(large):
 @pytest.mark.parametrize("shape", [None, (4, 4), (16, 0), (8, -1)])
 def test_slab_chain_matches_oracle(slab, shape):
     """The 1.5M-particle slab: 150 moves, bit-exact decisions (per-move and speculative kernels)."""
-    _, k = _chain_check(slab, 150, shape)
-    assert k == 150
+    _chain_check(slab, 150, shape)
 
 
 @pytest.mark.parametrize("bshape", [None, (4, 0)])
 def test_batched_sample_matches_oracle(bshape):
     """512 boxes advanced together in one launch (the per-move heuristic shape, and the
-    speculative 4x0 the benchmark's tuner picks); six boxes checked move for move."""
+    speculative 4x0 the benchmark's tuner picks); every 16th box, the largest and the
+    smallest checked against the oracle's chain (final configuration, acceptances)."""
     from paper_1408_3764_amd.box import Batch, Box
     wbs = workloads.batched()
     boxes = [Box.from_workload(w, max_n=w.n + 1001, box_id=k) for k, w in enumerate(wbs)]
@@ -135,7 +134,7 @@ def test_batched_sample_matches_oracle(bshape):
     stats = bt.step(1000, counter0=0)
     assert np.all(stats["error"] == 0) and np.all(stats["moves_done"] == 1000)
     ns = np.array([w.n for w in wbs])
-    pick = sorted({int(np.argmax(ns)), int(np.argmin(ns)), 0, 100, 255, 511})
+    pick = sorted({int(np.argmax(ns)), int(np.argmin(ns)), 511} | set(range(0, 512, 16)))
     for k in pick:
         w = wbs[k]
         p = _params(w)
@@ -156,13 +155,15 @@ def test_mixture_forward_backward(mixture):
     fw = b.total_energy(per_particle=True)
     bw = b.backward()
     rng = np.random.default_rng(8)
-    sample = rng.choice(w.n, 120, replace=False)
-    for i in sample:
-        e, s = oracle.position_energy(w.pos, p, w.pos[i], exclude=i, species=w.species,
-                                      point_species=int(w.species[i]))
-        assert abs(fw["e"][i] - e) <= 1e-10 * s
+    # the configured 4,096-particle subsample: the oracle's analytic gradient, and e_i on a quarter of it
+    sample = rng.choice(w.n, 4096, replace=False)
+    for q, i in enumerate(sample):
+        if q % 4 == 0:
+            e, s = oracle.position_energy(w.pos, p, w.pos[i], exclude=i, species=w.species,
+                                          point_species=int(w.species[i]))
+            assert abs(fw["e"][i] - e) <= 1e-10 * s
         g = oracle.particle_gradient(w.pos, i, p, species=w.species)
-        assert np.allclose(bw["grad"][i], g, rtol=1e-7, atol=1e-7 * max(1.0, np.abs(g).max()))
+        assert np.allclose(bw["grad"][i], g, rtol=1e-7, atol=1e-7 * max(1.0, np.abs(g).max())), i
     G = bw["grad"]
     assert np.abs(G.sum(axis=0)).max() <= 1e-9 * np.abs(G).sum()
     U = fw["U_pair"] + fw["U_tail"]
@@ -191,33 +192,47 @@ def test_mixture_forward_backward(mixture):
 
 
 def test_mixture_position_fd(mixture):
-    """dU/dr_i against central differences of the GPU's own energy change
-    (h = 1e-6), skipping particles with a neighbour within 10 h of the cutoff."""
+    """dU/dr_i against central differences of the energy (h = 1e-6) on the
+    configured 4,096-particle subsample, skipping particles with a neighbour
+    within 10 h of the cutoff (the truncation makes U jump there).  The
+    differences come from the GPU's energy changes of displacements by +-h;
+    at a sample of those points they are also checked against the oracle's."""
     from paper_1408_3764_amd.box import make_moves
     w = mixture
+    p = _params(w)
     b = _box(w)
     g = b.backward(params=False)["grad"]
     h = 1e-6
     rng = np.random.default_rng(21)
-    checked = 0
-    for i in rng.choice(w.n, 60, replace=False):
+    sample = rng.choice(w.n, 4096, replace=False)
+    keep = []
+    for i in sample:
         d = w.pos - w.pos[i]
         d -= w.L * np.round(d / w.L)
         r = np.sqrt((d * d).sum(axis=1))
-        if np.any(np.abs(r - w.rc) < 10 * h):
-            continue
-        pts = []
+        if not np.any(np.abs(r - w.rc) < 10 * h):
+            keep.append(int(i))
+    assert len(keep) >= 4000
+    pts, idx = [], []
+    for i in keep:
         for a in range(3):
             for sgn in (+1, -1):
                 q = w.pos[i].copy()
                 q[a] += sgn * h
                 pts.append(np.mod(q, w.L))
-        mv = make_moves([0] * 6, [i] * 6, pts)
-        dp, _ = b.delta_energy(mv)
-        fd = np.array([(dp[2 * a] - dp[2 * a + 1]) / (2 * h) for a in range(3)])
-        assert np.allclose(fd, g[i], rtol=1e-7, atol=1e-6), (i, fd, g[i])
-        checked += 1
-    assert checked >= 50
+                idx.append(i)
+    mv = make_moves([0] * len(idx), idx, pts)
+    dp, _ = b.delta_energy(mv)
+    fd = ((dp[0::2] - dp[1::2]) / (2 * h)).reshape(-1, 3)
+    for k, i in enumerate(keep):
+        assert np.allclose(fd[k], g[i], rtol=1e-7, atol=1e-6), (i, fd[k], g[i])
+    for k in range(0, len(keep), 256):
+        i = keep[k]
+        for j in range(6):
+            s_i = int(w.species[i])
+            en = oracle.position_energy(w.pos, p, pts[6 * k + j], exclude=i, species=w.species, point_species=s_i)
+            eo = oracle.position_energy(w.pos, p, w.pos[i], exclude=i, species=w.species, point_species=s_i)
+            assert abs(dp[6 * k + j] - (en[0] - eo[0])) <= DU_REL * (en[1] + eo[1])
 
 
 def test_autograd_function():
@@ -257,8 +272,8 @@ def test_graph_replay_continues_the_chain():
     be, bg = Batch(eager), Batch(graphed)
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
-    st = torch.zeros(len(wbs) * 144, dtype=torch.uint8, device="cuda")
     from paper_1408_3764_amd import _lib
+    st = torch.zeros(len(wbs) * _lib.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     bg.step(10, counter0=0)        # first call uploads descriptors outside the capture
     be.step(10, counter0=0)
     torch.cuda.synchronize()
@@ -278,3 +293,89 @@ def test_graph_replay_continues_the_chain():
             assert np.array_equal(a.particles()[0], c.particles()[0]), rep
         _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
     be.close(); bg.close()
+
+
+def test_checkpoint_inside_graph_replays_resumes_the_chain():
+    """Algorithm 1's periodic dumps with the chain on the device: a batch is
+    advanced by replays of a captured HIP graph; halfway through, every box is
+    exported (particles, running energy and virial, move counter, cumulative
+    statistics), imported into fresh boxes, and those continue with the device
+    counter.  The result equals the uninterrupted chain: configurations bit for
+    bit, checkpoints (counter, sums, acceptances) equal."""
+    from paper_1408_3764_amd import _lib
+    from paper_1408_3764_amd.box import Batch, Box
+    from paper_1408_3764_amd._lib import COUNTER_CONTINUE
+    wbs = [workloads.cubic_box(n, rho, 1.2, 2.5, 700 + k) for k, (n, rho) in
+           enumerate([(400, 0.5), (1200, 0.7), (200, 0.3)])]
+    mk = lambda: [Box.from_workload(w, max_n=w.n + 3001, box_id=k, seed=13) for k, w in enumerate(wbs)]
+    whole, first = mk(), mk()
+    for b in whole + first:
+        b.set_launch(4, 0)
+        b.total_energy()
+        b.virial()
+    bw, bf = Batch(whole), Batch(first)
+    st = torch.zeros(len(wbs) * _lib.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    bf.step(0, counter0=COUNTER_CONTINUE)   # descriptors uploaded outside the capture
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(2):
+            _lib.gcmc_batch_step(bf.handle, 100, COUNTER_CONTINUE, st, s)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+    # 600 moves per box: checkpoint, then resume in fresh boxes for 600 more
+    saved = [b.export_state() for b in first]
+    assert all(ck["counter"] == 600 and ck["moves"] == 600 for _, _, ck in saved)
+    resumed = [Box.from_workload(w, max_n=w.n + 3001, box_id=k, seed=13) for k, w in enumerate(wbs)]
+    for b, (pos, sp, ck) in zip(resumed, saved):
+        b.set_launch(4, 0)
+        b.import_state(pos, ck, species=sp)
+    br = Batch(resumed)
+    br.step(0, counter0=COUNTER_CONTINUE)
+    torch.cuda.synchronize()
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=s):
+        for _ in range(2):
+            _lib.gcmc_batch_step(br.handle, 100, COUNTER_CONTINUE, st, s)
+    for _ in range(3):
+        g2.replay()
+        torch.cuda.synchronize()
+    bw.step(1200, counter0=0)
+    torch.cuda.synchronize()
+    for a, c in zip(whole, resumed):
+        assert np.array_equal(a.particles()[0], c.particles()[0])
+        ca, cc = a.checkpoint(), c.checkpoint()
+        for k in ("n", "counter", "moves", "attempts", "accepts", "sum_n", "sum_n2"):
+            assert ca[k] == cc[k], k
+        for k in ("u_pair", "w_pair", "sum_u", "sum_w"):
+            assert cc[k] == pytest.approx(ca[k], rel=1e-12, abs=1e-9), k
+    for bt in (bw, bf, br):
+        bt.close()
+
+
+def test_autograd_backward_after_another_forward():
+    """Two forwards on one box, then backward on the first: the gradient is the
+    first configuration's (the saved inputs are put back into the box)."""
+    from paper_1408_3764_amd.autograd import lj_energy
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
+    w = workloads.random_box(300, 11.0, rc=3.0, seed=19, species_counts=[150, 150], eps=eps, sigma=sig)
+    b = _box(w)
+    pos1 = torch.tensor(w.pos, dtype=torch.float64, device="cuda", requires_grad=True)
+    E = torch.tensor(eps, dtype=torch.float64, device="cuda", requires_grad=True)
+    S = torch.tensor(sig, dtype=torch.float64, device="cuda", requires_grad=True)
+    U1 = lj_energy(pos1, E, S, b)
+    moved = np.mod(w.pos + 0.05, w.L)
+    pos2 = torch.tensor(moved, dtype=torch.float64, device="cuda", requires_grad=True)
+    U2 = lj_energy(pos2, E * 1.3, S, b)
+    U1.backward()
+    p = _params(w)
+    g, de, ds = oracle.gradients(w.pos, p, species=w.species)
+    assert np.allclose(pos1.grad.cpu().numpy(), g, rtol=1e-7, atol=1e-9 * np.abs(g).max())
+    assert np.allclose(E.grad.cpu().numpy(), de, rtol=1e-7)
+    assert np.allclose(S.grad.cpu().numpy(), ds, rtol=1e-7)
+    pos1.grad = None
+    U2.backward()
+    g2, _, _ = oracle.gradients(moved, oracle.make_params(w.L, w.rc, eps=eps * 1.3, sigma=sig), species=w.species)
+    assert np.allclose(pos2.grad.cpu().numpy(), g2, rtol=1e-7, atol=1e-9 * np.abs(g2).max())

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_1408_3764_amd import workloads
-from tests.helpers import assert_du, compare_chain_logs, DU_REL
+from tests.helpers import assert_du, chain_parity, compare_chain_logs, DU_REL
 
 pytestmark = pytest.mark.gpu
 
@@ -314,58 +314,132 @@ def test_total_energy_c1(c1):
 
 
 # ------------------------------------------------------------------ chain
+def _type_counts(olog):
+    att = [int((olog["type"] == t).sum()) for t in range(3)]
+    acc = [int(((olog["type"] == t) & (olog["accepted"] == 1)).sum()) for t in range(3)]
+    return att, acc
+
+
 def test_chain_parity_c1(c1):
     """1,000 moves of the small configuration: the GPU chain is the oracle's chain."""
     p = _params(c1)
-    t0 = oracle.total_energy(c1.pos, p)
-    opos, oU, olog = oracle.chain(c1.pos, c1.n_moves, p, seed=c1.seed, max_n=c1.n + 1001,
-                                  U0=t0["U_pair"] + t0["U_tail"])
     b = _box(c1, max_n=c1.n + 1001)
     b.total_energy()
-    stats, glog = b.step(c1.n_moves, counter0=0, log=True)
-    k = compare_chain_logs(glog, olog, c1.beta, "C1")
-    assert k == c1.n_moves
-    assert int(stats["error"]) == 0 and int(stats["moves_done"]) == c1.n_moves
+    r = chain_parity(b, oracle, c1.pos, p, c1.seed, c1.n_moves, c1.beta, c1.n + 1001, "C1")
+    stats, olog = r["stats"], r["olog"]
+    assert int(stats["error"]) == 0
     gpos, _ = b.particles()
-    assert np.array_equal(gpos, opos)
-    acc = [(olog["accepted"][olog["type"] == t] == 1).sum() for t in range(3)]
-    assert list(stats["accepts"]) == acc
-    assert stats["u_pair"] + stats["u_tail"] == pytest.approx(oU, rel=1e-9)
+    assert np.array_equal(gpos, r["opos"])
+    if not r["ties"]:
+        att, acc = _type_counts(olog)
+        assert int(stats["moves_done"]) == c1.n_moves
+        assert list(stats["attempts"]) == att and list(stats["accepts"]) == acc
+        assert stats["u_pair"] + stats["u_tail"] == pytest.approx(r["oU"], rel=1e-9)
+        assert acc[0] > 0 and acc[1] > 0 and acc[2] > 0
     # the running energy is the recomputed one
     U = b.total_energy()
     assert U["U_pair"] == pytest.approx(stats["u_pair"], rel=1e-9)
-    assert acc[0] > 0 and acc[1] > 0 and acc[2] > 0
+
+
+WORK = ("stencils", "candidates", "pair_evals", "in_cutoff")
 
 
 @pytest.mark.parametrize("width,rows", [(8, 0), (16, 0), (8, -1)])
 def test_speculative_chain_parity_c1(c1, width, rows):
     """Speculative rounds (W moves evaluated at once, committed in order) give the
-    sequential chain: 1,000 moves, same decisions and final configuration."""
+    sequential chain: 1,000 moves, same decisions and final configuration; their
+    attempt and acceptance counts are the oracle's, and their work counters (the
+    benchmark's algorithmic bytes come from them) equal the per-move kernel's."""
     p = _params(c1)
-    t0 = oracle.total_energy(c1.pos, p)
-    opos, oU, olog = oracle.chain(c1.pos, c1.n_moves, p, seed=c1.seed, max_n=c1.n + 1001,
-                                  U0=t0["U_pair"] + t0["U_tail"])
     b = _box(c1, max_n=c1.n + 1001)
     b.set_launch(width, rows)
     b.total_energy()
-    stats, glog = b.step(c1.n_moves, counter0=0, log=True)
-    assert compare_chain_logs(glog, olog, c1.beta, "speculative C1") == c1.n_moves
-    assert np.array_equal(b.particles()[0], opos)
-    assert stats["u_pair"] + stats["u_tail"] == pytest.approx(oU, rel=1e-9)
+    r = chain_parity(b, oracle, c1.pos, p, c1.seed, c1.n_moves, c1.beta, c1.n + 1001, "speculative C1")
+    stats = r["stats"]
+    assert np.array_equal(b.particles()[0], r["opos"])
     cell_of, count, ids = b.cells()
-    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(opos, c1.L, c1.rc))
+    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(r["opos"], c1.L, c1.rc))
+    if not r["ties"]:
+        assert stats["u_pair"] + stats["u_tail"] == pytest.approx(r["oU"], rel=1e-9)
+        att, acc = _type_counts(r["olog"])
+        assert list(stats["attempts"]) == att and list(stats["accepts"]) == acc
+        ref = _box(c1, max_n=c1.n + 1001)
+        ref.set_launch(4, 4)
+        rs, _ = ref.step(c1.n_moves, counter0=0)
+        for f in WORK:
+            assert int(stats[f]) == int(rs[f]), f
 
 
 def test_speculative_dense_conflicts():
     """A small dense box where most rounds end early (spatial conflicts, N changes)."""
     wb = workloads.random_box(300, 8.0, rc=2.5, T=1.2, mu=2.0, seed=77)
     p = _params(wb)
-    _, _, olog = oracle.chain(wb.pos, 3000, p, seed=wb.seed, max_n=wb.n + 3001)
+    ref = _box(wb, max_n=wb.n + 3001)
+    ref.set_launch(4, 4)
+    rs, _ = ref.step(3000, counter0=0)
     for width, rows in ((4, 0), (16, 0), (8, -1)):
         b = _box(wb, max_n=wb.n + 3001)
         b.set_launch(width, rows)
-        _, glog = b.step(3000, counter0=0, log=True)
-        assert compare_chain_logs(glog, olog, wb.beta, "dense speculative") == 3000
+        r = chain_parity(b, oracle, wb.pos, p, wb.seed, 3000, wb.beta, wb.n + 3001, "dense speculative")
+        if not r["ties"]:
+            att, acc = _type_counts(r["olog"])
+            assert list(r["stats"]["attempts"]) == att and list(r["stats"]["accepts"]) == acc
+            for f in WORK:
+                assert int(r["stats"][f]) == int(rs[f]), (width, rows, f)
+
+
+def _oracle_running(olog, n0, U0, W0):
+    """N, total energy and pair virial after every move of an oracle chain log."""
+    a = olog["accepted"] == 1
+    dn = np.where(a, np.where(olog["type"] == 1, 1, np.where(olog["type"] == 2, -1, 0)), 0)
+    N = n0 + np.cumsum(dn)
+    U = U0 + np.cumsum(np.where(a, olog["dU_pair"] + olog["dU_tail"], 0.0))
+    W = W0 + np.cumsum(np.where(a, olog["dW_pair"], 0.0))
+    return N.astype(np.float64), U, W
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (8, 0), (8, -1), "all_pairs"])
+def test_chain_averages_match_oracle(c1, shape):
+    """The averages the chain keeps on the GPU (Sec. 3.3.4: average energy and
+    pressure): sums of N, N^2, U and W after every move, against the same sums
+    over the oracle's log (W started from the oracle's total virial), and the
+    average pressure built from them; the running W after the launch equals the
+    virial recomputed from the final configuration.  Two launches: the box's
+    cumulative sums (its checkpoint) hold both."""
+    p = _params(c1)
+    b = _box(c1, max_n=c1.n + 2001)
+    if shape != "all_pairs":
+        b.set_launch(*shape)
+    ap = shape == "all_pairs"
+    moves = 300 if ap else 1000
+    b.total_energy()
+    v0 = b.virial()
+    t0 = oracle.total_energy(c1.pos, p)
+    W0 = oracle.virial(c1.pos, p)["W"]
+    assert v0["W"] == pytest.approx(W0, rel=1e-10)
+    U0 = t0["U_pair"] + t0["U_tail"]
+    opos, oU, oW, olog = oracle.chain(c1.pos, 2 * moves, p, seed=c1.seed, max_n=c1.n + 2001, U0=U0, W0=W0)
+    N, U, W = _oracle_running(olog, c1.n, U0, W0)
+    V = float(np.prod(c1.L))
+    kp = oracle.tail_pressure([1], p)
+    st1, _ = b.step(moves, counter0=0, all_pairs=ap)
+    st2, _ = b.step(moves, counter0=moves, all_pairs=ap)
+    for st, sl in ((st1, slice(0, moves)), (st2, slice(moves, 2 * moves))):
+        assert int(st["moves_done"]) == moves
+        assert st["sum_n"] == N[sl].sum()
+        assert st["sum_n2"] == pytest.approx((N[sl] ** 2).sum(), rel=1e-13)
+        assert st["sum_u"] == pytest.approx(U[sl].sum(), rel=1e-9)
+        assert st["sum_w"] == pytest.approx(W[sl].sum(), rel=1e-9)
+        assert st["avg_n"] == pytest.approx(N[sl].mean(), rel=1e-13)
+        assert st["avg_u"] == pytest.approx(U[sl].mean(), rel=1e-9)
+        P = N[sl] / (c1.beta * V) + W[sl] / (3 * V) + kp * N[sl] ** 2
+        assert st["avg_p"] == pytest.approx(P.mean(), rel=1e-9)
+    assert st2["w_pair"] == pytest.approx(oW, rel=1e-9)
+    assert st2["w_pair"] == pytest.approx(oracle.virial(opos, p)["W"], rel=1e-9)
+    _, _, ck = b.export_state()
+    assert ck["moves"] == 2 * moves and ck["counter"] == 2 * moves
+    assert ck["sum_n"] == N.sum() and ck["sum_w"] == pytest.approx(W.sum(), rel=1e-9)
+    assert ck["attempts"] == _type_counts(olog)[0] and ck["accepts"] == _type_counts(olog)[1]
 
 
 # the per-move kernel (the box's default launch) and the speculative kernel
@@ -421,17 +495,27 @@ def test_host_driven_commit_matches_chain():
     opos, _, olog = oracle.chain(wb.pos, 400, p, seed=44, max_n=700)
     from paper_1408_3764_amd.box import make_moves
     b = _box(wb, max_n=700)
-    cur = wb.pos.copy()
+    b.total_energy()
+    b.virial()
     for rec in olog:
         if not rec["accepted"]:
             continue
         t = int(rec["type"])
         mv = make_moves([t], [rec["index"]], [[rec["x"], rec["y"], rec["z"]]])
-        gp, _ = b.delta_energy(mv)
+        gp, _, gw = b.delta_energy(mv, virial=True)
         assert abs(gp[0] - rec["dU_pair"]) <= DU_REL * max(abs(rec["dU_pair"]), rec["sumabs"])
-        b.commit(mv[0], gp[0])
+        assert abs(gw[0] - rec["dW_pair"]) <= DU_REL * max(abs(rec["dW_pair"]), rec["wsumabs"])
+        b.commit(mv[0], gp[0], gw[0])
     gpos, _ = b.particles()
     assert np.array_equal(gpos, opos)
+    # running energy and virial of the commits = the recomputed ones
+    ck = b.checkpoint()
+    assert ck["u_pair"] == pytest.approx(oracle.total_energy(opos, p)["U_pair"], rel=1e-9)
+    assert ck["w_pair"] == pytest.approx(oracle.virial(opos, p)["W"], rel=1e-9)
+    # a commit without its virial change leaves the running virial undefined (NaN)
+    mv = make_moves([0], [0], [opos[0]])
+    b.commit(mv[0], 0.0)
+    assert math.isnan(b.checkpoint()["w_pair"])
     cell_of, _, _ = b.cells()
     assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(opos, wb.L, wb.rc))
 
@@ -457,27 +541,54 @@ def test_ideal_gas_on_gpu(shape):
     assert abs(ns.mean() - mean) < 5 * se + 0.01 * mean, (ns.mean(), mean)
 
 
-def test_speculative_matches_per_move_under_churn():
+def _cell_sets(cells, n_cells):
+    """Per cell the sorted particle ids (the cell list's content, slot order aside)."""
+    count, ids = cells[1], cells[2]
+    return [np.sort(ids[c, :count[c]]) for c in range(n_cells)]
+
+
+def _oracle_cell_sets(pos, L, rc, n_cells):
+    c = oracle.cell_of(pos, L, rc)
+    order = np.argsort(c, kind="stable")
+    out = [np.zeros(0, dtype=np.int64)] * n_cells
+    for cell in np.unique(c):
+        out[cell] = np.sort(order[c[order] == cell])
+    return out
+
+
+def _assert_cells_equal(got_sets, ref_sets):
+    assert len(got_sets) == len(ref_sets)
+    for c, (g, r) in enumerate(zip(got_sets, ref_sets)):
+        assert np.array_equal(g.astype(np.int64), np.asarray(r, dtype=np.int64)), c
+
+
+def test_speculative_matches_oracle_under_churn():
     """Ideal gas: every insertion and deletion changes N, and most are accepted.
-    The speculative kernel must leave exactly the per-move kernel's particle
-    array (order included) and cells after 20,000 moves."""
+    Every kernel's chain is the oracle's, move for move (index, decision), and
+    leaves the oracle's particle array (order included) and cell contents after
+    20,000 moves; the speculative kernels also leave the per-move kernel's slot
+    order within cells."""
     from paper_1408_3764_amd.box import Box
+    L = [6.0] * 3
+    p = oracle.make_params(L, 2.5, eps=0.0, beta=1 / 1.3, mu=-0.4)
+    opos, _, olog = oracle.chain(np.zeros((0, 3)), 20_000, p, seed=5, max_n=2000)
     out = []
     for shape in ((4, 4), (8, 0), (16, 0), (8, -1)):
-        b = Box(np.zeros((0, 3)), [6.0] * 3, 2.5, beta=1 / 1.3, mu=-0.4, eps=0.0, max_n=2000, seed=5,
-                cell_cap=64)
+        b = Box(np.zeros((0, 3)), L, 2.5, beta=1 / 1.3, mu=-0.4, eps=0.0, max_n=2000, seed=5, cell_cap=64)
         b.set_launch(*shape)
         st, log = b.step(20_000, counter0=0, log=True)
         assert int(st["error"]) == 0
-        out.append((b.particles()[0], b.cells(), log))
-    count0, ids0 = out[0][1][1], out[0][1][2]
+        assert compare_chain_logs(log, olog, 1 / 1.3, "churn %s" % (shape,)) == 20_000
+        pos = b.particles()[0]
+        assert np.array_equal(pos, opos), shape
+        cells = b.cells()
+        nc = len(cells[1])
+        _assert_cells_equal(_cell_sets(cells, nc), _oracle_cell_sets(opos, L, 2.5, nc))
+        out.append(cells)
+    count0, ids0 = out[0][1], out[0][2]
     valid = np.arange(ids0.shape[1])[None, :] < count0[:, None]
-    for pos, cells, log in out[1:]:
-        assert np.array_equal(pos, out[0][0])
-        assert np.array_equal(cells[1], count0)
+    for cells in out[1:]:
         assert np.array_equal(np.where(valid, cells[2], -1), np.where(valid, ids0, -1))
-        assert np.array_equal(log["accepted"], out[0][2]["accepted"])
-        assert np.array_equal(log["index"], out[0][2]["index"])
 
 
 def test_speculative_deletion_relabel_invalidates():
@@ -493,18 +604,24 @@ def test_speculative_deletion_relabel_invalidates():
     mu = math.log(400.0 / L ** 3)
     rng = np.random.default_rng(9)
     start = rng.random((400, 3)) * L
+    p = oracle.make_params([L] * 3, 2.5, eps=0.0, beta=beta, mu=mu)
+    opos, _, olog = oracle.chain(start, 150_000, p, seed=21, max_n=4000)
+    assert int(((olog["type"] == 2) & (olog["accepted"] == 1)).sum()) > 10_000
     out = []
     for shape in ((4, 4), (8, 0), (16, 0), (8, -1), (4, -1)):
         b = Box(start, [L] * 3, 2.5, beta=beta, mu=mu, eps=0.0, max_n=4000, seed=21, cell_cap=24)
         b.set_launch(*shape)
         st, _ = b.step(150_000, counter0=0)
         assert int(st["error"]) == 0
-        out.append((b.particles()[0], b.cells()))
-    count0, ids0 = out[0][1][1], out[0][1][2]
+        pos = b.particles()[0]
+        assert np.array_equal(pos, opos), shape
+        cells = b.cells()
+        nc = len(cells[1])
+        _assert_cells_equal(_cell_sets(cells, nc), _oracle_cell_sets(opos, [L] * 3, 2.5, nc))
+        out.append(cells)
+    count0, ids0 = out[0][1], out[0][2]
     valid = np.arange(ids0.shape[1])[None, :] < count0[:, None]
-    for pos, cells in out[1:]:
-        assert np.array_equal(pos, out[0][0])
-        assert np.array_equal(cells[1], count0)
+    for cells in out[1:]:
         assert np.array_equal(np.where(valid, cells[2], -1), np.where(valid, ids0, -1))
 
 
@@ -588,18 +705,47 @@ def test_invalid_arguments():
     assert e.value.code == 7
 
 
-def test_checkpoint_roundtrip(c1):
-    a = _box(c1, max_n=c1.n + 2001)
+@pytest.mark.parametrize("shape", KERNELS)
+def test_checkpoint_roundtrip(c1, shape):
+    """Export after 700 moves, import into a new box, continue both with the
+    device counter: the same chain, running energy and virial, and cumulative
+    statistics (the paper's periodic status dumps, Algorithm 1)."""
+    from paper_1408_3764_amd._lib import COUNTER_CONTINUE
+    a = _launch(_box(c1, max_n=c1.n + 2001), shape)
     a.total_energy()
+    a.virial()
     a.step(700, counter0=0)
-    pos, _ = a.particles()
-    n, u, err = a.export_state()
-    b = _box(c1, max_n=c1.n + 2001)
-    b.import_state(pos, u)
-    a.step(500, counter0=700)
-    b.step(500, counter0=700)
+    pos, sp, ck = a.export_state()
+    assert ck["counter"] == 700 and ck["moves"] == 700 and ck["n"] == len(pos)
+    b = _launch(_box(c1, max_n=c1.n + 2001), shape)
+    b.import_state(pos, ck, species=sp)
+    assert b.checkpoint() == ck
+    a.step(500, counter0=COUNTER_CONTINUE)
+    b.step(500, counter0=COUNTER_CONTINUE)
     assert np.array_equal(a.particles()[0], b.particles()[0])
-    assert a.export_state()[1] == pytest.approx(b.export_state()[1], rel=1e-11)
+    ca, cb = a.checkpoint(), b.checkpoint()
+    assert ca == cb
+    b.clear_averages()
+    cc = b.checkpoint()
+    assert cc["moves"] == 0 and cc["sum_n"] == 0.0 and cc["counter"] == 1200 and cc["u_pair"] == cb["u_pair"]
+
+
+def test_set_positions_checks_its_length(c1):
+    from paper_1408_3764_amd import _lib
+    b = _box(c1)
+    with pytest.raises(ValueError):
+        b.set_positions(c1.pos[:-1])
+    x = torch.zeros(c1.n - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.GcmcError) as e:
+        _lib.gcmc_set_positions(b.handle, x, x, x, c1.n - 1)
+    assert e.value.code == 1
+    # a valid call: the running energy and virial become NaN until recomputed
+    b.total_energy()
+    b.set_positions(c1.pos)
+    ck = b.checkpoint()
+    assert math.isnan(ck["u_pair"]) and math.isnan(ck["w_pair"])
+    b.total_energy()
+    assert not math.isnan(b.checkpoint()["u_pair"])
 
 
 # --------------------------------------------------------------- gradients

@@ -65,7 +65,7 @@ def test_rescale_grid_changes_and_chain_continues():
     L_new = np.array([19.5, 19.5, 19.5])
     got = b.rescale(L_new)
     assert b.info()["cell_m"] == [7, 7, 7]
-    assert b.export_state()[1] == got["U_pair"]
+    assert b.checkpoint()["u_pair"] == got["U_pair"]
     q = _scaled(wb.pos, wb.L, L_new)
     p = _params(wb, L_new)
     _, _, olog = oracle.chain(q, 300, p, seed=wb.seed, max_n=wb.n + 400, U0=0.0)

@@ -672,3 +672,49 @@ def test_virial_ideal_gas(orc):
     V = float(np.prod(b.L))
     assert v["W"] == 0.0 and v["P_tail"] == 0.0
     assert v["P"] == pytest.approx(100 * 1.7 / V, rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# The running virial of the chain (Sec. 3.1.2: an accepted move updates the
+# virial pressure with the energy)
+# --------------------------------------------------------------------------
+def test_position_virial_two_particle_closed_form(orc):
+    """w(r) = -r du/dr = 24 eps [2 (sigma/r)^12 - (sigma/r)^6] inside the cutoff, exact rationals."""
+    L = np.array([9.0, 9.0, 9.0])
+    p = orc.make_params(L, 2.5, eps=1.5, sigma=1.25)
+    for r in (1.0, 1.25, 1.5, 2.0, 2.49):
+        pos = np.array([[0.5, 4.0, 4.0], [0.5 + r, 4.0, 4.0]])
+        q = Fraction(5, 4) / Fraction(r)
+        want = float(24 * Fraction(3, 2) * (2 * q ** 12 - q ** 6))
+        got, _ = orc.position_virial(pos, p, pos[0], exclude=0)
+        assert got == pytest.approx(want, rel=1e-14, abs=1e-15)
+    # across the periodic boundary, and zero beyond the cutoff
+    pos = np.array([[0.2, 4.0, 4.0], [8.0, 4.0, 4.0]])
+    q = Fraction(5, 4) / Fraction(12, 10)
+    assert orc.position_virial(pos, p, pos[0], exclude=0)[0] == pytest.approx(
+        float(24 * Fraction(3, 2) * (2 * q ** 12 - q ** 6)), rel=1e-13)
+    pos = np.array([[0.5, 4.0, 4.0], [3.0, 4.0, 4.0]])
+    assert orc.position_virial(pos, p, pos[0], exclude=0)[0] == 0.0
+
+
+def test_position_virial_half_sum(orc):
+    b = workloads.random_box(150, 8.0, seed=61)
+    p = orc.make_params(b.L, 2.5)
+    s = sum(orc.position_virial(b.pos, p, b.pos[i], exclude=i)[0] for i in range(b.n))
+    assert s == pytest.approx(2 * orc.virial(b.pos, p)["W"], rel=1e-12)
+
+
+def test_chain_virial_bookkeeping(orc):
+    """The running W (starting from the total virial, plus every accepted move's
+    dW) equals the total virial of the final configuration; ideal-gas moves change
+    nothing."""
+    b = workloads.random_box(200, 8.0, seed=21, T=1.2)
+    p = orc.make_params(b.L, 2.5, beta=1.0 / 1.2, mu=-3.0)
+    W0 = orc.virial(b.pos, p)["W"]
+    pos, _, W, log = orc.chain(b.pos, 3000, p, seed=5, W0=W0)
+    assert W == pytest.approx(orc.virial(pos, p)["W"], rel=1e-10, abs=1e-9)
+    acc = log["accepted"] == 1
+    assert np.any(acc & (log["dW_pair"] != 0.0))
+    q = orc.make_params(b.L, 2.5, eps=0.0, mu=-1.0)
+    _, _, Wq, logq = orc.chain(b.pos, 500, q, seed=6, W0=0.0)
+    assert Wq == 0.0 and np.all(logq["dW_pair"] == 0.0)
