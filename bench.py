@@ -1,11 +1,15 @@
 """Benchmark: GCMC trial moves/s and pair evaluations/s on one MI355X.
 
 Workload (default): the two-phase slab, box a x a x 4a with a liquid slab at
-reduced density 0.8 inside vapour at 0.02, N ~ 1,500,000, rc = 2.5, T* = 0.85,
+reduced density 0.8 inside vapour at 0.02, N = 1,500,000, rc = 2.5, T* = 0.85,
 mu* = -3, the 1/3-1/3-1/3 move mix; one step = one persistent launch of
-200,000 moves of the chain.  Inputs are seeded synthetic configurations
-(random sequential addition with overlap rejection), resident in HBM before the
-timed region starts.
+200,000 moves of the chain, always from the initial 1.5M-particle
+configuration: before every step (outside its timed region) the box is put
+back into that state with the same move counter, so every timed step is the
+same 200,000 moves from N = 1,500,000 (the slab is not stationary at this
+state point: left running, it loses particles).  Inputs are seeded synthetic
+configurations (random sequential addition with overlap rejection), resident
+in HBM before the timed region starts.
 
 Prints one JSON line: moves/s (value), pair evaluations/s, the roofline of the
 chain kernel (algorithmic bytes per launch / average launch time, against the
@@ -283,17 +287,29 @@ def workload_by_name(name):
     return {"slab": workloads.slab, "large": workloads.large, "small": workloads.small}[name]()
 
 
-def run_cpu_baseline(wb, budget_s, max_moves):
-    """The oracle chain (all-pairs, one thread) on the first moves of the same chain."""
+def host_cores():
+    """CPU cores this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def run_cpu_baseline(wb, budget_s, max_moves, **mode):
+    """The oracle chain on the first moves of the same chain from the same
+    configuration, sized to about budget_s of CPU time (a 10-move probe sets the
+    sample size).  mode: the oracle's chain variant (threads=T: all pairs over
+    T threads; mode="cells": its cell list); default the plain all-pairs loop."""
     import oracle
     p = oracle.make_params(wb.L, wb.rc, beta=wb.beta, mu=wb.mu, lambda3=wb.lambda3, max_disp=wb.max_disp,
                            p_disp=wb.p_disp)
+    probe = 10 if mode.get("mode") != "cells" else 2000
     t = time.perf_counter()
-    oracle.chain(wb.pos, 10, p, seed=wb.seed, max_n=wb.n + 20)
-    per = max((time.perf_counter() - t) / 10, 1e-7)
+    oracle.chain(wb.pos, probe, p, seed=wb.seed, max_n=wb.n + probe + 1, **mode)
+    per = max((time.perf_counter() - t) / probe, 1e-7)
     n = int(max(20, min(max_moves, budget_s / per)))
     t = time.perf_counter()
-    _, _, olog = oracle.chain(wb.pos, n, p, seed=wb.seed, max_n=wb.n + n + 1)
+    _, _, olog = oracle.chain(wb.pos, n, p, seed=wb.seed, max_n=wb.n + n + 1, **mode)
     dt = time.perf_counter() - t
     return n, dt, olog
 
@@ -307,7 +323,7 @@ def main():
     ap.add_argument("--moves-per-step", type=int, default=0, help="0: the workload's move count")
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0, help="with --waves: rows per wavefront; 0 = speculative rounds, -1 = pipelined kernel")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time per CPU mode")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the small-box chain and the mixture forward/backward")
@@ -375,27 +391,38 @@ def main():
     info = box.info()
     nst = info["n_stencil"]
     U0 = box.total_energy()
+    box.virial()
     log("box: cells %s cap %d stencil %d, launch %dx%d, U0=%.6f" % (info["cell_m"], info["cell_cap"], nst,
                                                                      shape[0], shape[1], U0["U_pair"]))
-    from paper_1408_3764_amd._lib import COUNTER_CONTINUE
+    from paper_1408_3764_amd import _lib
+    from paper_1408_3764_amd._lib import COUNTER_CONTINUE, STATS_DTYPE
     stream = torch.cuda.current_stream()
+    # the state every step starts from: the initial configuration, its energy and virial,
+    # move counter c0 (the tuner leaves the box there)
+    snap = box.snapshot()
+    c0, n0 = snap[4]["counter"], snap[4]["n"]
+    st_dev = torch.zeros(STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     for w in range(args.warmup):
-        box.step(mps, counter0=COUNTER_CONTINUE)
+        box.restore(snap)
+        _lib.gcmc_step(box.handle, mps, c0, st_dev, None, box.stream)
     torch.cuda.synchronize()
-    evs = []
-    stats_all = []
-    t0 = time.perf_counter()
+    evs, walls, stats_all = [], [], []
     for k in range(args.steps):
+        box.restore(snap)            # outside the timed region: N = n0 again, same counters
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         e0.record(stream)
-        st, _ = box.step(mps, counter0=COUNTER_CONTINUE)
+        _lib.gcmc_step(box.handle, mps, c0, st_dev, None, box.stream)
         e1.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
         evs.append((e0, e1))
-        stats_all.append(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
+        stats_all.append(np.frombuffer(st_dev.cpu().numpy().tobytes(), dtype=STATS_DTYPE)[0].copy())
+        log("step %d: N %d -> %d, %.2f ms, %.1f candidates/move" % (
+            k, n0, int(stats_all[-1]["n"]), 1e3 * walls[-1], int(stats_all[-1]["candidates"]) / mps))
+    wall = sum(walls)
     for st in stats_all:
         if int(st["error"]) != 0:
             raise SystemExit("chain error %d at move %d" % (int(st["error"]), int(st["error_move"])))
@@ -427,9 +454,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded random sequential addition, overlap rejection at 0.8 sigma)",
-        "config": {"workload": wb.name, "n": wb.n, "moves_per_step": mps, "rc": wb.rc, "T": 1.0 / wb.beta,
+        "config": {"workload": wb.name, "n": n0, "moves_per_step": mps, "rc": wb.rc, "T": 1.0 / wb.beta,
                    "mu": wb.mu, "cells": info["cell_m"], "cell_cap": info["cell_cap"], "stencil_cells": nst,
-                   "launch": {"waves": shape[0], "rows": shape[1]}},
+                   "launch": {"waves": shape[0], "rows": shape[1]},
+                   "every_step_starts_from": "the initial configuration (N = %d, move counter %d)" % (n0, c0)},
+        "n_start_per_step": [n0] * args.steps,
+        "n_end_per_step": [int(s["n"]) for s in stats_all],
+        "averages_last_step": {"n": float(stats_all[-1]["avg_n"]), "u": float(stats_all[-1]["avg_u"]),
+                               "p": float(stats_all[-1]["avg_p"])},
         "pair_evals_per_s": pair_evals / wall,
         "in_cutoff_pairs_per_s": incut / wall,
         "candidates_per_move": cand / moves,
@@ -568,6 +600,7 @@ def main():
         out.update(extra_configs(Box, tune, stream))
 
     if not args.no_cpu:
+        cores = host_cores()
         n_cpu, dt, olog = run_cpu_baseline(wb, args.cpu_budget, 20000)
         # the same moves on the GPU, for a parity check of the timed chain
         pb = Box.from_workload(wb, max_n=wb.n + n_cpu + 1, cell_m=cell_m)
@@ -575,11 +608,31 @@ def main():
         _, glog = pb.step(n_cpu, counter0=0, log=True)
         same = bool(np.array_equal(glog["type"], olog["type"]) and np.array_equal(glog["accepted"], olog["accepted"])
                     and np.array_equal(glog["index"], olog["index"]))
-        out["cpu_baseline"] = {"value": n_cpu / dt, "unit": "moves/s", "cores": 1, "kind": "oracle",
-                               "sample": "first %d moves of the same chain from the same initial configuration "
-                                         "(all-pairs FP64 oracle, one thread, %.1fs)" % (n_cpu, dt),
-                               "gpu_chain_matches_on_sample": same}
         pb.close()
+        n_mt, dt_mt, _ = run_cpu_baseline(wb, args.cpu_budget, 20000, threads=cores)
+        n_cl, dt_cl, _ = run_cpu_baseline(wb, args.cpu_budget, mps, mode="cells")
+        out["cpu_baseline"] = {
+            "value": n_cpu / dt, "unit": "moves/s", "cores": 1, "kind": "oracle", "host_cores": cores,
+            "sample": "first %d moves of the same chain from the same initial configuration "
+                      "(all-pairs FP64 oracle, one thread, %.1fs)" % (n_cpu, dt),
+            "gpu_chain_matches_on_sample": same,
+            "modes": {
+                "all_pairs_1_thread": {"value": n_cpu / dt, "unit": "moves/s", "cores": 1, "moves": n_cpu,
+                                       "seconds": dt},
+                "all_pairs_all_cores": {"value": n_mt / dt_mt, "unit": "moves/s", "cores": cores, "moves": n_mt,
+                                        "seconds": dt_mt,
+                                        "note": "each position's sums split into contiguous particle ranges, "
+                                                "one per thread, partials added in range order"},
+                "cell_list_1_thread": {"value": n_cl / dt_cl, "unit": "moves/s", "cores": 1, "moves": n_cl,
+                                       "seconds": dt_cl,
+                                       "note": "the oracle's host cell list (linked cells on the paper's grid, "
+                                               "27-cell stencils), the best CPU algorithm here; the first %d "
+                                               "moves of the timed step" % n_cl},
+            },
+            "gpu_vs_cpu_cell_list": (moves / wall) / (n_cl / dt_cl),
+        }
+        log("CPU oracle: %.1f moves/s (1 thread, all pairs), %.1f (%d threads), %.0f (cell list, 1 thread)" % (
+            n_cpu / dt, n_mt / dt_mt, cores, n_cl / dt_cl))
     print(json.dumps(out), flush=True)
 
 

@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIB):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
@@ -93,6 +93,10 @@ def lib():
         L.oracle_accept.restype = C.c_int32
         L.oracle_chain.argtypes = [C.c_int64, dp, dp, dp, lp, dp, dp, pp, C.c_uint64, C.c_uint32, C.c_uint64,
                                    C.c_int64, C.c_void_p]
+        for name in ("oracle_chain_mt", "oracle_chain_cells"):
+            f = getattr(L, name)
+            f.argtypes = L.oracle_chain.argtypes + ([C.c_int32] if name == "oracle_chain_mt" else [])
+            f.restype = C.c_int
         L.oracle_position_virial.argtypes = [C.c_int64, dp, dp, dp, ip, C.c_double, C.c_double, C.c_double,
                                              C.c_int32, C.c_int64, pp, dp]
         L.oracle_chain.restype = C.c_int
@@ -233,9 +237,12 @@ class ChainError(RuntimeError):
     pass
 
 
-def chain(pos, n_moves, p, seed, box=0, counter0=0, max_n=None, U0=0.0, W0=None):
+def chain(pos, n_moves, p, seed, box=0, counter0=0, max_n=None, U0=0.0, W0=None, mode="allpairs", threads=1):
     """Run the serial GCMC chain.  Returns (pos[n], U, log array), or with W0
-    given (the starting pair virial) (pos[n], U, W, log array)."""
+    given (the starting pair virial) (pos[n], U, W, log array).  mode
+    "allpairs" (threads > 1: each position's sums split over that many
+    threads) or "cells" (sums over the stencil cells of a cell list): the
+    CPU-baseline variants; the parity tests use the default."""
     n0 = pos.shape[0]
     max_n = max_n if max_n is not None else n0 + n_moves + 1
     x = np.zeros(max_n); y = np.zeros(max_n); z = np.zeros(max_n)
@@ -244,8 +251,14 @@ def chain(pos, n_moves, p, seed, box=0, counter0=0, max_n=None, U0=0.0, W0=None)
     U = C.c_double(U0)
     W = C.c_double(0.0 if W0 is None else W0)
     log = np.zeros(int(n_moves), dtype=LOG_DTYPE)
-    rc = lib().oracle_chain(int(max_n), _d(x), _d(y), _d(z), C.byref(n), C.byref(U), C.byref(W), C.byref(p),
-                            int(seed), int(box), int(counter0), int(n_moves), log.ctypes.data_as(C.c_void_p))
+    args = [int(max_n), _d(x), _d(y), _d(z), C.byref(n), C.byref(U), C.byref(W), C.byref(p), int(seed), int(box),
+            int(counter0), int(n_moves), log.ctypes.data_as(C.c_void_p)]
+    if mode == "cells":
+        rc = lib().oracle_chain_cells(*args)
+    elif threads > 1:
+        rc = lib().oracle_chain_mt(*args, int(threads))
+    else:
+        rc = lib().oracle_chain(*args)
     if rc != 0:
         raise ChainError("oracle_chain returned %d" % rc)
     k = n.value

@@ -358,9 +358,26 @@ static double wrap_coord(double x, double L)
 /* Returns 0, or -1 if an insertion would exceed max_n (an error, never a   */
 /* rejection), or -2 for an unsupported parameter set.                      */
 /* ------------------------------------------------------------------------ */
-int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, double* U_io, double* W_io,
-                 const oracle_params* p, uint64_t seed, uint32_t box, uint64_t counter0, int64_t n_moves,
-                 oracle_log* log_out)
+struct cell_list;
+/* How the chain sums a position's pair energy and virial: over all particles
+ * (threads == 1: the plain loops of oracle_position_energy/virial; threads >
+ * 1: the same terms in `threads` contiguous index ranges summed at once and
+ * combined in range order), or over the stencil cells of a cell list. */
+typedef struct {
+    int threads;
+    struct cell_list* cells;
+} sum_mode;
+
+static void position_sums(const sum_mode* md, int64_t n, const double* x, const double* y, const double* z,
+                          double px, double py, double pz, int64_t exclude, const oracle_params* p, double e[2],
+                          double w[2]);
+static void cells_insert(struct cell_list* cl, int64_t i, double px, double py, double pz);
+static void cells_remove(struct cell_list* cl, int64_t i);
+static void cells_relabel(struct cell_list* cl, int64_t from, int64_t to);
+
+static int chain_run(const sum_mode* md, int64_t max_n, double* x, double* y, double* z, int64_t* n_io,
+                     double* U_io, double* W_io, const oracle_params* p, uint64_t seed, uint32_t box,
+                     uint64_t counter0, int64_t n_moves, oracle_log* log_out)
 {
     if (p->ns != 1)
         return -2;
@@ -402,10 +419,8 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
             ny = wrap_coord(y[i] + p->max_disp * (2.0 * u[5] - 1.0), p->L[1]);
             nz = wrap_coord(z[i] + p->max_disp * (2.0 * u[6] - 1.0), p->L[2]);
             double eo[2], en[2], wo[2], wn[2];
-            oracle_position_energy(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, eo);
-            oracle_position_energy(n, x, y, z, NULL, nx, ny, nz, 0, i, p, en);
-            oracle_position_virial(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, wo);
-            oracle_position_virial(n, x, y, z, NULL, nx, ny, nz, 0, i, p, wn);
+            position_sums(md, n, x, y, z, x[i], y[i], z[i], i, p, eo, wo);
+            position_sums(md, n, x, y, z, nx, ny, nz, i, p, en, wn);
             dUp = en[0] - eo[0];
             sabs = en[1] + eo[1];
             dWp = wn[0] - wo[0];
@@ -416,8 +431,7 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
             ny = wrap_coord(p->L[1] * u[5], p->L[1]);
             nz = wrap_coord(p->L[2] * u[6], p->L[2]);
             double en[2], wn[2];
-            oracle_position_energy(n, x, y, z, NULL, nx, ny, nz, 0, -1, p, en);
-            oracle_position_virial(n, x, y, z, NULL, nx, ny, nz, 0, -1, p, wn);
+            position_sums(md, n, x, y, z, nx, ny, nz, -1, p, en, wn);
             int64_t counts[1] = {n};
             dUp = en[0];
             sabs = en[1];
@@ -428,8 +442,7 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
         } else {
             nx = x[i]; ny = y[i]; nz = z[i];
             double eo[2], wo[2];
-            oracle_position_energy(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, eo);
-            oracle_position_virial(n, x, y, z, NULL, x[i], y[i], z[i], 0, i, p, wo);
+            position_sums(md, n, x, y, z, x[i], y[i], z[i], i, p, eo, wo);
             int64_t counts[1] = {n};
             dUp = -eo[0];
             sabs = eo[1];
@@ -450,7 +463,11 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
         rec.arg = arg;
         if (acc) {
             if (type == 0) {
+                if (md->cells)
+                    cells_remove(md->cells, i);
                 x[i] = nx; y[i] = ny; z[i] = nz;
+                if (md->cells)
+                    cells_insert(md->cells, i, nx, ny, nz);
             } else if (type == 1) {
                 if (n >= max_n) {
                     *n_io = n;
@@ -460,8 +477,15 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
                     return -1;
                 }
                 x[n] = nx; y[n] = ny; z[n] = nz;
+                if (md->cells)
+                    cells_insert(md->cells, n, nx, ny, nz);
                 n += 1;
             } else {
+                if (md->cells) {
+                    cells_remove(md->cells, i);
+                    if (i != n - 1)
+                        cells_relabel(md->cells, n - 1, i);
+                }
                 x[i] = x[n - 1]; y[i] = y[n - 1]; z[i] = z[n - 1];
                 n -= 1;
             }
@@ -477,6 +501,199 @@ int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, 
     if (W_io)
         *W_io = W;
     return 0;
+}
+
+int oracle_chain(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, double* U_io, double* W_io,
+                 const oracle_params* p, uint64_t seed, uint32_t box, uint64_t counter0, int64_t n_moves,
+                 oracle_log* log_out)
+{
+    sum_mode md = {1, NULL};
+    return chain_run(&md, max_n, x, y, z, n_io, U_io, W_io, p, seed, box, counter0, n_moves, log_out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same chain for the CPU baselines of the measurements (not used by    */
+/* the parity tests): all pairs on several threads, and a cell list.        */
+/* ------------------------------------------------------------------------ */
+#define ORACLE_MAX_THREADS 256
+
+static void range_sums(int64_t j0, int64_t j1, const double* x, const double* y, const double* z, double px,
+                       double py, double pz, int64_t exclude, const oracle_params* p, nsum acc[4])
+{
+    for (int64_t j = j0; j < j1; ++j) {
+        if (j == exclude)
+            continue;
+        double r2 = oracle_dist2(p->L, px, py, pz, x[j], y[j], z[j]);
+        double u = pair_u(p, 0, 0, r2);
+        double w = pair_w(p, 0, 0, r2);
+        nsum_add(&acc[0], u);
+        nsum_add(&acc[1], fabs(u));
+        nsum_add(&acc[2], w);
+        nsum_add(&acc[3], fabs(w));
+    }
+}
+
+/* The plain cell list of Sec. 3.2 on the host: each cell a doubly linked list
+ * of particle indices (O(1) insertion and removal), the paper's grid
+ * (M = max(3, floor(L / rc)), stencil of 2k + 1 cells per axis, whole axis
+ * when that covers it). */
+typedef struct cell_list {
+    int32_t M[3], k[3], span[3];
+    double invS[3];
+    int64_t ncells;
+    int64_t* head;
+    int64_t* next;
+    int64_t* prev;
+    int64_t* cell;
+} cell_list;
+
+static int32_t axis_cell(double x, double invS, int32_t M);
+
+static void cells_insert(cell_list* cl, int64_t i, double px, double py, double pz)
+{
+    int64_t c = ((int64_t)axis_cell(pz, cl->invS[2], cl->M[2]) * cl->M[1] + axis_cell(py, cl->invS[1], cl->M[1])) *
+                    cl->M[0] + axis_cell(px, cl->invS[0], cl->M[0]);
+    cl->cell[i] = c;
+    cl->prev[i] = -1;
+    cl->next[i] = cl->head[c];
+    if (cl->head[c] >= 0)
+        cl->prev[cl->head[c]] = i;
+    cl->head[c] = i;
+}
+
+static void cells_remove(cell_list* cl, int64_t i)
+{
+    int64_t c = cl->cell[i];
+    if (cl->prev[i] >= 0)
+        cl->next[cl->prev[i]] = cl->next[i];
+    else
+        cl->head[c] = cl->next[i];
+    if (cl->next[i] >= 0)
+        cl->prev[cl->next[i]] = cl->prev[i];
+}
+
+/* Particle `from` takes index `to` (which is in no cell). */
+static void cells_relabel(cell_list* cl, int64_t from, int64_t to)
+{
+    int64_t c = cl->cell[from];
+    cl->cell[to] = c;
+    cl->prev[to] = cl->prev[from];
+    cl->next[to] = cl->next[from];
+    if (cl->prev[to] >= 0)
+        cl->next[cl->prev[to]] = to;
+    else
+        cl->head[c] = to;
+    if (cl->next[to] >= 0)
+        cl->prev[cl->next[to]] = to;
+}
+
+static void cell_sums(const cell_list* cl, const double* x, const double* y, const double* z, double px,
+                      double py, double pz, int64_t exclude, const oracle_params* p, nsum acc[4])
+{
+    int32_t c0[3] = {axis_cell(px, cl->invS[0], cl->M[0]), axis_cell(py, cl->invS[1], cl->M[1]),
+                     axis_cell(pz, cl->invS[2], cl->M[2])};
+    int32_t lo[3], cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        int full = cl->span[a] == cl->M[a];
+        lo[a] = full ? 0 : c0[a] - cl->k[a];
+        cnt[a] = full ? cl->M[a] : 2 * cl->k[a] + 1;
+    }
+    for (int32_t tz = 0; tz < cnt[2]; ++tz) {
+        int32_t cz = ((lo[2] + tz) % cl->M[2] + cl->M[2]) % cl->M[2];
+        for (int32_t ty = 0; ty < cnt[1]; ++ty) {
+            int32_t cy = ((lo[1] + ty) % cl->M[1] + cl->M[1]) % cl->M[1];
+            for (int32_t tx = 0; tx < cnt[0]; ++tx) {
+                int32_t cx = ((lo[0] + tx) % cl->M[0] + cl->M[0]) % cl->M[0];
+                for (int64_t j = cl->head[((int64_t)cz * cl->M[1] + cy) * cl->M[0] + cx]; j >= 0; j = cl->next[j]) {
+                    if (j == exclude)
+                        continue;
+                    double r2 = oracle_dist2(p->L, px, py, pz, x[j], y[j], z[j]);
+                    double u = pair_u(p, 0, 0, r2);
+                    double w = pair_w(p, 0, 0, r2);
+                    nsum_add(&acc[0], u);
+                    nsum_add(&acc[1], fabs(u));
+                    nsum_add(&acc[2], w);
+                    nsum_add(&acc[3], fabs(w));
+                }
+            }
+        }
+    }
+}
+
+static void position_sums(const sum_mode* md, int64_t n, const double* x, const double* y, const double* z,
+                          double px, double py, double pz, int64_t exclude, const oracle_params* p, double e[2],
+                          double w[2])
+{
+    if (!md->cells && md->threads <= 1) {
+        oracle_position_energy(n, x, y, z, NULL, px, py, pz, 0, exclude, p, e);
+        oracle_position_virial(n, x, y, z, NULL, px, py, pz, 0, exclude, p, w);
+        return;
+    }
+    nsum tot[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    if (md->cells) {
+        cell_sums(md->cells, x, y, z, px, py, pz, exclude, p, tot);
+    } else {
+        int T = md->threads > ORACLE_MAX_THREADS ? ORACLE_MAX_THREADS : md->threads;
+        nsum part[ORACLE_MAX_THREADS][4];
+#pragma omp parallel for num_threads(T) schedule(static, 1)
+        for (int t = 0; t < T; ++t) {
+            for (int q = 0; q < 4; ++q)
+                part[t][q].s = part[t][q].c = 0.0;
+            range_sums(n * t / T, n * (t + 1) / T, x, y, z, px, py, pz, exclude, p, part[t]);
+        }
+        for (int t = 0; t < T; ++t)
+            for (int q = 0; q < 4; ++q) {
+                nsum_add(&tot[q], part[t][q].s);
+                nsum_add(&tot[q], part[t][q].c);
+            }
+    }
+    e[0] = nsum_get(&tot[0]);
+    e[1] = nsum_get(&tot[1]);
+    w[0] = nsum_get(&tot[2]);
+    w[1] = nsum_get(&tot[3]);
+}
+
+/* oracle_chain with every position's sums split over `threads` threads. */
+int oracle_chain_mt(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, double* U_io, double* W_io,
+                    const oracle_params* p, uint64_t seed, uint32_t box, uint64_t counter0, int64_t n_moves,
+                    oracle_log* log_out, int32_t threads)
+{
+    sum_mode md = {threads < 1 ? 1 : threads, NULL};
+    return chain_run(&md, max_n, x, y, z, n_io, U_io, W_io, p, seed, box, counter0, n_moves, log_out);
+}
+
+void oracle_grid(const double L[3], double rc, const int32_t req_m[3], int32_t M[3], double invS[3],
+                 int32_t k[3], int32_t span[3]);
+
+/* oracle_chain with every position's sums taken over its stencil cells (the
+ * paper's grid), the cell list kept current move by move (Sec. 3.2.5).
+ * Returns -3 if the cell list cannot be allocated. */
+int oracle_chain_cells(int64_t max_n, double* x, double* y, double* z, int64_t* n_io, double* U_io, double* W_io,
+                       const oracle_params* p, uint64_t seed, uint32_t box, uint64_t counter0, int64_t n_moves,
+                       oracle_log* log_out)
+{
+    cell_list cl;
+    memset(&cl, 0, sizeof cl);
+    oracle_grid(p->L, p->rc, NULL, cl.M, cl.invS, cl.k, cl.span);
+    cl.ncells = (int64_t)cl.M[0] * cl.M[1] * cl.M[2];
+    cl.head = malloc(sizeof(int64_t) * (size_t)cl.ncells);
+    cl.next = malloc(sizeof(int64_t) * (size_t)(max_n > 0 ? max_n : 1));
+    cl.prev = malloc(sizeof(int64_t) * (size_t)(max_n > 0 ? max_n : 1));
+    cl.cell = malloc(sizeof(int64_t) * (size_t)(max_n > 0 ? max_n : 1));
+    int rc = -3;
+    if (cl.head && cl.next && cl.prev && cl.cell) {
+        for (int64_t c = 0; c < cl.ncells; ++c)
+            cl.head[c] = -1;
+        for (int64_t i = *n_io - 1; i >= 0; --i)
+            cells_insert(&cl, i, x[i], y[i], z[i]);
+        sum_mode md = {1, &cl};
+        rc = chain_run(&md, max_n, x, y, z, n_io, U_io, W_io, p, seed, box, counter0, n_moves, log_out);
+    }
+    free(cl.head);
+    free(cl.next);
+    free(cl.prev);
+    free(cl.cell);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

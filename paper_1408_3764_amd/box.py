@@ -231,6 +231,21 @@ class Box:
         _lib.gcmc_import_state(self.handle, x, y, z, sp, checkpoint_struct(ck), self.stream)
         self.version += 1
 
+    def snapshot(self):
+        """A checkpoint held in device memory: (x, y, z, species, checkpoint dict)."""
+        cap = max(self.max_n, 1)
+        x = torch.empty(cap, dtype=torch.float64, device=self.device)
+        y, z = torch.empty_like(x), torch.empty_like(x)
+        sp = torch.empty(cap, dtype=torch.int32, device=self.device)
+        ck = _lib.gcmc_export_state(self.handle, x, y, z, sp, cap, self.stream)
+        return x, y, z, sp, checkpoint_dict(ck)
+
+    def restore(self, snap):
+        """Put a snapshot back (positions, energies, move counter, sums)."""
+        x, y, z, sp, ck = snap
+        _lib.gcmc_import_state(self.handle, x, y, z, sp, checkpoint_struct(ck), self.stream)
+        self.version += 1
+
     def clear_averages(self):
         _lib.gcmc_clear_averages(self.handle, self.stream)
 

@@ -77,20 +77,27 @@ def _cache_path():
 
 
 def autotune_live(box, n_moves=3000, shapes=None):
-    """Time each launch shape on the box itself, continuing its chain (the
-    device move counter), and leave the fastest set.  Returns (shape, timings)."""
+    """Time each launch shape on the box itself and leave the fastest set.
+    Every shape runs identical work: the box's state is snapshotted first and
+    put back before each shape's warm-up and before its timed launch, so each
+    timing covers the same n_moves moves (same counters) from the same
+    configuration; afterwards the box is back in that state.  Returns (shape,
+    timings)."""
     import torch
-    from ._lib import COUNTER_CONTINUE
     if shapes is None:
         shapes = SHAPES + (SPEC_SHAPES if spec_supported(box) else []) + (ASYNC_SHAPES if async_supported(box) else [])
+    snap = box.snapshot()
+    c0 = snap[4]["counter"]
     timings = {}
     best = None
     for w, r in shapes:
         box.set_launch(w, r)
-        box.step(300, counter0=COUNTER_CONTINUE)
+        box.restore(snap)
+        box.step(min(300, n_moves), counter0=c0)
+        box.restore(snap)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        st, _ = box.step(n_moves, counter0=COUNTER_CONTINUE)
+        st, _ = box.step(n_moves, counter0=c0)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         if int(st["error"]) != 0:
@@ -98,6 +105,7 @@ def autotune_live(box, n_moves=3000, shapes=None):
         timings["%dx%d" % (w, r)] = dt
         if best is None or dt < best[0]:
             best = (dt, (w, r))
+    box.restore(snap)
     box.set_launch(*best[1])
     return best[1], timings
 
@@ -107,9 +115,9 @@ def autotune_cells(make_box, factors=(1, 2), n_moves=3000):
     cell_m None gives the paper's cells (side >= rc, 27-cell stencils); factor
     f > 1 asks for f times as many cells per axis (microcells, whose stencils
     drop the cells beyond the cutoff).  Every launch shape that applies is
-    timed on each box with autotune_live (its chain continues on the device
-    counter); the fastest box is returned open with its shape set and the
-    others are closed.  Returns (box, cell_m or None, shape, timings keyed
+    timed on each box with autotune_live (identical work for every shape, the
+    box left in its starting state); the fastest box is returned open with its
+    shape set and the others are closed.  Returns (box, cell_m or None, shape, timings keyed
     "MxMxM/WxR")."""
     best = None
     base = None

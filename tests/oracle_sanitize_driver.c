@@ -76,6 +76,14 @@ int main(void)
     int rc = oracle_chain(max_n, x, y, z, &nc, &U, &Wr, &p, 99, 0, 0, moves, lg);
     if (rc != 0)
         return 3;
+    /* the CPU-baseline variants of the chain: several threads, a cell list */
+    int64_t nc2 = nc;
+    double U2 = U, W2 = Wr;
+    if (oracle_chain_mt(max_n, x, y, z, &nc2, &U2, &W2, &p, 99, 0, moves, moves, lg, 3) != 0)
+        return 3;
+    if (oracle_chain_cells(max_n, x, y, z, &nc2, &U2, &W2, &p, 99, 0, 2 * moves, moves, lg) != 0)
+        return 3;
+    nc = nc2;
     p.ns = 2;
     p.eps[0] = 1.0; p.eps[1] = 0.9; p.eps[2] = 0.9; p.eps[3] = 0.8;
     p.sigma[0] = 1.0; p.sigma[1] = 1.1; p.sigma[2] = 1.1; p.sigma[3] = 1.2;

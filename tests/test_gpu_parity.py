@@ -803,8 +803,8 @@ def test_autotune_cells_picks_a_timed_configuration_and_keeps_the_chain(c1):
     """The cell-size and launch-shape tuner: it times the paper's cells and
     twice as many per axis, keeps the fastest (box, shape) it timed, offers no
     speculative shape where the stencil is too large for it, and the box it
-    returns is still the oracle's chain: after its tuning moves the next moves
-    are the oracle's moves at the same counters."""
+    returns is back in its starting state: its next moves (device counter) are
+    the oracle's first moves."""
     from paper_1408_3764_amd import tune
     from paper_1408_3764_amd.box import Box
     from paper_1408_3764_amd._lib import COUNTER_CONTINUE
@@ -822,9 +822,8 @@ def test_autotune_cells_picks_a_timed_configuration_and_keeps_the_chain(c1):
     assert min(t, key=t.get) == "%s/%dx%d" % ("x".join(map(str, grid)), shape[0], shape[1])
     assert any(k.startswith("8x8x8/") and k.endswith("x0") for k in t)
     assert not any(k.startswith("16x16x16/") and (k.endswith("x0") or k.endswith("x-1")) for k in t)
-    # moves the chosen box ran while it was tuned: (300 + 200) per shape timed on it
-    ran = 500 * sum(1 for k in t if k.startswith("x".join(map(str, grid)) + "/"))
     p = _params(c1)
-    _, _, olog = oracle.chain(c1.pos, ran + 100, p, seed=c1.seed, max_n=c1.n + 20_000, U0=0.0)
+    _, _, olog = oracle.chain(c1.pos, 100, p, seed=c1.seed, max_n=c1.n + 20_000, U0=0.0)
+    assert box.checkpoint()["counter"] == 0
     _, glog = box.step(100, counter0=COUNTER_CONTINUE, log=True)
-    assert compare_chain_logs(glog, olog[ran:], c1.beta) == 100
+    assert compare_chain_logs(glog, olog, c1.beta) == 100

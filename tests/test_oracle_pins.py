@@ -718,3 +718,28 @@ def test_chain_virial_bookkeeping(orc):
     q = orc.make_params(b.L, 2.5, eps=0.0, mu=-1.0)
     _, _, Wq, logq = orc.chain(b.pos, 500, q, seed=6, W0=0.0)
     assert Wq == 0.0 and np.all(logq["dW_pair"] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# The CPU-baseline variants of the oracle chain (several threads; a cell
+# list): the same chain as the plain all-pairs loop, decision for decision
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,L,seed,mu", [(400, 10.0, 3, -2.0), (120, 7.4, 4, -1.0), (300, [8.0, 9.5, 12.7], 5, 0.5)])
+def test_chain_variants_equal_plain_chain(orc, n, L, seed, mu):
+    b = workloads.random_box(n, L, seed=seed, T=1.2)
+    p = orc.make_params(b.L, 2.5, beta=1.0 / 1.2, mu=mu)
+    t0 = orc.total_energy(b.pos, p)
+    U0 = t0["U_pair"] + t0["U_tail"]
+    W0 = orc.virial(b.pos, p)["W"]
+    ref = orc.chain(b.pos, 2000, p, seed=11, max_n=n + 2001, U0=U0, W0=W0)
+    acc = ref[3]["accepted"] == 1
+    assert acc.sum() > 100 and np.any(acc & (ref[3]["type"] == 2)) and np.any(acc & (ref[3]["type"] == 1))
+    for kw in ({"threads": 4}, {"threads": 7}, {"mode": "cells"}):
+        got = orc.chain(b.pos, 2000, p, seed=11, max_n=n + 2001, U0=U0, W0=W0, **kw)
+        for f in ("type", "index", "accepted", "flags", "x", "y", "z"):
+            assert np.array_equal(got[3][f], ref[3][f]), (kw, f)
+        assert np.allclose(got[3]["dU_pair"], ref[3]["dU_pair"], rtol=0,
+                           atol=1e-12 * max(1.0, np.abs(ref[3]["sumabs"]).max()))
+        assert np.array_equal(got[0], ref[0])
+        assert got[1] == pytest.approx(ref[1], rel=1e-12)
+        assert got[2] == pytest.approx(ref[2], rel=1e-12)
