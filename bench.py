@@ -534,21 +534,11 @@ def main():
                                                                  time.perf_counter() - tb))
         boxes = [Box.from_workload(w, max_n=w.n + 3001, box_id=k) for k, w in enumerate(wbs)]
         bt = Batch(boxes)
-        # time the shapes that fit a batch (one workgroup per box) and keep the fastest
-        btimes = {}
-        for bshape in ((1, 8), (2, 8), (4, 4), (4, 2), (2, 0), (4, 0), (8, 0)):
-            for b in boxes:
-                b.set_launch(*bshape)
-            bt.step(50, counter0=COUNTER_CONTINUE)
-            torch.cuda.synchronize()
-            tq = time.perf_counter()
-            bt.step(300, counter0=COUNTER_CONTINUE)
-            torch.cuda.synchronize()
-            btimes[bshape] = time.perf_counter() - tq
-        bshape = min(btimes, key=btimes.get)
-        for b in boxes:
-            b.set_launch(*bshape)
-        log("batched tuning (s per 300 moves/box): %s" % {"%dx%d" % k: round(v, 4) for k, v in btimes.items()})
+        # launch shapes per box (uniform, or the largest boxes wider), each rule timed on identical
+        # work; the boxes are left in their starting state with the fastest rule applied
+        brule, btimes = tune.autotune_batch(bt, boxes, n_moves=300)
+        bshape = tune.rule_name(brule)
+        log("batched tuning (s per 300 moves/box): %s" % {k: round(v, 4) for k, v in btimes.items()})
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -563,7 +553,7 @@ def main():
         b_ms = e0.elapsed_time(e1)
         out["batched"] = {"boxes": len(boxes), "moves_per_box": 1000, "moves_per_s": bmoves / db,
                           "pair_evals_per_s": float(np.sum(bst["pair_evals"])) / db,
-                          "launch_ms": b_ms, "launch": {"waves": bshape[0], "rows": bshape[1]},
+                          "launch_ms": b_ms, "launch_rule": bshape, "rule_timings_300_moves_s": btimes,
                           "errors": int(np.count_nonzero(bst["error"])),
                           "roofline": {"bound": "hbm", "alg_bytes_per_launch": b_alg,
                                        "achieved": b_alg / (b_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -332,6 +332,20 @@ int gcmc_step_allpairs(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_s
  * Also resets the running energy of the chain to d_U[0]. */
 int gcmc_total_energy(gcmc_box* box, int32_t all_pairs, double* d_U, double* d_e, void* stream);
 
+/* gcmc_total_energy for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same kernels,
+ * the same results bit for bit, with the pass's scratch in a 16 MiB array
+ * (2^21 doubles) that the library holds per GPU until the process ends
+ * instead of the box's scratch.  A pass over the cell list needs about
+ * N / 256 + (N + cells) / 2 doubles, so N + cells up to about 4.1 million
+ * fit; a larger box is refused with GCMC_ERR_INVALID_ARG (nothing launched).
+ * Calls no allocating routine.  It still reads the box state back to the host
+ * (as gcmc_total_energy does), so it blocks on `stream`.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  The current
+ * device must be the box's. */
+int gcmc_total_energy_noalloc(gcmc_box* box, int32_t all_pairs, double* d_U, double* d_e, void* stream);
+
 /* Gradient of U = U_pair + U_tail (Eq. 1 differentiated; rc held fixed):
  * d_grad[3*N] (SoA: x block, y block, z block) = dU/dr_i; d_deps and d_dsig
  * [n_species^2] = dU/d eps_ab and dU/d sigma_ab, where an unordered species
@@ -367,9 +381,14 @@ int gcmc_batch_destroy(gcmc_batch* batch);
 /* Advance every box of the batch by moves_per_box moves (counter0 + m, the
  * box's own box_id and seed; GCMC_COUNTER_CONTINUE: each box's device
  * counter).  d_stats[n_boxes] (may be NULL), in the order the boxes were
- * given.  Enqueues one kernel and no host synchronisation, so it can be
- * captured in a HIP graph (unless a box was rebuilt since the last call, which
- * re-uploads the descriptors). */
+ * given.  Boxes are grouped by their launch path and shape (at most 8
+ * groups): one kernel per group, the first on `stream`, the others on side
+ * streams of the batch forked from `stream` and joined back to it with
+ * events, so the groups run at the same time and everything is ordered on
+ * `stream`.  No host synchronisation, so it can be captured in a HIP graph,
+ * except on the first call and after a box was rebuilt or its launch shape
+ * changed: that call re-uploads the descriptors and, for several groups,
+ * creates the side streams and events. */
 int gcmc_batch_step(gcmc_batch* batch, int64_t moves_per_box, uint64_t counter0, gcmc_stats* d_stats,
                     void* stream);
 

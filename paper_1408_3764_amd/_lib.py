@@ -32,7 +32,8 @@ EXPORTS = [
     "gcmc_box_create", "gcmc_box_destroy", "gcmc_box_get_info", "gcmc_cell_build", "gcmc_set_positions",
     "gcmc_set_params", "gcmc_box_rescale",
     "gcmc_delta_energy", "gcmc_delta_energy_allpairs", "gcmc_commit", "gcmc_box_set_launch", "gcmc_box_set_wait_limit", "gcmc_step",
-    "gcmc_step_allpairs", "gcmc_total_energy", "gcmc_backward", "gcmc_virial", "gcmc_batch_create",
+    "gcmc_step_allpairs", "gcmc_total_energy", "gcmc_total_energy_noalloc", "gcmc_backward", "gcmc_virial",
+    "gcmc_batch_create",
     "gcmc_batch_destroy",
     "gcmc_batch_step", "gcmc_get_particles", "gcmc_get_cells", "gcmc_neighbor_ids", "gcmc_export_state",
     "gcmc_import_state", "gcmc_clear_averages", "gcmc_sync_status", "gcmc_last_error", "gcmc_version",
@@ -118,6 +119,7 @@ def lib():
         "gcmc_step": [vp, i64, u64, dp, dp, vp],
         "gcmc_step_allpairs": [vp, i64, u64, dp, dp, vp],
         "gcmc_total_energy": [vp, i32, dp, dp, vp],
+        "gcmc_total_energy_noalloc": [vp, i32, dp, dp, vp],
         "gcmc_backward": [vp, dp, dp, dp, vp],
         "gcmc_virial": [vp, dp, vp],
         "gcmc_batch_create": [C.POINTER(vp), i32, C.POINTER(vp)],
@@ -232,6 +234,10 @@ def gcmc_step_allpairs(box, n_moves, counter0, stats, log, stream=None):
 
 def gcmc_total_energy(box, all_pairs, U, e, stream=None):
     check(lib().gcmc_total_energy(box, int(all_pairs), ptr(U), ptr(e), stream_handle(stream)))
+
+
+def gcmc_total_energy_noalloc(box, all_pairs, U, e, stream=None):
+    check(lib().gcmc_total_energy_noalloc(box, int(all_pairs), ptr(U), ptr(e), stream_handle(stream)))
 
 
 def gcmc_backward(box, grad, deps, dsig, stream=None):

@@ -24,8 +24,7 @@ int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows) {
     if (rows == 0) {
         if (!spec_cfg_exists(waves)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported speculative width");
         if (!spec_supported(box->d))
-            return set_error(GCMC_ERR_UNSUPPORTED, "speculative rounds need one species, <= 32 stencil cells "
-                                                   "and 2 x stencil x cell_cap <= 8192");
+            return set_error(GCMC_ERR_UNSUPPORTED, "speculative rounds need one species and <= 512 stencil cells");
     } else if (rows == -1) {
         if (!async_cfg_exists(waves)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported pipeline width");
         if (!async_supported(box->d))
@@ -90,7 +89,7 @@ int gcmc_step(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_s
                                (hipStream_t)stream);
     else if (box->rows == 0 && spec_supported(box->d))
         r = launch_chain_spec(box->d_desc, nullptr, 1, box->waves, n_moves, counter0, d_stats, d_log,
-                              (hipStream_t)stream);
+                              (hipStream_t)stream, spec_needs_groups(box->d));
     else
         r = launch_chain(box->d_desc, nullptr, 1, box->waves, box->rows > 0 ? box->rows : 4, n_moves, counter0,
                          d_stats, d_log, (hipStream_t)stream);
@@ -200,12 +199,12 @@ int gcmc_batch_create(gcmc_box* const* boxes, int32_t n_boxes, gcmc_batch** out)
         gcmc_batch_destroy(bt);
         return set_error(GCMC_ERR_OOM, "batch allocation failed");
     }
+    bt->by_n = new int32_t[n_boxes];
     bt->h_order = new int32_t[n_boxes];
-    for (int32_t b = 0; b < n_boxes; ++b) bt->h_order[b] = order[b];
     bt->h_descs = new DevBox[n_boxes];
-    for (int32_t q = 0; q < n_boxes; ++q) bt->h_descs[q] = bt->boxes[order[q]]->d;
-    GCMC_HIP(hipMemcpy(bt->d_descs, bt->h_descs, sizeof(DevBox) * n_boxes, hipMemcpyHostToDevice));
-    GCMC_HIP(hipMemcpy(bt->d_order, order.data(), sizeof(int32_t) * n_boxes, hipMemcpyHostToDevice));
+    for (int32_t b = 0; b < n_boxes; ++b) bt->by_n[b] = bt->h_order[b] = order[b];
+    // the descriptors and order are uploaded by the first step (launch groups from the boxes' shapes)
+    memset(bt->h_descs, 0xFF, sizeof(DevBox) * n_boxes);
     *out = bt;
     return GCMC_OK;
 }
@@ -215,41 +214,114 @@ int gcmc_batch_destroy(gcmc_batch* bt) {
     (void)hipDeviceSynchronize();
     if (bt->d_descs) (void)hipFree(bt->d_descs);
     if (bt->d_order) (void)hipFree(bt->d_order);
+    for (int g = 0; g < kMaxBatchGroups; ++g) {
+        if (bt->side[g]) (void)hipStreamDestroy(bt->side[g]);
+        if (bt->ev_join[g]) (void)hipEventDestroy(bt->ev_join[g]);
+    }
+    if (bt->ev_fork) (void)hipEventDestroy(bt->ev_fork);
     delete[] bt->boxes;
+    delete[] bt->by_n;
     delete[] bt->h_order;
     delete[] bt->h_descs;
     delete bt;
     return GCMC_OK;
 }
 
+// Launch path and shape of a box as gcmc_step would run it.
+static void launch_key(const gcmc_box* b, int32_t* key) {
+    if (b->rows == -1 && async_supported(b->d)) {
+        key[0] = 1; key[1] = b->waves; key[2] = -1;
+    } else if (b->rows == 0 && spec_supported(b->d)) {
+        key[0] = 0; key[1] = b->waves; key[2] = 0;
+    } else {
+        key[0] = 2; key[1] = b->waves; key[2] = b->rows > 0 ? b->rows : 4;
+    }
+}
+
 int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gcmc_stats* d_stats, void* stream) {
     if (!bt || moves_per_box < 0) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
-    // descriptors in launch order: re-uploaded only when a box was rebuilt
-    bool changed = false;
-    for (int32_t q = 0; q < bt->n && !changed; ++q)
-        changed = memcmp(&bt->h_descs[q], &bt->boxes[bt->h_order[q]]->d, sizeof(DevBox)) != 0;
-    if (changed) {
-        for (int32_t q = 0; q < bt->n; ++q) bt->h_descs[q] = bt->boxes[bt->h_order[q]]->d;
-        GCMC_HIP(hipMemcpyAsync(bt->d_descs, bt->h_descs, sizeof(DevBox) * bt->n, hipMemcpyHostToDevice, s));
-        GCMC_HIP(hipStreamSynchronize(s));
+    // boxes grouped by launch path and shape (groups in the order of their largest box, decreasing
+    // N within a group): one launch per group
+    int32_t ng = 0, gkey[kMaxBatchGroups][3], gcount[kMaxBatchGroups] = {0};
+    std::vector<int32_t> grp(bt->n);
+    for (int32_t q = 0; q < bt->n; ++q) {
+        int32_t key[3];
+        launch_key(bt->boxes[bt->by_n[q]], key);
+        int g = 0;
+        while (g < ng && memcmp(gkey[g], key, sizeof key) != 0) ++g;
+        if (g == ng) {
+            if (ng == kMaxBatchGroups) return set_error(GCMC_ERR_INVALID_ARG, "more than 8 launch shapes in a batch");
+            memcpy(gkey[ng++], key, sizeof key);
+        }
+        grp[q] = g;
+        gcount[g] += 1;
     }
-    const gcmc_box* b0 = bt->boxes[0];
-    bool spec = b0->rows == 0, pipe = b0->rows == -1;
-    for (int32_t q = 0; q < bt->n && spec; ++q) spec = spec_supported(bt->boxes[q]->d);
-    for (int32_t q = 0; q < bt->n && pipe; ++q) pipe = async_supported(bt->boxes[q]->d);
-    int r;
-    if (pipe)
-        r = launch_chain_async(bt->d_descs, bt->d_order, bt->n, b0->waves, moves_per_box, counter0, d_stats,
-                               nullptr, s);
-    else if (spec)
-        r = launch_chain_spec(bt->d_descs, bt->d_order, bt->n, b0->waves, moves_per_box, counter0, d_stats, nullptr,
-                              s);
-    else
-        r = launch_chain(bt->d_descs, bt->d_order, bt->n, b0->waves, b0->rows > 0 ? b0->rows : 4, moves_per_box,
-                         counter0, d_stats, nullptr, s);
-    if (r) return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
-    GCMC_HIP(hipGetLastError());
+    std::vector<int32_t> order;
+    order.reserve(bt->n);
+    int32_t gstart[kMaxBatchGroups];
+    for (int g = 0; g < ng; ++g) {
+        gstart[g] = (int32_t)order.size();
+        for (int32_t q = 0; q < bt->n; ++q)
+            if (grp[q] == g) order.push_back(bt->by_n[q]);
+    }
+    // descriptors and order in launch order: re-uploaded only when a box was rebuilt or the grouping
+    // changed
+    bool changed = ng != bt->ngroups;
+    for (int32_t q = 0; q < bt->n && !changed; ++q)
+        changed = order[q] != bt->h_order[q] ||
+                  memcmp(&bt->h_descs[q], &bt->boxes[order[q]]->d, sizeof(DevBox)) != 0;
+    if (changed) {
+        for (int32_t q = 0; q < bt->n; ++q) {
+            bt->h_order[q] = order[q];
+            bt->h_descs[q] = bt->boxes[order[q]]->d;
+        }
+        GCMC_HIP(hipMemcpyAsync(bt->d_descs, bt->h_descs, sizeof(DevBox) * bt->n, hipMemcpyHostToDevice, s));
+        GCMC_HIP(hipMemcpyAsync(bt->d_order, bt->h_order, sizeof(int32_t) * bt->n, hipMemcpyHostToDevice, s));
+        GCMC_HIP(hipStreamSynchronize(s));
+        bt->ngroups = ng;
+        for (int g = 0; g < ng; ++g) {
+            bt->gstart[g] = gstart[g];
+            bt->gcount[g] = gcount[g];
+            memcpy(bt->gkey[g], gkey[g], sizeof gkey[g]);
+        }
+    }
+    // groups after the first run on side streams (default priority) forked from and joined to `s`
+    if (ng > 1) {
+        if (!bt->ev_fork) GCMC_HIP(hipEventCreateWithFlags(&bt->ev_fork, hipEventDisableTiming));
+        for (int g = 1; g < ng; ++g) {
+            if (!bt->side[g]) GCMC_HIP(hipStreamCreateWithFlags(&bt->side[g], hipStreamNonBlocking));
+            if (!bt->ev_join[g]) GCMC_HIP(hipEventCreateWithFlags(&bt->ev_join[g], hipEventDisableTiming));
+        }
+        GCMC_HIP(hipEventRecord(bt->ev_fork, s));
+        for (int g = 1; g < ng; ++g) GCMC_HIP(hipStreamWaitEvent(bt->side[g], bt->ev_fork, 0));
+    }
+    for (int g = 0; g < ng; ++g) {
+        const hipStream_t sg = g == 0 ? s : bt->side[g];
+        const DevBox* dd = bt->d_descs + bt->gstart[g];
+        const int32_t* od = bt->d_order + bt->gstart[g];
+        const int cnt = bt->gcount[g];
+        const int32_t* key = bt->gkey[g];
+        int r;
+        if (key[0] == 1) {
+            r = launch_chain_async(dd, od, cnt, key[1], moves_per_box, counter0, d_stats, nullptr, sg);
+        } else if (key[0] == 0) {
+            int ngr = 0;
+            for (int32_t q = 0; q < cnt; ++q)
+                ngr = std::max(ngr, spec_needs_groups(bt->boxes[bt->h_order[bt->gstart[g] + q]]->d));
+            r = launch_chain_spec(dd, od, cnt, key[1], moves_per_box, counter0, d_stats, nullptr, sg, ngr);
+        } else {
+            r = launch_chain(dd, od, cnt, key[1], key[2], moves_per_box, counter0, d_stats, nullptr, sg);
+        }
+        if (r) return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
+        GCMC_HIP(hipGetLastError());
+    }
+    if (ng > 1) {
+        for (int g = 1; g < ng; ++g) {
+            GCMC_HIP(hipEventRecord(bt->ev_join[g], bt->side[g]));
+            GCMC_HIP(hipStreamWaitEvent(s, bt->ev_join[g], 0));
+        }
+    }
     return GCMC_OK;
 }
 

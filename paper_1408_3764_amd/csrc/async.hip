@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             const int64_t N = uni64((int64_t)(uint32_t)cn);
             const double a_ins = unid(S.acc[0]), a_del = unid(S.acc[1]);
             const int s = target % kSlots;
-            spec_eval<CR>(B, tab, offs, own[e], ctr0 + (uint64_t)C, target - C, N, no_full, a_ins, a_del, &S.rec[s]);
+            spec_eval<CR, 0>(B, tab, offs, own[e], ctr0 + (uint64_t)C, target - C, N, no_full, a_ins, a_del, &S.rec[s]);
             if (lane == 0) {
                 S.slot_move[s] = target;
                 S.slot_epoch[s] = vis;
@@ -502,8 +502,12 @@ static const AsyncCfg kAsyncCfgs[] = {
 };
 
 // Cells are logged packed in 10 bits per axis.
+// The pipelined kernel evaluates with the 32-cell path of the speculative
+// evaluation only.
 bool async_supported(const DevBox& hb) {
-    return spec_supported(hb) && hb.M[0] <= 1024 && hb.M[1] <= 1024 && hb.M[2] <= 1024;
+    return hb.ns == 1 && hb.nstencil <= 32 && (int64_t)2 * hb.nstencil * hb.cap <= kSpecOwn &&
+           hb.ncells * (int64_t)hb.cap < ((int64_t)1 << 31) && hb.M[0] <= 1024 && hb.M[1] <= 1024 &&
+           hb.M[2] <= 1024;
 }
 
 bool async_cfg_exists(int waves) {

@@ -440,13 +440,21 @@ struct gcmc_box {
     double h_sig[gcmc::kMaxSpecies * gcmc::kMaxSpecies];
 };
 
+constexpr int kMaxBatchGroups = 8;   // launch shapes one batch may mix
+
 struct gcmc_batch {
     gcmc_box** boxes;        // host array, in the caller's order
     int32_t n;
-    gcmc::DevBox* d_descs;   // device array, launch order (decreasing N)
+    gcmc::DevBox* d_descs;   // device array, launch order (by group, decreasing N within a group)
     gcmc::DevBox* h_descs;   // what d_descs holds (to detect a rebuilt box)
     int32_t* d_order;        // launch slot -> caller index (device)
     int32_t* h_order;        // the same on the host
+    int32_t* by_n;           // caller indices by decreasing N at create
+    int32_t ngroups;         // boxes grouped by launch path and shape
+    int32_t gstart[kMaxBatchGroups], gcount[kMaxBatchGroups];
+    int32_t gkey[kMaxBatchGroups][3];   // path (0 speculative, 1 pipelined, 2 per-move), waves, rows
+    hipStream_t side[kMaxBatchGroups];  // streams of groups 1.. (created when first needed)
+    hipEvent_t ev_fork, ev_join[kMaxBatchGroups];
 };
 
 namespace gcmc {
@@ -466,7 +474,8 @@ bool async_cfg_exists(int waves);
 int launch_chain_async(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
                        uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 int launch_chain_spec(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
-                      uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
+                      uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s, int ng);
+int spec_needs_groups(const DevBox& hb);
 int launch_delta(const DevBox* d_box, bool mix, int64_t n_moves, const gcmc_move* moves, double* dp, double* dt,
                  double* dw, hipStream_t s);
 void launch_commit(const DevBox* d_box, const gcmc_move* move, const double* dU, const double* dW, hipStream_t s);

@@ -33,6 +33,10 @@
 // touched particle record.  The first move that
 // fails the check ends the round and is evaluated again in the next one, so
 // every move is decided on exactly the state the sequential chain would have.
+//
+// NG > 0: stencils of more than 32 cells (microcells, Sec. 3.3) go through
+// the evaluation's path with NG groups of 64 cells; the round and the commit
+// are the same.
 #include "spec_eval.h"
 
 namespace gcmc {
@@ -50,14 +54,15 @@ __device__ __forceinline__ double spec_arg(const DevBox& B, int type, double dUp
     return is_disp ? -(B.beta * dU) : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
 }
 
-template <int W, int CR>
+template <int W, int CR, int NG>
 __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restrict__ boxes,
                                                           const int32_t* __restrict__ order, int64_t n_moves,
                                                           uint64_t ctr0, gcmc_stats* stats, gcmc_log* trace) {
+    constexpr int kOffs = NG ? NG * kWave / 2 : 64;    // stencil slots with a precomputed linear offset
     __shared__ uint32_t tab[kMaxStencil];
-    __shared__ int32_t offs[64];
+    __shared__ int32_t offs[kOffs];
     __shared__ SpecRec recs[W];
-    __shared__ uint8_t own[W][kSpecOwn];
+    __shared__ uint32_t own[W][kSpecOwn / 4];         // owner bytes, or record indices (NG > 0)
     __shared__ double4 top[2 * W];              // records of particles base .. base + 2W - 1
     __shared__ double lp_ins[2 * W], lp_del[2 * W];   // acceptance prefactors at N = base + t
     __shared__ int64_t sh_state[4];       // N, moves done, error, error move
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         const uint32_t pk = gload(B.stab + t);
         const int tx = pk & 0x3FF, ty = (pk >> 10) & 0x3FF, tz = pk >> 20;
         tab[t] = pk;
-        if (t < 64) offs[t] = ((tz - B.k[2]) * B.M[1] + (ty - B.k[1])) * B.M[0] + (tx - B.k[0]);
+        if (t < kOffs) offs[t] = ((tz - B.k[2]) * B.M[1] + (ty - B.k[1])) * B.M[0] + (tx - B.k[0]);
     }
     if (tid < W) ready[tid] = -1;
     __syncthreads();
@@ -128,7 +133,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         }
         // ------------------------------------------------ evaluate W moves
         if (m + wv < n_moves)
-            spec_eval<CR>(B, tab, offs, own[wv], ctr0 + (uint64_t)m, wv, N, no_full, a_ins, a_del, &recs[wv]);
+            spec_eval<CR, NG>(B, tab, offs, own[wv], ctr0 + (uint64_t)m, wv, N, no_full, a_ins, a_del, &recs[wv]);
         if (wv != 0) {
             // publish this move's record: wavefront 0 decides it as soon as its turn comes, while
             // slower wavefronts still evaluate.  A commit may then store to memory that a later
@@ -436,19 +441,38 @@ using spec_fn = void (*)(const DevBox*, const int32_t*, int64_t, uint64_t, gcmc_
 struct SpecCfg {
     int key;   // the waves value of gcmc_box_set_launch that selects it
     int w;
+    int ng;    // groups of 64 stencil cells of the microcell path, 0 for the 32-cell path
     spec_fn f;
 };
 
 static const SpecCfg kSpecCfgs[] = {
-    {2, 2, k_chain_spec<2, 8>}, {4, 4, k_chain_spec<4, 8>}, {8, 8, k_chain_spec<8, 8>},
-    {16, 16, k_chain_spec<16, 4>},
+    {2, 2, 0, k_chain_spec<2, 8, 0>},
+    {4, 4, 0, k_chain_spec<4, 8, 0>},
+    {8, 8, 0, k_chain_spec<8, 8, 0>},
+    {16, 16, 0, k_chain_spec<16, 4, 0>},
+    {2, 2, kSpecGroupsSmall, k_chain_spec<2, 8, kSpecGroupsSmall>},
+    {4, 4, kSpecGroupsSmall, k_chain_spec<4, 8, kSpecGroupsSmall>},
+    {8, 8, kSpecGroupsSmall, k_chain_spec<8, 8, kSpecGroupsSmall>},
+    {16, 16, kSpecGroupsSmall, k_chain_spec<16, 4, kSpecGroupsSmall>},
+    {2, 2, kSpecGroups, k_chain_spec<2, 8, kSpecGroups>},
+    {4, 4, kSpecGroups, k_chain_spec<4, 8, kSpecGroups>},
+    {8, 8, kSpecGroups, k_chain_spec<8, 8, kSpecGroups>},
+    {16, 16, kSpecGroups, k_chain_spec<16, 4, kSpecGroups>},
 };
 
-// The speculative kernel handles one species, stencils of at most 32 cells
-// and at most kSpecOwn flattened candidates per move.
+// Groups of 64 cells the box's stencils need: 0 (the 32-cell path) for
+// stencils of at most 32 cells whose candidates fit the owner table, else the
+// smallest instantiation of the microcell path that holds both stencils of a
+// displacement.
+static int spec_groups(const DevBox& hb) {
+    if (hb.nstencil <= 32 && (int64_t)2 * hb.nstencil * hb.cap <= kSpecOwn) return 0;
+    return 2 * hb.nstencil <= kSpecGroupsSmall * kWave ? kSpecGroupsSmall : kSpecGroups;
+}
+
+// The speculative kernel handles one species and stencils of at most 512
+// cells (32-bit cell slots).
 bool spec_supported(const DevBox& hb) {
-    return hb.ns == 1 && hb.nstencil <= 32 && (int64_t)2 * hb.nstencil * hb.cap <= kSpecOwn &&
-           hb.ncells * (int64_t)hb.cap < ((int64_t)1 << 31);
+    return hb.ns == 1 && hb.nstencil <= kSpecMaxStencil && hb.ncells * (int64_t)hb.cap < ((int64_t)1 << 31);
 }
 
 bool spec_cfg_exists(int waves) {
@@ -457,10 +481,12 @@ bool spec_cfg_exists(int waves) {
     return false;
 }
 
+// A batch launches the path with the most groups any of its boxes needs (the
+// microcell path serves any stencil that fits it).
 int launch_chain_spec(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
-                      uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s) {
+                      uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s, int ng) {
     for (const SpecCfg& c : kSpecCfgs) {
-        if (c.key == waves) {
+        if (c.key == waves && c.ng == ng) {
             hipLaunchKernelGGL(c.f, dim3(n_boxes), dim3(kWave * c.w), 0, s, d_boxes, d_order, n_moves, ctr0, stats,
                                log);
             return 0;
@@ -468,5 +494,7 @@ int launch_chain_spec(const DevBox* d_boxes, const int32_t* d_order, int n_boxes
     }
     return -1;
 }
+
+int spec_needs_groups(const DevBox& hb) { return spec_groups(hb); }
 
 }  // namespace gcmc

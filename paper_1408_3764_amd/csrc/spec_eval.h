@@ -8,12 +8,24 @@
 // counters of its stencil cells (one lane per cell), prefix-sums them, maps
 // each flattened candidate to its cell through an owner table in LDS, loads
 // exactly the candidates' records and reduces the pair sums.
+//
+// Stencils of more than 32 cells (microcells smaller than the cutoff, whose
+// stencils of 2k+1 cells per axis are pruned of the cells beyond it) take a
+// second path: the cells are loaded in groups of 64, one lane per cell (all
+// groups' counters in one memory round trip), prefix-summed across the
+// groups, and the flattened candidates' record indices are written to an LDS
+// table that is filled and consumed in windows, so a move may have any number
+// of candidates.
 #pragma once
 #include "trial.h"
 
 namespace gcmc {
 
-constexpr int kSpecOwn = 8192;   // flattened candidates per wavefront (owner table bytes)
+constexpr int kSpecOwn = 8192;       // flattened candidates per wavefront (owner table bytes)
+constexpr int kSpecRecWin = kSpecOwn / 4;   // record indices per window of the microcell path (same bytes)
+constexpr int kSpecGroups = 16;      // groups of 64 stencil cells: stencils of up to 512 cells (two for a displacement)
+constexpr int kSpecMaxStencil = kSpecGroups * kWave / 2;
+constexpr int kSpecGroupsSmall = 4;  // the instantiation for stencils of up to 128 cells (fewer registers)
 
 struct SpecRec {
     double dUp, lnA, u2, dWp;   // pair energy change, ln A, pick draw, pair virial change
@@ -66,9 +78,31 @@ __device__ __forceinline__ bool in_stencil(const DevBox& B, int32_t x, int32_t y
     return in;
 }
 
-// Wavefront k evaluates move ctr_round + k against the current state.
-template <int CR>
-__device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, const int32_t* offs, uint8_t* own,
+// One candidate record against the move's position(s): energy and virial sums.
+__device__ __forceinline__ void spec_pair(const DevBox& B, int type, int two, bool second, const double* p0,
+                                          const double* p1, const double4& e, double& sa, double& sb, double& wa,
+                                          double& wb, int32_t& n_eval, int64_t& incut) {
+    if (type != GCMC_MOVE_DISPLACE) {
+        sa += pair_uw<false>(B, p0, 0, e, incut, wa);
+        n_eval += 1;
+    } else if (!two) {
+        sa += pair_uw<false>(B, p0, 0, e, incut, wa);
+        sb += pair_uw<false>(B, p1, 0, e, incut, wb);
+        n_eval += 2;
+    } else if (second) {
+        sb += pair_uw<false>(B, p1, 0, e, incut, wb);
+        n_eval += 1;
+    } else {
+        sa += pair_uw<false>(B, p0, 0, e, incut, wa);
+        n_eval += 1;
+    }
+}
+
+// Wavefront k evaluates move ctr_round + k against the current state.  NG:
+// 0 for the 32-cell path, else the number of groups of 64 stencil cells the
+// microcell path provides (see above).
+template <int CR, int NG>
+__device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, const int32_t* offs, void* ownbuf,
                                           uint64_t ctr_round, int k, int64_t N, bool no_full, double a_ins,
                                           double a_del, SpecRec* out) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -152,72 +186,154 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
                                      c1[2] <= B.M[2] - 1 - B.k[2])))
                               ? 1
                               : 0) != 0;
-    const int wh = lane >= nst ? 1 : 0;
-    const int t = lane - wh * nst;
-    const bool cell_lane = lane < ncs;
-    int32_t cell = cl0;
-    if (cell_lane) {
-        if (fast) {
-            cell = (wh ? cl1 : cl0) + offs[t];
-        } else {
-            cell = (int32_t)stencil_cell(B, tab[t], wh ? c1[0] : c0[0], wh ? c1[1] : c0[1], wh ? c1[2] : c0[2]);
-        }
-    }
-    const int32_t cnt = cell_lane ? gload(B.count + cell) : 0;
-    const int32_t incl = wave_incl_scan(cnt);
-    const int32_t pre = incl - cnt;
-    const int32_t total = __builtin_amdgcn_readlane(incl, 63);
-    // lanes of the two centre cells (each appears once in its stencil)
-    const int tc = (int)__builtin_ctzll(__ballot(cell_lane && !wh && cell == cl0));
-    const int tc1 = two ? (int)__builtin_ctzll(__ballot(cell_lane && wh && cell == cl1)) : tc;
-    const int32_t cnt0 = __builtin_amdgcn_readlane(cnt, tc);
-    const int32_t cnt1 = __builtin_amdgcn_readlane(cnt, tc1);
-    // ---- owner of each flattened candidate
-    const int kmax = wave_max_i32_uniform(cnt);
-    for (int k = 0; k < kmax; ++k)
-        if (k < cnt) own[pre + k] = (uint8_t)lane;
-    const int32_t cellbase = cell * B.cap - pre;   // record index of flattened candidate q: q + cellbase[owner]
-    __builtin_amdgcn_wave_barrier();
-    // last entry of the old centre cell (removal by swap-with-last)
+    int32_t cnt0 = 0, cnt1 = 0;
     double4 elast = make_double4(0, 0, 0, 0);
-    if (cnt0 > 0) elast = gload(B.ent + ((size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)));
-    // ---- candidates
     const int32_t excl = (int32_t)idx;
     double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
     int32_t n_cand = 0, n_eval = 0, n_in = 0;
     int64_t incut = 0;
-    for (int base = 0; base < total; base += kWave * CR) {
-        double4 e[CR];
-        int32_t wsel[CR];
-        bool ok[CR];
-#pragma unroll
-        for (int r = 0; r < CR; ++r) {
-            const int q = base + r * kWave + lane;
-            ok[r] = q < total;
-            const int j = ok[r] ? own[q] : 0;
-            const int32_t cb = __shfl(cellbase, j, kWave);
-            wsel[r] = j >= nst ? 1 : 0;
-            e[r] = gload(B.ent + (size_t)(uint32_t)(ok[r] ? cb + q : cl0 * B.cap));
+    if constexpr (NG == 0) {
+        const int wh = lane >= nst ? 1 : 0;
+        const int t = lane - wh * nst;
+        const bool cell_lane = lane < ncs;
+        int32_t cell = cl0;
+        if (cell_lane) {
+            if (fast) {
+                cell = (wh ? cl1 : cl0) + offs[t];
+            } else {
+                cell = (int32_t)stencil_cell(B, tab[t], wh ? c1[0] : c0[0], wh ? c1[1] : c0[1], wh ? c1[2] : c0[2]);
+            }
         }
-#pragma unroll
-        for (int r = 0; r < CR; ++r) {
-            if (ok[r] && meta_low(e[r].w) != excl) {
-                n_cand += 1;
-                if (type != GCMC_MOVE_DISPLACE) {
-                    sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
-                    n_eval += 1;
-                } else if (!two) {
-                    sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
-                    sb += pair_uw<false>(B, p1, 0, e[r], incut, wb);
-                    n_eval += 2;
-                } else if (wsel[r]) {
-                    sb += pair_uw<false>(B, p1, 0, e[r], incut, wb);
-                    n_eval += 1;
-                } else {
-                    sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
-                    n_eval += 1;
+        const int32_t cnt = cell_lane ? gload(B.count + cell) : 0;
+        const int32_t incl = wave_incl_scan(cnt);
+        const int32_t pre = incl - cnt;
+        const int32_t total = __builtin_amdgcn_readlane(incl, 63);
+        // lanes of the two centre cells (each appears once in its stencil)
+        const int tc = (int)__builtin_ctzll(__ballot(cell_lane && !wh && cell == cl0));
+        const int tc1 = two ? (int)__builtin_ctzll(__ballot(cell_lane && wh && cell == cl1)) : tc;
+        cnt0 = __builtin_amdgcn_readlane(cnt, tc);
+        cnt1 = __builtin_amdgcn_readlane(cnt, tc1);
+        // ---- owner of each flattened candidate
+        uint8_t* own = static_cast<uint8_t*>(ownbuf);
+        const int kmax = wave_max_i32_uniform(cnt);
+        for (int k = 0; k < kmax; ++k)
+            if (k < cnt) own[pre + k] = (uint8_t)lane;
+        const int32_t cellbase = cell * B.cap - pre;   // record index of flattened candidate q: q + cellbase[owner]
+        __builtin_amdgcn_wave_barrier();
+        // last entry of the old centre cell (removal by swap-with-last)
+        if (cnt0 > 0) elast = gload(B.ent + ((size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)));
+        // ---- candidates
+        for (int base = 0; base < total; base += kWave * CR) {
+            double4 e[CR];
+            int32_t wsel[CR];
+            bool ok[CR];
+    #pragma unroll
+            for (int r = 0; r < CR; ++r) {
+                const int q = base + r * kWave + lane;
+                ok[r] = q < total;
+                const int j = ok[r] ? own[q] : 0;
+                const int32_t cb = __shfl(cellbase, j, kWave);
+                wsel[r] = j >= nst ? 1 : 0;
+                e[r] = gload(B.ent + (size_t)(uint32_t)(ok[r] ? cb + q : cl0 * B.cap));
+            }
+    #pragma unroll
+            for (int r = 0; r < CR; ++r) {
+                if (ok[r] && meta_low(e[r].w) != excl) {
+                    n_cand += 1;
+                    if (type != GCMC_MOVE_DISPLACE) {
+                        sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
+                        n_eval += 1;
+                    } else if (!two) {
+                        sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
+                        sb += pair_uw<false>(B, p1, 0, e[r], incut, wb);
+                        n_eval += 2;
+                    } else if (wsel[r]) {
+                        sb += pair_uw<false>(B, p1, 0, e[r], incut, wb);
+                        n_eval += 1;
+                    } else {
+                        sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
+                        n_eval += 1;
+                    }
                 }
             }
+        }
+
+    } else {
+        // ---- microcell stencils: groups of 64 cells, one lane per cell
+        const int G = (ncs + kWave - 1) / kWave;
+        int32_t cellg[NG], cntg[NG], preg[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            cellg[g] = cl0;
+            cntg[g] = 0;
+            if (g < G) {
+                const int f = g * kWave + lane;
+                const int wh = f >= nst ? 1 : 0;
+                const int t = f - wh * nst;
+                if (f < ncs)
+                    cellg[g] = fast ? (wh ? cl1 : cl0) + offs[t]
+                                    : (int32_t)stencil_cell(B, tab[t], wh ? c1[0] : c0[0], wh ? c1[1] : c0[1],
+                                                            wh ? c1[2] : c0[2]);
+                cntg[g] = f < ncs ? gload(B.count + cellg[g]) : 0;
+            }
+        }
+        int32_t total = 0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            preg[g] = 0;
+            if (g < G) {
+                const int f = g * kWave + lane;
+                const bool on = f < ncs;
+                const int wh = f >= nst ? 1 : 0;
+                const int32_t incl = wave_incl_scan(cntg[g]);
+                preg[g] = total + incl - cntg[g];
+                total += __builtin_amdgcn_readlane(incl, 63);
+                // the centre cells (each appears once in its stencil)
+                const uint64_t b0 = __ballot(on && !wh && cellg[g] == cl0);
+                if (b0) cnt0 = __builtin_amdgcn_readlane(cntg[g], (int)__builtin_ctzll(b0));
+                const uint64_t b1 = __ballot(on && wh && cellg[g] == cl1);
+                if (b1) cnt1 = __builtin_amdgcn_readlane(cntg[g], (int)__builtin_ctzll(b1));
+            }
+        }
+        if (!two) cnt1 = cnt0;
+        if (cnt0 > 0) elast = gload(B.ent + ((size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)));
+        // ---- record indices of the flattened candidates, window by window (bit 31: second stencil)
+        uint32_t* recw = static_cast<uint32_t*>(ownbuf);
+        for (int q0 = 0; q0 < total; q0 += kSpecRecWin) {
+            const int q1 = (total - q0) < kSpecRecWin ? total : q0 + kSpecRecWin;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (g < G) {
+                    const uint32_t second = (g * kWave + lane) >= nst ? 0x80000000u : 0u;
+                    const uint32_t rb = (uint32_t)cellg[g] * (uint32_t)B.cap;
+                    const int kmax = wave_max_i32_uniform(cntg[g]);
+                    for (int kk = 0; kk < kmax; ++kk) {
+                        const int q = preg[g] + kk;
+                        if (kk < cntg[g] && q >= q0 && q < q1) recw[q - q0] = (rb + (uint32_t)kk) | second;
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int base = q0; base < q1; base += kWave * CR) {
+                double4 e[CR];
+                bool ok[CR], sec[CR];
+#pragma unroll
+                for (int r = 0; r < CR; ++r) {
+                    const int q = base + r * kWave + lane;
+                    ok[r] = q < q1;
+                    const uint32_t v = ok[r] ? recw[q - q0] : (uint32_t)cl0 * (uint32_t)B.cap;
+                    sec[r] = (v & 0x80000000u) != 0;
+                    e[r] = gload(B.ent + (size_t)(v & 0x7FFFFFFFu));
+                }
+#pragma unroll
+                for (int r = 0; r < CR; ++r) {
+                    if (ok[r] && meta_low(e[r].w) != excl) {
+                        n_cand += 1;
+                        spec_pair(B, type, two, sec[r], p0, p1, e[r], sa, sb, wa, wb, n_eval, incut);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();   // every lane has read this window before the next overwrites it
         }
     }
     n_in = (int32_t)incut;

@@ -21,7 +21,8 @@ SPEC_SHAPES = [(2, 0), (4, 0), (8, 0), (16, 0)]
 # rows = -1: the pipelined kernel, one committer and waves - 1 evaluator wavefronts
 # (the same limits, plus at most 1024 cells per axis)
 ASYNC_SHAPES = [(4, -1), (8, -1)]
-SPEC_OWN = 8192   # flattened candidates a speculative wavefront can hold
+SPEC_OWN = 8192   # flattened candidates the 32-cell path of the speculative kernel can hold
+SPEC_MAX_STENCIL = 512   # stencil cells the speculative kernel takes (microcell path above 32)
 CACHE_ENV = "GCMC_TUNE_CACHE"
 
 
@@ -38,12 +39,14 @@ def _slots(box):
 
 def spec_supported(box):
     info = box.info()
-    nst = info["n_stencil"]
-    return info["n_species"] == 1 and nst <= 32 and 2 * nst * info["cell_cap"] <= SPEC_OWN
+    return info["n_species"] == 1 and info["n_stencil"] <= SPEC_MAX_STENCIL
 
 
 def async_supported(box):
-    return spec_supported(box) and max(box.info()["cell_m"]) <= 1024
+    info = box.info()
+    nst = info["n_stencil"]
+    return (info["n_species"] == 1 and nst <= 32 and 2 * nst * info["cell_cap"] <= SPEC_OWN
+            and max(info["cell_m"]) <= 1024)
 
 
 def chain_shape(box):
@@ -70,6 +73,72 @@ def batch_shape(boxes):
         if 64 * w * r >= need:
             return (w, r)
     return (8, 4)
+
+
+BATCH_RULES = [("uniform", (2, 0)), ("uniform", (4, 0)), ("uniform", (8, 0)), ("uniform", (4, 4)),
+               ("split", 0.25, (8, 0), (4, 0)), ("split", 0.5, (8, 0), (4, 0)), ("split", 0.25, (8, 0), (2, 0)),
+               ("split", 0.5, (4, 0), (2, 0)), ("split", 0.125, (16, 0), (4, 0))]
+
+
+def apply_batch_rule(boxes, rule):
+    """Set every box's launch shape by a rule: ("uniform", shape), or ("split",
+    f, big, small): the fraction f of the boxes with the most particles take
+    `big`, the others `small` (a shape the box cannot take falls back to the
+    per-move 4x4)."""
+    if rule[0] == "uniform":
+        shapes = [rule[1]] * len(boxes)
+    else:
+        _, f, big, small = rule
+        ns = [b.n for b in boxes]
+        order = sorted(range(len(boxes)), key=lambda k: -ns[k])
+        top = set(order[:max(1, int(round(f * len(boxes))))])
+        shapes = [big if k in top else small for k in range(len(boxes))]
+    for b, sh in zip(boxes, shapes):
+        if sh[1] == 0 and not spec_supported(b):
+            sh = (4, 4)
+        b.set_launch(*sh)
+    return shapes
+
+
+def rule_name(rule):
+    if rule[0] == "uniform":
+        return "%dx%d" % rule[1]
+    return "top%g:%dx%d/%dx%d" % (rule[1], rule[2][0], rule[2][1], rule[3][0], rule[3][1])
+
+
+def autotune_batch(batch, boxes, n_moves=300, rules=None):
+    """Launch shapes of a batch: every rule of BATCH_RULES timed on identical
+    work (each box's snapshot restored before the warm-up and before the timed
+    launch, which continue each box's own counter); the fastest rule is left
+    applied and the boxes back in their starting state.  Returns (rule,
+    timings keyed by rule_name)."""
+    import torch
+    from ._lib import COUNTER_CONTINUE
+    rules = rules or BATCH_RULES
+    snaps = [b.snapshot() for b in boxes]
+    timings, best = {}, None
+    for rule in rules:
+        apply_batch_rule(boxes, rule)
+        for b, sn in zip(boxes, snaps):
+            b.restore(sn)
+        batch.step(min(50, n_moves), counter0=COUNTER_CONTINUE)
+        for b, sn in zip(boxes, snaps):
+            b.restore(sn)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = batch.step(n_moves, counter0=COUNTER_CONTINUE)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if int((st["error"] != 0).sum()):
+            raise RuntimeError("chain error while tuning the batch")
+        timings[rule_name(rule)] = dt
+        if best is None or dt < best[0]:
+            best = (dt, rule)
+    apply_batch_rule(boxes, best[1])
+    for b, sn in zip(boxes, snaps):
+        b.restore(sn)
+    torch.cuda.synchronize()
+    return best[1], timings
 
 
 def _cache_path():

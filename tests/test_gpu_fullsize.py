@@ -260,14 +260,23 @@ def test_autograd_function():
     assert float(U2) == pytest.approx(t2["U_pair"] + t2["U_tail"], rel=1e-11)
 
 
-def test_graph_replay_continues_the_chain():
+@pytest.mark.parametrize("mixed", [False, True])
+def test_graph_replay_continues_the_chain(mixed):
     """Batched steps captured in a HIP graph (device-side move counters) and
-    replayed several times, with eager work in between, equal the eager chain."""
+    replayed several times, with eager work in between, equal the eager chain;
+    also with one launch shape per box (three launch groups on forked streams
+    inside the graph)."""
     from paper_1408_3764_amd.box import Batch, Box
     from paper_1408_3764_amd._lib import COUNTER_CONTINUE
     wbs = [workloads.cubic_box(n, rho, 1.2, 2.5, 900 + k) for k, (n, rho) in
            enumerate([(300, 0.5), (800, 0.6), (150, 0.4)])]
-    mk = lambda: [Box.from_workload(w, max_n=w.n + 2001, box_id=k, seed=5) for k, w in enumerate(wbs)]
+
+    def mk():
+        bs = [Box.from_workload(w, max_n=w.n + 2001, box_id=k, seed=5) for k, w in enumerate(wbs)]
+        if mixed:
+            for b, sh in zip(bs, [(8, 0), (4, 4), (2, 0)]):
+                b.set_launch(*sh)
+        return bs
     eager, graphed = mk(), mk()
     be, bg = Batch(eager), Batch(graphed)
     torch.cuda.synchronize()

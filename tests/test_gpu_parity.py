@@ -205,7 +205,7 @@ def test_chain_launch_shapes_agree(c1, waves, rows):
 
 
 @pytest.mark.parametrize("cm", [[16, 16, 16], [21, 21, 21], [24, 24, 24]])
-@pytest.mark.parametrize("waves,rows", [(4, 4), (8, 2)])
+@pytest.mark.parametrize("waves,rows", [(4, 4), (8, 2), (8, 0), (4, 0), (16, 0)])
 def test_chain_microcells_agree(c1, cm, waves, rows):
     """Microcells (k = 2, 3; pruned stencils of up to several hundred cells): the
     chain kernel gives the oracle's chain, and the cell list it leaves behind
@@ -215,13 +215,51 @@ def test_chain_microcells_agree(c1, cm, waves, rows):
     req = np.array(cm, dtype=np.int32)
     b = _box(c1, max_n=c1.n + 400, cell_m=req)
     assert b.info()["n_stencil"] == oracle.stencil_count(c1.L, c1.rc, req)
-    b.set_launch(waves, rows)
+    b.set_launch(waves, rows)      # rows = 0 on these stencils (125 to 335 cells): the microcell path
     _, glog = b.step(300, counter0=0, log=True)
     assert compare_chain_logs(glog, olog, c1.beta) == 300
     gpos = b.particles()[0]
     assert np.array_equal(gpos, opos)
     cell_of, _, _ = b.cells()
     assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(gpos, c1.L, c1.rc, req))
+
+
+@pytest.mark.parametrize("cm", [[16, 16, 16], [24, 24, 24]])
+def test_speculative_microcells_long_chain(c1, cm):
+    """The speculative kernel's microcell path over 3,000 moves of the small box
+    (r_c/2 and r_c/3 cells): every decision, the final configuration, the cell
+    list, and the work counters of the per-move kernel on the same chain."""
+    p = _params(c1)
+    req = np.array(cm, dtype=np.int32)
+    b = _box(c1, max_n=c1.n + 3001, cell_m=req)
+    b.set_launch(8, 0)
+    b.total_energy()
+    r = chain_parity(b, oracle, c1.pos, p, c1.seed, 3000, c1.beta, c1.n + 3001, "speculative microcells")
+    assert np.array_equal(b.particles()[0], r["opos"])
+    cell_of, _, _ = b.cells()
+    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(r["opos"], c1.L, c1.rc, req))
+    if not r["ties"]:
+        ref = _box(c1, max_n=c1.n + 3001, cell_m=req)
+        ref.set_launch(4, 4)
+        rs, _ = ref.step(3000, counter0=0)
+        for f in WORK:
+            assert int(r["stats"][f]) == int(rs[f]), f
+
+
+def test_speculative_microcells_dense_many_candidates():
+    """A dense box on a small-cell grid with a large capacity, so that a move's
+    candidates exceed one LDS window of record indices (2,048) and the window
+    loop runs more than once."""
+    wb = workloads.random_box(2500, 14.0, rc=4.0, T=1.2, mu=2.0, seed=78)
+    req = np.array([5, 5, 5], dtype=np.int32)      # cells of 2.8 < rc: k = 2 covers every axis, 125 cells
+    p = _params(wb)
+    b = _box(wb, max_n=wb.n + 2001, cell_m=req, cell_cap=96)
+    assert b.info()["n_stencil"] > 32
+    b.set_launch(8, 0)
+    r = chain_parity(b, oracle, wb.pos, p, wb.seed, 2000, wb.beta, wb.n + 2001, "dense microcells")
+    assert np.array_equal(b.particles()[0], r["opos"])
+    # every stencil is the whole box (N - 1 candidates): above one window
+    assert int(r["stats"]["candidates"]) / max(1, int(r["stats"]["stencils"])) > 2048
 
 
 @pytest.mark.parametrize("cm", [[21, 21, 21], [24, 24, 24]])
@@ -777,15 +815,20 @@ def test_backward_single_species(c1):
 
 
 # ------------------------------------------------------------------ batch
-@pytest.mark.parametrize("shape", [(2, 8), (8, 0), (4, -1)])
+MIXED = [(8, 0), (4, 4), (2, 0), (8, -1), (8, 0)]   # one shape per box: four launch groups
+
+
+@pytest.mark.parametrize("shape", [(2, 8), (8, 0), (4, -1), "mixed"])
 def test_batch_matches_single_boxes(shape):
+    """Boxes of one batch (one launch per launch shape, the groups on forked
+    streams) each follow their own oracle chain."""
     from paper_1408_3764_amd.box import Batch, Box
     sizes = [130, 400, 900, 260, 1500]
     wbs = [workloads.cubic_box(n, rho, T, 2.5, 500 + k) for k, (n, rho, T) in
            enumerate(zip(sizes, [0.3, 0.5, 0.8, 0.6, 0.4], [0.9, 1.2, 1.5, 1.0, 1.1]))]
     boxes = [Box.from_workload(w, max_n=w.n + 301, box_id=k, seed=99) for k, w in enumerate(wbs)]
-    for b in boxes:
-        b.set_launch(*shape)
+    for k, b in enumerate(boxes):
+        b.set_launch(*(MIXED[k] if shape == "mixed" else shape))
     bt = Batch(boxes)
     stats = bt.step(300, counter0=0)
     for k, w in enumerate(wbs):

@@ -1,0 +1,62 @@
+"""gcmc_total_energy_noalloc (the entry point for callers that cannot
+allocate) against gcmc_total_energy, through the C ABI: two calls in a row on
+boxes of decreasing size (the second smaller than the first), cell-list and
+all-pairs passes, per-particle energies too; a box whose pass needs more than
+the static buffer is refused."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1408_3764_amd import _lib, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(b, all_pairs):
+    n = b.n
+    U1 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    U2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    e1 = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+    e2 = torch.full((max(n, 1),), -1.0, dtype=torch.float64, device="cuda")
+    _lib.gcmc_total_energy(b.handle, all_pairs, U1, e1)
+    _lib.gcmc_total_energy_noalloc(b.handle, all_pairs, U2, e2)
+    torch.cuda.synchronize()
+    return U1.cpu().numpy(), U2.cpu().numpy(), e1[:n].cpu().numpy(), e2[:n].cpu().numpy()
+
+
+def test_noalloc_total_energy_equals_the_allocating_entry_point():
+    from paper_1408_3764_amd.box import Box
+    big = workloads.large()                                  # N = 262,144, 13,824 cells
+    small = workloads.random_box(500, 12.0, seed=5)         # the second call: a smaller input
+    for wb in (big, small):
+        b = Box.from_workload(wb)
+        for ap in (0, 1):
+            if ap and wb.n > 100_000:
+                continue
+            U1, U2, e1, e2 = _both(b, ap)
+            assert np.array_equal(U1, U2), (wb.name, ap)
+            assert np.array_equal(e1, e2), (wb.name, ap)
+        p = oracle.make_params(wb.L, wb.rc)
+        if wb.n <= 1000:
+            t = oracle.total_energy(wb.pos, p)
+            assert abs(U2[0] - t["U_pair"]) <= 1e-10 * t["sumabs"]
+            assert U2[1] == pytest.approx(t["U_tail"], rel=1e-12)
+        # the running energy the pass resets is the same either way
+        assert b.checkpoint()["u_pair"] == U1[0]
+        b.close()
+
+
+def test_noalloc_refuses_a_pass_beyond_its_buffer():
+    from paper_1408_3764_amd.box import Box
+    rng = np.random.default_rng(3)
+    pos = rng.random((100, 3)) * 200.0
+    b = Box(pos, [200.0] * 3, 2.5, cell_m=[170, 170, 170])   # 4.9M cells: about 2.5M doubles of scratch
+    U = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.GcmcError) as e:
+        _lib.gcmc_total_energy_noalloc(b.handle, 0, U, None)
+    assert e.value.code == _lib.GCMC_ERR_INVALID_ARG and "static buffer" in str(e.value)
+    # the all-pairs pass of the same box fits, and equals the allocating entry point
+    U1, U2, e1, e2 = _both(b, 1)
+    assert np.array_equal(U1, U2) and np.array_equal(e1, e2)
+    b.close()
