@@ -90,9 +90,13 @@ int gcmc_step(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_s
     else if (box->rows == 0 && spec_supported(box->d))
         r = launch_chain_spec(box->d_desc, nullptr, 1, box->waves, n_moves, counter0, d_stats, d_log,
                               (hipStream_t)stream, spec_needs_groups(box->d));
-    else
-        r = launch_chain(box->d_desc, nullptr, 1, box->waves, box->rows > 0 ? box->rows : 4, n_moves, counter0,
-                         d_stats, d_log, (hipStream_t)stream);
+    else {
+        // a shape the box's kernel cannot take falls back to the per-move 4x4
+        const int rows = box->rows > 0 ? box->rows : 4;
+        const bool ok = chain_cfg_exists(box->waves, rows);
+        r = launch_chain(box->d_desc, nullptr, 1, ok ? box->waves : 4, ok ? rows : 4, n_moves, counter0, d_stats,
+                         d_log, (hipStream_t)stream);
+    }
     if (r) return set_error(GCMC_ERR_INVALID_ARG, "unsupported launch shape");
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
@@ -234,7 +238,10 @@ static void launch_key(const gcmc_box* b, int32_t* key) {
     } else if (b->rows == 0 && spec_supported(b->d)) {
         key[0] = 0; key[1] = b->waves; key[2] = 0;
     } else {
-        key[0] = 2; key[1] = b->waves; key[2] = b->rows > 0 ? b->rows : 4;
+        // a shape the box's kernel cannot take falls back to the per-move 4x4
+        const int rows = b->rows > 0 ? b->rows : 4;
+        const bool ok = chain_cfg_exists(b->waves, rows);
+        key[0] = 2; key[1] = ok ? b->waves : 4; key[2] = ok ? rows : 4;
     }
 }
 

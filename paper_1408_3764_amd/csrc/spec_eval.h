@@ -313,7 +313,9 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
                     }
                 }
             }
+            // the indices other lanes of this wavefront wrote, visible to every lane
             __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
             for (int base = q0; base < q1; base += kWave * CR) {
                 double4 e[CR];
                 bool ok[CR], sec[CR];
@@ -333,7 +335,9 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
                     }
                 }
             }
-            __builtin_amdgcn_wave_barrier();   // every lane has read this window before the next overwrites it
+            // every lane has read this window before the next overwrites it
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
         }
     }
     n_in = (int32_t)incut;
