@@ -285,12 +285,19 @@ int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair,
  * speculative rounds, `waves` (2, 4, 8 or 16) consecutive moves evaluated at once,
  * one per wavefront, against the round's starting state and committed in
  * order, each only if nothing it read has changed since (the same chain, move
- * for move); needs one species, at most 32 stencil cells and
- * 2 x stencil cells x cell_cap <= 8192, else GCMC_ERR_UNSUPPORTED.  rows = -1:
- * pipelined, one wavefront decides the moves in order while waves - 1 (3 or
- * 7) wavefronts evaluate the moves ahead of it; an evaluation is used only if
- * no decision since it read memory changed what it read (the same chain, move
- * for move); the same limits plus at most 1024 cells per axis. */
+ * for move); needs one species and at most 512 stencil cells (stencils of
+ * more than 32 cells, or whose candidates exceed 8192 slots, go through a
+ * path that loads the stencil counters in groups of 64 cells and stages the
+ * candidates' record indices in LDS windows), else GCMC_ERR_UNSUPPORTED.
+ * rows = -1: pipelined, one wavefront decides the moves in order while
+ * waves - 1 (3 or 7) wavefronts evaluate the moves ahead of it; an evaluation
+ * is used only if no decision since it read memory changed what it read (the
+ * same chain, move for move); needs one species, at most 32 stencil cells,
+ * 2 x stencil cells x cell_cap <= 8192 and at most 1024 cells per axis.
+ * rows = -2:
+ * the paper's microcell thread mapping (Sec. 3.3.2), one move at a time, each
+ * thread of `waves` (4 or 8) wavefronts taking one stencil cell (several when
+ * the stencil is larger) and looping over the particles in it; any grid. */
 int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows);
 
 /* Bound on the in-kernel waits of the speculative and pipelined chains (a

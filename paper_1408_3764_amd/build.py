@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgcmc.so")
-SOURCES = ["box.hip", "moves.hip", "chain.hip", "spec.hip", "async.hip", "energy.hip", "api.hip", "noalloc.hip"]
+SOURCES = ["box.hip", "moves.hip", "chain.hip", "spec.hip", "async.hip", "micro.hip", "energy.hip", "api.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -452,7 +452,7 @@ struct gcmc_batch {
     int32_t* by_n;           // caller indices by decreasing N at create
     int32_t ngroups;         // boxes grouped by launch path and shape
     int32_t gstart[kMaxBatchGroups], gcount[kMaxBatchGroups];
-    int32_t gkey[kMaxBatchGroups][3];   // path (0 speculative, 1 pipelined, 2 per-move), waves, rows
+    int32_t gkey[kMaxBatchGroups][3];   // path (0 speculative, 1 pipelined, 2 per-move, 3 cell per thread), waves, rows
     hipStream_t side[kMaxBatchGroups];  // streams of groups 1.. (created when first needed)
     hipEvent_t ev_fork, ev_join[kMaxBatchGroups];
 };
@@ -465,6 +465,11 @@ int check_hip(hipError_t e, const char* what);
 int launch_chain(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int rows, int64_t n_moves,
                  uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 bool chain_cfg_exists(int waves, int rows);
+
+// micro.hip
+bool paper_cfg_exists(int waves);
+int launch_chain_paper(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
+                       uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 
 // spec.hip
 bool spec_supported(const DevBox& hb);

@@ -21,6 +21,8 @@ SPEC_SHAPES = [(2, 0), (4, 0), (8, 0), (16, 0)]
 # rows = -1: the pipelined kernel, one committer and waves - 1 evaluator wavefronts
 # (the same limits, plus at most 1024 cells per axis)
 ASYNC_SHAPES = [(4, -1), (8, -1)]
+# rows = -2: the paper's microcell mapping, one stencil cell per thread (any grid)
+PAPER_SHAPES = [(4, -2), (8, -2)]
 SPEC_OWN = 8192   # flattened candidates the 32-cell path of the speculative kernel can hold
 SPEC_MAX_STENCIL = 512   # stencil cells the speculative kernel takes (microcell path above 32)
 CACHE_ENV = "GCMC_TUNE_CACHE"

@@ -192,7 +192,7 @@ def test_delta_energy_c1_and_small_cells(c1):
 
 
 @pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (4, 8), (8, 4), (2, 0), (4, 0), (8, 0), (16, 0),
-                                        (4, -1), (8, -1)])
+                                        (4, -1), (8, -1), (4, -2), (8, -2)])
 def test_chain_launch_shapes_agree(c1, waves, rows):
     """Every launch shape gives the oracle's chain (the tuner may pick any)."""
     p = _params(c1)
@@ -205,7 +205,7 @@ def test_chain_launch_shapes_agree(c1, waves, rows):
 
 
 @pytest.mark.parametrize("cm", [[16, 16, 16], [21, 21, 21], [24, 24, 24]])
-@pytest.mark.parametrize("waves,rows", [(4, 4), (8, 2), (8, 0), (4, 0), (16, 0)])
+@pytest.mark.parametrize("waves,rows", [(4, 4), (8, 2), (8, 0), (4, 0), (16, 0), (8, -2)])
 def test_chain_microcells_agree(c1, cm, waves, rows):
     """Microcells (k = 2, 3; pruned stencils of up to several hundred cells): the
     chain kernel gives the oracle's chain, and the cell list it leaves behind
@@ -480,8 +480,9 @@ def test_chain_averages_match_oracle(c1, shape):
     assert ck["attempts"] == _type_counts(olog)[0] and ck["accepts"] == _type_counts(olog)[1]
 
 
-# the per-move kernel (the box's default launch) and the speculative kernel
-KERNELS = [None, (8, 0), (8, -1)]
+# the per-move kernel (the box's default launch), the speculative and pipelined kernels, and the
+# paper's cell-per-thread mapping
+KERNELS = [None, (8, 0), (8, -1), (8, -2)]
 
 
 def _launch(b, shape):
