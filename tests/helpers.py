@@ -76,8 +76,9 @@ def chain_parity(box, orc, start, p, seed, n_moves, beta, max_n, what="chain", U
     positions, energy and log ("opos", "oU", "olog"), the tie moves ("ties"),
     and the box's statistics of its last step ("stats"); fails on any
     difference away from a tie."""
-    t0 = orc.total_energy(start, p)
-    U0 = t0["U_pair"] + t0["U_tail"] if U0 is None else U0
+    if U0 is None:
+        t0 = orc.total_energy(start, p)
+        U0 = t0["U_pair"] + t0["U_tail"]
     opos, oU, olog = orc.chain(start, n_moves, p, seed=seed, max_n=max_n, U0=U0)
     ties = []
     m0 = 0
