@@ -117,6 +117,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ int32_t offs[64];
     __shared__ uint8_t own[E][kSpecOwn];
+    __shared__ double pq[E][kPairRing];   // each evaluator's queue of in-cutoff pairs
     __shared__ AsyncShared S;
     const int bi = order ? order[blockIdx.x] : (int)blockIdx.x;
     const DevBox B = hot_copy(boxes[blockIdx.x]);
@@ -190,7 +191,8 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             const int64_t N = uni64((int64_t)(uint32_t)cn);
             const double a_ins = unid(S.acc[0]), a_del = unid(S.acc[1]);
             const int s = target % kSlots;
-            spec_eval<CR, 0>(B, tab, offs, own[e], ctr0 + (uint64_t)C, target - C, N, no_full, a_ins, a_del, &S.rec[s]);
+            spec_eval<CR, 0, 0>(B, tab, offs, own[e], pq[e], nullptr, ctr0 + (uint64_t)C, target - C, N, no_full, a_ins,
+                                a_del, &S.rec[s]);
             if (lane == 0) {
                 S.slot_move[s] = target;
                 S.slot_epoch[s] = vis;

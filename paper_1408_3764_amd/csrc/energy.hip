@@ -919,286 +919,6 @@ __global__ __launch_bounds__(kBlk) void k_grad_finish(const DevBox* __restrict__
     }
 }
 
-// ------------------------------------------- passes with the stencil in LDS
-// For the paper's grid (cells of side >= rc: k = 1 on every axis, at least 4
-// cells per axis) the total energy, virial and gradient passes stage the
-// stencil in LDS: a workgroup takes T consecutive cells of one x-row as home
-// cells (T times the largest occupancy <= 256: one lane per home particle), and
-// for each of the nine (dy, dz) rows of their stencils loads the T + 2 cells
-// x0 - 1 .. x0 + T of that row, with the row's entries read by consecutive
-// threads (a cell's entries are contiguous), into LDS; every lane then takes
-// its particle through the three staged cells around its own.  A candidate
-// record comes from HBM/L2 once per workgroup instead of once per home cell.
-// The visiting order (dz, dy, dx, slot) is the stencil order of the passes
-// above.
-constexpr int kStageRecs = 640;   // staged entries (20 KB of LDS)
-
-struct StageTile {
-    int32_t y, z, x0, T;   // home cells (x0 .. x0 + T - 1, y, z)
-    bool wrap;             // a staged cell lies across a periodic face
-};
-
-__device__ __forceinline__ StageTile stage_tile(const DevBox& B, int T) {
-    const int tiles_x = (B.M[0] + T - 1) / T;
-    const int64_t b = blockIdx.x;
-    StageTile t;
-    t.x0 = (int32_t)(b % tiles_x) * T;
-    const int64_t row = b / tiles_x;
-    t.y = (int32_t)(row % B.M[1]);
-    t.z = (int32_t)(row / B.M[1]);
-    t.T = (B.M[0] - t.x0) < T ? B.M[0] - t.x0 : T;
-    t.wrap = t.x0 == 0 || t.x0 + t.T == B.M[0] || t.y == 0 || t.y == B.M[1] - 1 || t.z == 0 || t.z == B.M[2] - 1;
-    return t;
-}
-
-__device__ __forceinline__ int32_t wrap_idx(int32_t v, int32_t M) { return v < 0 ? v + M : (v >= M ? v - M : v); }
-
-// The tile's home particles: hoff[i] = first lane of home cell i (hoff[T] =
-// particles), and this lane's cell and slot.
-__device__ __forceinline__ void stage_homes(const DevBox& B, const StageTile& t, int32_t* hoff, int& hi,
-                                            int32_t& slot, bool& live) {
-    const int tid = threadIdx.x;
-    const int64_t c0 = ((int64_t)t.z * B.M[1] + t.y) * B.M[0] + t.x0;
-    if (tid < t.T) {
-        int32_t cnt = gload(B.count + c0 + tid);
-        hoff[tid + 1] = cnt < B.cap ? cnt : B.cap;
-    }
-    if (tid == 0) hoff[0] = 0;
-    __syncthreads();
-    if (tid == 0)
-        for (int i = 1; i <= t.T; ++i) hoff[i] += hoff[i - 1];
-    __syncthreads();
-    live = tid < hoff[t.T];
-    hi = 0;
-    if (live)
-        while (hoff[hi + 1] <= tid) ++hi;
-    slot = (int32_t)((c0 + hi) * B.cap + (tid - hoff[hi]));
-}
-
-// Stage row (dy, dz) of the tile's stencils: scnt[j] and srec[j * cap + k]
-// for the cells x0 - 1 + j, j = 0 .. T + 1.
-__device__ __forceinline__ void stage_row(const DevBox& B, const StageTile& t, int dy, int dz, int32_t* scnt,
-                                          double4* srec) {
-    const int tid = threadIdx.x;
-    const int32_t yy = wrap_idx(t.y + dy, B.M[1]), zz = wrap_idx(t.z + dz, B.M[2]);
-    const int64_t rowc = ((int64_t)zz * B.M[1] + yy) * B.M[0];
-    const int nc = t.T + 2;
-    __syncthreads();   // the previous row has been used
-    if (tid < nc) {
-        const int32_t cnt = gload(B.count + rowc + wrap_idx(t.x0 - 1 + tid, B.M[0]));
-        scnt[tid] = cnt < B.cap ? cnt : B.cap;
-    }
-    __syncthreads();
-    const int tot = nc * B.cap;
-    for (int idx = tid; idx < tot; idx += blockDim.x) {
-        const int j = idx / B.cap, k = idx - j * B.cap;
-        if (k < scnt[j]) srec[idx] = gload(B.ent + (rowc + wrap_idx(t.x0 - 1 + j, B.M[0])) * B.cap + k);
-    }
-    __syncthreads();
-}
-
-// e_i (or the per-particle virial) over the staged rows, pairs inside the
-// cutoff queued per wavefront as in home_energy.
-template <bool MIX, bool VIR, bool WRAP>
-__device__ __forceinline__ double staged_energy(const DevBox& B, const PassConst& K, const StageTile& t,
-                                                const double* te4, const double* ts2, int32_t* scnt, double4* srec,
-                                                const double4& me, int32_t myid, int sa, int ns, int hi, bool live,
-                                                const PairQueue& Q) {
-    const int lane = threadIdx.x & (kWave - 1);
-    Q.acc[lane] = 0.0;
-    uint32_t head = 0, tail = 0;
-    const int cap = B.cap;
-    for (int dz = -1; dz <= 1; ++dz) {
-        for (int dy = -1; dy <= 1; ++dy) {
-            stage_row(B, t, dy, dz, scnt, srec);
-            for (int a = 0; a < 3; ++a) {
-                const int j = hi + a;
-                const int32_t nc = live ? scnt[j] : 0;
-                const int32_t ncmax = wave_max_i32_uniform(nc);
-                const double4* ne = srec + j * cap;
-                for (int k = 0; k < ncmax; ++k) {
-                    bool in = false;
-                    double r2 = 0.0;
-                    int q = 0;
-                    if (k < nc) {
-                        const double4 o = ne[k];
-                        if (meta_low(o.w) != myid) {
-                            const double dx = image_diff(o.x - me.x, K.L[0], K.hL[0], WRAP);
-                            const double dyy = image_diff(o.y - me.y, K.L[1], K.hL[1], WRAP);
-                            const double dzz = image_diff(o.z - me.z, K.L[2], K.hL[2], WRAP);
-                            r2 = (dx * dx + dyy * dyy) + dzz * dzz;
-                            q = MIX ? sa * ns + meta_species(o.w) : 0;
-                            in = r2 < K.rc2 && (MIX ? te4[q] : K.e4) != 0.0;
-                        }
-                    }
-                    const uint64_t m = __ballot(in);
-                    if (in) {
-                        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        const uint32_t e = (tail + below) & (kRing - 1);
-                        Q.r2[e] = r2;
-                        Q.meta[e] = lane | (q << 8);
-                    }
-                    tail += (uint32_t)__builtin_popcountll(m);
-                    if (tail - head >= (uint32_t)kWave) {
-                        drain_pairs<MIX, VIR>(K, te4, ts2, Q, head, kWave, lane);
-                        head += kWave;
-                    }
-                }
-            }
-        }
-    }
-    if (tail != head) drain_pairs<MIX, VIR>(K, te4, ts2, Q, head, tail - head, lane);
-    return Q.acc[lane];
-}
-
-template <bool MIX, bool VIR = false>
-__global__ __launch_bounds__(kBlk) void k_total_staged(const DevBox* __restrict__ boxp, int T, double* e_out,
-                                                        double* partial) {
-    __shared__ double4 srec[kStageRecs];
-    __shared__ int32_t scnt[kBlk + 2];
-    __shared__ int32_t hoff[kBlk + 1];
-    __shared__ double red[kBlk / kWave];
-    __shared__ double te4[kMaxSpecies * kMaxSpecies], ts2[kMaxSpecies * kMaxSpecies];
-    __shared__ double q_r2[kBlk / kWave][kRing];
-    __shared__ int32_t q_meta[kBlk / kWave][kRing];
-    __shared__ double q_acc[kBlk];
-    const DevBox& B = *boxp;
-    load_species_tables(B, te4, ts2);
-    const PassConst K = pass_const(B);
-    const StageTile t = stage_tile(B, T);
-    int hi;
-    int32_t slot;
-    bool live;
-    stage_homes(B, t, hoff, hi, slot, live);
-    const int w = threadIdx.x / kWave;
-    const PairQueue Q{q_r2[w], q_meta[w], q_acc + w * kWave};
-    const double4 me = gload(B.ent + (live ? slot : 0));
-    const int32_t myid = meta_low(me.w);
-    const int sa = meta_species(me.w);
-    const int ns = uni(B.ns);
-    double ei = t.wrap ? staged_energy<MIX, VIR, true>(B, K, t, te4, ts2, scnt, srec, me, myid, sa, ns, hi, live, Q)
-                       : staged_energy<MIX, VIR, false>(B, K, t, te4, ts2, scnt, srec, me, myid, sa, ns, hi, live, Q);
-    if (!live) ei = 0.0;
-    if (live && e_out) e_out[myid] = ei;
-    const double s = block_sum(ei, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-template <bool MIX>
-__global__ __launch_bounds__(kBlk) void k_grad_staged(const DevBox* __restrict__ boxp, int T, int64_t n,
-                                                       double* grad, double* partial) {
-    __shared__ double4 srec[kStageRecs];
-    __shared__ int32_t scnt[kBlk + 2];
-    __shared__ int32_t hoff[kBlk + 1];
-    __shared__ double red[kBlk / kWave];
-    __shared__ double te4[kMaxSpecies * kMaxSpecies], ts2[kMaxSpecies * kMaxSpecies];
-    const DevBox& B = *boxp;
-    load_species_tables(B, te4, ts2);
-    const PassConst K = pass_const(B);
-    const StageTile t = stage_tile(B, T);
-    int hi;
-    int32_t slot;
-    bool live;
-    stage_homes(B, t, hoff, hi, slot, live);
-    const int ns = uni(B.ns);
-    const double4 me = gload(B.ent + (live ? slot : 0));
-    const int32_t myid = meta_low(me.w);
-    const int sa = meta_species(me.w);
-    GradAcc A;
-    A.gx = A.gy = A.gz = 0.0;
-#pragma unroll
-    for (int b = 0; b < kMaxSpecies; ++b) A.de[b] = A.ds[b] = 0.0;
-    const int cap = B.cap;
-    for (int dz = -1; dz <= 1; ++dz) {
-        for (int dy = -1; dy <= 1; ++dy) {
-            stage_row(B, t, dy, dz, scnt, srec);
-            if (!live) continue;
-            for (int a = 0; a < 3; ++a) {
-                const int j = hi + a;
-                const int32_t nc = scnt[j];
-                const double4* ne = srec + j * cap;
-                for (int k = 0; k < nc; ++k) {
-                    const double4 o = ne[k];
-                    if (meta_low(o.w) == myid) continue;
-                    // the minimum image always (as the gradient pass above)
-                    const double dx = nearest_image(o.x - me.x, K.L[0], K.hL[0]);
-                    const double dyy = nearest_image(o.y - me.y, K.L[1], K.hL[1]);
-                    const double dzz = nearest_image(o.z - me.z, K.L[2], K.hL[2]);
-                    const double r2 = (dx * dx + dyy * dyy) + dzz * dzz;
-                    if (!(r2 < K.rc2) || r2 == 0.0) continue;
-                    const int sb = meta_species(o.w);
-                    const int q = MIX ? sa * ns + sb : 0;
-                    const double eps4 = MIX ? te4[q] : K.e4, sig2 = MIX ? ts2[q] : K.s2;
-                    const double sr2 = sig2 / r2;
-                    const double s6 = sr2 * sr2 * sr2;
-                    const double s12 = s6 * s6;
-                    const double coef = (6.0 * eps4 / r2) * (2.0 * s12 - s6);
-                    A.gx += coef * dx;
-                    A.gy += coef * dyy;
-                    A.gz += coef * dzz;
-                    const double t_e = 0.5 * 4.0 * (s12 - s6);
-                    const double t_s = 0.5 * (eps4 / sqrt(sig2)) * (12.0 * s12 - 6.0 * s6);
-                    if (MIX) {
-#pragma unroll
-                        for (int b = 0; b < kMaxSpecies; ++b)
-                            if (b == sb) {
-                                A.de[b] += t_e;
-                                A.ds[b] += t_s;
-                            }
-                    } else {
-                        A.de[0] += t_e;
-                        A.ds[0] += t_s;
-                    }
-                }
-            }
-        }
-    }
-    if (live && grad) {
-        grad[myid] = A.gx;
-        grad[n + myid] = A.gy;
-        grad[2 * n + myid] = A.gz;
-    }
-    for (int a = 0; a < ns; ++a) {
-        for (int b = 0; b < ns; ++b) {
-            const bool mine = live && sa == a;
-            double le = 0.0, ls = 0.0;
-#pragma unroll
-            for (int q = 0; q < kMaxSpecies; ++q)
-                if (q == b) {
-                    le = A.de[q];
-                    ls = A.ds[q];
-                }
-            const double ve = block_sum(mine ? le : 0.0, red);
-            const double vs = block_sum(mine ? ls : 0.0, red);
-            if (threadIdx.x == 0) {
-                partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + a * ns + b] = ve;
-                partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + kMaxSpecies * kMaxSpecies + a * ns + b] =
-                    vs;
-            }
-        }
-    }
-}
-
-// Home cells per workgroup of the staged passes, or 0 where they do not apply
-// (another grid; occupancies too large for one row of cells in LDS).
-static int stage_cells(const DevBox& hb, int32_t maxc) {
-    for (int a = 0; a < 3; ++a)
-        if (hb.k[a] != 1 || hb.full[a] || hb.M[a] < 4) return 0;
-    if (hb.nstencil != 27) return 0;
-    const int m = maxc < 1 ? 1 : (maxc > hb.cap ? hb.cap : maxc);
-    int T = kBlk / m;
-    const int by_lds = kStageRecs / hb.cap - 2;
-    if (by_lds < T) T = by_lds;
-    if (T > hb.M[0]) T = hb.M[0];
-    if (T > kBlk - 2) T = kBlk - 2;   // one thread per staged cell counter (T + 2 cells)
-    return T >= 1 ? T : 0;
-}
-
-static int64_t stage_blocks(const DevBox& hb, int T) {
-    return (int64_t)((hb.M[0] + T - 1) / T) * hb.M[1] * hb.M[2];
-}
-
 // ------------------------------------------------------------ launchers
 // Scratch layout of a cell-list pass (in doubles): the block partials (times
 // `stride` doubles per block), then, as int32, the particles in cell order
@@ -1236,13 +956,6 @@ int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_p
             hipLaunchKernelGGL(k_total_allpairs<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, e_out, partial);
         else
             hipLaunchKernelGGL(k_total_allpairs<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, e_out, partial);
-    } else if (const int T = stage_cells(hb, maxc)) {
-        nb = stage_blocks(hb, T);
-        if (nb > partial_len) return -1;
-        if (mix)
-            hipLaunchKernelGGL(k_total_staged<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, T, e_out, partial);
-        else
-            hipLaunchKernelGGL(k_total_staged<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, T, e_out, partial);
     } else {
         nb = cell_pass_blocks(n);
         if (cell_pass_doubles(hb, n, 1) > partial_len) return -1;
@@ -1260,62 +973,40 @@ int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_p
 
 int launch_virial(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* partial, int64_t partial_len,
                   double* out, hipStream_t s, int64_t n) {
-    int64_t nb;
-    if (const int T = stage_cells(hb, maxc)) {
-        nb = stage_blocks(hb, T);
-        if (nb > partial_len) return -1;
-        if (hb.ns > 1)
-            hipLaunchKernelGGL((k_total_staged<true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, T, nullptr,
-                               partial);
-        else
-            hipLaunchKernelGGL((k_total_staged<false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, T,
-                               nullptr, partial);
-    } else {
-        nb = cell_pass_blocks(n);
-        if (cell_pass_doubles(hb, n, 1) > partial_len) return -1;
-        const int32_t* home = cell_order(hb, n, partial, nb, s);
-        if (hb.ns > 1)
-            hipLaunchKernelGGL((k_total_cells<true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
-                               nullptr, partial);
-        else
-            hipLaunchKernelGGL((k_total_cells<false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
-                               nullptr, partial);
-    }
+    (void)maxc;
+    const int64_t nb = cell_pass_blocks(n);
+    if (cell_pass_doubles(hb, n, 1) > partial_len) return -1;
+    const int32_t* home = cell_order(hb, n, partial, nb, s);
+    if (hb.ns > 1)
+        hipLaunchKernelGGL((k_total_cells<true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
+                           nullptr, partial);
+    else
+        hipLaunchKernelGGL((k_total_cells<false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
+                           nullptr, partial);
     hipLaunchKernelGGL(k_virial_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, out);
     return 0;
 }
 
 int64_t total_partials_needed(const DevBox& hb, int32_t maxc, bool all_pairs, int64_t n) {
+    (void)maxc;
     if (all_pairs) return (n + kBlk - 1) / kBlk + 1;
-    if (const int T = stage_cells(hb, maxc)) return stage_blocks(hb, T);
     return cell_pass_doubles(hb, n, 1);
 }
 
 int64_t grad_partials_needed(const DevBox& hb, int32_t maxc, int64_t n) {
-    if (const int T = stage_cells(hb, maxc)) return stage_blocks(hb, T) * 2 * kMaxSpecies * kMaxSpecies;
+    (void)maxc;
     return cell_pass_doubles(hb, n, 2 * kMaxSpecies * kMaxSpecies);
 }
 
 int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* grad, double* partial, double* deps,
                 double* dsig, hipStream_t s, int64_t n) {
-    int64_t nb;
-    if (const int T = stage_cells(hb, maxc)) {
-        nb = stage_blocks(hb, T);
-        if (hb.ns > 1)
-            hipLaunchKernelGGL(k_grad_staged<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, T, n, grad, partial);
-        else
-            hipLaunchKernelGGL(k_grad_staged<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, T, n, grad,
-                               partial);
-    } else {
-        nb = cell_pass_blocks(n);
-        const int32_t* home = cell_order(hb, n, partial, nb * 2 * kMaxSpecies * kMaxSpecies, s);
-        if (hb.ns > 1)
-            hipLaunchKernelGGL(k_grad_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad,
-                               partial);
-        else
-            hipLaunchKernelGGL(k_grad_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad,
-                               partial);
-    }
+    (void)maxc;
+    const int64_t nb = cell_pass_blocks(n);
+    const int32_t* home = cell_order(hb, n, partial, nb * 2 * kMaxSpecies * kMaxSpecies, s);
+    if (hb.ns > 1)
+        hipLaunchKernelGGL(k_grad_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad, partial);
+    else
+        hipLaunchKernelGGL(k_grad_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad, partial);
     if (deps || dsig)
         hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, deps, dsig);
     return 0;

@@ -54,6 +54,19 @@ __device__ __forceinline__ double spec_arg(const DevBox& B, int type, double dUp
     return is_disp ? -(B.beta * dU) : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
 }
 
+// Entry t of a prefactor table starting at N = nb: t < 4W, the log insertion
+// prefactor V / (Lambda^3 (N + 1)) at N = nb + t; t >= 4W, the log deletion
+// prefactor Lambda^3 N / V at N = nb + t - 4W (entries at N < 0 are never read).
+template <int W>
+__device__ __forceinline__ void spec_prefactor(const DevBox& B, double* lpi, double* lpd, int64_t nb, int t) {
+    const bool del = t >= 4 * W;
+    const int64_t n = nb + (del ? t - 4 * W : t);
+    const double x = del ? (B.lambda3 * (double)n) / B.V : B.V / (B.lambda3 * (double)(n + 1));
+    const double lx = log(x);
+    if (del) lpd[t - 4 * W] = lx;
+    else lpi[t] = lx;
+}
+
 template <int W, int CR, int NG>
 __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restrict__ boxes,
                                                           const int32_t* __restrict__ order, int64_t n_moves,
@@ -64,7 +77,12 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     __shared__ SpecRec recs[W];
     __shared__ uint32_t own[W][kSpecOwn / 4];         // owner bytes, or record indices (NG > 0)
     __shared__ double4 top[2 * W];              // records of particles base .. base + 2W - 1
-    __shared__ double lp_ins[2 * W], lp_del[2 * W];   // acceptance prefactors at N = base + t
+    // log acceptance prefactors at N = lp_base[b] + t, t < 4W, two buffers: the round's and the next round's
+    __shared__ double lp_ins[2][4 * W], lp_del[2][4 * W];
+    __shared__ int64_t lp_base[2];
+    __shared__ DrawRing<2 * W> dring;           // draws of moves m .. m + 2W - 1
+    __shared__ double pq[W][kPairRing];         // each wavefront's queue of in-cutoff pairs
+    __shared__ int32_t ticket;                  // round whose next-round tables a wavefront has taken on
     __shared__ int64_t sh_state[4];       // N, moves done, error, error move
     __shared__ double sh_u, sh_w;
     __shared__ double sh_acc[2];
@@ -105,6 +123,11 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         if (t < kOffs) offs[t] = ((tz - B.k[2]) * B.M[1] + (ty - B.k[1])) * B.M[0] + (tx - B.k[0]);
     }
     if (tid < W) ready[tid] = -1;
+    if (tid == 0) ticket = 0;
+    // draws of the first 2W moves and the prefactors of the first round (its buffer: 1)
+    for (int t = tid; t < 8 * W; t += blockDim.x) draw_block(B, &dring, ctr0 + (uint64_t)(t >> 2), t & 3);
+    for (int t = tid; t < 8 * W; t += blockDim.x) spec_prefactor<W>(B, lp_ins[1], lp_del[1], N - 2 * W, t);
+    if (tid == 0) lp_base[1] = N - 2 * W;
     __syncthreads();
     if (err == GCMC_OK && B.ns != 1) {
         err = GCMC_ERR_UNSUPPORTED;
@@ -116,24 +139,23 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     while (err == GCMC_OK && m < n_moves) {
         const int64_t base = N - W;
         rnd = rnd == INT32_MAX ? 1 : rnd + 1;   // round numbers stay positive (a flag starts at -1)
-        // ------------------------------------------------ the round tables (wavefront 0 decides with them)
+        // issue priority on each SIMD: the moves decided first evaluate first (the two
+        // wavefronts sharing a SIMD are w and w + 4 when W = 8); wavefront 0 raises its own
+        // for the commit
+        if (wv < (W + 1) / 2) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(1);
+        // the round's prefactor table (filled before the round began)
+        const int tb = rnd & 1;
+        const int64_t lbase = lp_base[tb];
+        const double* lpi = lp_ins[tb];
+        const double* lpd = lp_del[tb];
+        // ------------------------------------------------ the round's particle records (wavefront 0 commits with them)
         double4 tv = make_double4(0, 0, 0, 0);
-        if (wv == 0) {
-            if (lane < W && base + lane >= 0) tv = gload(B.pos + base + lane);
-            // lanes 0 .. 2W-1: insertion prefactor at N = base + lane; lanes 2W .. 4W-1: deletion
-            // prefactor at N = base + lane - 2W
-            if (lane < 4 * W) {
-                const bool del = lane >= 2 * W;
-                const int64_t n = base + (del ? lane - 2 * W : lane);
-                const double x = del ? (B.lambda3 * (double)n) / B.V : B.V / (B.lambda3 * (double)(n + 1));
-                const double lx = log(x);
-                if (del) lp_del[lane - 2 * W] = lx;
-                else lp_ins[lane] = lx;
-            }
-        }
+        if (wv == 0 && lane < W && base + lane >= 0) tv = gload(B.pos + base + lane);
         // ------------------------------------------------ evaluate W moves
         if (m + wv < n_moves)
-            spec_eval<CR, NG>(B, tab, offs, own[wv], ctr0 + (uint64_t)m, wv, N, no_full, a_ins, a_del, &recs[wv]);
+            spec_eval<CR, NG, 2 * W>(B, tab, offs, own[wv], pq[wv], &dring, ctr0 + (uint64_t)m, wv, N, no_full, a_ins,
+                                     a_del, &recs[wv]);
         if (wv != 0) {
             // publish this move's record: wavefront 0 decides it as soon as its turn comes, while
             // slower wavefronts still evaluate.  A commit may then store to memory that a later
@@ -141,9 +163,24 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
             // stencil holds a modified cell, or its particle was touched) and is discarded.
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
             if (lane == 0) __hip_atomic_store(&ready[wv], rnd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_s_setprio(0);
+            // the first wavefront to publish prepares the next round's tables while the others
+            // still evaluate: the draws of moves m + W .. m + 2W - 1 (the next round takes moves
+            // m + k .. m + k + W - 1 with 1 <= k <= W; the others are in the ring already) and
+            // the prefactors for every N the next round can reach (within 2W - 1 of this
+            // round's N).  The barrier at the end of the round makes them visible.
+            int32_t prev = 0;
+            if (lane == 0) prev = __hip_atomic_exchange(&ticket, rnd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (__builtin_amdgcn_readfirstlane(prev) != rnd) {
+                if (lane < 4 * W)
+                    draw_block(B, &dring, ctr0 + (uint64_t)(m + W) + (uint64_t)(lane >> 2), lane & 3);
+                for (int t = lane; t < 8 * W; t += kWave) spec_prefactor<W>(B, lp_ins[tb ^ 1], lp_del[tb ^ 1], N - 2 * W, t);
+                if (lane == 0) lp_base[tb ^ 1] = N - 2 * W;
+            }
         }
         // ------------------------------------------------ in-order commit
         if (wv == 0) {
+            __builtin_amdgcn_s_setprio(3);
             if (lane < W && base + lane >= 0) top[lane] = tv;
             // this wavefront's own table and record writes, seen by all of its lanes
             __builtin_amdgcn_wave_barrier();
@@ -197,7 +234,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
                 const double dUp = R.dUp;
                 double dUt;
-                const double arg = spec_arg(B, type, dUp, N, base, lp_ins, lp_del, tk, dUt);
+                const double arg = spec_arg(B, type, dUp, N, lbase, lpi, lpd, tk, dUt);
                 const double dU = dUp + dUt;
                 const bool ok = __builtin_amdgcn_readfirstlane((dU == dU && R.lnA < arg) ? 1 : 0) != 0;
                 const int two = R.two;
@@ -363,7 +400,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                         const int64_t dn = a ? (t == GCMC_MOVE_INSERT ? 1 : (t == GCMC_MOVE_DELETE ? -1 : 0)) : 0;
                         const int64_t n_before = after_n[lane] - dn;
                         double dUt;
-                        r.arg = spec_arg(B, t, S.dUp, n_before, base, lp_ins, lp_del, tk, dUt);
+                        r.arg = spec_arg(B, t, S.dUp, n_before, lbase, lpi, lpd, tk, dUt);
                         r.index = t == GCMC_MOVE_INSERT ? (int32_t)n_before : (int32_t)S.idx;
                         r.accepted = a ? 1 : 0;
                         r.flags = 0;
@@ -390,6 +427,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 sh_acc[1] = (acc2 + 1.0) / (att2 + 2.0);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();   // commit stores done and visible; the new state published
         N = sh_state[0];
         m = sh_state[1];

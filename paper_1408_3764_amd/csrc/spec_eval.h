@@ -16,6 +16,17 @@
 // groups, and the flattened candidates' record indices are written to an LDS
 // table that is filled and consumed in windows, so a move may have any number
 // of candidates.
+//
+// Only about one candidate in seven lies inside the cutoff, and a wavefront
+// executes the Lennard-Jones arithmetic whenever one of its lanes needs it.
+// So the candidate pass only computes squared distances; the in-cutoff ones
+// are queued in a per-wavefront ring in LDS (the sign bit marks the second
+// position of a displacement) and the pair energies and virials are
+// evaluated 64 at a time, one per lane.
+//
+// The draws (move type, pick, position, ln A) come either from a ring of
+// draws in LDS that the round kernel fills once per round for the moves it may
+// take next, or are computed here (the pipelined kernel).
 #pragma once
 #include "trial.h"
 
@@ -26,6 +37,119 @@ constexpr int kSpecRecWin = kSpecOwn / 4;   // record indices per window of the 
 constexpr int kSpecGroups = 16;      // groups of 64 stencil cells: stencils of up to 512 cells (two for a displacement)
 constexpr int kSpecMaxStencil = kSpecGroups * kWave / 2;
 constexpr int kSpecGroupsSmall = 4;  // the instantiation for stencils of up to 128 cells (fewer registers)
+constexpr int kPairRing = 128;       // queued in-cutoff pairs per wavefront (a power of two, >= 2 x 64)
+
+// Draws of the moves a round may take, one slot per move (slot = move counter
+// mod RING, RING a power of two): move type, pick draw, ln A, and the three
+// position draws (insertion point, or the displacement).
+template <int RING>
+struct DrawRing {
+    double u2[RING], lnA[RING], px[RING], py[RING], pz[RING];
+    int32_t type[RING];
+};
+
+// Philox block `b` of move `ctr` into its ring slot (one lane per block:
+// block 0 gives the type, 1 the pick draw and ln A, 2 and 3 the position
+// draws).
+template <int RING>
+__device__ __forceinline__ void draw_block(const DevBox& B, DrawRing<RING>* dr, uint64_t ctr, int b) {
+    uint32_t c0 = (uint32_t)ctr, c1 = (uint32_t)(ctr >> 32), c2 = B.box_id, c3 = (uint32_t)b;
+    philox_block(c0, c1, c2, c3, (uint32_t)B.seed, (uint32_t)(B.seed >> 32));
+    const double ua = to_unit(c0, c1), ub = to_unit(c2, c3);
+    const int s = (int)(ctr & (uint64_t)(RING - 1));
+    if (b == 0) {
+        dr->type[s] = (ua < B.p_disp) ? GCMC_MOVE_DISPLACE : ((ub < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
+    } else if (b == 1) {
+        dr->u2[s] = ua;
+        dr->lnA[s] = log(ub);
+    } else if (b == 2) {
+        dr->px[s] = ua;
+        dr->py[s] = ub;
+    } else {
+        dr->pz[s] = ua;
+    }
+}
+
+// Per-wavefront queue of in-cutoff squared distances.  push: the lanes with
+// `in` append v (ballot order); drain: lane l takes entry head + l of the
+// next `cnt` and adds its pair energy and virial to the first position's sums,
+// or the second's when v carries the sign bit.
+__device__ __forceinline__ void pair_push(double* q, uint32_t& tail, bool in, double v) {
+    const uint64_t m = __ballot(in);
+    if (in) {
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        q[(tail + below) & (kPairRing - 1)] = v;
+    }
+    tail += (uint32_t)__builtin_popcountll(m);
+}
+
+__device__ __forceinline__ void pair_drain(const DevBox& B, const double* q, uint32_t head, uint32_t cnt, double& sa,
+                                           double& sb, double& wa, double& wb) {
+    // the entries other lanes wrote, visible to every lane
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    if (lane < cnt) {
+        const double v = q[(head + lane) & (kPairRing - 1)];
+        const bool second = __builtin_signbit(v);
+        const double r2 = second ? -v : v;
+        double w = 0.0;
+        const double u = lj_uw_from_r2(r2, B.rc2, B.eps4[0], B.sig2[0], w);
+        if (second) {
+            sb += u;
+            wb += w;
+        } else {
+            sa += u;
+            wa += w;
+        }
+    }
+    // every lane has read its entry before later pushes reuse the slots
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+}
+
+// Squared distances of one candidate record to the move's position(s),
+// queued when inside the cutoff (counts of evaluated and in-cutoff pairs kept
+// per lane).
+__device__ __forceinline__ void spec_pair_queue(const DevBox& B, int type, int two, bool valid, bool second,
+                                                const double* p0, const double* p1, const double3& e, double* q,
+                                                uint32_t& head, uint32_t& tail, double& sa, double& sb, double& wa,
+                                                double& wb, int32_t& n_eval, int64_t& incut) {
+    const bool disp = type == GCMC_MOVE_DISPLACE;
+    // the first position: every move but the second stencil of a displacement that leaves its cell
+    const bool use0 = valid && !(disp && two && second);
+    const bool use1 = valid && disp && (!two || second);
+    double r2a = 0.0, r2b = 0.0;
+    if (use0) r2a = dist2(B, p0[0], p0[1], p0[2], e.x, e.y, e.z);
+    const bool in0 = use0 && r2a < B.rc2;
+    n_eval += use0 ? 1 : 0;
+    incut += in0 ? 1 : 0;
+    pair_push(q, tail, in0, r2a);
+    if (tail - head >= (uint32_t)kWave) {
+        pair_drain(B, q, head, kWave, sa, sb, wa, wb);
+        head += kWave;
+    }
+    if (disp) {
+        if (use1) r2b = dist2(B, p1[0], p1[1], p1[2], e.x, e.y, e.z);
+        const bool in1 = use1 && r2b < B.rc2;
+        n_eval += use1 ? 1 : 0;
+        incut += in1 ? 1 : 0;
+        pair_push(q, tail, in1, -r2b);
+        if (tail - head >= (uint32_t)kWave) {
+            pair_drain(B, q, head, kWave, sa, sb, wa, wb);
+            head += kWave;
+        }
+    }
+}
+
+// The coordinates of a 32-byte record (its fourth word, the id, is not
+// needed: a move's own particle is excluded by its slot).
+__device__ __forceinline__ double3 gload_xyz(const double4* p) {
+    typedef double gcmc_d2v __attribute__((ext_vector_type(2)));
+    const GCMC_GLOBAL_AS double* q = (const GCMC_GLOBAL_AS double*)p;
+    const gcmc_d2v xy = *(const GCMC_GLOBAL_AS gcmc_d2v*)q;
+    return make_double3(xy.x, xy.y, q[2]);
+}
 
 struct SpecRec {
     double dUp, lnA, u2, dWp;   // pair energy change, ln A, pick draw, pair virial change
@@ -78,62 +202,68 @@ __device__ __forceinline__ bool in_stencil(const DevBox& B, int32_t x, int32_t y
     return in;
 }
 
-// One candidate record against the move's position(s): energy and virial sums.
-__device__ __forceinline__ void spec_pair(const DevBox& B, int type, int two, bool second, const double* p0,
-                                          const double* p1, const double4& e, double& sa, double& sb, double& wa,
-                                          double& wb, int32_t& n_eval, int64_t& incut) {
-    if (type != GCMC_MOVE_DISPLACE) {
-        sa += pair_uw<false>(B, p0, 0, e, incut, wa);
-        n_eval += 1;
-    } else if (!two) {
-        sa += pair_uw<false>(B, p0, 0, e, incut, wa);
-        sb += pair_uw<false>(B, p1, 0, e, incut, wb);
-        n_eval += 2;
-    } else if (second) {
-        sb += pair_uw<false>(B, p1, 0, e, incut, wb);
-        n_eval += 1;
-    } else {
-        sa += pair_uw<false>(B, p0, 0, e, incut, wa);
-        n_eval += 1;
-    }
-}
-
 // Wavefront k evaluates move ctr_round + k against the current state.  NG:
 // 0 for the 32-cell path, else the number of groups of 64 stencil cells the
-// microcell path provides (see above).
-template <int CR, int NG>
+// microcell path provides (see above).  RING > 0: the draws come from `dr`
+// (the moves ctr_round .. ctr_round + k must be in it); RING = 0: computed
+// here, for k < 16.  pq: this wavefront's pair queue (kPairRing doubles of
+// LDS).
+template <int CR, int NG, int RING>
 __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, const int32_t* offs, void* ownbuf,
-                                          uint64_t ctr_round, int k, int64_t N, bool no_full, double a_ins,
-                                          double a_del, SpecRec* out) {
+                                          double* pq, const DrawRing<RING>* dr, uint64_t ctr_round, int k, int64_t N,
+                                          bool no_full, double a_ins, double a_del, SpecRec* out) {
     const int lane = threadIdx.x & (kWave - 1);
-    // draws of the round's moves: lane 4j + b computes Philox block b of move ctr_round + j
-    double ua, ub;
-    {
-        const uint64_t c = ctr_round + (uint64_t)(lane >> 2);
-        uint32_t c0 = (uint32_t)c, c1 = (uint32_t)(c >> 32), c2 = B.box_id, c3 = (uint32_t)(lane & 3);
-        philox_block(c0, c1, c2, c3, (uint32_t)B.seed, (uint32_t)(B.seed >> 32));
-        ua = to_unit(c0, c1);
-        ub = to_unit(c2, c3);
-    }
-    U8 u;
+    int type;
+    double u2, lnA, ux, uy, uz;
+    int64_t D, I;
+    if constexpr (RING > 0) {
+        // the round's draws from the ring; lane j < k reads the type of the j-th earlier move
+        const int s = (int)((ctr_round + (uint64_t)k) & (uint64_t)(RING - 1));
+        type = uni(dr->type[s]);
+        u2 = dr->u2[s];
+        lnA = dr->lnA[s];
+        ux = dr->px[s];
+        uy = dr->py[s];
+        uz = dr->pz[s];
+        const int tj = lane < k ? dr->type[(int)((ctr_round + (uint64_t)lane) & (uint64_t)(RING - 1))] : -1;
+        D = __popcll(__ballot(tj == GCMC_MOVE_DELETE));
+        I = __popcll(__ballot(tj == GCMC_MOVE_INSERT));
+    } else {
+        // draws of the round's moves: lane 4j + b computes Philox block b of move ctr_round + j
+        double ua, ub;
+        {
+            const uint64_t c = ctr_round + (uint64_t)(lane >> 2);
+            uint32_t c0 = (uint32_t)c, c1 = (uint32_t)(c >> 32), c2 = B.box_id, c3 = (uint32_t)(lane & 3);
+            philox_block(c0, c1, c2, c3, (uint32_t)B.seed, (uint32_t)(B.seed >> 32));
+            ua = to_unit(c0, c1);
+            ub = to_unit(c2, c3);
+        }
+        U8 u;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        u.u[2 * q] = read_lane(ua, 4 * k + q);
-        u.u[2 * q + 1] = read_lane(ub, 4 * k + q);
+        for (int q = 0; q < 4; ++q) {
+            u.u[2 * q] = read_lane(ua, 4 * k + q);
+            u.u[2 * q + 1] = read_lane(ub, 4 * k + q);
+        }
+        type = __builtin_amdgcn_readfirstlane(spec_type(B, u));
+        u2 = u.u[2];
+        lnA = log(u.u[3]);
+        ux = u.u[4];
+        uy = u.u[5];
+        uz = u.u[6];
+        // insertions (I) and deletions (D) among the earlier moves of the round: N at this
+        // move's commit lies in [N - D, N + I]
+        const int tj = (ua < B.p_disp) ? GCMC_MOVE_DISPLACE : ((ub < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
+        const bool earlier = (lane & 3) == 0 && (lane >> 2) < k;
+        D = __popcll(__ballot(earlier && tj == GCMC_MOVE_DELETE));
+        I = __popcll(__ballot(earlier && tj == GCMC_MOVE_INSERT));
     }
-    const int type = __builtin_amdgcn_readfirstlane(spec_type(B, u));
-    // insertions (I) and deletions (D) among the earlier moves of the round: N at this
-    // move's commit lies in [N - D, N + I]
-    const int tj = (ua < B.p_disp) ? GCMC_MOVE_DISPLACE : ((ub < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
-    const bool earlier = (lane & 3) == 0 && (lane >> 2) < k;
-    const int64_t D = __popcll(__ballot(earlier && tj == GCMC_MOVE_DELETE));
-    const int64_t I = __popcll(__ballot(earlier && tj == GCMC_MOVE_INSERT));
+    const double ud[3] = {ux, uy, uz};
     if (type != GCMC_MOVE_INSERT && N == 0) {
         if (lane == 0) {
             out->type = type;
             out->flags = 1;
             out->lnA = 0.0;
-            out->u2 = u.u[2];
+            out->u2 = u2;
             out->cand = out->evals = out->incut = 0;
         }
         return;
@@ -143,13 +273,13 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     double p0[3], p1[3];
     if (type == GCMC_MOVE_INSERT) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) p0[a] = wrap_into_box(B.L[a] * u.u[4 + a], B.L[a]);
+        for (int a = 0; a < 3; ++a) p0[a] = wrap_into_box(B.L[a] * ud[a], B.L[a]);
     } else {
         // the pick at the N expected at commit from the running acceptance rates
         const int64_t n_lo = (N - D) > 1 ? (N - D) : 1, n_hi = N + I;
         int64_t n_c = (int64_t)floor((double)N + (double)I * a_ins - (double)D * a_del + 0.5);
         n_c = uni64(n_c < n_lo ? n_lo : (n_c > n_hi ? n_hi : n_c));
-        idx = spec_pick(u.u[2], n_c);
+        idx = spec_pick(u2, n_c);
         rec = gload(B.pos + idx);
         p0[0] = rec.x; p0[1] = rec.y; p0[2] = rec.z;
     }
@@ -162,7 +292,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     if (type == GCMC_MOVE_DISPLACE) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            p1[a] = wrap_into_box(p0[a] + B.max_disp * (2.0 * u.u[4 + a] - 1.0), B.L[a]);
+            p1[a] = wrap_into_box(p0[a] + B.max_disp * (2.0 * ud[a] - 1.0), B.L[a]);
             c1[a] = spec_axis_cell(p1[a], B.invS[a], B.M[a]);
         }
         cl1 = (c1[2] * B.M[1] + c1[1]) * B.M[0] + c1[0];
@@ -188,10 +318,12 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
                               : 0) != 0;
     int32_t cnt0 = 0, cnt1 = 0;
     double4 elast = make_double4(0, 0, 0, 0);
-    const int32_t excl = (int32_t)idx;
+    // the slot of the moving particle's own record in the cell array (never a candidate of itself)
+    const int32_t excl_slot = type == GCMC_MOVE_INSERT ? -1 : meta_low(rec.w);
     double sa = 0.0, sb = 0.0, wa = 0.0, wb = 0.0;
     int32_t n_cand = 0, n_eval = 0, n_in = 0;
     int64_t incut = 0;
+    uint32_t qhead = 0, qtail = 0;   // the in-cutoff pair queue (wave-uniform counters)
     if constexpr (NG == 0) {
         const int wh = lane >= nst ? 1 : 0;
         const int t = lane - wh * nst;
@@ -224,37 +356,25 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
         if (cnt0 > 0) elast = gload(B.ent + ((size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)));
         // ---- candidates
         for (int base = 0; base < total; base += kWave * CR) {
-            double4 e[CR];
+            double3 e[CR];
             int32_t wsel[CR];
             bool ok[CR];
     #pragma unroll
             for (int r = 0; r < CR; ++r) {
                 const int q = base + r * kWave + lane;
-                ok[r] = q < total;
-                const int j = ok[r] ? own[q] : 0;
+                const int j = q < total ? own[q] : 0;
                 const int32_t cb = __shfl(cellbase, j, kWave);
+                const int32_t ri = q < total ? cb + q : cl0 * B.cap;
+                ok[r] = q < total && ri != excl_slot;
                 wsel[r] = j >= nst ? 1 : 0;
-                e[r] = gload(B.ent + (size_t)(uint32_t)(ok[r] ? cb + q : cl0 * B.cap));
+                e[r] = gload_xyz(B.ent + (size_t)(uint32_t)ri);
             }
     #pragma unroll
             for (int r = 0; r < CR; ++r) {
-                if (ok[r] && meta_low(e[r].w) != excl) {
-                    n_cand += 1;
-                    if (type != GCMC_MOVE_DISPLACE) {
-                        sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
-                        n_eval += 1;
-                    } else if (!two) {
-                        sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
-                        sb += pair_uw<false>(B, p1, 0, e[r], incut, wb);
-                        n_eval += 2;
-                    } else if (wsel[r]) {
-                        sb += pair_uw<false>(B, p1, 0, e[r], incut, wb);
-                        n_eval += 1;
-                    } else {
-                        sa += pair_uw<false>(B, p0, 0, e[r], incut, wa);
-                        n_eval += 1;
-                    }
-                }
+                const bool valid = ok[r];
+                n_cand += valid ? 1 : 0;
+                spec_pair_queue(B, type, two, valid, wsel[r] != 0, p0, p1, e[r], pq, qhead, qtail, sa, sb, wa, wb,
+                                n_eval, incut);
             }
         }
 
@@ -317,22 +437,22 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
             for (int base = q0; base < q1; base += kWave * CR) {
-                double4 e[CR];
+                double3 e[CR];
                 bool ok[CR], sec[CR];
 #pragma unroll
                 for (int r = 0; r < CR; ++r) {
                     const int q = base + r * kWave + lane;
-                    ok[r] = q < q1;
-                    const uint32_t v = ok[r] ? recw[q - q0] : (uint32_t)cl0 * (uint32_t)B.cap;
+                    const uint32_t v = q < q1 ? recw[q - q0] : (uint32_t)cl0 * (uint32_t)B.cap;
                     sec[r] = (v & 0x80000000u) != 0;
-                    e[r] = gload(B.ent + (size_t)(v & 0x7FFFFFFFu));
+                    ok[r] = q < q1 && (int32_t)(v & 0x7FFFFFFFu) != excl_slot;
+                    e[r] = gload_xyz(B.ent + (size_t)(v & 0x7FFFFFFFu));
                 }
 #pragma unroll
                 for (int r = 0; r < CR; ++r) {
-                    if (ok[r] && meta_low(e[r].w) != excl) {
-                        n_cand += 1;
-                        spec_pair(B, type, two, sec[r], p0, p1, e[r], sa, sb, wa, wb, n_eval, incut);
-                    }
+                    const bool valid = ok[r];
+                    n_cand += valid ? 1 : 0;
+                    spec_pair_queue(B, type, two, valid, sec[r], p0, p1, e[r], pq, qhead, qtail, sa, sb, wa, wb,
+                                    n_eval, incut);
                 }
             }
             // every lane has read this window before the next overwrites it
@@ -340,6 +460,8 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
         }
     }
+    // the pairs still queued
+    if (qtail != qhead) pair_drain(B, pq, qhead, qtail - qhead, sa, sb, wa, wb);
     n_in = (int32_t)incut;
     const double ea = wave_sum_uniform(sa);
     const double eb = (type == GCMC_MOVE_DISPLACE) ? wave_sum_uniform(sb) : 0.0;
@@ -351,12 +473,11 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     n_cand = wave_sum_i32_uniform(n_cand);
     n_eval = wave_sum_i32_uniform(n_eval);
     n_in = wave_sum_i32_uniform(n_in);
-    const double lnA = log(u.u[3]);
     if (lane == 0) {
         out->dUp = dUp;
         out->dWp = dWp;
         out->lnA = lnA;
-        out->u2 = u.u[2];
+        out->u2 = u2;
         out->type = type;
         out->flags = 0;
         out->two = two;

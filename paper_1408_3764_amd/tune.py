@@ -16,7 +16,7 @@ import time
 
 SHAPES = [(1, 8), (2, 8), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4)]
 # rows = 0: the speculative kernel, W consecutive moves evaluated at once and
-# committed in order (one species, stencils of at most 32 cells)
+# committed in order (one species, stencils of at most 512 cells)
 SPEC_SHAPES = [(2, 0), (4, 0), (8, 0), (16, 0)]
 # rows = -1: the pipelined kernel, one committer and waves - 1 evaluator wavefronts
 # (the same limits, plus at most 1024 cells per axis)
@@ -108,16 +108,31 @@ def rule_name(rule):
     return "top%g:%dx%d/%dx%d" % (rule[1], rule[2][0], rule[2][1], rule[3][0], rule[3][1])
 
 
+def _timed_launch(launch):
+    """GPU time (s) of launch() on the current stream, from HIP events around it."""
+    import torch
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
 def autotune_batch(batch, boxes, n_moves=300, rules=None):
     """Launch shapes of a batch: every rule of BATCH_RULES timed on identical
     work (each box's snapshot restored before the warm-up and before the timed
-    launch, which continue each box's own counter); the fastest rule is left
-    applied and the boxes back in their starting state.  Returns (rule,
-    timings keyed by rule_name)."""
+    launch, which continue each box's own counter; the launch timed with HIP
+    events); the fastest rule is left applied and the boxes back in their
+    starting state.  Returns (rule, timings keyed by rule_name)."""
+    import numpy as np
     import torch
-    from ._lib import COUNTER_CONTINUE
+    from . import _lib
+    from ._lib import COUNTER_CONTINUE, STATS_DTYPE
     rules = rules or BATCH_RULES
     snaps = [b.snapshot() for b in boxes]
+    st = torch.zeros(len(boxes) * STATS_DTYPE.itemsize, dtype=torch.uint8, device=boxes[0].device)
     timings, best = {}, None
     for rule in rules:
         apply_batch_rule(boxes, rule)
@@ -127,11 +142,9 @@ def autotune_batch(batch, boxes, n_moves=300, rules=None):
         for b, sn in zip(boxes, snaps):
             b.restore(sn)
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        st = batch.step(n_moves, counter0=COUNTER_CONTINUE)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        if int((st["error"] != 0).sum()):
+        dt = _timed_launch(lambda s: _lib.gcmc_batch_step(batch.handle, n_moves, COUNTER_CONTINUE, st, s))
+        stats = np.frombuffer(st.cpu().numpy().tobytes(), dtype=STATS_DTYPE)
+        if int((stats["error"] != 0).sum()):
             raise RuntimeError("chain error while tuning the batch")
         timings[rule_name(rule)] = dt
         if best is None or dt < best[0]:
@@ -154,11 +167,15 @@ def autotune_live(box, n_moves=3000, shapes=None):
     timing covers the same n_moves moves (same counters) from the same
     configuration; afterwards the box is back in that state.  Returns (shape,
     timings)."""
+    import numpy as np
     import torch
+    from . import _lib
+    from ._lib import STATS_DTYPE
     if shapes is None:
         shapes = SHAPES + (SPEC_SHAPES if spec_supported(box) else []) + (ASYNC_SHAPES if async_supported(box) else [])
     snap = box.snapshot()
     c0 = snap[4]["counter"]
+    st_dev = torch.zeros(STATS_DTYPE.itemsize, dtype=torch.uint8, device=box.device)
     timings = {}
     best = None
     for w, r in shapes:
@@ -167,10 +184,8 @@ def autotune_live(box, n_moves=3000, shapes=None):
         box.step(min(300, n_moves), counter0=c0)
         box.restore(snap)
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        st, _ = box.step(n_moves, counter0=c0)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
+        dt = _timed_launch(lambda s: _lib.gcmc_step(box.handle, n_moves, c0, st_dev, None, s))
+        st = np.frombuffer(st_dev.cpu().numpy().tobytes(), dtype=STATS_DTYPE)[0]
         if int(st["error"]) != 0:
             raise RuntimeError("chain error %d while tuning" % int(st["error"]))
         timings["%dx%d" % (w, r)] = dt

@@ -845,10 +845,11 @@ def test_batch_matches_single_boxes(shape):
 # ------------------------------------------------------------------ tuner
 def test_autotune_cells_picks_a_timed_configuration_and_keeps_the_chain(c1):
     """The cell-size and launch-shape tuner: it times the paper's cells and
-    twice as many per axis, keeps the fastest (box, shape) it timed, offers no
-    speculative shape where the stencil is too large for it, and the box it
-    returns is back in its starting state: its next moves (device counter) are
-    the oracle's first moves."""
+    twice as many per axis, keeps the fastest (box, shape) it timed, offers the
+    speculative shapes on both grids (the microcells' 125-cell stencils take its
+    microcell path) but the pipelined shapes only where the stencil has at most
+    32 cells, and the box it returns is back in its starting state: its next
+    moves (device counter) are the oracle's first moves."""
     from paper_1408_3764_amd import tune
     from paper_1408_3764_amd.box import Box
     from paper_1408_3764_amd._lib import COUNTER_CONTINUE
@@ -865,7 +866,9 @@ def test_autotune_cells_picks_a_timed_configuration_and_keeps_the_chain(c1):
     assert shape in tune.SHAPES + tune.SPEC_SHAPES + tune.ASYNC_SHAPES
     assert min(t, key=t.get) == "%s/%dx%d" % ("x".join(map(str, grid)), shape[0], shape[1])
     assert any(k.startswith("8x8x8/") and k.endswith("x0") for k in t)
-    assert not any(k.startswith("16x16x16/") and (k.endswith("x0") or k.endswith("x-1")) for k in t)
+    assert any(k.startswith("8x8x8/") and k.endswith("x-1") for k in t)
+    assert any(k.startswith("16x16x16/") and k.endswith("x0") for k in t)
+    assert not any(k.startswith("16x16x16/") and k.endswith("x-1") for k in t)
     p = _params(c1)
     _, _, olog = oracle.chain(c1.pos, 100, p, seed=c1.seed, max_n=c1.n + 20_000, U0=0.0)
     assert box.checkpoint()["counter"] == 0
