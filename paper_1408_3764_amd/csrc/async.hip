@@ -191,8 +191,9 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             const int64_t N = uni64((int64_t)(uint32_t)cn);
             const double a_ins = unid(S.acc[0]), a_del = unid(S.acc[1]);
             const int s = target % kSlots;
+            SpecKey key;
             spec_eval<CR, 0, 0>(B, tab, offs, own[e], pq[e], nullptr, ctr0 + (uint64_t)C, target - C, N, no_full, a_ins,
-                                a_del, &S.rec[s]);
+                                a_del, &S.rec[s], key);
             if (lane == 0) {
                 S.slot_move[s] = target;
                 S.slot_epoch[s] = vis;

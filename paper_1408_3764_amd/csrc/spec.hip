@@ -153,9 +153,31 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         double4 tv = make_double4(0, 0, 0, 0);
         if (wv == 0 && lane < W && base + lane >= 0) tv = gload(B.pos + base + lane);
         // ------------------------------------------------ evaluate W moves
-        if (m + wv < n_moves)
+        if (m + wv < n_moves) {
+            SpecKey key;
             spec_eval<CR, NG, 2 * W>(B, tab, offs, own[wv], pq[wv], &dring, ctr0 + (uint64_t)m, wv, N, no_full, a_ins,
-                                     a_del, &recs[wv]);
+                                     a_del, &recs[wv], key);
+            // the decision at every N the move can meet (within W - 1 of the round's N; lane o takes
+            // N - (W - 1) + o): the pick still the evaluated one, and the Metropolis test (Eqs. 3-5)
+            // with the tail change and prefactor at that N -- the same operations the commit
+            // would do, so the commit only reads the bit of its N
+            if (!(key.flags & 1)) {
+                const int64_t np = N - (W - 1) + lane;
+                bool valid = false, acc = false;
+                if (lane < 2 * W - 1 && np >= 0) {
+                    valid = key.type == GCMC_MOVE_INSERT || spec_pick(key.u2, np) == key.idx;
+                    double dUt;
+                    const double arg = spec_arg(B, key.type, key.dUp, np, lbase, lpi, lpd, tk, dUt);
+                    const double dU = key.dUp + dUt;
+                    acc = dU == dU && key.lnA < arg;
+                }
+                const uint64_t pm = __ballot(valid), am = __ballot(acc);
+                if (lane == 0) {
+                    recs[wv].pickmask = (uint32_t)pm;
+                    recs[wv].okmask = (uint32_t)am;
+                }
+            }
+        }
         if (wv != 0) {
             // publish this move's record: wavefront 0 decides it as soon as its turn comes, while
             // slower wavefronts still evaluate.  A commit may then store to memory that a later
@@ -185,6 +207,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
             // this wavefront's own table and record writes, seen by all of its lanes
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local");
+            const int64_t n_round = N;   // N at the round's start: the masks' reference
             int32_t modx = 0, mody = 0, modz = 0, touched = -1;   // lane-held lists of this round
             int nmod = 0, ntouch = 0;
             uint64_t okbits = 0;   // bit k: move k of the round accepted
@@ -218,8 +241,9 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     continue;
                 }
                 const int64_t idx = R.idx;
+                const int o = (int)(N - n_round) + (W - 1);   // 0 .. 2W - 2 (N moved by at most k < W)
                 if (type != GCMC_MOVE_INSERT) {
-                    if (spec_pick(R.u2, N) != idx) break;
+                    if (((R.pickmask >> o) & 1u) == 0) break;
                     if (__ballot(lane < ntouch && touched == (int32_t)idx) != 0) break;
                 }
                 // a cell changed by an earlier commit of this round inside one of its stencils
@@ -232,11 +256,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 if (__ballot(hit) != 0) break;
                 // ---- decide at the current N
                 const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
-                const double dUp = R.dUp;
-                double dUt;
-                const double arg = spec_arg(B, type, dUp, N, lbase, lpi, lpd, tk, dUt);
-                const double dU = dUp + dUt;
-                const bool ok = __builtin_amdgcn_readfirstlane((dU == dU && R.lnA < arg) ? 1 : 0) != 0;
+                const bool ok = ((R.okmask >> o) & 1u) != 0;
                 const int two = R.two;
                 const int32_t cnt0 = R.cnt0, cnt1 = R.cnt1;
                 if (ok) {
@@ -348,7 +368,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     if (is_ins && cnt0 + 1 > maxc) maxc = cnt0 + 1;
                     okbits |= 1ull << k;
                     N += is_ins ? 1 : (type == GCMC_MOVE_DELETE ? -1 : 0);
-                    U += dUp;
+                    U += R.dUp;
                     Wvir += R.dWp;
                 }
                 if (lane == 0) {

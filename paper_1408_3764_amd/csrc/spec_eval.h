@@ -111,16 +111,31 @@ __device__ __forceinline__ void pair_drain(const DevBox& B, const double* q, uin
 // Squared distances of one candidate record to the move's position(s),
 // queued when inside the cutoff (counts of evaluated and in-cutoff pairs kept
 // per lane).
+// Squared distance of a candidate to a position; the minimum image only where
+// the stencil may cross a periodic face (wrap false: every candidate lies
+// within (k + 1) cells of the position along each axis, at least half a cell
+// short of L/2, where the minimum image returns the difference unchanged, bit
+// for bit).
+__device__ __forceinline__ double spec_dist2(const DevBox& B, const double* p, const double3& e, bool wrap) {
+    double dx = e.x - p[0], dy = e.y - p[1], dz = e.z - p[2];
+    if (wrap) {
+        dx = nearest_image(dx, B.L[0], B.hL[0]);
+        dy = nearest_image(dy, B.L[1], B.hL[1]);
+        dz = nearest_image(dz, B.L[2], B.hL[2]);
+    }
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
 __device__ __forceinline__ void spec_pair_queue(const DevBox& B, int type, int two, bool valid, bool second,
-                                                const double* p0, const double* p1, const double3& e, double* q,
-                                                uint32_t& head, uint32_t& tail, double& sa, double& sb, double& wa,
-                                                double& wb, int32_t& n_eval, int64_t& incut) {
+                                                const double* p0, const double* p1, const double3& e, bool wrap,
+                                                double* q, uint32_t& head, uint32_t& tail, double& sa, double& sb,
+                                                double& wa, double& wb, int32_t& n_eval, int64_t& incut) {
     const bool disp = type == GCMC_MOVE_DISPLACE;
     // the first position: every move but the second stencil of a displacement that leaves its cell
     const bool use0 = valid && !(disp && two && second);
     const bool use1 = valid && disp && (!two || second);
     double r2a = 0.0, r2b = 0.0;
-    if (use0) r2a = dist2(B, p0[0], p0[1], p0[2], e.x, e.y, e.z);
+    if (use0) r2a = spec_dist2(B, p0, e, wrap);
     const bool in0 = use0 && r2a < B.rc2;
     n_eval += use0 ? 1 : 0;
     incut += in0 ? 1 : 0;
@@ -130,7 +145,7 @@ __device__ __forceinline__ void spec_pair_queue(const DevBox& B, int type, int t
         head += kWave;
     }
     if (disp) {
-        if (use1) r2b = dist2(B, p1[0], p1[1], p1[2], e.x, e.y, e.z);
+        if (use1) r2b = spec_dist2(B, p1, e, wrap);
         const bool in1 = use1 && r2b < B.rc2;
         n_eval += use1 ? 1 : 0;
         incut += in1 ? 1 : 0;
@@ -152,14 +167,24 @@ __device__ __forceinline__ double3 gload_xyz(const double4* p) {
 }
 
 struct SpecRec {
-    double dUp, lnA, u2, dWp;   // pair energy change, ln A, pick draw, pair virial change
+    // what the in-order commit reads for every move, first
+    int32_t type, flags;
+    uint32_t pickmask, okmask;   // bit o: the pick still valid / the move accepted at N = N_round - (W - 1) + o
+    int64_t idx;
+    int32_t c0[3], c1[3];
+    // what it reads for an accepted move
+    int32_t two, cnt0, cnt1, cl0, cl1, pad;
+    double dUp, dWp, lnA, u2;    // pair energy change, pair virial change, ln A, pick draw
     double p0[3], p1[3];
     double4 rec, elast;
-    int64_t idx;
-    int32_t type, flags, two, pad;
-    int32_t c0[3], c1[3];
-    int32_t cl0, cl1, cnt0, cnt1;
     int32_t cand, evals, incut, pad2;
+};
+
+// The values of an evaluation the round kernel decides with in advance.
+struct SpecKey {
+    int32_t type, flags;
+    int64_t idx;
+    double u2, lnA, dUp;
 };
 
 // Inclusive prefix sum over the wavefront's lanes (DPP row shifts, then the
@@ -211,7 +236,7 @@ __device__ __forceinline__ bool in_stencil(const DevBox& B, int32_t x, int32_t y
 template <int CR, int NG, int RING>
 __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, const int32_t* offs, void* ownbuf,
                                           double* pq, const DrawRing<RING>* dr, uint64_t ctr_round, int k, int64_t N,
-                                          bool no_full, double a_ins, double a_del, SpecRec* out) {
+                                          bool no_full, double a_ins, double a_del, SpecRec* out, SpecKey& key) {
     const int lane = threadIdx.x & (kWave - 1);
     int type;
     double u2, lnA, ux, uy, uz;
@@ -258,7 +283,14 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
         I = __popcll(__ballot(earlier && tj == GCMC_MOVE_INSERT));
     }
     const double ud[3] = {ux, uy, uz};
+    key.type = type;
+    key.flags = 0;
+    key.u2 = u2;
+    key.lnA = lnA;
+    key.idx = -1;
+    key.dUp = 0.0;
     if (type != GCMC_MOVE_INSERT && N == 0) {
+        key.flags = 1;
         if (lane == 0) {
             out->type = type;
             out->flags = 1;
@@ -316,6 +348,8 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
                                      c1[2] <= B.M[2] - 1 - B.k[2])))
                               ? 1
                               : 0) != 0;
+    // candidates need the minimum image unless the stencils stay inside the box with room to spare
+    const bool wrap = !(fast && B.M[0] >= 2 * B.k[0] + 3 && B.M[1] >= 2 * B.k[1] + 3 && B.M[2] >= 2 * B.k[2] + 3);
     int32_t cnt0 = 0, cnt1 = 0;
     double4 elast = make_double4(0, 0, 0, 0);
     // the slot of the moving particle's own record in the cell array (never a candidate of itself)
@@ -345,13 +379,29 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
         const int tc1 = two ? (int)__builtin_ctzll(__ballot(cell_lane && wh && cell == cl1)) : tc;
         cnt0 = __builtin_amdgcn_readlane(cnt, tc);
         cnt1 = __builtin_amdgcn_readlane(cnt, tc1);
-        // ---- owner of each flattened candidate
-        uint8_t* own = static_cast<uint8_t*>(ownbuf);
-        const int kmax = wave_max_i32_uniform(cnt);
-        for (int k = 0; k < kmax; ++k)
-            if (k < cnt) own[pre + k] = (uint8_t)lane;
-        const int32_t cellbase = cell * B.cap - pre;   // record index of flattened candidate q: q + cellbase[owner]
+        // ---- owner of each flattened candidate: the nonempty cells, in lane order, are numbered
+        // k = 0, 1, ...; cbk[k] = the cell's record index minus its first flattened position,
+        // and bit q of the row masks marks a flattened position q where a nonempty cell begins,
+        // so the owner of q is the number of marks at or below q, minus one
+        uint32_t* cbk = static_cast<uint32_t*>(ownbuf);                // [64]
+        uint64_t* smask = reinterpret_cast<uint64_t*>(cbk + kWave);   // [kSpecOwn / 64]
+        const int nrows = (total + kWave - 1) / kWave;
+        for (int r = lane; r < nrows; r += kWave) smask[r] = 0;
         __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+        {
+            const bool nonempty = cnt > 0;
+            const uint64_t nzm = __ballot(nonempty);
+            if (nonempty) {
+                const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(nzm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nzm, 0u));
+                cbk[k] = (uint32_t)(cell * B.cap - pre);
+                __hip_atomic_fetch_or(&smask[pre >> 6], 1ull << (pre & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+        }
+        const int32_t first2 = __builtin_amdgcn_readlane(incl, nst - 1);   // flattened start of the second stencil
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+        uint32_t starts = 0;   // nonempty cells beginning before the current row (wave-uniform)
         // last entry of the old centre cell (removal by swap-with-last)
         if (cnt0 > 0) elast = gload(B.ent + ((size_t)(uint32_t)cl0 * (uint32_t)B.cap + (cnt0 - 1)));
         // ---- candidates
@@ -362,19 +412,24 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     #pragma unroll
             for (int r = 0; r < CR; ++r) {
                 const int q = base + r * kWave + lane;
-                const int j = q < total ? own[q] : 0;
-                const int32_t cb = __shfl(cellbase, j, kWave);
+                const int row = (base >> 6) + r;
+                const uint64_t m = row < nrows ? smask[row] : 0;
+                const uint32_t k = starts + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) +
+                                   (uint32_t)((m >> lane) & 1ull) - 1u;
+                starts += (uint32_t)__builtin_popcountll(m);
+                const int32_t cb = q < total ? (int32_t)cbk[k & (kWave - 1)] : 0;
                 const int32_t ri = q < total ? cb + q : cl0 * B.cap;
                 ok[r] = q < total && ri != excl_slot;
-                wsel[r] = j >= nst ? 1 : 0;
+                wsel[r] = (nst < ncs && q >= first2) ? 1 : 0;
                 e[r] = gload_xyz(B.ent + (size_t)(uint32_t)ri);
             }
     #pragma unroll
             for (int r = 0; r < CR; ++r) {
                 const bool valid = ok[r];
                 n_cand += valid ? 1 : 0;
-                spec_pair_queue(B, type, two, valid, wsel[r] != 0, p0, p1, e[r], pq, qhead, qtail, sa, sb, wa, wb,
-                                n_eval, incut);
+                spec_pair_queue(B, type, two, valid, wsel[r] != 0, p0, p1, e[r], wrap, pq, qhead, qtail, sa, sb, wa,
+                                wb, n_eval, incut);
             }
         }
 
@@ -451,8 +506,8 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
                 for (int r = 0; r < CR; ++r) {
                     const bool valid = ok[r];
                     n_cand += valid ? 1 : 0;
-                    spec_pair_queue(B, type, two, valid, sec[r], p0, p1, e[r], pq, qhead, qtail, sa, sb, wa, wb,
-                                    n_eval, incut);
+                    spec_pair_queue(B, type, two, valid, sec[r], p0, p1, e[r], wrap, pq, qhead, qtail, sa, sb, wa,
+                                    wb, n_eval, incut);
                 }
             }
             // every lane has read this window before the next overwrites it
@@ -473,6 +528,8 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     n_cand = wave_sum_i32_uniform(n_cand);
     n_eval = wave_sum_i32_uniform(n_eval);
     n_in = wave_sum_i32_uniform(n_in);
+    key.idx = idx;
+    key.dUp = dUp;
     if (lane == 0) {
         out->dUp = dUp;
         out->dWp = dWp;

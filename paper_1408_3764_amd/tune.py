@@ -78,20 +78,29 @@ def batch_shape(boxes):
 
 
 BATCH_RULES = [("uniform", (2, 0)), ("uniform", (4, 0)), ("uniform", (8, 0)), ("uniform", (4, 4)),
-               ("split", 0.25, (8, 0), (4, 0)), ("split", 0.5, (8, 0), (4, 0)), ("split", 0.25, (8, 0), (2, 0)),
-               ("split", 0.5, (4, 0), (2, 0)), ("split", 0.125, (16, 0), (4, 0))]
+               ("split", 0.25, (8, 0), (4, 0)), ("split", 0.25, (8, 0), (2, 0)), ("split", 0.5, (4, 0), (2, 0)),
+               ("cost", 0.125, (8, 0), (2, 0)), ("cost", 0.25, (8, 0), (2, 0)), ("cost", 0.125, (8, 0), (4, 0)),
+               ("cost", 0.25, (4, 0), (2, 0))]
+
+
+def move_cost(box):
+    """Candidates a move of the box reads, about: the particles in one stencil
+    (the whole box when the stencil covers it)."""
+    info = box.info()
+    return box.n * min(1.0, info["n_stencil"] / max(1, info["n_cells"]))
 
 
 def apply_batch_rule(boxes, rule):
-    """Set every box's launch shape by a rule: ("uniform", shape), or ("split",
+    """Set every box's launch shape by a rule: ("uniform", shape); ("split",
     f, big, small): the fraction f of the boxes with the most particles take
-    `big`, the others `small` (a shape the box cannot take falls back to the
-    per-move 4x4)."""
+    `big`, the others `small`; ("cost", f, big, small): the same, ranked by the
+    candidates a move reads (move_cost).  A shape the box cannot take falls
+    back to the per-move 4x4."""
     if rule[0] == "uniform":
         shapes = [rule[1]] * len(boxes)
     else:
         _, f, big, small = rule
-        ns = [b.n for b in boxes]
+        ns = [b.n for b in boxes] if rule[0] == "split" else [move_cost(b) for b in boxes]
         order = sorted(range(len(boxes)), key=lambda k: -ns[k])
         top = set(order[:max(1, int(round(f * len(boxes))))])
         shapes = [big if k in top else small for k in range(len(boxes))]
@@ -105,7 +114,8 @@ def apply_batch_rule(boxes, rule):
 def rule_name(rule):
     if rule[0] == "uniform":
         return "%dx%d" % rule[1]
-    return "top%g:%dx%d/%dx%d" % (rule[1], rule[2][0], rule[2][1], rule[3][0], rule[3][1])
+    return "%s%g:%dx%d/%dx%d" % ("top" if rule[0] == "split" else "cost", rule[1], rule[2][0], rule[2][1], rule[3][0],
+                                 rule[3][1])
 
 
 def _timed_launch(launch):
