@@ -184,7 +184,7 @@ def cell_size_sweep():
             b = Box.from_workload(wb, max_n=wb.n + 20 * mps + 1000, **kw)
             info = b.info()
             base = base or info["cell_m"]
-            shapes = ([(8, 0)] if tune.spec_supported(b) else []) + [(4, 4), (8, 2), (8, 4)]
+            shapes = ([(8, 0)] if tune.spec_supported(b) else []) + [(4, 4), (8, 2), (8, 4), (8, -2)]
             for shape in shapes:
                 b.set_launch(*shape)
                 b.step(mps, counter0=COUNTER_CONTINUE)
@@ -219,7 +219,9 @@ def paper_studies(sizes, cutoffs):
     chain against N (density 0.67, rc = 2.5) and against the cutoff (87,296
     particles in 128K sigma^3, rc = 2.5 ... 4.25), for the chain without a cell
     list (all pairs), with traditional cells (the per-move kernel and, where it
-    applies, the speculative kernel) and with microcells of about rc/2."""
+    applies, the speculative kernel) and with microcells of about rc/2 (the
+    per-move kernel, the paper's one-cell-per-thread mapping and the
+    speculative kernel)."""
     import numpy as np
     import torch
     from paper_1408_3764_amd import tune, workloads
@@ -267,11 +269,19 @@ def paper_studies(sizes, cutoffs):
             if best is None or v > best[0]:
                 best = (v, c, shape)
         r["microcells_per_move"], r["microcell_candidates_per_move"] = best[0], best[1]
+        # the paper's microcell mapping (one stencil cell per thread) and the speculative kernel
+        b.set_launch(8, -2)
+        r["microcells_paper_mapping"] = rate(b, moves)[0]
+        r["microcells_speculative"] = None
+        if tune.spec_supported(b):
+            b.set_launch(8, 0)
+            r["microcells_speculative"] = rate(b, moves)[0]
         b.close()
-        log("%s: all pairs %.0f, cells %.0f (%dx%d)%s, microcells %.0f moves/s" % (
+        log("%s: all pairs %.0f, cells %.0f (%dx%d)%s, microcells %.0f (paper mapping %.0f%s) moves/s" % (
             wb.name, r["all_pairs"], r["cells_per_move"], best[2][0], best[2][1],
             "" if r["cells_speculative"] is None else ", speculative %.0f" % r["cells_speculative"],
-            r["microcells_per_move"]))
+            r["microcells_per_move"], r["microcells_paper_mapping"],
+            "" if r["microcells_speculative"] is None else ", speculative %.0f" % r["microcells_speculative"]))
         return r
 
     out = {"size_study": [], "cutoff_study": []}

@@ -280,7 +280,8 @@ int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gc
             if (grp[q] == g) order.push_back(bt->by_n[q]);
     }
     // descriptors and order in launch order: re-uploaded only when a box was rebuilt or the grouping
-    // changed
+    // changed; the groups' launch paths and shapes are taken afresh on every call (a new shape for
+    // a group of the same boxes changes neither the order nor the descriptors)
     bool changed = ng != bt->ngroups;
     for (int32_t q = 0; q < bt->n && !changed; ++q)
         changed = order[q] != bt->h_order[q] ||
@@ -294,11 +295,11 @@ int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gc
         GCMC_HIP(hipMemcpyAsync(bt->d_order, bt->h_order, sizeof(int32_t) * bt->n, hipMemcpyHostToDevice, s));
         GCMC_HIP(hipStreamSynchronize(s));
         bt->ngroups = ng;
-        for (int g = 0; g < ng; ++g) {
-            bt->gstart[g] = gstart[g];
-            bt->gcount[g] = gcount[g];
-            memcpy(bt->gkey[g], gkey[g], sizeof gkey[g]);
-        }
+    }
+    for (int g = 0; g < ng; ++g) {
+        bt->gstart[g] = gstart[g];
+        bt->gcount[g] = gcount[g];
+        memcpy(bt->gkey[g], gkey[g], sizeof gkey[g]);
     }
     // groups after the first run on side streams (default priority) forked from and joined to `s`
     if (ng > 1) {

@@ -842,6 +842,27 @@ def test_batch_matches_single_boxes(shape):
                                              for t in range(3)]
 
 
+def test_batch_takes_new_launch_shapes(c1):
+    """Changing the boxes' launch shapes between two steps of one batch, with the
+    grouping of the boxes unchanged, launches the new shapes: under a wait bound
+    that fails at once, the per-move kernel (which never waits) runs clean, and the
+    speculative kernel that replaces it stops at its first wait with
+    GCMC_ERR_INTERNAL."""
+    from paper_1408_3764_amd.box import Batch
+    boxes = [_box(c1, max_n=c1.n + 2001, box_id=k) for k in range(3)]
+    for b in boxes:
+        b.set_launch(4, 4)
+        b.set_wait_limit(-1)
+    bt = Batch(boxes)
+    st = bt.step(200, counter0=0)
+    assert np.all(st["error"] == 0)
+    for b in boxes:
+        b.set_launch(8, 0)
+    st = bt.step(200, counter0=200)
+    assert np.any(st["error"] == 8), st["error"]
+    bt.close()
+
+
 # ------------------------------------------------------------------ tuner
 def test_autotune_cells_picks_a_timed_configuration_and_keeps_the_chain(c1):
     """The cell-size and launch-shape tuner: it times the paper's cells and
