@@ -315,8 +315,12 @@ int gcmc_box_set_wait_limit(gcmc_box* box, int32_t polls);
  * persistent launch (Sec. 3.3.4: one kernel call for many moves): move m uses
  * the Philox4x32-10 stream with key = seed and counter
  * (counter0 + m low, high, box_id, j), j = 0..3, giving eight uniforms
- * (R, Source, particle pick, A, three position draws, spare); R < p_disp is a
- * displacement, else Source < 0.5 a deletion, else an insertion.  Single
+ * (R, Source, particle pick u2, A, three position draws, pick fields u7);
+ * R < p_disp is a displacement, else Source < 0.5 a deletion, else an
+ * insertion.  A displacement or deletion among N particles takes the first
+ * b-bit field of u7's 53 bits (u7 = k 2^-53, high field first, 2^b the
+ * smallest power of two >= N) whose value is below N, else min(floor(u2 N),
+ * N - 1): Algorithm 2's random particle, uniform over 0 .. N-1.  Single
  * species only.  counter0 = GCMC_COUNTER_CONTINUE starts at the box's device
  * counter (the move after the last one run), so a captured HIP graph of
  * gcmc_step calls continues the chain each time it is replayed.  d_stats (may

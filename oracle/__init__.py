@@ -76,6 +76,8 @@ def lib():
         L.oracle_u01.argtypes = [C.c_uint32, C.c_uint32]
         L.oracle_u01.restype = C.c_double
         L.oracle_move_draws.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, dp]
+        L.oracle_pick.argtypes = [C.c_double, C.c_double, C.c_int64]
+        L.oracle_pick.restype = C.c_int64
         L.oracle_lj_r2.argtypes = [C.c_double] * 4
         L.oracle_lj_r2.restype = C.c_double
         L.oracle_min_image.argtypes = [C.c_double, C.c_double]
@@ -170,6 +172,13 @@ def move_draws(seed, move, box=0):
     u = np.zeros(8)
     lib().oracle_move_draws(int(seed), int(move), int(box), _d(u))
     return u
+
+
+def pick(u_pick, u_spare, n):
+    """The particle a displacement or deletion picks among n >= 1 (Algorithm 2's
+    random particle): the first b-bit field of u_spare's 53 bits (2^b >= n) below
+    n, else min(floor(u_pick n), n - 1)."""
+    return int(lib().oracle_pick(float(u_pick), float(u_spare), int(n)))
 
 
 def lj_r2(r2, eps, sigma, rc):

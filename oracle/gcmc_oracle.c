@@ -125,7 +125,7 @@ double oracle_u01(uint32_t a, uint32_t b)
  * two doubles, from output words (0,1) and (2,3).
  *   u[0] = R of Algorithm 1 (move type)     u[1] = Source of Algorithm 1
  *   u[2] = particle pick                    u[3] = A of the acceptance test
- *   u[4..6] = position / displacement       u[7] = spare                     */
+ *   u[4..6] = position / displacement       u[7] = pick fields (oracle_pick) */
 void oracle_move_draws(uint64_t seed, uint64_t move, uint32_t box, double u[8])
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -136,6 +136,35 @@ void oracle_move_draws(uint64_t seed, uint64_t move, uint32_t box, double u[8])
         u[2 * j] = oracle_u01(w[0], w[1]);
         u[2 * j + 1] = oracle_u01(w[2], w[3]);
     }
+}
+
+/* The random particle of a displacement (Algorithm 2) or a deletion        */
+/* (Algorithm 5) among n >= 1 particles.  The paper asks only for a uniform */
+/* pick; this one is uniform and rarely changes when n changes by a few:    */
+/* with b the smallest bit count such that 2^b >= n, the 53 bits of u_spare */
+/* (u_spare = k / 2^53) are cut into floor(53 / b) fields of b bits, high   */
+/* field first; the pick is the first field whose value is below n.  When   */
+/* none is, it is min(floor(u_pick n), n - 1).  Each field is uniform on    */
+/* 0 .. 2^b - 1 and independent of the others and of u_pick, so every index */
+/* has probability 1/n.                                                     */
+int64_t oracle_pick(double u_pick, double u_spare, int64_t n)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < n)
+        b++;
+    if (b == 0)
+        return 0;
+    uint64_t k = (uint64_t)(u_spare * 9007199254740992.0);
+    int fields = 53 / b;
+    for (int t = 1; t <= fields; ++t) {
+        uint64_t v = (k >> (53 - b * t)) & (((uint64_t)1 << b) - 1);
+        if (v < (uint64_t)n)
+            return (int64_t)v;
+    }
+    int64_t i = (int64_t)floor(u_pick * (double)n);
+    if (i > n - 1)
+        i = n - 1;
+    return i;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -348,7 +377,7 @@ static double wrap_coord(double x, double L)
 /*                                                                          */
 /* Per move (counter = counter0 + m):                                       */
 /*   R < p_disp -> displacement; else Source < 0.5 -> deletion; else        */
-/*   insertion.  Displacement and deletion pick i = min(floor(u N), N-1)    */
+/*   insertion.  Displacement and deletion pick i = oracle_pick(u2, u7, N)  */
 /*   and are rejected when N == 0.  Displacement: x' = wrap(x + d (2u-1))   */
 /*   per axis.  Insertion: x = wrap(L u).  On accepted insertion the new    */
 /*   particle gets index N; on accepted deletion particle N-1 takes index i.*/
@@ -407,11 +436,8 @@ static int chain_run(const sum_mode* md, int64_t max_n, double* x, double* y, do
             continue;
         }
         int64_t i = 0;
-        if (type != 1) {
-            i = (int64_t)floor(u[2] * (double)n);
-            if (i > n - 1)
-                i = n - 1;
-        }
+        if (type != 1)
+            i = oracle_pick(u[2], u[7], n);
         double dUp = 0.0, dUt = 0.0, sabs = 0.0, dWp = 0.0, wabs = 0.0;
         double nx = 0, ny = 0, nz = 0;
         if (type == 0) {

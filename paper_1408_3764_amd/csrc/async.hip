@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kWave*(E + 1)) void k_chain_async(const DevBox* __r
             type = __builtin_amdgcn_readfirstlane(R.type);
             if (type != GCMC_MOVE_INSERT && N == 0) break;   // empty box: rejected without an evaluation
             bool valid = !(R.flags & 1);
-            if (type != GCMC_MOVE_INSERT) valid = valid && spec_pick(R.u2, N) == R.idx;
+            if (type != GCMC_MOVE_INSERT) valid = valid && spec_pick(R.u2, R.u7, N) == R.idx;
             // decisions since the evaluation's epoch that may have changed what it read
             const int32_t ep = uni(S.slot_epoch[s]);
             const int32_t nd = (int32_t)j - ep;

@@ -35,10 +35,7 @@ __device__ __forceinline__ int move_type(const DevBox& B, const U8& u) {
     return (u.u[0] < B.p_disp) ? GCMC_MOVE_DISPLACE : ((u.u[1] < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
 }
 
-__device__ __forceinline__ int64_t pick_index(const U8& u, int64_t n) {
-    int64_t i = (int64_t)floor(u.u[2] * (double)n);
-    return i > n - 1 ? n - 1 : i;
-}
+__device__ __forceinline__ int64_t pick_index(const U8& u, int64_t n) { return pick_particle(u.u[2], u.u[7], n); }
 
 // Draws, type and pick of move ctr for N = n; issues the record loads.
 __device__ __forceinline__ void head_of(const DevBox& B, uint64_t ctr, int64_t n, Head& H) {

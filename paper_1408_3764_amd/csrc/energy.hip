@@ -547,8 +547,7 @@ __device__ __forceinline__ APTrial ap_trial_from_draws(const DevBox& B, const U8
         T.valid = false;
         return T;
     }
-    int64_t i = (int64_t)floor(u.u[2] * (double)n);
-    if (i > n - 1) i = n - 1;
+    const int64_t i = pick_particle(u.u[2], u.u[7], n);
     T.idx = i;
     const double4 pi = gload(B.pos + i);
     T.p[0][0] = pi.x; T.p[0][1] = pi.y; T.p[0][2] = pi.z;

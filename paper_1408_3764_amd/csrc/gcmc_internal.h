@@ -200,6 +200,26 @@ __device__ __forceinline__ double wrap_into_box(double x, double L) {
     return x;
 }
 
+// The particle a displacement (Algorithm 2) or a deletion (Algorithm 5)
+// picks among n >= 1: uniform over 0 .. n-1.  With 2^b the smallest power of
+// two >= n, the 53 random bits of u7 (u7 = k 2^-53) form floor(53 / b) fields
+// of b bits, high field first; the pick is the first field below n, else
+// min(floor(u2 n), n - 1).  A field below n names the same particle for every
+// N above it, so a move evaluated before an earlier insertion or deletion is
+// decided almost always keeps its particle.
+__device__ __forceinline__ int64_t pick_particle(double u2, double u7, int64_t n) {
+    if (n <= 1) return 0;
+    const int b = 64 - __clzll((long long)(n - 1));
+    const uint64_t k = (uint64_t)(u7 * 9007199254740992.0);
+    const uint64_t mask = (1ull << b) - 1ull;
+    for (int sh = 53 - b; sh >= 0; sh -= b) {
+        const uint64_t v = (k >> sh) & mask;
+        if (v < (uint64_t)n) return (int64_t)v;
+    }
+    const int64_t i = (int64_t)floor(u2 * (double)n);
+    return i > n - 1 ? n - 1 : i;
+}
+
 __device__ __forceinline__ int32_t axis_cell(double x, double invS, int32_t M) {
     int32_t c = (int32_t)floor(x * invS);
     return c > M - 1 ? M - 1 : (c < 0 ? 0 : c);

@@ -74,8 +74,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_paper(const DevBox* __restri
             for (int a = 0; a < 3; ++a) T.p[0][a] = wrap_into_box(B.L[a] * u.u[4 + a], B.L[a]);
             locate(B, T, 0);
         } else {
-            int64_t i = (int64_t)floor(u.u[2] * (double)N);
-            T.idx = i > N - 1 ? N - 1 : i;
+            T.idx = pick_particle(u.u[2], u.u[7], N);
             const double4 rec = gload(B.pos + T.idx);
             T.meta = rec.w;
             T.p[0][0] = rec.x; T.p[0][1] = rec.y; T.p[0][2] = rec.z;

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ int32_t offs[kOffs];
     __shared__ SpecRec recs[W];
-    __shared__ uint32_t own[W][kSpecOwn / 4];         // owner bytes, or record indices (NG > 0)
+    __shared__ __align__(8) uint32_t own[W][spec_own_words(NG)];   // cell bases and start masks, or record indices
     __shared__ double4 top[2 * W];              // records of particles base .. base + 2W - 1
     // log acceptance prefactors at N = lp_base[b] + t, t < 4W, two buffers: the round's and the next round's
     __shared__ double lp_ins[2][4 * W], lp_del[2][4 * W];
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 const int64_t np = N - (W - 1) + lane;
                 bool valid = false, acc = false;
                 if (lane < 2 * W - 1 && np >= 0) {
-                    valid = key.type == GCMC_MOVE_INSERT || spec_pick(key.u2, np) == key.idx;
+                    valid = key.type == GCMC_MOVE_INSERT || spec_pick(key.u2, key.u7, np) == key.idx;
                     double dUt;
                     const double arg = spec_arg(B, key.type, key.dUp, np, lbase, lpi, lpd, tk, dUt);
                     const double dU = key.dUp + dUt;

@@ -34,6 +34,9 @@ namespace gcmc {
 
 constexpr int kSpecOwn = 8192;       // flattened candidates per wavefront (owner table bytes)
 constexpr int kSpecRecWin = kSpecOwn / 4;   // record indices per window of the microcell path (same bytes)
+// 32-bit words of a wavefront's owner buffer: the 32-cell path keeps 64 cell bases and one
+// start mask per 64 flattened candidates; the microcell path a window of record indices
+constexpr int spec_own_words(int ng) { return ng ? kSpecRecWin : kWave + 2 * (kSpecOwn / 64); }
 constexpr int kSpecGroups = 16;      // groups of 64 stencil cells: stencils of up to 512 cells (two for a displacement)
 constexpr int kSpecMaxStencil = kSpecGroups * kWave / 2;
 constexpr int kSpecGroupsSmall = 4;  // the instantiation for stencils of up to 128 cells (fewer registers)
@@ -44,13 +47,13 @@ constexpr int kPairRing = 128;       // queued in-cutoff pairs per wavefront (a 
 // position draws (insertion point, or the displacement).
 template <int RING>
 struct DrawRing {
-    double u2[RING], lnA[RING], px[RING], py[RING], pz[RING];
+    double u2[RING], u7[RING], lnA[RING], px[RING], py[RING], pz[RING];
     int32_t type[RING];
 };
 
 // Philox block `b` of move `ctr` into its ring slot (one lane per block:
 // block 0 gives the type, 1 the pick draw and ln A, 2 and 3 the position
-// draws).
+// draws and the pick fields).
 template <int RING>
 __device__ __forceinline__ void draw_block(const DevBox& B, DrawRing<RING>* dr, uint64_t ctr, int b) {
     uint32_t c0 = (uint32_t)ctr, c1 = (uint32_t)(ctr >> 32), c2 = B.box_id, c3 = (uint32_t)b;
@@ -67,6 +70,7 @@ __device__ __forceinline__ void draw_block(const DevBox& B, DrawRing<RING>* dr, 
         dr->py[s] = ub;
     } else {
         dr->pz[s] = ua;
+        dr->u7[s] = ub;
     }
 }
 
@@ -174,7 +178,7 @@ struct SpecRec {
     int32_t c0[3], c1[3];
     // what it reads for an accepted move
     int32_t two, cnt0, cnt1, cl0, cl1, pad;
-    double dUp, dWp, lnA, u2;    // pair energy change, pair virial change, ln A, pick draw
+    double dUp, dWp, lnA, u2, u7;   // pair energy change, pair virial change, ln A, pick draws
     double p0[3], p1[3];
     double4 rec, elast;
     int32_t cand, evals, incut, pad2;
@@ -184,7 +188,7 @@ struct SpecRec {
 struct SpecKey {
     int32_t type, flags;
     int64_t idx;
-    double u2, lnA, dUp;
+    double u2, u7, lnA, dUp;
 };
 
 // Inclusive prefix sum over the wavefront's lanes (DPP row shifts, then the
@@ -203,10 +207,7 @@ __device__ __forceinline__ int spec_type(const DevBox& B, const U8& u) {
     return (u.u[0] < B.p_disp) ? GCMC_MOVE_DISPLACE : ((u.u[1] < 0.5) ? GCMC_MOVE_DELETE : GCMC_MOVE_INSERT);
 }
 
-__device__ __forceinline__ int64_t spec_pick(double u, int64_t n) {
-    int64_t i = (int64_t)floor(u * (double)n);
-    return i > n - 1 ? n - 1 : i;
-}
+__device__ __forceinline__ int64_t spec_pick(double u2, double u7, int64_t n) { return pick_particle(u2, u7, n); }
 
 __device__ __forceinline__ int32_t spec_axis_cell(double x, double invS, int32_t M) {
     return __builtin_amdgcn_readfirstlane(axis_cell(x, invS, M));
@@ -239,13 +240,14 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
                                           bool no_full, double a_ins, double a_del, SpecRec* out, SpecKey& key) {
     const int lane = threadIdx.x & (kWave - 1);
     int type;
-    double u2, lnA, ux, uy, uz;
+    double u2, u7, lnA, ux, uy, uz;
     int64_t D, I;
     if constexpr (RING > 0) {
         // the round's draws from the ring; lane j < k reads the type of the j-th earlier move
         const int s = (int)((ctr_round + (uint64_t)k) & (uint64_t)(RING - 1));
         type = uni(dr->type[s]);
         u2 = dr->u2[s];
+        u7 = dr->u7[s];
         lnA = dr->lnA[s];
         ux = dr->px[s];
         uy = dr->py[s];
@@ -271,6 +273,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
         }
         type = __builtin_amdgcn_readfirstlane(spec_type(B, u));
         u2 = u.u[2];
+        u7 = u.u[7];
         lnA = log(u.u[3]);
         ux = u.u[4];
         uy = u.u[5];
@@ -286,6 +289,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     key.type = type;
     key.flags = 0;
     key.u2 = u2;
+    key.u7 = u7;
     key.lnA = lnA;
     key.idx = -1;
     key.dUp = 0.0;
@@ -296,6 +300,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
             out->flags = 1;
             out->lnA = 0.0;
             out->u2 = u2;
+            out->u7 = u7;
             out->cand = out->evals = out->incut = 0;
         }
         return;
@@ -311,7 +316,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
         const int64_t n_lo = (N - D) > 1 ? (N - D) : 1, n_hi = N + I;
         int64_t n_c = (int64_t)floor((double)N + (double)I * a_ins - (double)D * a_del + 0.5);
         n_c = uni64(n_c < n_lo ? n_lo : (n_c > n_hi ? n_hi : n_c));
-        idx = spec_pick(u2, n_c);
+        idx = spec_pick(u2, u7, n_c);
         rec = gload(B.pos + idx);
         p0[0] = rec.x; p0[1] = rec.y; p0[2] = rec.z;
     }
@@ -535,6 +540,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
         out->dWp = dWp;
         out->lnA = lnA;
         out->u2 = u2;
+        out->u7 = u7;
         out->type = type;
         out->flags = 0;
         out->two = two;

@@ -53,6 +53,18 @@ int main(void)
     oracle_total_energy(n, x, y, z, NULL, &p, tot, e);
     oracle_position_energy(n, x, y, z, NULL, 1.0, 2.0, 3.0, 0, -1, &p, pe);
     oracle_move_draws(7, 3, 1, u);
+    /* picks at the extremes of both uniforms and of n (one field per pick at 2^31 - 1) */
+    const int64_t pn[6] = {1, 2, 3, 37, 1500000, 2147483647};
+    const double pu[3] = {0.0, u[7], 1.0 - 1.0 / 9007199254740992.0};
+    int64_t picks = 0;
+    for (int q = 0; q < 6; ++q)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                int64_t i = oracle_pick(pu[a], pu[b], pn[q]);
+                if (i < 0 || i >= pn[q])
+                    return 3;
+                picks += i;
+            }
     int64_t counts[ORACLE_MAX_SPECIES] = {n, 0, 0, 0};
     double tail = oracle_tail_energy(counts, &p) + oracle_tail_delta(counts, 0, +1, &p) +
                   oracle_tail_pressure(counts, &p);
@@ -100,8 +112,9 @@ int main(void)
     oracle_virial(nc, x, y, z, sp, &p, vir);
     oracle_total_energy(nc, x, y, z, sp, &p, tot, NULL);
 
-    printf("n=%lld U=%.6f tail=%.6f acc=%d nn=%lld/%lld kept=%d cell=%lld g=%.6f W=%.6f\n", (long long)nc,
-           tot[0], tail, (int)acc, (long long)nn0, (long long)nn1, (int)kept, (long long)c, gx[0] + g1[0], vir[0]);
+    printf("n=%lld U=%.6f tail=%.6f acc=%d nn=%lld/%lld kept=%d cell=%lld g=%.6f W=%.6f picks=%lld\n", (long long)nc,
+           tot[0], tail, (int)acc, (long long)nn0, (long long)nn1, (int)kept, (long long)c, gx[0] + g1[0], vir[0],
+           (long long)picks);
     free(x); free(y); free(z); free(e); free(sp); free(ids); free(lg); free(gx); free(gy); free(gz);
     return 0;
 }

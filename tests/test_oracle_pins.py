@@ -348,7 +348,8 @@ def test_ideal_gas_displacements_all_accepted(orc):
 # Algorithm 2 (a random particle, moved within a cube around it) and
 # Algorithm 1's move draws: the displacement proposal and the particle pick,
 # pinned by their distributions (uniform cube of half-width max_disp, each
-# axis its own draw, wrapped into [0, L); index uniform over 0 .. N-1).
+# axis its own draw, wrapped into [0, L); index uniform over 0 .. N-1, from
+# the bit fields of the spare draw with floor(u N) as the fallback).
 # --------------------------------------------------------------------------
 def _displacement_law_ok(d, half, n_sigma=5.0):
     """d: (m, 3) minimum-image displacements.  Uniform on [-half, half)^3 with
@@ -460,6 +461,87 @@ def test_pick_uniform_while_n_changes(orc):
     assert stats.kstest((idx + w) / nb, "uniform").pvalue > 1e-6
     # the last particle is picked 1/N of the time
     assert abs(np.mean(idx == nb - 1) - np.mean(1.0 / nb)) < 6 * math.sqrt(np.mean(1.0 / nb) / len(idx))
+
+
+def _pick_draws(orc, moves, seed=41):
+    """(u_pick, u_spare) of the first `moves` moves of a stream: u[2] and u[7]."""
+    u = np.array([orc.move_draws(seed, m) for m in range(moves)])
+    return u[:, 2], u[:, 7]
+
+
+def _pick_binned_ok(idx, n, bins=64):
+    """Picks among n > 64 particles: 64 equal index ranges hit uniformly
+    (chi-square on counts with the ranges' exact sizes) and (idx + w) / n with
+    w ~ U[0, 1) uniform (Kolmogorov-Smirnov)."""
+    from scipy import stats
+    bad = []
+    if idx.min() < 0 or idx.max() > n - 1:
+        bad.append("range")
+    edges = (np.arange(bins + 1) * n) // bins
+    cnt = np.histogram(idx, bins=edges)[0]
+    exp = len(idx) * np.diff(edges) / n
+    if stats.chisquare(cnt, exp).pvalue < 1e-6:
+        bad.append("chi2")
+    w = np.random.default_rng(9).random(len(idx))
+    if stats.kstest((idx + w) / n, "uniform").pvalue < 1e-6:
+        bad.append("ks")
+    return bad
+
+
+def test_pick_uniform_at_every_field_width(orc):
+    """The pick is uniform over 0 .. n-1 where the b-bit fields of the spare
+    draw almost always hit (n = 2^b), where about half of each field's values
+    miss (n = 2^(b-1) + 1), where several fields fit in 53 bits and where only
+    one does (b >= 27: the floor(u n) branch then decides half the picks)."""
+    u2, u7 = _pick_draws(orc, 60_000)
+    pick = np.vectorize(orc.pick, otypes=[np.int64])
+    assert np.all(pick(u2[:50], u7[:50], 1) == 0)
+    for n in (2, 3, 5, 17, 33, 37, 63, 64, 65):
+        assert _pick_law_ok(pick(u2, u7, n), n) == [], n
+    for n in (1000, 4097, 1_500_000, (1 << 26) + 1, (1 << 27) + 5, 3 << 25, (1 << 31) - 1):
+        assert _pick_binned_ok(pick(u2, u7, n), n) == [], n
+
+
+def test_pick_rarely_changes_with_n(orc):
+    """What the pick is for: one pair of draws names the same particle at
+    neighbouring N (a move evaluated before an earlier insertion or deletion
+    is decided keeps its particle), unlike floor(u N), which differs about
+    half the time.  (Where n and the neighbouring N straddle a power of two
+    the field width changes and the picks differ.)"""
+    u2, u7 = _pick_draws(orc, 4000)
+    pick = np.vectorize(orc.pick, otypes=[np.int64])
+    assert np.mean(pick(u2, u7, 1 << 18) == pick(u2, u7, (1 << 18) + 1)) < 0.1
+    for n in (300, 4000, 262_000, 1_500_000):
+        a, b, c = pick(u2, u7, n), pick(u2, u7, n + 1), pick(u2, u7, n - 3)
+        assert np.mean(a == b) > 0.9 and np.mean(a == c) > 0.8, n
+        f0, f1 = np.floor(u2 * n), np.floor(u2 * (n + 1))
+        assert np.mean(f0 == f1) < 0.6
+
+
+def test_pick_checks_have_power(orc):
+    """The uniformity checks reject misreadings of the pick built from the same
+    draws: fields one bit too narrow (2^b < n: the top indices come only from
+    the fallback) and a field kept when it equals n."""
+    u2, u7 = _pick_draws(orc, 60_000)
+    k = (u7 * 2.0 ** 53).astype(np.uint64)
+
+    def variant(n, narrow=False, le=False):
+        b = max(0, int(math.ceil(math.log2(n))) - (1 if narrow else 0))
+        out = np.full(len(k), -1, dtype=np.int64)
+        for t in range(1, (53 // b if b else 1) + 1):
+            v = ((k >> np.uint64(53 - b * t)) & np.uint64((1 << b) - 1)).astype(np.int64)
+            hit = (out < 0) & ((v <= n) if le else (v < n))
+            out[hit] = v[hit]
+        fb = np.minimum(np.floor(u2 * n), n - 1).astype(np.int64)
+        return np.where(out < 0, fb, out)
+
+    assert _pick_law_ok(variant(37), 37) == []
+    assert _pick_law_ok(variant(37, narrow=True), 37) != []
+    assert _pick_law_ok(variant(37, le=True), 37) != []
+    assert _pick_law_ok(variant(33, le=True), 33) != []
+    for n in ((1 << 27) + 5, 3 << 25):
+        assert _pick_binned_ok(variant(n), n) == []
+    assert _pick_binned_ok(variant(3 << 25, narrow=True), 3 << 25) != []
 
 
 def test_pick_and_displacement_checks_have_power(orc):
