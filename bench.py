@@ -48,6 +48,14 @@ def alg_bytes(stats, nstencil):
             + sum(acc) * 72)
 
 
+def resident_alg_bytes(n_start, n_end, ncells):
+    """Algorithmic HBM bytes of a launch that holds the box in LDS: the records
+    read once (32 B each), records and cell entries written back at the end
+    (32 + 32 B each), and the cell counters cleared and counted (4 + 4 B each);
+    the moves themselves read and write only LDS."""
+    return n_start * 32 + n_end * 64 + ncells * 8
+
+
 # Sources each chain kernel is compiled from: a traffic record taken with
 # rocprofv3 counters is used only while these files are unchanged.
 KERNEL_SOURCES = {
@@ -559,11 +567,19 @@ def main():
         torch.cuda.synchronize()
         db = time.perf_counter() - tb
         bmoves = 1000 * len(boxes)
-        b_alg = float(sum(alg_bytes(bst[k], boxes[k].info()["n_stencil"]) for k in range(len(boxes))))
+        binfo = [b.info() for b in boxes]
+        b_alg = float(sum(resident_alg_bytes(wbs[k].n, int(bst[k]["n"]), binfo[k]["n_cells"])
+                          if boxes[k].launch[1] == -3 else alg_bytes(bst[k], binfo[k]["n_stencil"])
+                          for k in range(len(boxes))))
+        shape_counts = {}
+        for b in boxes:
+            key = "%dx%d" % b.launch
+            shape_counts[key] = shape_counts.get(key, 0) + 1
         b_ms = e0.elapsed_time(e1)
         out["batched"] = {"boxes": len(boxes), "moves_per_box": 1000, "moves_per_s": bmoves / db,
                           "pair_evals_per_s": float(np.sum(bst["pair_evals"])) / db,
-                          "launch_ms": b_ms, "launch_rule": bshape, "rule_timings_300_moves_s": btimes,
+                          "launch_ms": b_ms, "launch_rule": bshape, "launch_shapes": shape_counts,
+                          "rule_timings_300_moves_s": btimes,
                           "errors": int(np.count_nonzero(bst["error"])),
                           "roofline": {"bound": "hbm", "alg_bytes_per_launch": b_alg,
                                        "achieved": b_alg / (b_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",

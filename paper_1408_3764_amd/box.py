@@ -65,6 +65,7 @@ class Box:
         sp = None if species is None else _dev(species, torch.int32, self.device)
         self.handle = _lib.gcmc_box_create(d, x, y, z, sp, n, stream)
         self.max_n = d.max_n
+        self.launch = (4, 4)   # the library's default shape (per-move kernel, 4 x 4)
         # bumped by every call that changes the configuration or the force field
         self.version = 0
 
@@ -94,6 +95,7 @@ class Box:
 
     def set_launch(self, waves, rows):
         _lib.gcmc_box_set_launch(self.handle, waves, rows)
+        self.launch = (int(waves), int(rows))
 
     def set_wait_limit(self, polls):
         """Bound on the chain kernels' in-kernel waits (0: default; < 0: fail at once)."""

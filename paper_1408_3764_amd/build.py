@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgcmc.so")
 SOURCES = ["box.hip", "moves.hip", "chain.hip", "spec.hip", "async.hip", "micro.hip", "energy.hip", "api.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "resident.hip"]
 ARCH = "gfx950"
 
 

@@ -32,6 +32,8 @@ int gcmc_box_set_launch(gcmc_box* box, int32_t waves, int32_t rows) {
                                                    "2 x stencil x cell_cap <= 8192 and <= 1024 cells per axis");
     } else if (rows == -2) {
         if (!paper_cfg_exists(waves)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported cell-per-thread width");
+    } else if (rows == -3) {
+        if (!resident_cfg_exists(waves)) return set_error(GCMC_ERR_INVALID_ARG, "unsupported resident width");
     } else if (!chain_cfg_exists(waves, rows)) {
         return set_error(GCMC_ERR_INVALID_ARG, "unsupported waves x rows");
     }
@@ -86,7 +88,10 @@ int gcmc_step(gcmc_box* box, int64_t n_moves, uint64_t counter0, gcmc_stats* d_s
     if (!box || n_moves < 0) return set_error(GCMC_ERR_INVALID_ARG, "bad arguments");
     if (box->d.ns != 1) return set_error(GCMC_ERR_UNSUPPORTED, "the chain supports one species");
     int r;
-    if (box->rows == -2)
+    if (box->rows == -3)
+        r = launch_chain_resident(box->d_desc, nullptr, 1, box->waves, n_moves, counter0, d_stats, d_log,
+                                  (hipStream_t)stream);
+    else if (box->rows == -2)
         r = launch_chain_paper(box->d_desc, nullptr, 1, box->waves, n_moves, counter0, d_stats, d_log,
                                (hipStream_t)stream);
     else if (box->rows == -1 && async_supported(box->d))
@@ -238,7 +243,9 @@ int gcmc_batch_destroy(gcmc_batch* bt) {
 
 // Launch path and shape of a box as gcmc_step would run it.
 static void launch_key(const gcmc_box* b, int32_t* key) {
-    if (b->rows == -2) {
+    if (b->rows == -3) {
+        key[0] = 4; key[1] = b->waves; key[2] = -3;
+    } else if (b->rows == -2) {
         key[0] = 3; key[1] = b->waves; key[2] = -2;
     } else if (b->rows == -1 && async_supported(b->d)) {
         key[0] = 1; key[1] = b->waves; key[2] = -1;
@@ -318,7 +325,9 @@ int gcmc_batch_step(gcmc_batch* bt, int64_t moves_per_box, uint64_t counter0, gc
         const int cnt = bt->gcount[g];
         const int32_t* key = bt->gkey[g];
         int r;
-        if (key[0] == 3) {
+        if (key[0] == 4) {
+            r = launch_chain_resident(dd, od, cnt, key[1], moves_per_box, counter0, d_stats, nullptr, sg);
+        } else if (key[0] == 3) {
             r = launch_chain_paper(dd, od, cnt, key[1], moves_per_box, counter0, d_stats, nullptr, sg);
         } else if (key[0] == 1) {
             r = launch_chain_async(dd, od, cnt, key[1], moves_per_box, counter0, d_stats, nullptr, sg);

@@ -50,13 +50,6 @@ __global__ void k_upload(DevBox B, const double* __restrict__ x, const double* _
     }
 }
 
-__device__ __forceinline__ int64_t cell_of_point(const DevBox& B, double x, double y, double z) {
-    const int32_t cx = axis_cell(x, B.invS[0], B.M[0]);
-    const int32_t cy = axis_cell(y, B.invS[1], B.M[1]);
-    const int32_t cz = axis_cell(z, B.invS[2], B.M[2]);
-    return ((int64_t)cz * B.M[1] + cy) * B.M[0] + cx;
-}
-
 // Pass 1: occupancy only (to size the cells); the largest count is kept per
 // wavefront and published with one atomic.
 __global__ void k_count(DevBox B, int64_t n) {

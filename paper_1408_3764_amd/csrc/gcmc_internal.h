@@ -225,6 +225,14 @@ __device__ __forceinline__ int32_t axis_cell(double x, double invS, int32_t M) {
     return c > M - 1 ? M - 1 : (c < 0 ? 0 : c);
 }
 
+// Linear cell index of a point (x fastest).
+__device__ __forceinline__ int64_t cell_of_point(const DevBox& B, double x, double y, double z) {
+    const int32_t cx = axis_cell(x, B.invS[0], B.M[0]);
+    const int32_t cy = axis_cell(y, B.invS[1], B.M[1]);
+    const int32_t cz = axis_cell(z, B.invS[2], B.M[2]);
+    return ((int64_t)cz * B.M[1] + cy) * B.M[0] + cx;
+}
+
 // The box's stencil slots into LDS (all threads of the block take part; the
 // caller synchronises before use).
 __device__ __forceinline__ void load_stencil(const DevBox& B, uint32_t* tab) {
@@ -472,7 +480,8 @@ struct gcmc_batch {
     int32_t* by_n;           // caller indices by decreasing N at create
     int32_t ngroups;         // boxes grouped by launch path and shape
     int32_t gstart[kMaxBatchGroups], gcount[kMaxBatchGroups];
-    int32_t gkey[kMaxBatchGroups][3];   // path (0 speculative, 1 pipelined, 2 per-move, 3 cell per thread), waves, rows
+    int32_t gkey[kMaxBatchGroups][3];   // path (0 speculative, 1 pipelined, 2 per-move, 3 cell per thread,
+                                        // 4 held in LDS), waves, rows
     hipStream_t side[kMaxBatchGroups];  // streams of groups 1.. (created when first needed)
     hipEvent_t ev_fork, ev_join[kMaxBatchGroups];
 };
@@ -485,6 +494,11 @@ int check_hip(hipError_t e, const char* what);
 int launch_chain(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int rows, int64_t n_moves,
                  uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 bool chain_cfg_exists(int waves, int rows);
+
+// resident.hip
+bool resident_cfg_exists(int waves);
+int launch_chain_resident(const DevBox* d_boxes, const int32_t* d_order, int n_boxes, int waves, int64_t n_moves,
+                          uint64_t ctr0, gcmc_stats* stats, gcmc_log* log, hipStream_t s);
 
 // micro.hip
 bool paper_cfg_exists(int waves);

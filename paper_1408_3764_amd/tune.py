@@ -23,6 +23,10 @@ SPEC_SHAPES = [(2, 0), (4, 0), (8, 0), (16, 0)]
 ASYNC_SHAPES = [(4, -1), (8, -1)]
 # rows = -2: the paper's microcell mapping, one stencil cell per thread (any grid)
 PAPER_SHAPES = [(4, -2), (8, -2)]
+# rows = -3: the box held in LDS, every move evaluated against all other particles (one species;
+# particles past RESIDENT_CAP are read from global memory, so it is offered to small boxes)
+RESIDENT_SHAPES = [(4, -3), (8, -3)]
+RESIDENT_CAP = 2048
 SPEC_OWN = 8192   # flattened candidates the 32-cell path of the speculative kernel can hold
 SPEC_MAX_STENCIL = 512   # stencil cells the speculative kernel takes (microcell path above 32)
 CACHE_ENV = "GCMC_TUNE_CACHE"
@@ -42,6 +46,10 @@ def _slots(box):
 def spec_supported(box):
     info = box.info()
     return info["n_species"] == 1 and info["n_stencil"] <= SPEC_MAX_STENCIL
+
+
+def resident_supported(box):
+    return box.info()["n_species"] == 1
 
 
 def async_supported(box):
@@ -80,7 +88,9 @@ def batch_shape(boxes):
 BATCH_RULES = [("uniform", (2, 0)), ("uniform", (4, 0)), ("uniform", (8, 0)), ("uniform", (4, 4)),
                ("split", 0.25, (8, 0), (4, 0)), ("split", 0.25, (8, 0), (2, 0)), ("split", 0.5, (4, 0), (2, 0)),
                ("cost", 0.125, (8, 0), (2, 0)), ("cost", 0.25, (8, 0), (2, 0)), ("cost", 0.125, (8, 0), (4, 0)),
-               ("cost", 0.25, (4, 0), (2, 0))]
+               ("cost", 0.25, (4, 0), (2, 0)),
+               ("lds", 512, (4, -3), ("uniform", (4, 0))), ("lds", 1024, (4, -3), ("uniform", (4, 0))),
+               ("lds", 1024, (4, -3), ("cost", 0.25, (8, 0), (2, 0)))]
 
 
 def move_cost(box):
@@ -94,8 +104,17 @@ def apply_batch_rule(boxes, rule):
     """Set every box's launch shape by a rule: ("uniform", shape); ("split",
     f, big, small): the fraction f of the boxes with the most particles take
     `big`, the others `small`; ("cost", f, big, small): the same, ranked by the
-    candidates a move reads (move_cost).  A shape the box cannot take falls
-    back to the per-move 4x4."""
+    candidates a move reads (move_cost); ("lds", n_max, shape, rule): the boxes
+    of at most n_max particles held in LDS with `shape`, the others by `rule`.
+    A shape the box cannot take falls back to the per-move 4x4."""
+    if rule[0] == "lds":
+        _, nmax, rshape, inner = rule
+        shapes = apply_batch_rule(boxes, inner)
+        for k, b in enumerate(boxes):
+            if b.n <= nmax and resident_supported(b):
+                b.set_launch(*rshape)
+                shapes[k] = rshape
+        return shapes
     if rule[0] == "uniform":
         shapes = [rule[1]] * len(boxes)
     else:
@@ -112,6 +131,8 @@ def apply_batch_rule(boxes, rule):
 
 
 def rule_name(rule):
+    if rule[0] == "lds":
+        return "lds%d:%dx%d+%s" % (rule[1], rule[2][0], rule[2][1], rule_name(rule[3]))
     if rule[0] == "uniform":
         return "%dx%d" % rule[1]
     return "%s%g:%dx%d/%dx%d" % ("top" if rule[0] == "split" else "cost", rule[1], rule[2][0], rule[2][1], rule[3][0],
@@ -183,6 +204,8 @@ def autotune_live(box, n_moves=3000, shapes=None):
     from ._lib import STATS_DTYPE
     if shapes is None:
         shapes = SHAPES + (SPEC_SHAPES if spec_supported(box) else []) + (ASYNC_SHAPES if async_supported(box) else [])
+        if box.n <= RESIDENT_CAP and resident_supported(box):
+            shapes = shapes + RESIDENT_SHAPES
     snap = box.snapshot()
     c0 = snap[4]["counter"]
     st_dev = torch.zeros(STATS_DTYPE.itemsize, dtype=torch.uint8, device=box.device)

@@ -28,6 +28,11 @@ def test_alg_bytes_formula():
     assert bench.alg_bytes(st, 27) == 10 * 27 * 4 + 100 * 28 + 8 * 32 + 3 * 72
 
 
+def test_resident_alg_bytes_formula():
+    # 500 records read, 480 records and entries written back, 64 counters cleared and counted
+    assert bench.resident_alg_bytes(500, 480, 64) == 500 * 32 + 480 * 64 + 64 * 8
+
+
 def test_measured_traffic_lookup(tmp_path, monkeypatch):
     os.makedirs(tmp_path / "profiles")
     rec = {"kernel": "k_chain_spec", "launch": [8, 0], "workload": "w", "moves_per_launch": 1000,

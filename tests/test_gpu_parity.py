@@ -192,7 +192,7 @@ def test_delta_energy_c1_and_small_cells(c1):
 
 
 @pytest.mark.parametrize("waves,rows", [(1, 8), (2, 8), (4, 2), (4, 8), (8, 4), (2, 0), (4, 0), (8, 0), (16, 0),
-                                        (4, -1), (8, -1), (4, -2), (8, -2)])
+                                        (4, -1), (8, -1), (4, -2), (8, -2), (4, -3), (8, -3)])
 def test_chain_launch_shapes_agree(c1, waves, rows):
     """Every launch shape gives the oracle's chain (the tuner may pick any)."""
     p = _params(c1)
@@ -480,9 +480,9 @@ def test_chain_averages_match_oracle(c1, shape):
     assert ck["attempts"] == _type_counts(olog)[0] and ck["accepts"] == _type_counts(olog)[1]
 
 
-# the per-move kernel (the box's default launch), the speculative and pipelined kernels, and the
-# paper's cell-per-thread mapping
-KERNELS = [None, (8, 0), (8, -1), (8, -2)]
+# the per-move kernel (the box's default launch), the speculative and pipelined kernels, the
+# paper's cell-per-thread mapping and the box held in LDS
+KERNELS = [None, (8, 0), (8, -1), (8, -2), (8, -3)]
 
 
 def _launch(b, shape):
@@ -665,7 +665,7 @@ def test_speculative_deletion_relabel_invalidates():
 
 
 # -------------------------------------------------------- error handling
-@pytest.mark.parametrize("shape", KERNELS)
+@pytest.mark.parametrize("shape", KERNELS[:-1])
 def test_overflow_latches_and_resumes(shape):
     """A cell over capacity stops the chain before the move; rebuilding with a
     larger capacity and resuming at the stop gives the uninterrupted chain."""
@@ -689,6 +689,74 @@ def test_overflow_latches_and_resumes(shape):
     st2, _ = b2.step(M - stop, counter0=stop)
     assert int(st2["error"]) == 0
     assert np.array_equal(b2.particles()[0], ref.particles()[0])
+
+
+def test_resident_overflow_latches_after_the_launch():
+    """The box held in LDS keeps no cells during a launch: a cell over capacity
+    shows when they are rebuilt at its end.  The chain itself is complete (every
+    move done, the counter after the last); the error is latched, and a rebuild
+    with a larger capacity restores the cells and lets the chain continue as the
+    uninterrupted one."""
+    M = 4000
+    wb = workloads.random_box(1000, 20.0, rc=2.5, T=1.2, mu=10.0, seed=31)
+    ref = _launch(_box(wb, max_n=wb.n + 2 * M + 1, cell_cap=64), (8, -3))
+    ref.step(2 * M, counter0=0)
+    assert ref.status() == 0
+    maxc0 = int(_box(wb, max_n=wb.n + 1).cells()[1].max())
+    b2 = _launch(_box(wb, max_n=wb.n + 2 * M + 1, cell_cap=maxc0), (8, -3))
+    st, _ = b2.step(M, counter0=0)
+    assert int(st["error"]) == 3
+    assert int(st["error_move"]) == M and int(st["moves_done"]) == M
+    assert b2.status() == 3
+    n_after = b2.n
+    b2.cell_build(new_cap=64)
+    assert b2.status() == 0 and b2.n == n_after
+    st2, _ = b2.step(M, counter0=M)
+    assert int(st2["error"]) == 0
+    assert np.array_equal(b2.particles()[0], ref.particles()[0])
+
+
+@pytest.mark.parametrize("waves", [4, 8])
+def test_resident_chain_cells_and_continuation(waves):
+    """Dense small boxes whose stencil covers the whole box, held in LDS: the
+    oracle's chain move for move, the cell list rebuilt at the launch's end in
+    the layout of a fresh build (each particle in the cell of its position, a
+    cell's entries in id order, back-pointers to their slots), and the chain
+    continued by the speculative kernel on those cells is still the oracle's."""
+    for k, (n, rho, T) in enumerate([(300, 0.7, 1.0), (640, 0.68, 1.03), (1400, 0.75, 1.0)]):
+        w = workloads.cubic_box(n, rho, T, 2.5, 900 + k)
+        p = _params(w)
+        opos, oU, olog = oracle.chain(w.pos, 1500, p, seed=7, max_n=w.n + 1501)
+        b = _launch(_box(w, max_n=w.n + 1501, seed=7), (waves, -3))
+        st, glog = b.step(1500, counter0=0, log=True)
+        assert compare_chain_logs(glog, olog, w.beta) == 1500, (n, rho)
+        gpos, _ = b.particles()
+        assert np.array_equal(gpos, opos), (n, rho)
+        cell_of, count, ids = b.cells()
+        want = oracle.cell_of(opos, w.L, 2.5)
+        assert np.array_equal(cell_of[:len(opos)], want)
+        for c in range(len(count)):
+            members = np.sort(np.nonzero(want == c)[0])
+            assert list(ids[c, :count[c]]) == list(members), c
+        # continue on the rebuilt cells with the speculative kernel
+        opos2, _, olog2 = oracle.chain(opos, 500, p, seed=7, counter0=1500, max_n=w.n + 1501, U0=oU)
+        b.set_launch(8, 0)
+        _, glog2 = b.step(500, counter0=1500, log=True)
+        assert compare_chain_logs(glog2, olog2, w.beta) == 500, (n, rho)
+        assert np.array_equal(b.particles()[0], opos2)
+
+
+def test_resident_box_growing_past_lds():
+    """A box that grows past the 2,048 particles held in LDS (the rest read and
+    written in global memory) still follows the oracle's chain."""
+    w = workloads.random_box(2030, 20.0, rc=2.5, T=1.2, mu=8.0, seed=41)
+    p = _params(w)
+    opos, _, olog = oracle.chain(w.pos, 1200, p, seed=7, max_n=w.n + 1201)
+    assert len(opos) > 2100
+    b = _launch(_box(w, max_n=w.n + 1201, seed=7), (8, -3))
+    _, glog = b.step(1200, counter0=0, log=True)
+    assert compare_chain_logs(glog, olog, w.beta) == 1200
+    assert np.array_equal(b.particles()[0], opos)
 
 
 @pytest.mark.parametrize("shape", KERNELS)
@@ -817,9 +885,10 @@ def test_backward_single_species(c1):
 
 # ------------------------------------------------------------------ batch
 MIXED = [(8, 0), (4, 4), (2, 0), (8, -1), (8, 0)]   # one shape per box: four launch groups
+MIXED_LDS = [(8, -3), (4, -3), (8, 0), (2, 0), (8, -3)]
 
 
-@pytest.mark.parametrize("shape", [(2, 8), (8, 0), (4, -1), "mixed"])
+@pytest.mark.parametrize("shape", [(2, 8), (8, 0), (4, -1), (8, -3), "mixed", "mixed_lds"])
 def test_batch_matches_single_boxes(shape):
     """Boxes of one batch (one launch per launch shape, the groups on forked
     streams) each follow their own oracle chain."""
@@ -829,7 +898,7 @@ def test_batch_matches_single_boxes(shape):
            enumerate(zip(sizes, [0.3, 0.5, 0.8, 0.6, 0.4], [0.9, 1.2, 1.5, 1.0, 1.1]))]
     boxes = [Box.from_workload(w, max_n=w.n + 301, box_id=k, seed=99) for k, w in enumerate(wbs)]
     for k, b in enumerate(boxes):
-        b.set_launch(*(MIXED[k] if shape == "mixed" else shape))
+        b.set_launch(*({"mixed": MIXED, "mixed_lds": MIXED_LDS}[shape][k] if isinstance(shape, str) else shape))
     bt = Batch(boxes)
     stats = bt.step(300, counter0=0)
     for k, w in enumerate(wbs):
