@@ -300,11 +300,11 @@ int gcmc_commit(gcmc_box* box, const gcmc_move* d_move, const double* d_dU_pair,
  * the stencil is larger) and looping over the particles in it; any grid.
  * rows = -3: the box held in LDS (for small boxes, Sec. 5's many simulations
  * on one GPU): the coordinates of particles 0 .. 2047 are copied into the
- * workgroup's local memory once per launch, `waves` (4 or 8) wavefronts
- * evaluate each move together against every other particle (the pairs inside
- * the cutoff are the ones the cell list finds), and an accepted move is
- * committed there; particles past 2047 stay in global memory (correct,
- * slower).  The cell list is not updated during the launch; at its end it is
+ * workgroup's local memory once per launch; rounds of `waves` (4 or 8) moves
+ * are evaluated against every other particle (the pairs inside the cutoff are
+ * the ones the cell list finds) and decided in order, each corrected for the
+ * earlier accepted moves of its round (the same chain, move for move);
+ * particles past 2047 stay in global memory (correct, slower).  The cell list is not updated during the launch; at its end it is
  * rebuilt in gcmc_cell_build's layout (a cell that overflows latches
  * GCMC_ERR_CELL_OVERFLOW after the launch's last move, and a rebuild with a
  * larger capacity clears it).  One species. */

@@ -89,8 +89,9 @@ BATCH_RULES = [("uniform", (2, 0)), ("uniform", (4, 0)), ("uniform", (8, 0)), ("
                ("split", 0.25, (8, 0), (4, 0)), ("split", 0.25, (8, 0), (2, 0)), ("split", 0.5, (4, 0), (2, 0)),
                ("cost", 0.125, (8, 0), (2, 0)), ("cost", 0.25, (8, 0), (2, 0)), ("cost", 0.125, (8, 0), (4, 0)),
                ("cost", 0.25, (4, 0), (2, 0)),
-               ("lds", 512, (4, -3), ("uniform", (4, 0))), ("lds", 1024, (4, -3), ("uniform", (4, 0))),
-               ("lds", 1024, (4, -3), ("cost", 0.25, (8, 0), (2, 0)))]
+               ("lds", 1024, (4, -3), ("uniform", (4, 0))), ("lds", 1536, (4, -3), ("uniform", (4, 0))),
+               ("lds", 1536, (4, -3), ("split", 0.25, (8, 0), (4, 0))), ("lds", 1536, (8, -3), ("uniform", (4, 0))),
+               ("lds", 2048, (8, -3), ("uniform", (8, 0)))]
 
 
 def move_cost(box):
