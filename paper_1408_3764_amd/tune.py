@@ -89,9 +89,10 @@ BATCH_RULES = [("uniform", (2, 0)), ("uniform", (4, 0)), ("uniform", (8, 0)), ("
                ("split", 0.25, (8, 0), (4, 0)), ("split", 0.25, (8, 0), (2, 0)), ("split", 0.5, (4, 0), (2, 0)),
                ("cost", 0.125, (8, 0), (2, 0)), ("cost", 0.25, (8, 0), (2, 0)), ("cost", 0.125, (8, 0), (4, 0)),
                ("cost", 0.25, (4, 0), (2, 0)),
-               ("lds", 1024, (4, -3), ("uniform", (4, 0))), ("lds", 1536, (4, -3), ("uniform", (4, 0))),
-               ("lds", 1536, (4, -3), ("split", 0.25, (8, 0), (4, 0))), ("lds", 1536, (8, -3), ("uniform", (4, 0))),
-               ("lds", 2048, (8, -3), ("uniform", (8, 0)))]
+               ("lds", ((1024, (4, -3)),), ("uniform", (4, 0))), ("lds", ((1536, (4, -3)),), ("uniform", (4, 0))),
+               ("lds", ((768, (4, -3)), (1536, (8, -3))), ("uniform", (4, 0))),
+               ("lds", ((1024, (4, -3)), (2048, (8, -3))), ("uniform", (4, 0))),
+               ("lds", ((768, (4, -3)), (1536, (8, -3))), ("split", 0.25, (8, 0), (4, 0)))]
 
 
 def move_cost(box):
@@ -105,16 +106,22 @@ def apply_batch_rule(boxes, rule):
     """Set every box's launch shape by a rule: ("uniform", shape); ("split",
     f, big, small): the fraction f of the boxes with the most particles take
     `big`, the others `small`; ("cost", f, big, small): the same, ranked by the
-    candidates a move reads (move_cost); ("lds", n_max, shape, rule): the boxes
-    of at most n_max particles held in LDS with `shape`, the others by `rule`.
+    candidates a move reads (move_cost); ("lds", ((n_1, shape_1), (n_2,
+    shape_2), ...), rule): a box of at most n_1 particles held in LDS with
+    shape_1, else of at most n_2 with shape_2, ..., the others by `rule`.
     A shape the box cannot take falls back to the per-move 4x4."""
     if rule[0] == "lds":
-        _, nmax, rshape, inner = rule
+        _, tiers, inner = rule
         shapes = apply_batch_rule(boxes, inner)
         for k, b in enumerate(boxes):
-            if b.n <= nmax and resident_supported(b):
-                b.set_launch(*rshape)
-                shapes[k] = rshape
+            if not resident_supported(b):
+                continue
+            n = b.n
+            for nmax, rshape in tiers:
+                if n <= nmax:
+                    b.set_launch(*rshape)
+                    shapes[k] = rshape
+                    break
         return shapes
     if rule[0] == "uniform":
         shapes = [rule[1]] * len(boxes)
@@ -133,7 +140,7 @@ def apply_batch_rule(boxes, rule):
 
 def rule_name(rule):
     if rule[0] == "lds":
-        return "lds%d:%dx%d+%s" % (rule[1], rule[2][0], rule[2][1], rule_name(rule[3]))
+        return "lds" + ",".join("%d:%dx%d" % (n, sh[0], sh[1]) for n, sh in rule[1]) + "+" + rule_name(rule[2])
     if rule[0] == "uniform":
         return "%dx%d" % rule[1]
     return "%s%g:%dx%d/%dx%d" % ("top" if rule[0] == "split" else "cost", rule[1], rule[2][0], rule[2][1], rule[3][0],

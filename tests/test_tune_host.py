@@ -17,12 +17,12 @@ class FakeBox:
 
 def test_lds_rule_holds_small_boxes_and_applies_the_inner_rule_to_the_rest():
     boxes = [FakeBox(300), FakeBox(512), FakeBox(513), FakeBox(20000, n_cells=2197), FakeBox(400, ns=2)]
-    rule = ("lds", 512, (4, -3), ("uniform", (4, 0)))
+    rule = ("lds", ((300, (4, -3)), (512, (8, -3))), ("uniform", (4, 0)))
     shapes = tune.apply_batch_rule(boxes, rule)
     # the two-species box cannot take the speculative kernel either: per-move 4x4
-    assert [b.launch for b in boxes] == [(4, -3), (4, -3), (4, 0), (4, 0), (4, 4)]
-    assert shapes[:4] == [(4, -3), (4, -3), (4, 0), (4, 0)]
-    assert tune.rule_name(rule) == "lds512:4x-3+4x0"
+    assert [b.launch for b in boxes] == [(4, -3), (8, -3), (4, 0), (4, 0), (4, 4)]
+    assert shapes[:4] == [(4, -3), (8, -3), (4, 0), (4, 0)]
+    assert tune.rule_name(rule) == "lds300:4x-3,512:8x-3+4x0"
 
 
 def test_cost_rule_ranks_by_candidates_per_move():
