@@ -227,7 +227,8 @@ def paper_studies(sizes, cutoffs):
     chain against N (density 0.67, rc = 2.5) and against the cutoff (87,296
     particles in 128K sigma^3, rc = 2.5 ... 4.25), for the chain without a cell
     list (all pairs), with traditional cells (the per-move kernel and, where it
-    applies, the speculative kernel) and with microcells of about rc/2 (the
+    applies, the speculative kernel; boxes of at most 2,048 particles also held
+    in LDS) and with microcells of about rc/2 (the
     per-move kernel, the paper's one-cell-per-thread mapping and the
     speculative kernel)."""
     import numpy as np
@@ -265,6 +266,11 @@ def paper_studies(sizes, cutoffs):
         if tune.spec_supported(b):
             b.set_launch(8, 0)
             r["cells_speculative"] = rate(b, moves)[0]
+        # a box small enough to hold in LDS
+        r["held_in_lds"] = None
+        if wb.n <= tune.RESIDENT_CAP and tune.resident_supported(b):
+            b.set_launch(8, -3)
+            r["held_in_lds"] = rate(b, moves)[0]
         base = r["cells"]
         b.close()
         b = Box.from_workload(wb, max_n=wb.n + 4 * moves + 1000, cell_m=[2 * m for m in base])
@@ -285,9 +291,10 @@ def paper_studies(sizes, cutoffs):
             b.set_launch(8, 0)
             r["microcells_speculative"] = rate(b, moves)[0]
         b.close()
-        log("%s: all pairs %.0f, cells %.0f (%dx%d)%s, microcells %.0f (paper mapping %.0f%s) moves/s" % (
+        log("%s: all pairs %.0f, cells %.0f (%dx%d)%s%s, microcells %.0f (paper mapping %.0f%s) moves/s" % (
             wb.name, r["all_pairs"], r["cells_per_move"], best[2][0], best[2][1],
             "" if r["cells_speculative"] is None else ", speculative %.0f" % r["cells_speculative"],
+            "" if r["held_in_lds"] is None else ", held in LDS %.0f" % r["held_in_lds"],
             r["microcells_per_move"], r["microcells_paper_mapping"],
             "" if r["microcells_speculative"] is None else ", speculative %.0f" % r["microcells_speculative"]))
         return r

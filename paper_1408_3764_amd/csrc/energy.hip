@@ -233,7 +233,8 @@ __device__ __forceinline__ double home_energy(const DevBox& B, const PassConst& 
                     const double dz = image_diff(o[u].z - me.z, K.L[2], K.hL[2], WRAP);
                     r2 = (dx * dx + dy * dy) + dz * dz;
                     q = MIX ? sa * ns + meta_species(o[u].w) : 0;
-                    in = r2 < K.rc2 && (MIX ? te4[q] : K.e4) != 0.0;
+                    // (a pair with eps = 0 is queued too and adds zero)
+                    in = r2 < K.rc2;
                 }
                 const uint64_t m = __ballot(in);
                 if (in) {
@@ -784,10 +785,13 @@ struct GradAcc {
 
 // Force and parameter-derivative sums of one home particle over its stencil
 // (WRAP: apply the minimum image).
+// teo[q] = eps4 / sigma of species pair q (the sigma derivative's prefactor, so
+// no pair takes a square root).
 template <bool MIX, bool WRAP>
 __device__ __forceinline__ void home_gradient(const DevBox& B, const PassConst& K, const uint32_t* tab,
-                                              const double* te4, const double* ts2, const double4& me, int32_t myid,
-                                              int sa, int ns, int32_t cx, int32_t cy, int32_t cz, GradAcc& A) {
+                                              const double* te4, const double* ts2, const double* teo,
+                                              const double4& me, int32_t myid, int sa, int ns, int32_t cx, int32_t cy,
+                                              int32_t cz, GradAcc& A) {
     for (int t = 0; t < B.nstencil; ++t) {
         const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
         const int32_t nc = gload(B.count + nb);
@@ -808,15 +812,16 @@ __device__ __forceinline__ void home_gradient(const DevBox& B, const PassConst& 
                 const int sb = meta_species(o.w);
                 const int q = MIX ? sa * ns + sb : 0;
                 const double eps4 = MIX ? te4[q] : K.e4, sig2 = MIX ? ts2[q] : K.s2;
-                const double sr2 = sig2 / r2;
+                const double ir2 = 1.0 / r2;
+                const double sr2 = sig2 * ir2;
                 const double s6 = sr2 * sr2 * sr2;
                 const double s12 = s6 * s6;
-                const double coef = (6.0 * eps4 / r2) * (2.0 * s12 - s6);
+                const double coef = (6.0 * eps4 * ir2) * (2.0 * s12 - s6);
                 A.gx += coef * dx;
                 A.gy += coef * dy;
                 A.gz += coef * dz;
                 const double t_e = 0.5 * 4.0 * (s12 - s6);
-                const double t_s = 0.5 * (eps4 / sqrt(sig2)) * (12.0 * s12 - 6.0 * s6);
+                const double t_s = 0.5 * teo[q] * (12.0 * s12 - 6.0 * s6);
                 if (MIX) {
 #pragma unroll
                     for (int b = 0; b < kMaxSpecies; ++b)
@@ -839,9 +844,11 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
     __shared__ double te4[kMaxSpecies * kMaxSpecies], ts2[kMaxSpecies * kMaxSpecies];
+    __shared__ double teo[kMaxSpecies * kMaxSpecies];
     const DevBox& B = *boxp;
     load_stencil(B, tab);
     load_species_tables(B, te4, ts2);
+    if (threadIdx.x < kMaxSpecies * kMaxSpecies) teo[threadIdx.x] = B.eps4[threadIdx.x] / sqrt(B.sig2[threadIdx.x]);
     const PassConst K = pass_const(B);
     __syncthreads();
     const int64_t h = (int64_t)blockIdx.x * kBlk + threadIdx.x;
@@ -863,7 +870,7 @@ __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ 
         cell_coords(B, c, cx, cy, cz);
         // (one loop for every wavefront: a second, wrap-free copy as in the energy pass costs
         // more in registers than it saves here)
-        home_gradient<MIX, true>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz, A);
+        home_gradient<MIX, true>(B, K, tab, te4, ts2, teo, me, myid, sa, ns, cx, cy, cz, A);
         if (grad) {
             grad[myid] = A.gx;
             grad[n + myid] = A.gy;

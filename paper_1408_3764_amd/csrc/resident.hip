@@ -404,9 +404,12 @@ __global__ __launch_bounds__(kWave* W) void k_chain_resident(const DevBox* __res
                 if (disp) att0 += 1;
                 else if (ins) att1 += 1;
                 else att2 += 1;
-                cand += R.cand;
-                evals += R.evals;
-                incut += R.incut;
+                // work counters of the decided moves, kept by lane 0 (the lanes are summed at the end)
+                if (lane == 0) {
+                    cand += R.cand;
+                    evals += R.evals;
+                    incut += R.incut;
+                }
                 const int64_t n_old = Nc;
                 if (ok) {
                     if (lane == 0) {

@@ -730,6 +730,15 @@ def test_resident_chain_cells_and_continuation(waves):
         b = _launch(_box(w, max_n=w.n + 1501, seed=7), (waves, -3))
         st, glog = b.step(1500, counter0=0, log=True)
         assert compare_chain_logs(glog, olog, w.beta) == 1500, (n, rho)
+        # work counters: every decided move read all other particles of its round's state (N
+        # within the oracle's range over the chain), a displacement's two positions each
+        dn = np.where(olog["accepted"] == 1, np.where(olog["type"] == 1, 1, np.where(olog["type"] == 2, -1, 0)), 0)
+        traj = n + np.concatenate([[0], np.cumsum(dn)])
+        c = int(st["candidates"])
+        assert 1500 * (traj.min() - 1) <= c <= 1500 * traj.max(), (c, traj.min(), traj.max())
+        n_disp = int((olog["type"] == 0).sum())
+        assert int(st["pair_evals"]) <= c + n_disp * traj.max() and int(st["pair_evals"]) >= c
+        assert 0 < int(st["in_cutoff"]) < int(st["pair_evals"])
         gpos, _ = b.particles()
         assert np.array_equal(gpos, opos), (n, rho)
         cell_of, count, ids = b.cells()
