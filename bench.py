@@ -614,7 +614,20 @@ def main():
         out["batched"]["graph"] = {"launches": 10, "moves_per_launch": 100, "replay_ms": g_ms,
                                    "moves_per_s": bmoves / (g_ms / 1e3),
                                    "errors": int(np.count_nonzero(gstats["error"]))}
-        log("batched: one launch of 1,000 moves/box %.3f ms; graph of 10 x 100 moves/box %.3f ms" % (b_ms, g_ms))
+        # one more 1,000-move launch on the chains as they now stand (3,000 moves past the initial
+        # configurations: the densest boxes have lost a fifth or more of their particles), for
+        # comparison with timings taken on continued chains
+        c0e, c1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        c0e.record(stream)
+        cst = bt.step(1000, counter0=COUNTER_CONTINUE)
+        c1e.record(stream)
+        torch.cuda.synchronize()
+        out["batched"]["continued"] = {"moves_before": 3000, "launch_ms": c0e.elapsed_time(c1e),
+                                       "n_total_before": int(sum(int(v) for v in gstats["n"])),
+                                       "errors": int(np.count_nonzero(cst["error"]))}
+        log("batched: one launch of 1,000 moves/box %.3f ms; graph of 10 x 100 moves/box %.3f ms; a further "
+            "1,000-move launch on the continued chains %.3f ms" % (b_ms, g_ms, c0e.elapsed_time(c1e)))
         bt.close()
         for b in boxes:
             b.close()

@@ -527,6 +527,28 @@ def test_allpairs_chain_parity(c1):
     assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(pos, c1.L, c1.rc))
 
 
+def test_allpairs_chain_many_workgroups_and_its_capacity_error():
+    """The all-pairs chain over many workgroups (a box of 24,000 particles: 12
+    chunks of 2,048), against the oracle move for move and with its cell list
+    kept; then the capacity error: a chain that fills max_n stops there with
+    GCMC_ERR_CAPACITY."""
+    w = workloads.random_box(24_000, 34.0, rc=2.5, T=1.2, mu=-2.0, seed=12)
+    p = _params(w)
+    opos, _, olog = oracle.chain(w.pos, 400, p, seed=5, max_n=w.n + 401)
+    b = _box(w, max_n=w.n + 401, seed=5)
+    stats, glog = b.step(400, counter0=0, log=True, all_pairs=True)
+    assert compare_chain_logs(glog, olog, w.beta, "all-pairs chain, 12 workgroups") == 400
+    assert int(stats["moves_done"]) == 400 and int(stats["error"]) == 0
+    pos, _ = b.particles()
+    assert np.array_equal(pos, opos)
+    cell_of, _, _ = b.cells()
+    assert np.array_equal(cell_of.astype(np.int64), oracle.cell_of(pos, w.L, w.rc))
+    from paper_1408_3764_amd.box import Box
+    c = Box(np.zeros((0, 3)), [8.0] * 3, 2.5, mu=5.0, max_n=5, seed=1)
+    st, _ = c.step(500, all_pairs=True)
+    assert int(st["error"]) == 4 and int(st["n"]) == 5
+
+
 def test_host_driven_commit_matches_chain():
     """gcmc_delta_energy + gcmc_commit, driven from the host with the oracle's decisions."""
     wb = workloads.random_box(200, 9.0, seed=12, T=1.2)
