@@ -45,13 +45,26 @@ namespace gcmc {
 // (Eqs. 3-5; the log prefactors for N come from the round's tables): one
 // routine for the decision and for the per-move log written after the round,
 // so both hold the same bits.
-__device__ __forceinline__ double spec_arg(const DevBox& B, int type, double dUp, int64_t N, int64_t base,
-                                           const double* lp_ins, const double* lp_del, double tk, double& dUt) {
+// The parts of it that do not depend on the evaluation (the tail change and the log
+// prefactor at N), and the rest; the decision and the per-move log both go through them.
+__device__ __forceinline__ void spec_arg_pre(int type, int64_t N, int64_t base, const double* lp_ins,
+                                             const double* lp_del, double tk, double& dUt, double& lpref) {
     const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
     dUt = is_disp ? 0.0 : tk * (is_ins ? (2.0 * (double)N + 1.0) : (1.0 - 2.0 * (double)N));
+    lpref = is_disp ? 0.0 : (is_ins ? lp_ins[N - base] : lp_del[N - base]);
+}
+
+__device__ __forceinline__ double spec_arg_fin(const DevBox& B, int type, double dUp, double dUt, double lpref) {
+    const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
     const double dU = dUp + dUt;
-    const double lpref = is_disp ? 0.0 : (is_ins ? lp_ins[N - base] : lp_del[N - base]);
     return is_disp ? -(B.beta * dU) : (is_ins ? lpref + B.beta * (B.mu - dU) : lpref - B.beta * (B.mu + dU));
+}
+
+__device__ __forceinline__ double spec_arg(const DevBox& B, int type, double dUp, int64_t N, int64_t base,
+                                           const double* lp_ins, const double* lp_del, double tk, double& dUt) {
+    double lpref;
+    spec_arg_pre(type, N, base, lp_ins, lp_del, tk, dUt, lpref);
+    return spec_arg_fin(B, type, dUp, dUt, lpref);
 }
 
 // Entry t of a prefactor table starting at N = nb: t < 4W, the log insertion
@@ -155,23 +168,31 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
         // ------------------------------------------------ evaluate W moves
         if (m + wv < n_moves) {
             SpecKey key;
+            // what the decision at every N the move can meet (within W - 1 of the round's N; lane o
+            // takes N - (W - 1) + o) needs before the evaluation ends: the pick still the evaluated
+            // one, the tail change and the prefactor -- computed while the picked record is loaded
+            const int64_t np = N - (W - 1) + lane;
+            const bool lane_n = lane < 2 * W - 1 && np >= 0;
+            bool pick_ok = false;
+            double dUt = 0.0, lpref = 0.0;
+            auto early = [&](int type, double u2, double u7, int64_t idx) {
+                if (lane_n) {
+                    pick_ok = type == GCMC_MOVE_INSERT || spec_pick(u2, u7, np) == idx;
+                    spec_arg_pre(type, np, lbase, lpi, lpd, tk, dUt, lpref);
+                }
+            };
             spec_eval<CR, NG, 2 * W>(B, tab, offs, own[wv], pq[wv], &dring, ctr0 + (uint64_t)m, wv, N, no_full, a_ins,
-                                     a_del, &recs[wv], key);
-            // the decision at every N the move can meet (within W - 1 of the round's N; lane o takes
-            // N - (W - 1) + o): the pick still the evaluated one, and the Metropolis test (Eqs. 3-5)
-            // with the tail change and prefactor at that N -- the same operations the commit
-            // would do, so the commit only reads the bit of its N
+                                     a_del, &recs[wv], key, early);
+            // the Metropolis test (Eqs. 3-5) at each of those N -- the operations the commit would
+            // do, so the commit only reads the bit of its N
             if (!(key.flags & 1)) {
-                const int64_t np = N - (W - 1) + lane;
-                bool valid = false, acc = false;
-                if (lane < 2 * W - 1 && np >= 0) {
-                    valid = key.type == GCMC_MOVE_INSERT || spec_pick(key.u2, key.u7, np) == key.idx;
-                    double dUt;
-                    const double arg = spec_arg(B, key.type, key.dUp, np, lbase, lpi, lpd, tk, dUt);
+                bool acc = false;
+                if (lane_n) {
+                    const double arg = spec_arg_fin(B, key.type, key.dUp, dUt, lpref);
                     const double dU = key.dUp + dUt;
                     acc = dU == dU && key.lnA < arg;
                 }
-                const uint64_t pm = __ballot(valid), am = __ballot(acc);
+                const uint64_t pm = __ballot(pick_ok), am = __ballot(acc);
                 if (lane == 0) {
                     recs[wv].pickmask = (uint32_t)pm;
                     recs[wv].okmask = (uint32_t)am;

@@ -228,16 +228,23 @@ __device__ __forceinline__ bool in_stencil(const DevBox& B, int32_t x, int32_t y
     return in;
 }
 
+// The caller's work that needs only the move's type, draws and pick, run by
+// the evaluation while the picked record is being loaded (none by default).
+struct SpecNoEarly {
+    __device__ __forceinline__ void operator()(int, double, double, int64_t) const {}
+};
+
 // Wavefront k evaluates move ctr_round + k against the current state.  NG:
 // 0 for the 32-cell path, else the number of groups of 64 stencil cells the
 // microcell path provides (see above).  RING > 0: the draws come from `dr`
 // (the moves ctr_round .. ctr_round + k must be in it); RING = 0: computed
 // here, for k < 16.  pq: this wavefront's pair queue (kPairRing doubles of
 // LDS).
-template <int CR, int NG, int RING>
+template <int CR, int NG, int RING, typename Early = SpecNoEarly>
 __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, const int32_t* offs, void* ownbuf,
                                           double* pq, const DrawRing<RING>* dr, uint64_t ctr_round, int k, int64_t N,
-                                          bool no_full, double a_ins, double a_del, SpecRec* out, SpecKey& key) {
+                                          bool no_full, double a_ins, double a_del, SpecRec* out, SpecKey& key,
+                                          const Early& early = Early()) {
     const int lane = threadIdx.x & (kWave - 1);
     int type;
     double u2, u7, lnA, ux, uy, uz;
@@ -311,6 +318,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
     if (type == GCMC_MOVE_INSERT) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) p0[a] = wrap_into_box(B.L[a] * ud[a], B.L[a]);
+        early(type, u2, u7, idx);
     } else {
         // the pick at the N expected at commit from the running acceptance rates
         const int64_t n_lo = (N - D) > 1 ? (N - D) : 1, n_hi = N + I;
@@ -318,6 +326,7 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
         n_c = uni64(n_c < n_lo ? n_lo : (n_c > n_hi ? n_hi : n_c));
         idx = spec_pick(u2, u7, n_c);
         rec = gload(B.pos + idx);
+        early(type, u2, u7, idx);   // the caller's work that needs only the pick, while the record loads
         p0[0] = rec.x; p0[1] = rec.y; p0[2] = rec.z;
     }
     int32_t c0[3], c1[3];
