@@ -204,8 +204,12 @@ __device__ __forceinline__ void drain_pairs(const PassConst& K, const double* te
 // Energy (or pair virial) of each lane's home particle over its stencil.  Every
 // lane of the wavefront calls it (lanes without a home particle pass live =
 // false and have no candidates); the loops run to the wavefront's largest cell
-// count so that the queue is drained with all lanes active.
-template <bool MIX, bool VIR, bool WRAP>
+// count so that the queue is drained with all lanes active.  HALF: each pair
+// once, for a total only -- the stencil offsets after (0, 0, 0) in z, y, x
+// order and, in the home cell, the particles with a larger id (the stencil is
+// symmetric and no axis is covered whole, so every other pair of cells is
+// reached from exactly one side).
+template <bool MIX, bool VIR, bool WRAP, bool HALF>
 __device__ __forceinline__ double home_energy(const DevBox& B, const PassConst& K, const uint32_t* tab,
                                               const double* te4, const double* ts2, const double4& me, int32_t myid,
                                               int sa, int ns, int32_t cx, int32_t cy, int32_t cz, bool live,
@@ -214,7 +218,15 @@ __device__ __forceinline__ double home_energy(const DevBox& B, const PassConst& 
     Q.acc[lane] = 0.0;
     uint32_t head = 0, tail = 0;   // wave-uniform positions in the ring
     for (int t = 0; t < B.nstencil; ++t) {
-        const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
+        const uint32_t pk = tab[t];
+        bool centre = false;
+        if (HALF) {
+            const int32_t ox = (int32_t)(pk & 0x3FF) - B.k[0], oy = (int32_t)((pk >> 10) & 0x3FF) - B.k[1];
+            const int32_t oz = (int32_t)(pk >> 20) - B.k[2];
+            if (oz < 0 || (oz == 0 && (oy < 0 || (oy == 0 && ox < 0)))) continue;
+            centre = (ox | oy | oz) == 0;
+        }
+        const int64_t nb = stencil_cell(B, pk, cx, cy, cz);
         const int32_t nc = live ? gload(B.count + nb) : 0;
         const int32_t ncmax = wave_max_i32_uniform(nc);
         const double4* ne = B.ent + nb * B.cap;
@@ -227,7 +239,8 @@ __device__ __forceinline__ double home_energy(const DevBox& B, const PassConst& 
                 bool in = false;
                 double r2 = 0.0;
                 int q = 0;
-                if (j + u < nc && meta_low(o[u].w) != myid) {
+                const int32_t oid = meta_low(o[u].w);
+                if (j + u < nc && (HALF && centre ? oid > myid : oid != myid)) {
                     const double dx = image_diff(o[u].x - me.x, K.L[0], K.hL[0], WRAP);
                     const double dy = image_diff(o[u].y - me.y, K.L[1], K.hL[1], WRAP);
                     const double dz = image_diff(o[u].z - me.z, K.L[2], K.hL[2], WRAP);
@@ -258,7 +271,9 @@ __device__ __forceinline__ double home_energy(const DevBox& B, const PassConst& 
 
 // Per-particle energies e_i; partial[blockIdx] = sum of e_i of the block.
 // VIR: the pair virial -r du/dr in place of the pair energy (pressure).
-template <bool MIX, bool VIR = false>
+// HALF: each pair once (no e_out); the partial is twice the block's sum of
+// pairs, exactly, so that the finish's half of the sum is the sum of pairs.
+template <bool MIX, bool VIR = false, bool HALF = false>
 __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__ boxp, const int32_t* __restrict__ home,
                                                        int64_t n, double* e_out, double* partial) {
     __shared__ uint32_t tab[kMaxStencil];
@@ -288,13 +303,13 @@ __global__ __launch_bounds__(kBlk) void k_total_cells(const DevBox* __restrict__
     // the wrap is skipped when no lane of the wavefront needs it
     double ei;
     if (__ballot(live && !stencil_inside(B, cx, cy, cz)) != 0)
-        ei = home_energy<MIX, VIR, true>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz, live, Q);
+        ei = home_energy<MIX, VIR, true, HALF>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz, live, Q);
     else
-        ei = home_energy<MIX, VIR, false>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz, live, Q);
+        ei = home_energy<MIX, VIR, false, HALF>(B, K, tab, te4, ts2, me, myid, sa, ns, cx, cy, cz, live, Q);
     if (!live) ei = 0.0;
-    if (live && e_out) e_out[myid] = ei;
+    if (!HALF && live && e_out) e_out[myid] = ei;
     const double s = block_sum(ei, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (threadIdx.x == 0) partial[blockIdx.x] = HALF ? 2.0 * s : s;
 }
 
 // --------------------------------------------------------- all-pairs total
@@ -929,6 +944,9 @@ __global__ __launch_bounds__(kBlk) void k_grad_finish(const DevBox* __restrict__
 // Scratch layout of a cell-list pass (in doubles): the block partials (times
 // `stride` doubles per block), then, as int32, the particles in cell order
 // (n), the cell offsets (ncells) and the scan-block totals.
+// Each pair once needs a stencil that reaches every other pair of cells from
+// exactly one side: no axis it covers whole.
+static bool half_stencil_ok(const DevBox& hb) { return !(hb.full[0] | hb.full[1] | hb.full[2]); }
 static int64_t cell_pass_blocks(int64_t n) { return n > 0 ? (n + kBlk - 1) / kBlk : 1; }
 static int64_t scan_blocks(const DevBox& hb) { return (hb.ncells + kScanCells - 1) / kScanCells; }
 static int64_t cell_pass_doubles(const DevBox& hb, int64_t n, int64_t stride) {
@@ -966,12 +984,21 @@ int launch_total(const DevBox& hb, const DevBox* d_box, int32_t maxc, bool all_p
         nb = cell_pass_blocks(n);
         if (cell_pass_doubles(hb, n, 1) > partial_len) return -1;
         const int32_t* home = cell_order(hb, n, partial, nb, s);
-        if (mix)
+        // a total alone takes each pair once
+        if (!e_out && half_stencil_ok(hb)) {
+            if (mix)
+                hipLaunchKernelGGL((k_total_cells<true, false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box,
+                                   home, n, nullptr, partial);
+            else
+                hipLaunchKernelGGL((k_total_cells<false, false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box,
+                                   home, n, nullptr, partial);
+        } else if (mix) {
             hipLaunchKernelGGL(k_total_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, e_out,
                                partial);
-        else
+        } else {
             hipLaunchKernelGGL(k_total_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, e_out,
                                partial);
+        }
     }
     hipLaunchKernelGGL(k_total_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, U);
     return 0;
@@ -983,8 +1010,15 @@ int launch_virial(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* p
     const int64_t nb = cell_pass_blocks(n);
     if (cell_pass_doubles(hb, n, 1) > partial_len) return -1;
     const int32_t* home = cell_order(hb, n, partial, nb, s);
-    if (hb.ns > 1)
+    const bool half = half_stencil_ok(hb);
+    if (hb.ns > 1 && half)
+        hipLaunchKernelGGL((k_total_cells<true, true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
+                           nullptr, partial);
+    else if (hb.ns > 1)
         hipLaunchKernelGGL((k_total_cells<true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
+                           nullptr, partial);
+    else if (half)
+        hipLaunchKernelGGL((k_total_cells<false, true, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
                            nullptr, partial);
     else
         hipLaunchKernelGGL((k_total_cells<false, true>), dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n,
