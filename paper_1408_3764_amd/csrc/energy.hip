@@ -798,113 +798,168 @@ struct GradAcc {
     double de[kMaxSpecies], ds[kMaxSpecies];
 };
 
-// Force and parameter-derivative sums of one home particle over its stencil
-// (WRAP: apply the minimum image).
+// Force and parameter-derivative sums of each lane's home particle over its
+// stencil (WRAP: apply the minimum image), organised like the energy pass:
+// the candidate loop only forms the distance vector and r^2, the pairs inside
+// the cutoff wait in a per-wavefront ring in LDS, and every 64 of them are
+// evaluated one per lane (the force coefficient and the two parameter terms)
+// and added to their home particle's sums with LDS atomics, so the pair
+// arithmetic runs at full lane occupancy instead of under a mostly empty mask.
 // teo[q] = eps4 / sigma of species pair q (the sigma derivative's prefactor, so
 // no pair takes a square root).
-template <bool MIX, bool WRAP>
+struct GradQueue {
+    double* dx;   // [kRing] each: the distance vector (r^2 is formed again from it, bit for bit)
+    double* dy;
+    double* dz;
+    int32_t* meta;   // [kRing] home lane | other species << 8 | species pair << 16
+    double* gx;      // [kWave] force sums of each lane's home particle
+    double* gy;
+    double* gz;
+    double* de;      // [kWave * S] eps and sigma terms by the other particle's species
+    double* ds;
+};
+
+// S: a bound on the number of species (1, 2 or kMaxSpecies), the width of the
+// per-particle parameter sums in LDS.
+template <int S>
+__device__ __forceinline__ void drain_grad(const PassConst& K, const double* te4, const double* ts2,
+                                           const double* teo, const GradQueue& Q, uint32_t head, uint32_t cnt,
+                                           int lane) {
+    // the ring entries written by other lanes of this wavefront are visible to every lane
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+    if ((uint32_t)lane < cnt) {
+        constexpr bool MIX = S > 1;
+        const uint32_t e = (head + (uint32_t)lane) & (kRing - 1);
+        const double dx = Q.dx[e], dy = Q.dy[e], dz = Q.dz[e];
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        const int32_t mt = Q.meta[e];
+        const int h = mt & (kWave - 1), sb = (mt >> 8) & 0xFF, q = mt >> 16;
+        const double eps4 = MIX ? te4[q] : K.e4, sig2 = MIX ? ts2[q] : K.s2;
+        const double ir2 = 1.0 / r2;
+        const double sr2 = sig2 * ir2;
+        const double s6 = sr2 * sr2 * sr2;
+        const double s12 = s6 * s6;
+        const double coef = (6.0 * eps4 * ir2) * (2.0 * s12 - s6);
+        atomicAdd(&Q.gx[h], coef * dx);
+        atomicAdd(&Q.gy[h], coef * dy);
+        atomicAdd(&Q.gz[h], coef * dz);
+        const int slot = h * S + sb;
+        atomicAdd(&Q.de[slot], 0.5 * 4.0 * (s12 - s6));
+        atomicAdd(&Q.ds[slot], 0.5 * teo[q] * (12.0 * s12 - 6.0 * s6));
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+}
+
+template <int S, bool WRAP>
 __device__ __forceinline__ void home_gradient(const DevBox& B, const PassConst& K, const uint32_t* tab,
                                               const double* te4, const double* ts2, const double* teo,
                                               const double4& me, int32_t myid, int sa, int ns, int32_t cx, int32_t cy,
-                                              int32_t cz, GradAcc& A) {
+                                              int32_t cz, bool live, const GradQueue& Q) {
+    constexpr bool MIX = S > 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    Q.gx[lane] = Q.gy[lane] = Q.gz[lane] = 0.0;
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+        Q.de[lane * S + b] = 0.0;
+        Q.ds[lane * S + b] = 0.0;
+    }
+    uint32_t head = 0, tail = 0;   // wave-uniform positions in the ring
     for (int t = 0; t < B.nstencil; ++t) {
         const int64_t nb = stencil_cell(B, tab[t], cx, cy, cz);
-        const int32_t nc = gload(B.count + nb);
+        const int32_t nc = live ? gload(B.count + nb) : 0;
+        const int32_t ncmax = wave_max_i32_uniform(nc);
         const double4* ne = B.ent + nb * B.cap;
-        for (int j = 0; j < nc; j += kUnroll) {
+        for (int j = 0; j < ncmax; j += kUnroll) {
             double4 ob[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) ob[u] = gload(ne + (j + u < nc ? j + u : j));
+            for (int u = 0; u < kUnroll; ++u) ob[u] = gload(ne + (j + u < nc ? j + u : 0));
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const double4& o = ob[u];
-                if (j + u >= nc || meta_low(o.w) == myid) continue;
-                const double dx = image_diff(o.x - me.x, K.L[0], K.hL[0], WRAP);
-                const double dy = image_diff(o.y - me.y, K.L[1], K.hL[1], WRAP);
-                const double dz = image_diff(o.z - me.z, K.L[2], K.hL[2], WRAP);
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                if (!(r2 < K.rc2) || r2 == 0.0) continue;
-                const int sb = meta_species(o.w);
-                const int q = MIX ? sa * ns + sb : 0;
-                const double eps4 = MIX ? te4[q] : K.e4, sig2 = MIX ? ts2[q] : K.s2;
-                const double ir2 = 1.0 / r2;
-                const double sr2 = sig2 * ir2;
-                const double s6 = sr2 * sr2 * sr2;
-                const double s12 = s6 * s6;
-                const double coef = (6.0 * eps4 * ir2) * (2.0 * s12 - s6);
-                A.gx += coef * dx;
-                A.gy += coef * dy;
-                A.gz += coef * dz;
-                const double t_e = 0.5 * 4.0 * (s12 - s6);
-                const double t_s = 0.5 * teo[q] * (12.0 * s12 - 6.0 * s6);
-                if (MIX) {
-#pragma unroll
-                    for (int b = 0; b < kMaxSpecies; ++b)
-                        if (b == sb) {
-                            A.de[b] += t_e;
-                            A.ds[b] += t_s;
-                        }
-                } else {
-                    A.de[0] += t_e;
-                    A.ds[0] += t_s;
+                bool in = false;
+                double dx = 0.0, dy = 0.0, dz = 0.0;
+                int32_t mt = 0;
+                if (j + u < nc && meta_low(o.w) != myid) {
+                    dx = image_diff(o.x - me.x, K.L[0], K.hL[0], WRAP);
+                    dy = image_diff(o.y - me.y, K.L[1], K.hL[1], WRAP);
+                    dz = image_diff(o.z - me.z, K.L[2], K.hL[2], WRAP);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    const int sb = MIX ? meta_species(o.w) : 0;
+                    mt = lane | (sb << 8) | ((MIX ? sa * ns + sb : 0) << 16);
+                    in = r2 < K.rc2 && r2 != 0.0;
+                }
+                const uint64_t m = __ballot(in);
+                if (in) {
+                    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    const uint32_t e = (tail + below) & (kRing - 1);
+                    Q.dx[e] = dx;
+                    Q.dy[e] = dy;
+                    Q.dz[e] = dz;
+                    Q.meta[e] = mt;
+                }
+                tail += (uint32_t)__builtin_popcountll(m);
+                if (tail - head >= (uint32_t)kWave) {
+                    drain_grad<S>(K, te4, ts2, teo, Q, head, kWave, lane);
+                    head += kWave;
                 }
             }
         }
     }
+    if (tail != head) drain_grad<S>(K, te4, ts2, teo, Q, head, tail - head, lane);
+    // (drain_grad ends with a wavefront fence: every lane's sums are complete and visible)
 }
 
-template <bool MIX>
+template <int S>
 __global__ __launch_bounds__(kBlk) void k_grad_cells(const DevBox* __restrict__ boxp, const int32_t* __restrict__ home,
                                                       int64_t n, double* grad, double* partial) {
     __shared__ uint32_t tab[kMaxStencil];
     __shared__ double red[kBlk / kWave];
     __shared__ double te4[kMaxSpecies * kMaxSpecies], ts2[kMaxSpecies * kMaxSpecies];
     __shared__ double teo[kMaxSpecies * kMaxSpecies];
+    __shared__ double q_dx[kBlk / kWave][kRing], q_dy[kBlk / kWave][kRing], q_dz[kBlk / kWave][kRing];
+    __shared__ int32_t q_meta[kBlk / kWave][kRing];
+    __shared__ double a_gx[kBlk], a_gy[kBlk], a_gz[kBlk], a_de[kBlk * S], a_ds[kBlk * S];
     const DevBox& B = *boxp;
     load_stencil(B, tab);
     load_species_tables(B, te4, ts2);
     if (threadIdx.x < kMaxSpecies * kMaxSpecies) teo[threadIdx.x] = B.eps4[threadIdx.x] / sqrt(B.sig2[threadIdx.x]);
     const PassConst K = pass_const(B);
     __syncthreads();
+    const int w = threadIdx.x / kWave;
+    const GradQueue Q{q_dx[w], q_dy[w], q_dz[w], q_meta[w], a_gx + w * kWave, a_gy + w * kWave,
+                      a_gz + w * kWave, a_de + w * kWave * S, a_ds + w * kWave * S};
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t h = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const int ns = uni(B.ns);
-    GradAcc A;
-    A.gx = A.gy = A.gz = 0.0;
-#pragma unroll
-    for (int b = 0; b < kMaxSpecies; ++b) A.de[b] = A.ds[b] = 0.0;
-    int sa = 0;
     const bool own = h < n;
-    if (own) {
-        int32_t slot = home[h];
-        if (slot < 0 || (int64_t)slot >= B.ncells * B.cap) slot = 0;   // counters and N disagree: stay in bounds
-        const int64_t c = slot / B.cap;
-        const double4 me = gload(B.ent + slot);
-        const int32_t myid = meta_low(me.w);
-        sa = meta_species(me.w);
-        int32_t cx, cy, cz;
-        cell_coords(B, c, cx, cy, cz);
-        // (one loop for every wavefront: a second, wrap-free copy as in the energy pass costs
-        // more in registers than it saves here)
-        home_gradient<MIX, true>(B, K, tab, te4, ts2, teo, me, myid, sa, ns, cx, cy, cz, A);
-        if (grad) {
-            grad[myid] = A.gx;
-            grad[n + myid] = A.gy;
-            grad[2 * n + myid] = A.gz;
-        }
+    int32_t slot = own ? home[h] : 0;
+    if (slot < 0 || (int64_t)slot >= B.ncells * B.cap) slot = 0;   // counters and N disagree: stay in bounds
+    const int64_t c = slot / B.cap;
+    const double4 me = gload(B.ent + slot);
+    const int32_t myid = meta_low(me.w);
+    const int sa = own ? meta_species(me.w) : 0;
+    int32_t cx, cy, cz;
+    cell_coords(B, c, cx, cy, cz);
+    // the wrap is skipped when no lane of the wavefront needs it
+    if (__ballot(own && !stencil_inside(B, cx, cy, cz)) != 0)
+        home_gradient<S, true>(B, K, tab, te4, ts2, teo, me, myid, sa, ns, cx, cy, cz, own, Q);
+    else
+        home_gradient<S, false>(B, K, tab, te4, ts2, teo, me, myid, sa, ns, cx, cy, cz, own, Q);
+    if (own && grad) {
+        grad[myid] = Q.gx[lane];
+        grad[n + myid] = Q.gy[lane];
+        grad[2 * n + myid] = Q.gz[lane];
     }
     // parameter partials: entry (a, b) gets the lanes with own species a
     for (int a = 0; a < ns; ++a) {
         for (int b = 0; b < ns; ++b) {
             const bool mine = own && sa == a;
-            double le = 0.0, ls = 0.0;   // A.de[b], A.ds[b] read with static indices (registers, not scratch)
-#pragma unroll
-            for (int q = 0; q < kMaxSpecies; ++q)
-                if (q == b) {
-                    le = A.de[q];
-                    ls = A.ds[q];
-                }
-            const double ve = block_sum(mine ? le : 0.0, red);
-            const double vs = block_sum(mine ? ls : 0.0, red);
+            const int k = lane * S + b;
+            const double ve = block_sum(mine ? Q.de[k] : 0.0, red);
+            const double vs = block_sum(mine ? Q.ds[k] : 0.0, red);
             if (threadIdx.x == 0) {
                 partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + a * ns + b] = ve;
                 partial[(size_t)blockIdx.x * 2 * kMaxSpecies * kMaxSpecies + kMaxSpecies * kMaxSpecies + a * ns + b] =
@@ -1043,10 +1098,14 @@ int launch_grad(const DevBox& hb, const DevBox* d_box, int32_t maxc, double* gra
     (void)maxc;
     const int64_t nb = cell_pass_blocks(n);
     const int32_t* home = cell_order(hb, n, partial, nb * 2 * kMaxSpecies * kMaxSpecies, s);
-    if (hb.ns > 1)
-        hipLaunchKernelGGL(k_grad_cells<true>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad, partial);
+    // the width of the per-particle parameter sums in LDS: 1, 2 or up to kMaxSpecies species
+    if (hb.ns > 2)
+        hipLaunchKernelGGL(k_grad_cells<kMaxSpecies>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad,
+                           partial);
+    else if (hb.ns == 2)
+        hipLaunchKernelGGL(k_grad_cells<2>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad, partial);
     else
-        hipLaunchKernelGGL(k_grad_cells<false>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad, partial);
+        hipLaunchKernelGGL(k_grad_cells<1>, dim3((unsigned)nb), dim3(kBlk), 0, s, d_box, home, n, grad, partial);
     if (deps || dsig)
         hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(kBlk), 0, s, d_box, partial, nb, deps, dsig);
     return 0;

@@ -342,6 +342,27 @@ def test_virial_parity(case):
     assert abs(got["P"] - ref["P"]) <= 1e-10 * (abs(ref["P"]) + ref["sumabs"] / (3 * V))
 
 
+@pytest.mark.parametrize("cm", [None, [16, 16, 16], [24, 24, 24]])
+def test_total_energy_each_pair_once(c1, cm):
+    """A total alone takes each pair once (the stencil offsets after (0, 0, 0)
+    and larger ids in the home cell, also on pruned microcell stencils); with
+    per-particle energies the full stencil runs.  Both equal the oracle's U
+    within 1e-10 of the magnitude sum, and each other to the last few bits; the
+    pair virial likewise."""
+    p = _params(c1)
+    ref = oracle.total_energy(c1.pos, p)
+    kw = {} if cm is None else {"cell_m": np.array(cm, dtype=np.int32)}
+    b = _box(c1, **kw)
+    half = b.total_energy()
+    full = b.total_energy(per_particle=True)
+    for got in (half, full):
+        assert abs(got["U_pair"] - ref["U_pair"]) <= 1e-10 * ref["sumabs"]
+    assert half["U_pair"] == pytest.approx(full["U_pair"], rel=1e-12)
+    assert half["U_pair"] == pytest.approx(0.5 * math.fsum(full["e"]), rel=1e-12)
+    vref = oracle.virial(c1.pos, p)
+    assert abs(b.virial()["W"] - vref["W"]) <= 1e-10 * vref["sumabs"]
+
+
 def test_total_energy_c1(c1):
     p = _params(c1)
     ref = oracle.total_energy(c1.pos, p)
