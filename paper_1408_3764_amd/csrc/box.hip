@@ -50,9 +50,38 @@ __global__ void k_upload(DevBox B, const double* __restrict__ x, const double* _
     }
 }
 
+// The block's species counts (wave-uniform per-wavefront totals) and largest
+// occupancy, added to the box state with one atomic each per block: atomics
+// of every wavefront on the same few words serialise at the L2 and took most of
+// a cell build's time.  Every thread of the block calls it.
+template <int BLK>
+__device__ __forceinline__ void publish_counts(BoxState* st, int ns, const int64_t* nsp, int32_t maxc) {
+    __shared__ int64_t s_nsp[BLK / kWave][kMaxSpecies];
+    __shared__ int32_t s_max[BLK / kWave];
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; ++q) s_nsp[w][q] = nsp[q];
+        s_max[w] = maxc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t mx = 0;
+        for (int v = 0; v < BLK / kWave; ++v) mx = s_max[v] > mx ? s_max[v] : mx;
+        for (int q = 0; q < ns; ++q) {
+            int64_t t = 0;
+            for (int v = 0; v < BLK / kWave; ++v) t += s_nsp[v][q];
+            if (t) atomicAdd((unsigned long long*)&st->nsp[q], (unsigned long long)t);
+        }
+        if (mx > 0) atomicMax(&st->maxcount, mx);
+    }
+}
+
+constexpr int kCountBlocks = 1024;   // grid of the occupancy and sort passes (grid-stride loops)
+
 // Pass 1: occupancy only (to size the cells); the largest count is kept per
-// wavefront and published with one atomic.
-__global__ void k_count(DevBox B, int64_t n) {
+// wavefront and published once per block.
+__global__ __launch_bounds__(256) void k_count(DevBox B, int64_t n) {
     int32_t mx = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double4 p = B.pos[i];
@@ -61,7 +90,8 @@ __global__ void k_count(DevBox B, int64_t n) {
         mx = k + 1 > mx ? k + 1 : mx;
     }
     mx = wave_max_i32_uniform(mx);
-    if ((threadIdx.x & (kWave - 1)) == 0 && mx > 0) atomicMax(&B.st->maxcount, mx);
+    const int64_t none[kMaxSpecies] = {0, 0, 0, 0};
+    publish_counts<256>(B.st, 0, none, mx);
 }
 
 // Pass 2: claim a slot and write the cell entry.
@@ -80,8 +110,8 @@ __global__ void k_bin(DevBox B, int64_t n) {
 
 // Pass 3 (capacities above 64): order each cell by particle id, set the
 // back-pointers, and gather the maximum occupancy and the species counts (kept
-// per thread, summed per wavefront, one atomic each).
-__global__ void k_sort_cells(DevBox B) {
+// per thread, summed per wavefront, published once per block).
+__global__ __launch_bounds__(256) void k_sort_cells(DevBox B) {
     int32_t nsp[kMaxSpecies] = {0, 0, 0, 0};
     int32_t maxc = 0;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < B.ncells;
@@ -109,14 +139,11 @@ __global__ void k_sort_cells(DevBox B) {
         }
         maxc = cnt > maxc ? cnt : maxc;
     }
-    const int lane = threadIdx.x & (kWave - 1);
+    int64_t tot[kMaxSpecies];
 #pragma unroll
-    for (int q = 0; q < kMaxSpecies; ++q) {
-        const int32_t t = wave_sum_i32_uniform(nsp[q]);
-        if (lane == 0 && t > 0) atomicAdd((unsigned long long*)&B.st->nsp[q], (unsigned long long)t);
-    }
+    for (int q = 0; q < kMaxSpecies; ++q) tot[q] = wave_sum_i32_uniform(nsp[q]);
     maxc = wave_max_i32_uniform(maxc);
-    if (lane == 0 && maxc > 0) atomicMax(&B.st->maxcount, maxc);
+    publish_counts<256>(B.st, B.ns, tot, maxc);
 }
 
 // Pass 3 with one wavefront per cell, for capacities up to 64: lane k holds the
@@ -124,8 +151,8 @@ __global__ void k_sort_cells(DevBox B) {
 // number of the cell's entries with a smaller id, and every entry is written
 // once, straight to its slot (the layout is the one the per-thread sort above
 // produces).  Species counts and the largest occupancy are kept per wavefront
-// over its cells and added once at the end.
-__global__ __launch_bounds__(256) void k_sort_cells_wave(DevBox B) {
+// over its cells and published once per block.
+__global__ __launch_bounds__(1024) void k_sort_cells_wave(DevBox B) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -155,11 +182,7 @@ __global__ __launch_bounds__(256) void k_sort_cells_wave(DevBox B) {
         for (int q = 0; q < kMaxSpecies; ++q) nsp[q] += __popcll(__ballot(lane < cnt && sp == q));
         maxc = cnt > maxc ? cnt : maxc;
     }
-    if (lane == 0) {
-        for (int q = 0; q < ns; ++q)
-            if (nsp[q]) atomicAdd((unsigned long long*)&B.st->nsp[q], (unsigned long long)nsp[q]);
-        if (maxc) atomicMax(&B.st->maxcount, maxc);
-    }
+    publish_counts<1024>(B.st, ns, nsp, maxc);
 }
 
 // keep: a rebuild keeps the latched error, its move, the move counter and the
@@ -399,10 +422,11 @@ static int bin_particles(gcmc_box* box, int64_t n, hipStream_t s, bool keep, dou
     k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
     if (n > 0) k_bin<<<grid_for(n), 256, 0, s>>>(B, n);
     if (B.cap <= kWave) {
-        const int64_t blocks = std::min<int64_t>((B.ncells + 3) / 4, 4096);
-        k_sort_cells_wave<<<(unsigned)blocks, 256, 0, s>>>(B);
+        // 16 wavefronts per block, one cell at a time each (a cell's loads are a dependent chain)
+        const int64_t blocks = std::min<int64_t>((B.ncells + 15) / 16, kCountBlocks);
+        k_sort_cells_wave<<<(unsigned)blocks, 1024, 0, s>>>(B);
     } else {
-        k_sort_cells<<<grid_for(B.ncells), 256, 0, s>>>(B);
+        k_sort_cells<<<std::min(grid_for(B.ncells), kCountBlocks), 256, 0, s>>>(B);
     }
     GCMC_HIP(hipGetLastError());
     return GCMC_OK;
@@ -524,7 +548,7 @@ int gcmc_box_create(const gcmc_box_desc* desc, const double* d_x, const double* 
     k_reset_state<<<1, 1, 0, s>>>(B.st, n, 0.0, 0.0, 0);
     if (n > 0) k_upload<<<grid_for(n), 256, 0, s>>>(B, d_x, d_y, d_z, d_species, n);
     k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
-    if (n > 0) k_count<<<grid_for(n), 256, 0, s>>>(B, n);
+    if (n > 0) k_count<<<std::min(grid_for(n), kCountBlocks), 256, 0, s>>>(B, n);
     BoxState h;
     if ((rc = read_state(box, &h, s))) {
         free_box(box);
@@ -742,7 +766,7 @@ int gcmc_box_rescale(gcmc_box* box, const double* h_L, double* d_U, void* stream
     // the running virial is NaN until gcmc_virial sets it at the new volume
     k_reset_state<<<1, 1, 0, s>>>(B.st, h.n, h.u_pair, std::nan(""), 1);
     k_fill_i32<<<grid_for(B.ncells), 256, 0, s>>>(B.count, B.ncells, 0);
-    if (h.n > 0) k_count<<<grid_for(h.n), 256, 0, s>>>(B, h.n);
+    if (h.n > 0) k_count<<<std::min(grid_for(h.n), kCountBlocks), 256, 0, s>>>(B, h.n);
     BoxState h2;
     if ((rc_ = read_state(box, &h2, s))) return rc_;
     const int32_t cap = h2.maxcount > B.cap ? auto_cap(h2.maxcount) : B.cap;
