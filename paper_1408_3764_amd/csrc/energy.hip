@@ -793,10 +793,6 @@ __device__ int commit_ap(const DevBox& B, const APTrial& T, const double4& rec, 
 // particle id; parameter partials per block: [0, ns^2) d eps, [ns^2, 2 ns^2)
 // d sigma, each pair met twice contributing half from each end.  One lane per
 // particle in cell order, as the total energy.
-struct GradAcc {
-    double gx, gy, gz;
-    double de[kMaxSpecies], ds[kMaxSpecies];
-};
 
 // Force and parameter-derivative sums of each lane's home particle over its
 // stencil (WRAP: apply the minimum image), organised like the energy pass:
