@@ -250,9 +250,17 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     }
                 }
                 const SpecRec& R = recs[k];
-                const int type = __builtin_amdgcn_readfirstlane(R.type);
+                // what every decision reads, loaded together (one LDS round trip, not one per test)
+                const int32_t r_type = R.type, r_flags = R.flags;
+                const uint32_t r_pm = R.pickmask, r_om = R.okmask;
+                const int64_t r_idx = R.idx;
+                int32_t cc[3] = {R.c0[0], R.c0[1], R.c0[2]};
+                int32_t cn[3] = {R.c1[0], R.c1[1], R.c1[2]};
+                asm volatile("" ::"v"(r_type), "v"(r_flags), "v"(r_pm), "v"(r_om), "v"(r_idx), "v"(cc[0]), "v"(cc[1]),
+                             "v"(cc[2]), "v"(cn[0]), "v"(cn[1]), "v"(cn[2]));
+                const int type = __builtin_amdgcn_readfirstlane(r_type);
                 // the empty-box rejection holds only while the box is still empty
-                if (R.flags & 1) {
+                if (r_flags & 1) {
                     if (N != 0) break;
                     if (lane == 0) {
                         after_n[k] = N;
@@ -261,15 +269,13 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                     }
                     continue;
                 }
-                const int64_t idx = R.idx;
+                const int64_t idx = r_idx;
                 const int o = (int)(N - n_round) + (W - 1);   // 0 .. 2W - 2 (N moved by at most k < W)
                 if (type != GCMC_MOVE_INSERT) {
-                    if (((R.pickmask >> o) & 1u) == 0) break;
+                    if (((r_pm >> o) & 1u) == 0) break;
                     if (__ballot(lane < ntouch && touched == (int32_t)idx) != 0) break;
                 }
                 // a cell changed by an earlier commit of this round inside one of its stencils
-                int32_t cc[3] = {R.c0[0], R.c0[1], R.c0[2]};
-                int32_t cn[3] = {R.c1[0], R.c1[1], R.c1[2]};
                 bool hit = false;
                 if (lane < nmod)
                     hit = in_stencil(B, modx, mody, modz, cc) ||
@@ -277,7 +283,7 @@ __global__ __launch_bounds__(kWave* W) void k_chain_spec(const DevBox* __restric
                 if (__ballot(hit) != 0) break;
                 // ---- decide at the current N
                 const bool is_disp = type == GCMC_MOVE_DISPLACE, is_ins = type == GCMC_MOVE_INSERT;
-                const bool ok = ((R.okmask >> o) & 1u) != 0;
+                const bool ok = ((r_om >> o) & 1u) != 0;
                 const int two = R.two;
                 const int32_t cnt0 = R.cnt0, cnt1 = R.cnt1;
                 if (ok) {
