@@ -908,9 +908,13 @@ def test_set_positions_checks_its_length(c1):
 
 
 # --------------------------------------------------------------- gradients
-def test_backward_parity_mixture():
-    eps, sig = workloads.lorentz_berthelot([1.0, 1.2], [1.0, 0.8])
-    wb = workloads.random_box(400, 12.0, rc=3.0, seed=8, species_counts=[200, 200], eps=eps, sigma=sig)
+@pytest.mark.parametrize("counts", [[200, 200], [150, 150, 100]])
+def test_backward_parity_mixture(counts):
+    """Forces and parameter derivatives of a binary and a ternary mixture (the
+    pass keeps its per-particle parameter sums in LDS sized by the species
+    count: two species, or up to four)."""
+    eps, sig = workloads.lorentz_berthelot([1.0, 1.2, 0.9][: len(counts)], [1.0, 0.8, 1.1][: len(counts)])
+    wb = workloads.random_box(400, 12.0, rc=3.0, seed=8, species_counts=counts, eps=eps, sigma=sig)
     p = _params(wb)
     g_ref, de_ref, ds_ref = oracle.gradients(wb.pos, p, species=wb.species)
     b = _box(wb)
