@@ -520,6 +520,8 @@ __device__ __forceinline__ void spec_eval(const DevBox& B, const uint32_t* tab, 
                 }
 #pragma unroll
                 for (int r = 0; r < CR; ++r) {
+                    // rows past the window's last candidate hold nothing for any lane (wave-uniform)
+                    if (base + r * kWave >= q1) break;
                     const bool valid = ok[r];
                     n_cand += valid ? 1 : 0;
                     spec_pair_queue(B, type, two, valid, sec[r], p0, p1, e[r], wrap, pq, qhead, qtail, sa, sb, wa,
